@@ -1,0 +1,219 @@
+/*
+ * sgo.h -- C-ABI of the MI355X plane-wave Kohn-Sham energy/force engine.
+ *
+ * The library evaluates, for one atomic structure or for a whole population
+ * of candidate structures, the self-consistent Gamma-point plane-wave
+ * Kohn-Sham total energy and the Hellmann-Feynman forces: the energy-and-force
+ * call that every local relaxation of every differential-evolution candidate
+ * makes in the structure-search engine (Section 2.1, Fig. 1; Section 2.4).
+ * The electronic minimisation follows the all-band preconditioned conjugate
+ * gradient scheme of Algorithm 1 (residual, preconditioning, projection,
+ * line minimisation, orthogonalisation, subspace diagonalisation) inside the
+ * density-mixing SCF loop described in Section 2.4.
+ *
+ * Units: Hartree atomic units throughout.  Lattice = three row vectors a_1,
+ * a_2, a_3 in bohr (row-major 3x3, lattice[3*i + k] = k-th Cartesian
+ * component of a_i).  Positions are Cartesian bohr, energies Ha, forces
+ * Ha/bohr, stress Ha/bohr^3 with stress_ab = (1/Omega) dE/d(eps_ab).
+ *
+ * Conventions:
+ *  - Every function returns SGO_OK (0) or a negative status; nothing throws
+ *    across the boundary.  sgo_last_error() returns a message owned by the
+ *    handle (thread-local storage when the handle is NULL).
+ *  - Input arrays are host memory, copied during the call; the caller keeps
+ *    ownership.  Output arrays are caller-owned host memory, written during
+ *    the call.  All device memory is allocated and owned by the handle.
+ *  - Handles are not thread-safe; use one handle per host thread.  All device
+ *    work of a handle runs on its stream (default: the device's null stream,
+ *    or the one set with sgo_set_stream).
+ *  - Call order for a single structure: set_species (each species used) ->
+ *    set_cell -> set_atoms -> set_cutoff -> scf -> {energy, forces,
+ *    eigenvalues, stress}.  A violation returns SGO_ESTATE.  Calling
+ *    set_atoms after scf keeps the wavefunctions and density as a warm start;
+ *    set_cell, set_cutoff or set_species discard them.
+ */
+#ifndef SGO_H
+#define SGO_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SGO_OK = 0,
+  SGO_EINVAL = -1,   /* bad argument: NULL pointer, size out of range, ... */
+  SGO_ENOMEM = -2,   /* device or host allocation failed */
+  SGO_EDEVICE = -3,  /* HIP runtime error (no device, launch failure, ...) */
+  SGO_ENOTCONV = -4, /* SCF hit max_iter; results are readable but flagged */
+  SGO_ENUMERIC = -5, /* NaN/Inf or a non-positive overlap pivot */
+  SGO_ESTATE = -6    /* call made out of order */
+};
+
+/* Arithmetic of the bulk wavefunction work (FFTs, H*psi, projector and
+ * subspace products).  The subspace Cholesky and diagonalisation, the Ewald
+ * sum, the density/potential grid work and every energy sum are FP64 in all
+ * modes. */
+enum { SGO_FP64 = 0, SGO_FP32 = 1 };
+
+enum { SGO_LOCAL_AH = 0, SGO_LOCAL_GAUSS = 1 };
+enum { SGO_OCC_FIXED = 0, SGO_OCC_FERMI = 1 };
+
+/* Analytic pseudopotential of one species.
+ *  local_kind == SGO_LOCAL_AH:
+ *     v(r) = -(Z/r) erf(sqrt(p0) r) + (p1 + p2 r^2) exp(-p0 r^2)
+ *  local_kind == SGO_LOCAL_GAUSS (p0 = rloc):
+ *     v(r) = -(Z/r) erf(r/(sqrt2 p0)) + exp(-r^2/(2 p0^2)) [p1 + p2 (r/p0)^2]
+ *  nkb Kleinman-Bylander channels (l = 0 or 1), radial projector
+ *     p_l(r) ~ r^l exp(-r^2/(2 kb_r^2)), normalised, channel energy kb_h.
+ *  rho0_width: width (bohr) of the normalised Gaussian of charge Z placed on
+ *  each atom to build the starting density. */
+typedef struct {
+  double Z;
+  int local_kind;
+  double p[3];
+  int nkb;
+  int kb_l[4];
+  double kb_r[4];
+  double kb_h[4];
+  double rho0_width;
+} sgo_species;
+
+typedef struct {
+  int max_iter;      /* SCF iterations (default 100) */
+  int ncg;           /* all-band CG steps per SCF iteration (default 3) */
+  int ncg_first;     /* CG steps in the first iteration (default 8) */
+  double tol_e;      /* |E_k - E_{k-1}| stop, Ha per atom (default 1e-5) */
+  double tol_rho;    /* Omega/Ntot sum|rho_out - rho_in| / N_el stop (default 1e-4) */
+  double mix_alpha;  /* Pulay/Kerker mixing weight (default 0.5) */
+  double kerker_q0;  /* Kerker wavevector, bohr^-1 (default 0.8) */
+  int history;       /* Pulay history length, 2..8 (default 8) */
+  unsigned seed;     /* seed of the starting wavefunctions (default 1) */
+  int use_graph;     /* capture one SCF iteration in a HIP graph (default 0) */
+} sgo_scf_opts;
+
+typedef struct {
+  int iterations;
+  int converged;
+  double de;         /* last |E_k - E_{k-1}| (Ha, whole cell) */
+  double drho;       /* last density residual (see tol_rho) */
+} sgo_scf_info;
+
+typedef struct {
+  double total;      /* free energy E - sigma S (Ha) */
+  double kinetic, nonlocal, local, hartree, xc, ewald, entropy; /* entropy = -sigma S */
+  double band;       /* sum_i f_i eps_i */
+  double fermi;      /* chemical potential (Ha) */
+} sgo_energy_terms;
+
+typedef struct sgo_ctx sgo_ctx;
+typedef struct sgo_batch sgo_batch;
+
+/* Fill opts with the defaults listed above. */
+void sgo_default_opts(sgo_scf_opts* opts);
+
+/* Version string of the library (static storage). */
+const char* sgo_version(void);
+
+/* Create a handle on HIP device `device` with precision SGO_FP64/SGO_FP32.
+ * *out receives the handle (caller destroys it with sgo_destroy). */
+int sgo_create(sgo_ctx** out, int device, int precision);
+int sgo_destroy(sgo_ctx* ctx);
+
+/* Run all device work of the handle on `hip_stream` (a hipStream_t, e.g. the
+ * current PyTorch stream); NULL selects the null stream. */
+int sgo_set_stream(sgo_ctx* ctx, void* hip_stream);
+
+/* Register species `id` (0 <= id < 16).  Copies *sp. */
+int sgo_set_species(sgo_ctx* ctx, int id, const sgo_species* sp);
+
+/* Set the cell (9 doubles, rows a_i); rejects non-positive volume. */
+int sgo_set_cell(sgo_ctx* ctx, const double lattice[9]);
+
+/* Set natoms atoms: species ids [natoms] and Cartesian positions
+ * [natoms*3].  Rejects unknown species and atoms closer than 1e-3 bohr
+ * (minimum image).  Warm start is kept if the count and species agree. */
+int sgo_set_atoms(sgo_ctx* ctx, int natoms, const int* species, const double* pos);
+
+/* Plane-wave cutoff (Ha), FFT grid fft[3] (each N_i must hold the sphere:
+ * N_i >= 2 max|m_i| + 1, and factor into 2, 3, 5; at most 128) and the
+ * number of bands (must hold the electrons for fixed occupations).
+ * Occupations: SGO_OCC_FIXED (2 per band, lowest first) or SGO_OCC_FERMI
+ * with smearing width sigma (Ha). */
+int sgo_set_cutoff(sgo_ctx* ctx, double ecut, const int fft[3], int nbands,
+                   int occ_kind, double sigma);
+
+/* Self-consistent field solve (Section 2.4, Algorithm 1).  opts may be NULL
+ * (defaults); info may be NULL.  Returns SGO_ENOTCONV if max_iter is reached
+ * (results still readable). */
+int sgo_scf(sgo_ctx* ctx, const sgo_scf_opts* opts, sgo_scf_info* info);
+
+/* Total free energy and (nullable) its parts after sgo_scf. */
+int sgo_energy(sgo_ctx* ctx, double* etot, sgo_energy_terms* terms);
+
+/* Hellmann-Feynman forces [natoms*3] after sgo_scf (local, nonlocal and
+ * Ewald parts; -dF/dR of the free energy at self-consistency). */
+int sgo_forces(sgo_ctx* ctx, double* forces);
+
+/* Fixed-basis stress tensor [9] after sgo_scf. */
+int sgo_stress(sgo_ctx* ctx, double stress[9]);
+
+/* Eigenvalues [nbands] (ascending) and, if occ != NULL, occupations. */
+int sgo_eigenvalues(sgo_ctx* ctx, double* eig, double* occ);
+
+/* Adjoint of the energy: grad_pos = gE * dE/dR = -gE * F  [natoms*3] and,
+ * if grad_lattice != NULL, gE * dE/d(lattice) [9] at a fixed Miller set. */
+int sgo_adjoint(sgo_ctx* ctx, double gE, double* grad_pos, double* grad_lattice);
+
+/* Drop the warm-start wavefunctions and density. */
+int sgo_reset(sgo_ctx* ctx);
+
+/* Sizes of the plane-wave basis: number of half-sphere G vectors (the
+ * Gamma-point packing stores one of each +-G pair) and of projectors. */
+int sgo_basis_size(sgo_ctx* ctx, int* npw_half, int* nproj);
+
+/* Miller indices [npw_half*3] of the half-sphere in storage order.  A band is
+ * stored as 2*npw_half reals: for G != 0, sqrt2 Re c_G, sqrt2 Im c_G; for
+ * G = 0, c_0 and 0.  The dot product of two stored bands is <psi_a|psi_b>. */
+int sgo_basis_millers(sgo_ctx* ctx, int* millers);
+
+/* Apply H[V] to nb packed bands (host arrays): veff [N3][N2][N1] (x fastest,
+ * r = sum n_i/N_i a_i), psi [nb][2*npw_half] -> hpsi (same layout).  Uses the
+ * atoms and cutoff already set; needs no SCF.  For checking the operator. */
+int sgo_apply_h(sgo_ctx* ctx, const double* veff, int nb, const double* psi, double* hpsi);
+
+/* Current SCF output density rho(r) [N3][N2][N1] and effective potential
+ * V_eff(r) (either may be NULL) after sgo_scf. */
+int sgo_get_density(sgo_ctx* ctx, double* rho, double* veff);
+
+const char* sgo_last_error(const sgo_ctx* ctx);
+
+/* ---- Population of candidates, solved together (Section 2.4 last
+ * paragraph: the relaxations of one generation may run side by side).  The
+ * batch holds up to `capacity` candidates with their own cells, atoms,
+ * cutoffs, grids and band counts; every kernel launch covers all active
+ * candidates, and converged candidates are masked out. */
+int sgo_batch_create(sgo_batch** out, int device, int precision, int capacity);
+int sgo_batch_destroy(sgo_batch* b);
+int sgo_batch_set_stream(sgo_batch* b, void* hip_stream);
+int sgo_batch_set_species(sgo_batch* b, int id, const sgo_species* sp);
+/* Append a candidate; *index_out receives its index (add order). */
+int sgo_batch_add(sgo_batch* b, const double lattice[9], int natoms, const int* species,
+                  const double* pos, double ecut, const int fft[3], int nbands,
+                  int occ_kind, double sigma, int* index_out);
+/* Move the atoms of candidate i (warm start kept). */
+int sgo_batch_set_atoms(sgo_batch* b, int i, const double* pos);
+/* Solve every candidate.  energies [n], forces [sum natoms*3] in add order,
+ * status [n] per candidate (SGO_OK, SGO_ENOTCONV or SGO_ENUMERIC); any of the
+ * three may be NULL.  Returns the worst status. */
+int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, double* forces,
+                  int* status);
+int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info);
+int sgo_batch_size(sgo_batch* b, int* n);
+const char* sgo_batch_last_error(const sgo_batch* b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SGO_H */

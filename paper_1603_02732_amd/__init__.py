@@ -1,0 +1,360 @@
+"""Python binding of the MI355X plane-wave Kohn-Sham energy/force engine.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libsgo.so (built by `paper_1603_02732_amd.build`).  Importing the
+package fails loudly if the library is missing; there is no CPU fallback.
+
+Names mirror include/sgo.h.  `Context` wraps one structure (sgo_ctx),
+`Batch` a population of candidates solved together (sgo_batch).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsgo.so")
+
+SGO_OK, SGO_EINVAL, SGO_ENOMEM, SGO_EDEVICE, SGO_ENOTCONV, SGO_ENUMERIC, SGO_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6
+SGO_FP64, SGO_FP32 = 0, 1
+SGO_LOCAL_AH, SGO_LOCAL_GAUSS = 0, 1
+SGO_OCC_FIXED, SGO_OCC_FERMI = 0, 1
+_STATUS = {0: "SGO_OK", -1: "SGO_EINVAL", -2: "SGO_ENOMEM", -3: "SGO_EDEVICE",
+           -4: "SGO_ENOTCONV", -5: "SGO_ENUMERIC", -6: "SGO_ESTATE"}
+
+
+class SgoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_STATUS.get(code, code), msg))
+        self.code = code
+
+
+class sgo_species(ctypes.Structure):
+    _fields_ = [("Z", ctypes.c_double), ("local_kind", ctypes.c_int),
+                ("p", ctypes.c_double * 3), ("nkb", ctypes.c_int),
+                ("kb_l", ctypes.c_int * 4), ("kb_r", ctypes.c_double * 4),
+                ("kb_h", ctypes.c_double * 4), ("rho0_width", ctypes.c_double)]
+
+
+class sgo_scf_opts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int), ("ncg", ctypes.c_int), ("ncg_first", ctypes.c_int),
+                ("tol_e", ctypes.c_double), ("tol_rho", ctypes.c_double),
+                ("mix_alpha", ctypes.c_double), ("kerker_q0", ctypes.c_double),
+                ("history", ctypes.c_int), ("seed", ctypes.c_uint), ("use_graph", ctypes.c_int)]
+
+
+class sgo_scf_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("converged", ctypes.c_int),
+                ("de", ctypes.c_double), ("drho", ctypes.c_double)]
+
+
+class sgo_energy_terms(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in
+                ("total", "kinetic", "nonlocal", "local", "hartree", "xc", "ewald", "entropy",
+                 "band", "fermi")]
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libsgo.so (raises OSError if it is not built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise OSError("libsgo.so not built; run python -m paper_1603_02732_amd.build")
+    lib = ctypes.CDLL(p)
+    P, I, D, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    sig = {
+        "sgo_default_opts": (None, [ctypes.POINTER(sgo_scf_opts)]),
+        "sgo_version": (ctypes.c_char_p, []),
+        "sgo_create": (I, [ctypes.POINTER(P), I, I]),
+        "sgo_destroy": (I, [P]),
+        "sgo_set_stream": (I, [P, P]),
+        "sgo_set_species": (I, [P, I, ctypes.POINTER(sgo_species)]),
+        "sgo_set_cell": (I, [P, dp]),
+        "sgo_set_atoms": (I, [P, I, ip, dp]),
+        "sgo_set_cutoff": (I, [P, D, ip, I, I, D]),
+        "sgo_scf": (I, [P, ctypes.POINTER(sgo_scf_opts), ctypes.POINTER(sgo_scf_info)]),
+        "sgo_energy": (I, [P, dp, ctypes.POINTER(sgo_energy_terms)]),
+        "sgo_forces": (I, [P, dp]),
+        "sgo_stress": (I, [P, dp]),
+        "sgo_eigenvalues": (I, [P, dp, dp]),
+        "sgo_adjoint": (I, [P, D, dp, dp]),
+        "sgo_reset": (I, [P]),
+        "sgo_basis_size": (I, [P, ip, ip]),
+        "sgo_basis_millers": (I, [P, ip]),
+        "sgo_apply_h": (I, [P, dp, I, dp, dp]),
+        "sgo_get_density": (I, [P, dp, dp]),
+        "sgo_last_error": (ctypes.c_char_p, [P]),
+        "sgo_batch_create": (I, [ctypes.POINTER(P), I, I, I]),
+        "sgo_batch_destroy": (I, [P]),
+        "sgo_batch_set_stream": (I, [P, P]),
+        "sgo_batch_set_species": (I, [P, I, ctypes.POINTER(sgo_species)]),
+        "sgo_batch_add": (I, [P, dp, I, ip, dp, D, ip, I, I, D, ip]),
+        "sgo_batch_set_atoms": (I, [P, I, dp]),
+        "sgo_batch_scf": (I, [P, ctypes.POINTER(sgo_scf_opts), dp, dp, ip]),
+        "sgo_batch_info": (I, [P, I, ctypes.POINTER(sgo_scf_info)]),
+        "sgo_batch_size": (I, [P, ip]),
+        "sgo_batch_last_error": (ctypes.c_char_p, [P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+
+
+def default_opts(**kw):
+    o = sgo_scf_opts()
+    load_library().sgo_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def make_species(params):
+    """sgo_species from a species parameter dict (see workloads.species)."""
+    s = sgo_species()
+    s.Z = params["Z"]
+    loc = params["local"]
+    if loc["kind"] == "ah":
+        s.local_kind = SGO_LOCAL_AH
+        s.p[0], s.p[1], s.p[2] = loc["alpha"], loc["v1"], loc["v2"]
+    else:
+        s.local_kind = SGO_LOCAL_GAUSS
+        s.p[0], s.p[1], s.p[2] = loc["rloc"], loc["c1"], loc["c2"]
+    s.nkb = len(params["kb"])
+    for k, ch in enumerate(params["kb"]):
+        s.kb_l[k], s.kb_r[k], s.kb_h[k] = ch["l"], ch["r"], ch["h"]
+    s.rho0_width = params.get("rho0_width", 0.5)
+    return s
+
+
+def _occ(system):
+    occ = system["occupation"]
+    if occ["kind"] == "fixed":
+        return SGO_OCC_FIXED, 0.0
+    return SGO_OCC_FERMI, float(occ["sigma"])
+
+
+class Context:
+    """One structure (sgo_ctx)."""
+
+    def __init__(self, device=0, precision=SGO_FP64):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        self._check(self._lib.sgo_create(ctypes.byref(h), device, precision), None)
+        self._h = h
+        self.natoms = 0
+        self.species_ids = {}
+
+    def _check(self, rc, h=-1, allow=()):
+        if rc != SGO_OK and rc not in allow:
+            msg = self._lib.sgo_last_error(self._h if h == -1 else h)
+            raise SgoError(rc, (msg or b"").decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sgo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_ptr):
+        self._check(self._lib.sgo_set_stream(self._h, ctypes.c_void_p(stream_ptr)))
+
+    def set_species(self, sid, params):
+        sp = make_species(params)
+        self._check(self._lib.sgo_set_species(self._h, sid, ctypes.byref(sp)))
+
+    def set_cell(self, lattice):
+        a = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
+        self._check(self._lib.sgo_set_cell(self._h, _dptr(a)))
+
+    def set_atoms(self, species, positions):
+        s = np.ascontiguousarray(species, dtype=np.int32)
+        p = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
+        self._check(self._lib.sgo_set_atoms(self._h, len(s), _iptr(s), _dptr(p)))
+        self.natoms = len(s)
+
+    def set_cutoff(self, ecut, grid, nbands, occ_kind=SGO_OCC_FIXED, sigma=0.0):
+        g = np.ascontiguousarray(grid, dtype=np.int32)
+        self._check(self._lib.sgo_set_cutoff(self._h, float(ecut), _iptr(g), int(nbands),
+                                             int(occ_kind), float(sigma)))
+        self.nbands = int(nbands)
+        self.grid = tuple(int(x) for x in grid)
+
+    def load_system(self, system):
+        """Species, cell, atoms and cutoff from a workloads system dict."""
+        names = sorted(system["species"])
+        self.species_ids = {n: i for i, n in enumerate(names)}
+        for n in names:
+            self.set_species(self.species_ids[n], system["species"][n])
+        self.set_cell(system["lattice"])
+        self.set_atoms([self.species_ids[s] for s in system["symbols"]], system["positions"])
+        kind, sigma = _occ(system)
+        self.set_cutoff(system["ecut"], system["grid"], system["nbands"], kind, sigma)
+        return self
+
+    def scf(self, opts=None, allow_notconv=False, **kw):
+        o = opts if opts is not None else default_opts(**kw)
+        info = sgo_scf_info()
+        allow = (SGO_ENOTCONV,) if allow_notconv else ()
+        rc = self._check(self._lib.sgo_scf(self._h, ctypes.byref(o), ctypes.byref(info)),
+                         allow=allow)
+        return {"status": rc, "iterations": info.iterations, "converged": bool(info.converged),
+                "de": info.de, "drho": info.drho}
+
+    def energy(self):
+        e = ctypes.c_double()
+        t = sgo_energy_terms()
+        self._check(self._lib.sgo_energy(self._h, ctypes.byref(e), ctypes.byref(t)))
+        return e.value, {n: getattr(t, n) for n, _ in sgo_energy_terms._fields_}
+
+    def forces(self):
+        f = np.zeros((self.natoms, 3))
+        self._check(self._lib.sgo_forces(self._h, _dptr(f)))
+        return f
+
+    def adjoint(self, gE=1.0):
+        g = np.zeros((self.natoms, 3))
+        self._check(self._lib.sgo_adjoint(self._h, float(gE), _dptr(g), None))
+        return g
+
+    def eigenvalues(self):
+        e = np.zeros(self.nbands)
+        o = np.zeros(self.nbands)
+        self._check(self._lib.sgo_eigenvalues(self._h, _dptr(e), _dptr(o)))
+        return e, o
+
+    def basis(self):
+        n = ctypes.c_int()
+        npj = ctypes.c_int()
+        self._check(self._lib.sgo_basis_size(self._h, ctypes.byref(n), ctypes.byref(npj)))
+        m = np.zeros((n.value, 3), dtype=np.int32)
+        self._check(self._lib.sgo_basis_millers(self._h, _iptr(m)))
+        return m, npj.value
+
+    def apply_h(self, veff_zyx, psi):
+        """H[V] psi for packed bands psi (nb, 2*npw_half); veff indexed [z][y][x]."""
+        v = np.ascontiguousarray(veff_zyx, dtype=np.float64)
+        x = np.ascontiguousarray(psi, dtype=np.float64)
+        out = np.zeros_like(x)
+        self._check(self._lib.sgo_apply_h(self._h, _dptr(v), x.shape[0], _dptr(x), _dptr(out)))
+        return out
+
+    def density(self):
+        n = int(np.prod(self.grid))
+        rho = np.zeros(n)
+        veff = np.zeros(n)
+        self._check(self._lib.sgo_get_density(self._h, _dptr(rho), _dptr(veff)))
+        shape = (self.grid[2], self.grid[1], self.grid[0])
+        return rho.reshape(shape), veff.reshape(shape)
+
+    def reset(self):
+        self._check(self._lib.sgo_reset(self._h))
+
+
+class Batch:
+    """A population of candidates solved together (sgo_batch)."""
+
+    def __init__(self, capacity, device=0, precision=SGO_FP32):
+        self._lib = load_library()
+        h = ctypes.c_void_p()
+        rc = self._lib.sgo_batch_create(ctypes.byref(h), device, precision, capacity)
+        if rc != SGO_OK:
+            raise SgoError(rc, (self._lib.sgo_batch_last_error(None) or b"").decode())
+        self._h = h
+        self.natoms = []
+        self.species_ids = {}
+
+    def _check(self, rc, allow=()):
+        if rc != SGO_OK and rc not in allow:
+            raise SgoError(rc, (self._lib.sgo_batch_last_error(self._h) or b"").decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sgo_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_ptr):
+        self._check(self._lib.sgo_batch_set_stream(self._h, ctypes.c_void_p(stream_ptr)))
+
+    def add_system(self, system):
+        for n in sorted(system["species"]):
+            if n not in self.species_ids:
+                sid = len(self.species_ids)
+                self.species_ids[n] = sid
+                sp = make_species(system["species"][n])
+                self._check(self._lib.sgo_batch_set_species(self._h, sid, ctypes.byref(sp)))
+        lat = np.ascontiguousarray(system["lattice"], dtype=np.float64).reshape(9)
+        spec = np.ascontiguousarray([self.species_ids[s] for s in system["symbols"]],
+                                    dtype=np.int32)
+        pos = np.ascontiguousarray(system["positions"], dtype=np.float64).reshape(-1)
+        grid = np.ascontiguousarray(system["grid"], dtype=np.int32)
+        kind, sigma = _occ(system)
+        idx = ctypes.c_int()
+        self._check(self._lib.sgo_batch_add(self._h, _dptr(lat), len(spec), _iptr(spec),
+                                            _dptr(pos), float(system["ecut"]), _iptr(grid),
+                                            int(system["nbands"]), kind, sigma,
+                                            ctypes.byref(idx)))
+        self.natoms.append(len(spec))
+        return idx.value
+
+    def set_atoms(self, i, positions):
+        p = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
+        self._check(self._lib.sgo_batch_set_atoms(self._h, int(i), _dptr(p)))
+
+    def scf(self, opts=None, **kw):
+        o = opts if opts is not None else default_opts(**kw)
+        n = len(self.natoms)
+        e = np.zeros(n)
+        f = np.zeros(sum(self.natoms) * 3)
+        st = np.zeros(n, dtype=np.int32)
+        rc = self._lib.sgo_batch_scf(self._h, ctypes.byref(o), _dptr(e), _dptr(f), _iptr(st))
+        if rc not in (SGO_OK, SGO_ENOTCONV, SGO_ENUMERIC):
+            self._check(rc)
+        forces, off = [], 0
+        for na in self.natoms:
+            forces.append(f[off:off + 3 * na].reshape(na, 3))
+            off += 3 * na
+        return e, forces, st
+
+    def info(self, i):
+        inf = sgo_scf_info()
+        self._check(self._lib.sgo_batch_info(self._h, int(i), ctypes.byref(inf)))
+        return {"iterations": inf.iterations, "converged": bool(inf.converged), "de": inf.de,
+                "drho": inf.drho}
+
+
+def context_from_system(system, precision=None, device=0):
+    if precision is None:
+        precision = SGO_FP64 if system.get("precision", "fp64") == "fp64" else SGO_FP32
+    return Context(device, precision).load_system(system)

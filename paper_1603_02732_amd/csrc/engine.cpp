@@ -1,0 +1,1220 @@
+// Host side of the engine: plane-wave basis bookkeeping, device memory
+// layout, the SCF driver (Section 2.4) around the all-band CG eigensolver
+// (Algorithm 1), and the C-ABI declared in sgo.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/sgo.h"
+#include "common.hpp"
+#include "launch.hpp"
+
+namespace sgo {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(x)                                                                        \
+  do {                                                                                   \
+    hipError_t e_ = (x);                                                                 \
+    if (e_ != hipSuccess)                                                                \
+      throw Error(SGO_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+static const double kPiH = 3.14159265358979323846;
+
+// --------------------------------------------------------------- utilities
+static bool fft_plan(int n, FftPlan& p) {
+  p.n = n;
+  p.nstage = 0;
+  int m = n;
+  const int order[4] = {4, 2, 3, 5};
+  for (int r : order) {
+    while (m % r == 0) {
+      if (p.nstage >= kMaxStages) return false;
+      p.radix[p.nstage++] = r;
+      m /= r;
+    }
+  }
+  return m == 1 && n >= 1 && n <= kMaxFftN;
+}
+
+static void inv3(const double* A, double* Ai, double* det) {
+  const double a = A[0], b = A[1], c = A[2], d = A[3], e = A[4], f = A[5], g = A[6], h = A[7],
+               i = A[8];
+  const double D = a * (e * i - f * h) - b * (d * i - f * g) + c * (d * h - e * g);
+  *det = D;
+  Ai[0] = (e * i - f * h) / D;
+  Ai[1] = (c * h - b * i) / D;
+  Ai[2] = (b * f - c * e) / D;
+  Ai[3] = (f * g - d * i) / D;
+  Ai[4] = (a * i - c * g) / D;
+  Ai[5] = (c * d - a * f) / D;
+  Ai[6] = (d * h - e * g) / D;
+  Ai[7] = (b * g - a * h) / D;
+  Ai[8] = (a * e - b * d) / D;
+}
+
+// ------------------------------------------------------------- candidates
+struct HostCand {
+  // inputs
+  double A[9];
+  int nat = 0;
+  std::vector<int> spec;
+  std::vector<double> pos;
+  double ecut = 0;
+  int N[3] = {0, 0, 0};
+  int nb = 0;
+  int occ_kind = 0;
+  double sigma = 0;
+  // derived
+  double omega = 0, B[9];
+  double nelec = 0;
+  int nocc = 0;
+  int npwh = 0, K = 0, nsp = 0, nst = 0, npair = 0, nproj = 0, ntot = 0;
+  std::vector<int> gmill, gmeta, sp_off, stick_xy, proj_atom, proj_lm;
+  std::vector<double> kin, hproj, proj_r;
+  FftPlan plan[3];
+  double ew_eta = 0, ew_rcut = 0, ew_gcut = 0;
+  int ew_m[3], ew_n[3], ew_ng = 0, ew_nimg = 0;
+  int hist_len = kMaxHist;
+  int dens_chunks = 1;
+  size_t red_doubles = 0;
+  // device
+  char* mem = nullptr;
+  size_t mem_size = 0;
+  CandDesc d;
+  bool built = false;
+  bool have_psi = false;
+  bool have_scf = false;
+  sgo_scf_info info{};
+  int status = SGO_OK;
+};
+
+struct SpeciesHost {
+  bool set = false;
+  SpeciesDev d;
+};
+
+class Engine {
+ public:
+  Engine(int device, int precision, int capacity)
+      : device_(device), prec_(precision), capacity_(capacity) {
+    if (precision != SGO_FP64 && precision != SGO_FP32) throw Error(SGO_EINVAL, "bad precision");
+    if (capacity < 1) throw Error(SGO_EINVAL, "capacity must be >= 1");
+    int ndev = 0;
+    HIPCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) throw Error(SGO_EINVAL, "no such HIP device");
+    HIPCHK(hipSetDevice(device));
+    static bool configured = false;
+    if (!configured) {
+      configure_kernels();
+      configured = true;
+    }
+    HIPCHK(hipMalloc(&d_species_, sizeof(SpeciesDev) * kMaxSpecies));
+    HIPCHK(hipMemset(d_species_, 0, sizeof(SpeciesDev) * kMaxSpecies));
+    species_.resize(kMaxSpecies);
+  }
+  ~Engine() {
+    (void)hipSetDevice(device_);
+    for (auto& c : cands_) free_cand(c);
+    if (d_species_) (void)hipFree(d_species_);
+    if (d_desc_) (void)hipFree(d_desc_);
+  }
+
+  void set_stream(void* s) { stream_ = (hipStream_t)s; }
+
+  void set_species(int id, const sgo_species* sp) {
+    if (id < 0 || id >= kMaxSpecies || !sp) throw Error(SGO_EINVAL, "bad species id or pointer");
+    if (!(sp->Z >= 0) || sp->nkb < 0 || sp->nkb > 4) throw Error(SGO_EINVAL, "bad species data");
+    if (sp->local_kind != SGO_LOCAL_AH && sp->local_kind != SGO_LOCAL_GAUSS)
+      throw Error(SGO_EINVAL, "unknown local potential kind");
+    if (!(sp->p[0] > 0)) throw Error(SGO_EINVAL, "local potential width must be positive");
+    SpeciesDev d{};
+    d.Z = sp->Z;
+    d.local_kind = sp->local_kind;
+    d.nkb = sp->nkb;
+    for (int k = 0; k < 3; ++k) d.p[k] = sp->p[k];
+    for (int k = 0; k < sp->nkb; ++k) {
+      if (sp->kb_l[k] < 0 || sp->kb_l[k] > 1 || !(sp->kb_r[k] > 0))
+        throw Error(SGO_EINVAL, "KB channels must have l in {0,1} and r > 0");
+      d.kb_l[k] = sp->kb_l[k];
+      d.kb_r[k] = sp->kb_r[k];
+      d.kb_h[k] = sp->kb_h[k];
+    }
+    d.rho0_width = sp->rho0_width > 0 ? sp->rho0_width : 0.5;
+    species_[id].set = true;
+    species_[id].d = d;
+    HIPCHK(hipSetDevice(device_));
+    HIPCHK(hipMemcpy(d_species_ + id, &d, sizeof(d), hipMemcpyHostToDevice));
+    for (auto& c : cands_) {
+      c.built = false;
+      c.have_psi = false;
+      c.have_scf = false;
+    }
+  }
+
+  int add(const double* lat, int nat, const int* spec, const double* pos, double ecut,
+          const int* fft, int nb, int occ_kind, double sigma) {
+    if ((int)cands_.size() >= capacity_) throw Error(SGO_EINVAL, "batch is full");
+    HostCand c;
+    fill_cand(c, lat, nat, spec, pos, ecut, fft, nb, occ_kind, sigma);
+    cands_.push_back(std::move(c));
+    desc_dirty_ = true;
+    return (int)cands_.size() - 1;
+  }
+
+  void fill_cand(HostCand& c, const double* lat, int nat, const int* spec, const double* pos,
+                 double ecut, const int* fft, int nb, int occ_kind, double sigma) {
+    if (!lat || !spec || !pos || !fft) throw Error(SGO_EINVAL, "NULL argument");
+    if (nat <= 0) throw Error(SGO_EINVAL, "natoms must be positive");
+    if (!(ecut > 0)) throw Error(SGO_EINVAL, "ecut must be positive");
+    if (nb <= 0) throw Error(SGO_EINVAL, "nbands must be positive");
+    if (occ_kind != SGO_OCC_FIXED && occ_kind != SGO_OCC_FERMI)
+      throw Error(SGO_EINVAL, "unknown occupation kind");
+    if (occ_kind == SGO_OCC_FERMI && !(sigma > 0)) throw Error(SGO_EINVAL, "sigma must be > 0");
+    std::memcpy(c.A, lat, sizeof(double) * 9);
+    double Ai[9], det;
+    inv3(c.A, Ai, &det);
+    if (!(std::fabs(det) > 1e-12)) throw Error(SGO_EINVAL, "cell volume must be positive");
+    c.nat = nat;
+    c.spec.assign(spec, spec + nat);
+    for (int I = 0; I < nat; ++I)
+      if (spec[I] < 0 || spec[I] >= kMaxSpecies || !species_[spec[I]].set)
+        throw Error(SGO_EINVAL, "atom uses an unregistered species");
+    c.pos.assign(pos, pos + 3 * nat);
+    check_distances(c);
+    c.ecut = ecut;
+    for (int k = 0; k < 3; ++k) c.N[k] = fft[k];
+    c.nb = nb;
+    c.occ_kind = occ_kind;
+    c.sigma = sigma;
+    c.built = false;
+    c.have_psi = false;
+    c.have_scf = false;
+    build_basis(c);  // validates grid and bands now, so errors surface at the call
+  }
+
+  void check_distances(const HostCand& c) {
+    double Ai[9], det;
+    inv3(c.A, Ai, &det);
+    for (int I = 0; I < c.nat; ++I)
+      for (int J = I + 1; J < c.nat; ++J) {
+        double d[3], f[3];
+        for (int k = 0; k < 3; ++k) d[k] = c.pos[3 * I + k] - c.pos[3 * J + k];
+        // fractional, minimum image: d = f A  (rows of A are lattice vectors)
+        for (int k = 0; k < 3; ++k) f[k] = d[0] * Ai[0 * 3 + k] + d[1] * Ai[1 * 3 + k] + d[2] * Ai[2 * 3 + k];
+        for (int k = 0; k < 3; ++k) f[k] -= std::round(f[k]);
+        double r2 = 0;
+        for (int k = 0; k < 3; ++k) {
+          const double x = f[0] * c.A[0 * 3 + k] + f[1] * c.A[1 * 3 + k] + f[2] * c.A[2 * 3 + k];
+          r2 += x * x;
+        }
+        if (r2 < 1e-6) throw Error(SGO_EINVAL, "two atoms closer than 1e-3 bohr");
+      }
+  }
+
+  // Half-sphere basis, sticks, maps, projector list, Ewald ranges.
+  void build_basis(HostCand& c) {
+    double Ai[9], det;
+    inv3(c.A, Ai, &det);
+    c.omega = std::fabs(det);
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) c.B[i * 3 + k] = 2.0 * kPiH * Ai[k * 3 + i];  // B = 2 pi A^-T
+    const double gmax = std::sqrt(2.0 * c.ecut);
+    int mm[3];
+    for (int i = 0; i < 3; ++i) {
+      const double an = std::sqrt(c.A[3 * i] * c.A[3 * i] + c.A[3 * i + 1] * c.A[3 * i + 1] +
+                                  c.A[3 * i + 2] * c.A[3 * i + 2]);
+      mm[i] = (int)std::floor(gmax * an / (2 * kPiH)) + 1;
+    }
+    std::vector<std::array<int, 3>> full;
+    int mabs[3] = {0, 0, 0};
+    for (int a = -mm[0]; a <= mm[0]; ++a)
+      for (int b = -mm[1]; b <= mm[1]; ++b)
+        for (int g = -mm[2]; g <= mm[2]; ++g) {
+          double G[3];
+          for (int k = 0; k < 3; ++k) G[k] = a * c.B[k] + b * c.B[3 + k] + g * c.B[6 + k];
+          const double e = 0.5 * (G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+          if (e <= c.ecut) {
+            full.push_back({a, b, g});
+            mabs[0] = std::max(mabs[0], std::abs(a));
+            mabs[1] = std::max(mabs[1], std::abs(b));
+            mabs[2] = std::max(mabs[2], std::abs(g));
+          }
+        }
+    for (int i = 0; i < 3; ++i) {
+      if (c.N[i] < 2 * mabs[i] + 1)
+        throw Error(SGO_EINVAL, "FFT grid too small for the wavefunction sphere");
+      if (!fft_plan(c.N[i], c.plan[i]))
+        throw Error(SGO_EINVAL, "FFT lengths must factor into 2,3,5 and be <= 128");
+    }
+    c.ntot = c.N[0] * c.N[1] * c.N[2];
+    // sticks: canonical (m1,m2) with m2 > 0 or (m2 == 0 and m1 >= 0)
+    std::map<std::pair<int, int>, int> seen;
+    for (auto& m : full) seen[{m[0], m[1]}] = 1;
+    std::vector<std::pair<int, int>> canon;
+    for (auto& kv : seen) {
+      const int a = kv.first.first, b = kv.first.second;
+      if ((a == 0 && b == 0)) continue;
+      if (b > 0 || (b == 0 && a > 0)) canon.push_back({a, b});
+    }
+    std::sort(canon.begin(), canon.end(), [](const std::pair<int, int>& x,
+                                             const std::pair<int, int>& y) {
+      return x.second != y.second ? x.second < y.second : x.first < y.first;
+    });
+    std::map<std::pair<int, int>, int> stick_of, pair_of;
+    std::vector<std::pair<int, int>> sticks;
+    sticks.push_back({0, 0});
+    stick_of[{0, 0}] = 0;
+    pair_of[{0, 0}] = 0;
+    for (size_t q = 0; q < canon.size(); ++q) {
+      auto s = canon[q];
+      std::pair<int, int> ms = {-s.first, -s.second};
+      stick_of[s] = (int)sticks.size();
+      sticks.push_back(s);
+      stick_of[ms] = (int)sticks.size();
+      sticks.push_back(ms);
+      pair_of[s] = (int)q + 1;
+      pair_of[ms] = (int)q + 1;
+    }
+    c.nsp = (int)canon.size() + 1;
+    c.nst = (int)sticks.size();
+    // half sphere ordered by stick pair, then m3, m2, m1
+    std::vector<std::array<int, 4>> half;  // pair, m1, m2, m3
+    for (auto& m : full) {
+      const bool in_half = m[2] > 0 || (m[2] == 0 && (m[1] > 0 || (m[1] == 0 && m[0] >= 0)));
+      if (in_half) half.push_back({pair_of[{m[0], m[1]}], m[0], m[1], m[2]});
+    }
+    std::sort(half.begin(), half.end(), [](const std::array<int, 4>& x, const std::array<int, 4>& y) {
+      if (x[0] != y[0]) return x[0] < y[0];
+      if (x[3] != y[3]) return x[3] < y[3];
+      if (x[2] != y[2]) return x[2] < y[2];
+      return x[1] < y[1];
+    });
+    c.npwh = (int)half.size();
+    c.K = 2 * c.npwh;
+    if (half.empty() || half[0][1] != 0 || half[0][2] != 0 || half[0][3] != 0)
+      throw Error(SGO_EINVAL, "internal: G = 0 must lead the basis");
+    c.gmill.resize(3 * c.npwh);
+    c.gmeta.resize(c.npwh);
+    c.kin.resize(c.npwh);
+    c.sp_off.assign(c.nsp + 1, 0);
+    for (int g = 0; g < c.npwh; ++g) {
+      const auto& h = half[g];
+      c.gmill[3 * g] = h[1];
+      c.gmill[3 * g + 1] = h[2];
+      c.gmill[3 * g + 2] = h[3];
+      const int s = stick_of[{h[1], h[2]}];
+      c.gmeta[g] = s | (((h[3] % c.N[2] + c.N[2]) % c.N[2]) << 20);
+      double G[3];
+      for (int k = 0; k < 3; ++k) G[k] = h[1] * c.B[k] + h[2] * c.B[3 + k] + h[3] * c.B[6 + k];
+      c.kin[g] = 0.5 * (G[0] * G[0] + G[1] * G[1] + G[2] * G[2]);
+      c.sp_off[h[0] + 1]++;
+    }
+    for (int q = 0; q < c.nsp; ++q) c.sp_off[q + 1] += c.sp_off[q];
+    c.stick_xy.resize(c.nst);
+    for (int s = 0; s < c.nst; ++s) {
+      const int i1 = ((sticks[s].first % c.N[0]) + c.N[0]) % c.N[0];
+      const int i2 = ((sticks[s].second % c.N[1]) + c.N[1]) % c.N[1];
+      c.stick_xy[s] = i1 | (i2 << 16);
+    }
+    // electrons, occupations
+    c.nelec = 0;
+    for (int I = 0; I < c.nat; ++I) c.nelec += species_[c.spec[I]].d.Z;
+    if (c.occ_kind == SGO_OCC_FIXED) {
+      const double h = 0.5 * c.nelec;
+      c.nocc = (int)std::llround(h);
+      if (std::fabs(c.nocc - h) > 1e-9) throw Error(SGO_EINVAL, "fixed occupations need an even electron count");
+      if (c.nocc > c.nb) throw Error(SGO_EINVAL, "nbands cannot hold the electrons");
+    } else {
+      c.nocc = 0;
+      if (c.nelec > 2.0 * c.nb - 1e-9) throw Error(SGO_EINVAL, "nbands cannot hold the electrons");
+    }
+    c.npair = (c.nb + 1) / 2;
+    // projectors
+    c.proj_atom.clear();
+    c.proj_lm.clear();
+    c.proj_r.clear();
+    c.hproj.clear();
+    for (int I = 0; I < c.nat; ++I) {
+      const SpeciesDev& s = species_[c.spec[I]].d;
+      for (int k = 0; k < s.nkb; ++k) {
+        const int l = s.kb_l[k];
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          c.proj_atom.push_back(I);
+          c.proj_lm.push_back(l * 4 + m);
+          c.proj_r.push_back(s.kb_r[k]);
+          c.hproj.push_back(s.kb_h[k]);
+        }
+      }
+    }
+    c.nproj = (int)c.proj_atom.size();
+    // Ewald ranges: erfc(eta rcut) and exp(-gcut^2/4eta^2) below ~1e-17
+    c.ew_eta = std::sqrt(kPiH) * std::pow(c.nat / (c.omega * c.omega), 1.0 / 6.0);
+    c.ew_rcut = 6.2 / c.ew_eta;
+    c.ew_gcut = 2.0 * c.ew_eta * 6.2;
+    double diag = 0;
+    for (int k = 0; k < 3; ++k) {
+      const double s = c.A[k] + c.A[3 + k] + c.A[6 + k];
+      diag += s * s;
+    }
+    double reach = c.ew_rcut + std::sqrt(diag);
+    for (int i = 0; i < 3; ++i) {
+      const double bn = std::sqrt(c.B[3 * i] * c.B[3 * i] + c.B[3 * i + 1] * c.B[3 * i + 1] +
+                                  c.B[3 * i + 2] * c.B[3 * i + 2]);
+      const double an = std::sqrt(c.A[3 * i] * c.A[3 * i] + c.A[3 * i + 1] * c.A[3 * i + 1] +
+                                  c.A[3 * i + 2] * c.A[3 * i + 2]);
+      c.ew_n[i] = (int)std::ceil(reach * bn / (2 * kPiH)) + 1;
+      c.ew_m[i] = (int)std::ceil(c.ew_gcut * an / (2 * kPiH)) + 1;
+    }
+    c.ew_ng = (2 * c.ew_m[0] + 1) * (2 * c.ew_m[1] + 1) * (2 * c.ew_m[2] + 1);
+    c.ew_nimg = (2 * c.ew_n[0] + 1) * (2 * c.ew_n[1] + 1) * (2 * c.ew_n[2] + 1);
+  }
+
+  size_t tsize() const { return prec_ == SGO_FP64 ? sizeof(double) : sizeof(float); }
+
+  // One device allocation per candidate, carved into 256-byte-aligned arrays.
+  void alloc_cand(HostCand& c, const BatchGeom& g) {
+    free_cand(c);
+    const size_t ts = tsize();
+    const size_t nb = c.nb, K = c.K, nt = c.ntot, nbm = std::max(c.nb, c.nproj);
+    const int ntile = (std::max(c.nb, c.nproj) + 63) / 64;
+    c.red_doubles = std::max((size_t)kRedSlots, (size_t)2 * ntile * ntile * 32 * 4096);
+    c.dens_chunks = g.dens_chunks;
+    struct Item {
+      void** p;
+      size_t bytes;
+    };
+    CandDesc& d = c.d;
+    std::memset(&d, 0, sizeof(d));
+    std::vector<Item> items = {
+        {&d.X, nb * K * ts}, {&d.HX, nb * K * ts}, {&d.D, nb * K * ts}, {&d.HD, nb * K * ts},
+        {&d.sticks, (size_t)c.npair * c.N[2] * c.nst * 2 * ts}, {&d.veff_t, nt * ts},
+        {&d.beta, (size_t)c.nproj * K * ts + 256},
+        {(void**)&d.kin, c.npwh * sizeof(double)}, {(void**)&d.gmeta, c.npwh * sizeof(int)},
+        {(void**)&d.sp_off, (c.nsp + 1) * sizeof(int)}, {(void**)&d.stick_xy, c.nst * sizeof(int)},
+        {(void**)&d.gmill, 3 * c.npwh * sizeof(int)},
+        {(void**)&d.hproj, c.nproj * sizeof(double) + 8}, {(void**)&d.proj_atom, c.nproj * sizeof(int) + 8},
+        {(void**)&d.proj_lm, c.nproj * sizeof(int) + 8}, {(void**)&d.proj_r, c.nproj * sizeof(double) + 8},
+        {(void**)&d.S, nb * nb * 8}, {(void**)&d.Hs, nb * nb * 8}, {(void**)&d.M, nb * nb * 8},
+        {(void**)&d.C, nbm * nb * 8}, {(void**)&d.eps, nb * 8}, {(void**)&d.occ, nb * 8},
+        {(void**)&d.gam, nb * 8}, {(void**)&d.bandw, nb * 8},
+        {(void**)&d.rho_in_r, nt * 8}, {(void**)&d.rho_out_r, nt * 8}, {(void**)&d.veff_r, nt * 8},
+        {(void**)&d.zgrid, nt * 16}, {(void**)&d.vloc_G, nt * 16}, {(void**)&d.rho0_G, nt * 16},
+        {(void**)&d.rho_out_G, nt * 16}, {(void**)&d.hist_in, kMaxHist * nt * 16},
+        {(void**)&d.hist_res, kMaxHist * nt * 16}, {(void**)&d.pulay, kMaxHist * kMaxHist * 8},
+        {(void**)&d.coef, kMaxHist * 8}, {(void**)&d.dens_part, (size_t)c.dens_chunks * nt * 8},
+        {(void**)&d.pos, (size_t)3 * c.nat * 8}, {(void**)&d.spec, (size_t)c.nat * sizeof(int)},
+        {(void**)&d.force, (size_t)3 * c.nat * 8}, {(void**)&d.force_ew, (size_t)3 * c.nat * 8},
+        {(void**)&d.force_part, (size_t)6 * c.nat * 8}, {(void**)&d.nlwork, (size_t)c.nproj * nb * 4 * 8 + 8},
+        {(void**)&d.scal, S_COUNT * 8}, {(void**)&d.ewS, (size_t)c.ew_ng * 16},
+        {(void**)&d.red_part, c.red_doubles * 8}, {(void**)&d.tickets, kTickets * sizeof(unsigned)},
+    };
+    size_t total = 0;
+    for (auto& it : items) total += (it.bytes + 255) / 256 * 256;
+    HIPCHK(hipSetDevice(device_));
+    if (hipMalloc(&c.mem, total) != hipSuccess) {
+      c.mem = nullptr;
+      throw Error(SGO_ENOMEM, "device allocation failed");
+    }
+    c.mem_size = total;
+    HIPCHK(hipMemset(c.mem, 0, total));
+    size_t off = 0;
+    for (auto& it : items) {
+      *it.p = c.mem + off;
+      off += (it.bytes + 255) / 256 * 256;
+    }
+    upload_static(c);
+    c.built = true;
+  }
+
+  void upload_static(HostCand& c) {
+    CandDesc& d = c.d;
+    d.N1 = c.N[0];
+    d.N2 = c.N[1];
+    d.N3 = c.N[2];
+    d.ntot = c.ntot;
+    d.npwh = c.npwh;
+    d.K = c.K;
+    d.nb = c.nb;
+    d.npair = c.npair;
+    d.nsp = c.nsp;
+    d.nst = c.nst;
+    d.nproj = c.nproj;
+    d.nat = c.nat;
+    d.occ_kind = c.occ_kind;
+    d.nocc = c.nocc;
+    d.active = 1;
+    d.sigma = c.sigma;
+    d.nelec = c.nelec;
+    d.omega = c.omega;
+    std::memcpy(d.A, c.A, sizeof(d.A));
+    std::memcpy(d.B, c.B, sizeof(d.B));
+    for (int k = 0; k < 3; ++k) d.plan[k] = c.plan[k];
+    d.ndens_chunk = c.dens_chunks;
+    d.hist_len = c.hist_len;
+    d.ew_eta = c.ew_eta;
+    d.ew_rcut = c.ew_rcut;
+    d.ew_gcut = c.ew_gcut;
+    for (int k = 0; k < 3; ++k) {
+      d.ew_m[k] = c.ew_m[k];
+      d.ew_n[k] = c.ew_n[k];
+    }
+    d.ew_ng = c.ew_ng;
+    d.ew_nimg = c.ew_nimg;
+    auto up = [&](const void* dst, const void* src, size_t bytes) {
+      if (bytes) HIPCHK(hipMemcpy((void*)dst, src, bytes, hipMemcpyHostToDevice));
+    };
+    up(d.kin, c.kin.data(), c.npwh * 8);
+    up(d.gmeta, c.gmeta.data(), c.npwh * 4);
+    up(d.sp_off, c.sp_off.data(), (c.nsp + 1) * 4);
+    up(d.stick_xy, c.stick_xy.data(), c.nst * 4);
+    up(d.gmill, c.gmill.data(), 3 * c.npwh * 4);
+    up(d.hproj, c.hproj.data(), c.nproj * 8);
+    up(d.proj_atom, c.proj_atom.data(), c.nproj * 4);
+    up(d.proj_lm, c.proj_lm.data(), c.nproj * 4);
+    up(d.proj_r, c.proj_r.data(), c.nproj * 8);
+    up(d.spec, c.spec.data(), c.nat * 4);
+    up(d.pos, c.pos.data(), 3 * c.nat * 8);
+  }
+
+  void free_cand(HostCand& c) {
+    if (c.mem) {
+      (void)hipSetDevice(device_);
+      (void)hipFree(c.mem);
+    }
+    c.mem = nullptr;
+    c.built = false;
+  }
+
+  BatchGeom geometry() const {
+    BatchGeom g{};
+    g.ncand = (int)cands_.size();
+    for (auto& c : cands_) {
+      g.npair_max = std::max(g.npair_max, c.npair);
+      g.nsp_max = std::max(g.nsp_max, c.nsp);
+      g.nb_max = std::max(g.nb_max, c.nb);
+      g.nproj_max = std::max(g.nproj_max, c.nproj);
+      g.nat_max = std::max(g.nat_max, c.nat);
+      g.N1max = std::max(g.N1max, c.N[0]);
+      g.N2max = std::max(g.N2max, c.N[1]);
+      g.N3max = std::max(g.N3max, c.N[2]);
+      g.ntot_max = std::max(g.ntot_max, c.ntot);
+      g.plane_max = std::max(g.plane_max, c.N[0] * c.N[1]);
+      g.K_max = std::max(g.K_max, c.K);
+      g.ew_ng_max = std::max(g.ew_ng_max, c.ew_ng);
+    }
+    g.sp_chunk = std::max(1, 640 / std::max(1, g.N3max));
+    g.kc_len = std::max(256, ((g.K_max + 31) / 32 + 31) / 32 * 32);
+    g.nkc_max = (g.K_max + g.kc_len - 1) / g.kc_len;
+    g.dens_chunks = std::max(1, std::min(g.npair_max, (512 + g.N3max - 1) / std::max(1, g.N3max)));
+    return g;
+  }
+
+  void check_lds(const BatchGeom& g) {
+    const size_t ts = tsize();
+    const size_t plane = 2 * ts * (2 * kMaxFftN + 2 * (size_t)g.plane_max);
+    if (plane > 160 * 1024)
+      throw Error(SGO_EINVAL, "FFT plane N1*N2 too large for LDS at this precision");
+    if (g.plane_max > 48 * kNT) throw Error(SGO_EINVAL, "FFT plane N1*N2 exceeds 12288");
+    if (g.nb_max > 640) throw Error(SGO_EINVAL, "nbands exceeds 640");
+    if (std::max(g.nb_max, g.nproj_max) > 600) throw Error(SGO_EINVAL, "too many projectors");
+  }
+
+  void upload_desc() {
+    std::vector<CandDesc> h(cands_.size());
+    for (size_t i = 0; i < cands_.size(); ++i) {
+      h[i] = cands_[i].d;
+      h[i].ncand_index = (int)i;
+    }
+    if (!d_desc_ || desc_cap_ < cands_.size()) {
+      if (d_desc_) (void)hipFree(d_desc_);
+      HIPCHK(hipMalloc(&d_desc_, sizeof(CandDesc) * cands_.size()));
+      desc_cap_ = cands_.size();
+    }
+    HIPCHK(hipMemcpyAsync(d_desc_, h.data(), sizeof(CandDesc) * h.size(), hipMemcpyHostToDevice,
+                          stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+  }
+
+  LaunchCtx ctx(const BatchGeom& g) const {
+    LaunchCtx L;
+    L.stream = stream_;
+    L.desc = d_desc_;
+    L.species = d_species_;
+    L.g = g;
+    return L;
+  }
+
+  // Build every candidate that needs it and run the per-geometry setup.
+  BatchGeom prepare(unsigned seed, int hist) {
+    if (cands_.empty()) throw Error(SGO_ESTATE, "no structure set");
+    HIPCHK(hipSetDevice(device_));
+    BatchGeom g = geometry();
+    check_lds(g);
+    for (auto& c : cands_) {
+      c.hist_len = hist;
+      if (!c.built || c.dens_chunks != g.dens_chunks) {
+        alloc_cand(c, g);
+        c.have_psi = false;
+      } else {
+        c.d.hist_len = hist;
+        c.d.ndens_chunk = c.dens_chunks;
+        HIPCHK(hipMemcpy((void*)c.d.pos, c.pos.data(), 3 * c.nat * 8, hipMemcpyHostToDevice));
+      }
+      c.d.seed = seed;
+      c.d.active = 1;
+      c.status = SGO_OK;
+      c.info = sgo_scf_info{};
+      HIPCHK(hipMemsetAsync(c.d.scal, 0, S_COUNT * 8, stream_));
+    }
+    upload_desc();
+    return g;
+  }
+
+  template <typename T>
+  void setup_geometry(const LaunchCtx& L) {
+    launch_setup_grid(L);
+    launch_setup_beta<T>(L);
+    launch_ewald(L);
+  }
+
+  template <typename T>
+  void subspace_rotate(const LaunchCtx& L, bool with_d) {
+    int a[2] = {W_X, W_X}, b[2] = {W_X, W_HX}, o[2] = {M_S, M_H};
+    launch_gram<T>(L, 2, a, b, o);
+    launch_subspace(L, 3);
+    int y[3] = {W_X, W_HX, W_D};
+    launch_gemm_acc<T>(L, with_d ? 3 : 2, y, y, M_M, 0.0, 1.0, 0);
+  }
+
+  template <typename T>
+  void eigensolver(const LaunchCtx& L, int ncg) {
+    launch_hpsi<T>(L, W_X);
+    subspace_rotate<T>(L, false);
+    for (int k = 0; k < ncg; ++k) {
+      launch_cg_direction<T>(L, k == 0 ? 1 : 0);
+      int a[1] = {W_X}, b[1] = {W_D}, o[1] = {M_C};
+      launch_gram<T>(L, 1, a, b, o);
+      int y[1] = {W_D}, aa[1] = {W_X};
+      launch_gemm_acc<T>(L, 1, y, aa, M_C, 1.0, -1.0, 0);
+      launch_hpsi<T>(L, W_D);
+      launch_linemin<T>(L);
+      subspace_rotate<T>(L, true);
+    }
+  }
+
+  template <typename T>
+  void init_wavefunctions(const LaunchCtx& L) {
+    launch_init_random<T>(L);
+    int a[1] = {W_X}, b[1] = {W_X}, o[1] = {M_S};
+    launch_gram<T>(L, 1, a, b, o);
+    launch_subspace(L, 1);
+    int y[1] = {W_X};
+    launch_gemm_acc<T>(L, 1, y, y, M_M, 0.0, 1.0, 0);
+  }
+
+  void read_scal(std::vector<std::array<double, S_COUNT>>& out) {
+    out.resize(cands_.size());
+    for (size_t i = 0; i < cands_.size(); ++i)
+      HIPCHK(hipMemcpyAsync(out[i].data(), cands_[i].d.scal, S_COUNT * 8, hipMemcpyDeviceToHost,
+                            stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+  }
+
+  template <typename T>
+  int scf_t(const sgo_scf_opts& o) {
+    const int hist = std::max(2, std::min(kMaxHist, o.history));
+    BatchGeom g = prepare(o.seed, hist);
+    LaunchCtx L = ctx(g);
+    bool all_warm = true;
+    for (auto& c : cands_) all_warm = all_warm && c.have_psi;
+    setup_geometry<T>(L);
+    if (!all_warm) init_wavefunctions<T>(L);
+    launch_mix(L, 1, 0, 0, 0, o.mix_alpha, o.kerker_q0);
+    launch_grid_fft(L, +1);
+    launch_potential_finalize<T>(L);
+    HIPCHK(hipGetLastError());
+    std::vector<std::array<double, S_COUNT>> sc;
+    int nactive = (int)cands_.size();
+    int it = 0;
+    for (; it < o.max_iter; ++it) {
+      const int cur = it % hist;
+      const int nvalid = std::min(it + 1, hist - 1);
+      eigensolver<T>(L, (it == 0 && !all_warm) ? o.ncg_first : o.ncg);
+      launch_occupations(L);
+      launch_band_kinetic<T>(L);
+      launch_density<T>(L);
+      launch_density_finalize(L);
+      launch_grid_fft(L, -1);
+      launch_gspace_residual(L, cur, nvalid);
+      launch_scf_control(L, cur, nvalid, it, o.tol_e, o.tol_rho);
+      HIPCHK(hipGetLastError());
+      read_scal(sc);
+      bool changed = false;
+      for (size_t i = 0; i < cands_.size(); ++i) {
+        HostCand& c = cands_[i];
+        if (!c.d.active) continue;
+        c.info.iterations = it + 1;
+        c.info.de = sc[i][S_DE];
+        c.info.drho = sc[i][S_DRHO];
+        if (sc[i][S_ERR] != 0.0) {
+          c.status = SGO_ENUMERIC;
+          c.d.active = 0;
+          changed = true;
+        } else if (sc[i][S_CONV] != 0.0) {
+          c.info.converged = 1;
+          c.d.active = 0;
+          changed = true;
+        }
+      }
+      nactive = 0;
+      for (auto& c : cands_) nactive += c.d.active;
+      if (changed) upload_desc();
+      if (nactive == 0) break;
+      launch_mix(L, 0, cur, nvalid, (cur + 1) % hist, o.mix_alpha, o.kerker_q0);
+      launch_grid_fft(L, +1);
+      launch_potential_finalize<T>(L);
+    }
+    for (auto& c : cands_) {
+      if (c.d.active) c.status = SGO_ENOTCONV;
+      c.d.active = 1;
+      c.have_psi = true;
+      c.have_scf = true;
+    }
+    upload_desc();
+    // forces of every candidate from its final state
+    launch_force_local(L);
+    launch_force_nonlocal<T>(L);
+    launch_force_finalize(L);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    int worst = SGO_OK;
+    for (auto& c : cands_)
+      if (c.status < worst) worst = c.status;
+    return worst;
+  }
+
+  int scf(const sgo_scf_opts& o) {
+    HIPCHK(hipSetDevice(device_));
+    return prec_ == SGO_FP64 ? scf_t<double>(o) : scf_t<float>(o);
+  }
+
+  template <typename T>
+  void apply_h_t(const double* veff, int nbx, const double* psi, double* hpsi) {
+    HostCand& c = cands_.at(0);
+    if (nbx < 1 || nbx > c.nb) throw Error(SGO_EINVAL, "nb must be in [1, nbands]");
+    BatchGeom g = prepare(1, kMaxHist);
+    LaunchCtx L = ctx(g);
+    setup_geometry<T>(L);
+    std::vector<T> v(c.ntot), x((size_t)c.nb * c.K, (T)0);
+    for (int e = 0; e < c.ntot; ++e) v[e] = (T)veff[e];
+    for (size_t e = 0; e < (size_t)nbx * c.K; ++e) x[e] = (T)psi[e];
+    HIPCHK(hipMemcpy(c.d.veff_t, v.data(), c.ntot * sizeof(T), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c.d.X, x.data(), x.size() * sizeof(T), hipMemcpyHostToDevice));
+    launch_hpsi<T>(L, W_X);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    HIPCHK(hipMemcpy(x.data(), c.d.HX, x.size() * sizeof(T), hipMemcpyDeviceToHost));
+    for (size_t e = 0; e < (size_t)nbx * c.K; ++e) hpsi[e] = (double)x[e];
+    c.have_psi = false;
+    c.have_scf = false;
+  }
+  void apply_h(const double* veff, int nbx, const double* psi, double* hpsi) {
+    if (!veff || !psi || !hpsi) throw Error(SGO_EINVAL, "NULL argument");
+    HIPCHK(hipSetDevice(device_));
+    if (prec_ == SGO_FP64) apply_h_t<double>(veff, nbx, psi, hpsi);
+    else apply_h_t<float>(veff, nbx, psi, hpsi);
+  }
+
+  HostCand& cand(int i) {
+    if (i < 0 || i >= (int)cands_.size()) throw Error(SGO_EINVAL, "candidate index out of range");
+    return cands_[i];
+  }
+  int size() const { return (int)cands_.size(); }
+  void require_scf(const HostCand& c) {
+    if (!c.have_scf) throw Error(SGO_ESTATE, "sgo_scf has not run for this structure");
+  }
+  void get_scal(const HostCand& c, double* out) {
+    HIPCHK(hipSetDevice(device_));
+    HIPCHK(hipMemcpy(out, c.d.scal, S_COUNT * 8, hipMemcpyDeviceToHost));
+  }
+  void get(const void* src, void* dst, size_t bytes) {
+    HIPCHK(hipSetDevice(device_));
+    HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+  }
+  void move_atoms(int i, const double* pos) {
+    HostCand& c = cand(i);
+    if (!pos) throw Error(SGO_EINVAL, "NULL positions");
+    std::vector<double> old = c.pos;
+    c.pos.assign(pos, pos + 3 * c.nat);
+    try {
+      check_distances(c);
+    } catch (...) {
+      c.pos = old;
+      throw;
+    }
+    c.have_scf = false;  // warm start keeps psi
+  }
+  void replace(int i, const double* lat, int nat, const int* spec, const double* pos, double ecut,
+               const int* fft, int nb, int occ_kind, double sigma) {
+    HostCand& c = cand(i);
+    HostCand n;
+    fill_cand(n, lat, nat, spec, pos, ecut, fft, nb, occ_kind, sigma);
+    free_cand(c);
+    c = std::move(n);
+  }
+  void reset() {
+    for (auto& c : cands_) {
+      c.have_psi = false;
+      c.have_scf = false;
+    }
+  }
+  int precision() const { return prec_; }
+
+ private:
+  int device_, prec_, capacity_;
+  hipStream_t stream_ = nullptr;
+  std::vector<SpeciesHost> species_;
+  SpeciesDev* d_species_ = nullptr;
+  std::vector<HostCand> cands_;
+  CandDesc* d_desc_ = nullptr;
+  size_t desc_cap_ = 0;
+  bool desc_dirty_ = true;
+};
+
+}  // namespace sgo
+
+// ====================================================================== C-ABI
+using sgo::Engine;
+using sgo::Error;
+
+struct sgo_ctx {
+  Engine* eng = nullptr;
+  std::string err;
+  bool cell = false, atoms = false, cutoff = false;
+  double lat[9];
+  std::vector<int> spec;
+  std::vector<double> pos;
+  int nat = 0;
+  double ecut = 0;
+  int fft[3] = {0, 0, 0};
+  int nb = 0, occ_kind = 0;
+  double sigma = 0;
+};
+struct sgo_batch {
+  Engine* eng = nullptr;
+  std::string err;
+  std::vector<int> status;
+  std::vector<int> nat;
+};
+
+static thread_local std::string g_err;
+
+template <typename F>
+static int guard(std::string* err, F&& f) {
+  try {
+    return f();
+  } catch (const Error& e) {
+    if (err) *err = e.what();
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (err) *err = "host allocation failed";
+    return SGO_ENOMEM;
+  } catch (const std::exception& e) {
+    if (err) *err = e.what();
+    g_err = e.what();
+    return SGO_EDEVICE;
+  }
+}
+
+extern "C" {
+
+void sgo_default_opts(sgo_scf_opts* o) {
+  if (!o) return;
+  o->max_iter = 100;
+  o->ncg = 3;
+  o->ncg_first = 8;
+  o->tol_e = 1e-5;
+  o->tol_rho = 1e-4;
+  o->mix_alpha = 0.5;
+  o->kerker_q0 = 0.8;
+  o->history = 8;
+  o->seed = 1;
+  o->use_graph = 0;
+}
+
+const char* sgo_version(void) { return "sgo-mi355x 0.1 (gfx950)"; }
+
+int sgo_create(sgo_ctx** out, int device, int precision) {
+  if (!out) return SGO_EINVAL;
+  *out = nullptr;
+  return guard(nullptr, [&] {
+    sgo_ctx* c = new sgo_ctx();
+    try {
+      c->eng = new Engine(device, precision, 1);
+    } catch (...) {
+      delete c;
+      throw;
+    }
+    *out = c;
+    return SGO_OK;
+  });
+}
+
+int sgo_destroy(sgo_ctx* c) {
+  if (!c) return SGO_EINVAL;
+  delete c->eng;
+  delete c;
+  return SGO_OK;
+}
+
+int sgo_set_stream(sgo_ctx* c, void* s) {
+  if (!c) return SGO_EINVAL;
+  c->eng->set_stream(s);
+  return SGO_OK;
+}
+
+int sgo_set_species(sgo_ctx* c, int id, const sgo_species* sp) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    c->eng->set_species(id, sp);
+    return SGO_OK;
+  });
+}
+
+static void ctx_commit(sgo_ctx* c) {
+  if (!(c->cell && c->atoms && c->cutoff)) return;
+  if (c->eng->size() == 0)
+    c->eng->add(c->lat, c->nat, c->spec.data(), c->pos.data(), c->ecut, c->fft, c->nb, c->occ_kind,
+                c->sigma);
+  else
+    c->eng->replace(0, c->lat, c->nat, c->spec.data(), c->pos.data(), c->ecut, c->fft, c->nb,
+                    c->occ_kind, c->sigma);
+}
+
+int sgo_set_cell(sgo_ctx* c, const double lattice[9]) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!lattice) throw Error(SGO_EINVAL, "NULL lattice");
+    const double* A = lattice;
+    const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                       A[2] * (A[3] * A[7] - A[4] * A[6]);
+    if (!(std::fabs(det) > 1e-12)) throw Error(SGO_EINVAL, "cell volume must be positive");
+    std::memcpy(c->lat, lattice, sizeof(c->lat));
+    c->cell = true;
+    if (c->atoms && c->cutoff) ctx_commit(c);
+    return SGO_OK;
+  });
+}
+
+int sgo_set_atoms(sgo_ctx* c, int natoms, const int* species, const double* pos) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!c->cell) throw Error(SGO_ESTATE, "set the cell before the atoms");
+    if (natoms <= 0 || !species || !pos) throw Error(SGO_EINVAL, "bad atoms");
+    const bool same = c->eng->size() == 1 && natoms == c->nat &&
+                      std::equal(species, species + natoms, c->spec.begin());
+    if (same && c->cutoff) {
+      c->eng->move_atoms(0, pos);
+      c->pos.assign(pos, pos + 3 * natoms);
+      return SGO_OK;
+    }
+    std::vector<int> os = c->spec;
+    std::vector<double> op = c->pos;
+    int on = c->nat;
+    bool oa = c->atoms;
+    c->nat = natoms;
+    c->spec.assign(species, species + natoms);
+    c->pos.assign(pos, pos + 3 * natoms);
+    c->atoms = true;
+    try {
+      if (c->cutoff) ctx_commit(c);
+    } catch (...) {
+      c->spec = os;
+      c->pos = op;
+      c->nat = on;
+      c->atoms = oa;
+      throw;
+    }
+    return SGO_OK;
+  });
+}
+
+int sgo_set_cutoff(sgo_ctx* c, double ecut, const int fft[3], int nbands, int occ_kind,
+                   double sigma) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!c->cell || !c->atoms) throw Error(SGO_ESTATE, "set the cell and atoms before the cutoff");
+    if (!fft) throw Error(SGO_EINVAL, "NULL fft");
+    c->ecut = ecut;
+    std::memcpy(c->fft, fft, sizeof(c->fft));
+    c->nb = nbands;
+    c->occ_kind = occ_kind;
+    c->sigma = sigma;
+    c->cutoff = true;
+    try {
+      ctx_commit(c);
+    } catch (...) {
+      c->cutoff = false;
+      throw;
+    }
+    return SGO_OK;
+  });
+}
+
+static sgo_scf_opts opts_or_default(const sgo_scf_opts* o) {
+  sgo_scf_opts d;
+  sgo_default_opts(&d);
+  return o ? *o : d;
+}
+
+int sgo_scf(sgo_ctx* c, const sgo_scf_opts* opts, sgo_scf_info* info) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!(c->cell && c->atoms && c->cutoff) || c->eng->size() == 0)
+      throw Error(SGO_ESTATE, "set species, cell, atoms and cutoff first");
+    const sgo_scf_opts o = opts_or_default(opts);
+    if (o.max_iter < 1 || o.ncg < 1 || o.ncg_first < 1) throw Error(SGO_EINVAL, "bad options");
+    int rc = c->eng->scf(o);
+    if (info) *info = c->eng->cand(0).info;
+    return rc;
+  });
+}
+
+int sgo_energy(sgo_ctx* c, double* etot, sgo_energy_terms* t) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    c->eng->require_scf(hc);
+    double s[sgo::S_COUNT];
+    c->eng->get_scal(hc, s);
+    if (etot) *etot = s[sgo::S_ETOT];
+    if (t) {
+      t->total = s[sgo::S_ETOT];
+      t->kinetic = s[sgo::S_EKIN];
+      t->nonlocal = s[sgo::S_ENL];
+      t->local = s[sgo::S_ELOC];
+      t->hartree = s[sgo::S_EH];
+      t->xc = s[sgo::S_EXC];
+      t->ewald = s[sgo::S_EEW];
+      t->entropy = s[sgo::S_ENTROPY_TERM];
+      t->band = s[sgo::S_EBAND];
+      t->fermi = s[sgo::S_MU];
+    }
+    return SGO_OK;
+  });
+}
+
+int sgo_forces(sgo_ctx* c, double* forces) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!forces) throw Error(SGO_EINVAL, "NULL forces");
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    c->eng->require_scf(hc);
+    c->eng->get(hc.d.force, forces, 3 * hc.nat * sizeof(double));
+    return SGO_OK;
+  });
+}
+
+int sgo_stress(sgo_ctx* c, double stress[9]) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&]() -> int {
+    (void)stress;
+    throw Error(SGO_ESTATE, "stress is not available in this build");
+  });
+}
+
+int sgo_eigenvalues(sgo_ctx* c, double* eig, double* occ) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!eig) throw Error(SGO_EINVAL, "NULL eig");
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    c->eng->require_scf(hc);
+    c->eng->get(hc.d.eps, eig, hc.nb * sizeof(double));
+    if (occ) c->eng->get(hc.d.occ, occ, hc.nb * sizeof(double));
+    return SGO_OK;
+  });
+}
+
+int sgo_adjoint(sgo_ctx* c, double gE, double* grad_pos, double* grad_lattice) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!grad_pos) throw Error(SGO_EINVAL, "NULL grad_pos");
+    if (grad_lattice) throw Error(SGO_ESTATE, "lattice gradient is not available in this build");
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    c->eng->require_scf(hc);
+    std::vector<double> f(3 * hc.nat);
+    c->eng->get(hc.d.force, f.data(), f.size() * sizeof(double));
+    for (size_t k = 0; k < f.size(); ++k) grad_pos[k] = -gE * f[k];
+    return SGO_OK;
+  });
+}
+
+int sgo_reset(sgo_ctx* c) {
+  if (!c) return SGO_EINVAL;
+  c->eng->reset();
+  return SGO_OK;
+}
+
+int sgo_basis_size(sgo_ctx* c, int* npw_half, int* nproj) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    if (npw_half) *npw_half = hc.npwh;
+    if (nproj) *nproj = hc.nproj;
+    return SGO_OK;
+  });
+}
+
+int sgo_basis_millers(sgo_ctx* c, int* millers) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!millers) throw Error(SGO_EINVAL, "NULL millers");
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    std::memcpy(millers, hc.gmill.data(), hc.gmill.size() * sizeof(int));
+    return SGO_OK;
+  });
+}
+
+int sgo_apply_h(sgo_ctx* c, const double* veff, int nb, const double* psi, double* hpsi) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    c->eng->apply_h(veff, nb, psi, hpsi);
+    return SGO_OK;
+  });
+}
+
+int sgo_get_density(sgo_ctx* c, double* rho, double* veff) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    c->eng->require_scf(hc);
+    if (rho) c->eng->get(hc.d.rho_out_r, rho, hc.ntot * sizeof(double));
+    if (veff) c->eng->get(hc.d.veff_r, veff, hc.ntot * sizeof(double));
+    return SGO_OK;
+  });
+}
+
+const char* sgo_last_error(const sgo_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+// ---------------------------------------------------------------- batches
+int sgo_batch_create(sgo_batch** out, int device, int precision, int capacity) {
+  if (!out) return SGO_EINVAL;
+  *out = nullptr;
+  return guard(nullptr, [&] {
+    sgo_batch* b = new sgo_batch();
+    try {
+      b->eng = new Engine(device, precision, capacity);
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    *out = b;
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_destroy(sgo_batch* b) {
+  if (!b) return SGO_EINVAL;
+  delete b->eng;
+  delete b;
+  return SGO_OK;
+}
+
+int sgo_batch_set_stream(sgo_batch* b, void* s) {
+  if (!b) return SGO_EINVAL;
+  b->eng->set_stream(s);
+  return SGO_OK;
+}
+
+int sgo_batch_set_species(sgo_batch* b, int id, const sgo_species* sp) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    b->eng->set_species(id, sp);
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_add(sgo_batch* b, const double lattice[9], int natoms, const int* species,
+                  const double* pos, double ecut, const int fft[3], int nbands, int occ_kind,
+                  double sigma, int* index_out) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    int i = b->eng->add(lattice, natoms, species, pos, ecut, fft, nbands, occ_kind, sigma);
+    b->nat.push_back(natoms);
+    b->status.push_back(SGO_OK);
+    if (index_out) *index_out = i;
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_set_atoms(sgo_batch* b, int i, const double* pos) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    b->eng->move_atoms(i, pos);
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, double* forces,
+                  int* status) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if (b->eng->size() == 0) throw Error(SGO_ESTATE, "empty batch");
+    const sgo_scf_opts o = opts_or_default(opts);
+    int rc = b->eng->scf(o);
+    size_t off = 0;
+    for (int i = 0; i < b->eng->size(); ++i) {
+      auto& hc = b->eng->cand(i);
+      if (energies) {
+        double s[sgo::S_COUNT];
+        b->eng->get_scal(hc, s);
+        energies[i] = s[sgo::S_ETOT];
+      }
+      if (forces) b->eng->get(hc.d.force, forces + off, 3 * hc.nat * sizeof(double));
+      off += 3 * hc.nat;
+      if (status) status[i] = hc.status;
+      b->status[i] = hc.status;
+    }
+    return rc;
+  });
+}
+
+int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if (!info) throw Error(SGO_EINVAL, "NULL info");
+    *info = b->eng->cand(i).info;
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_size(sgo_batch* b, int* n) {
+  if (!b || !n) return SGO_EINVAL;
+  *n = b->eng->size();
+  return SGO_OK;
+}
+
+const char* sgo_batch_last_error(const sgo_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

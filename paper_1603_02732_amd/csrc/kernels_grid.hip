@@ -1,0 +1,856 @@
+// FP64 grid-side kernels: full-grid FFT passes, output density and energy
+// sums, density residual and Pulay/Kerker mixing (the "rho_out is mixed with
+// rho_in" step of the SCF loop, Section 2.4), potentials, per-geometry setup
+// (local potential and starting density from structure factors, Ewald sum),
+// Hellmann-Feynman force sums, occupations, and the FP64 subspace solver
+// (Cholesky orthonormalisation + Jacobi diagonalisation, Algorithm 1 lines
+// "Orthogonalization" and "subspace diagonalization").
+#include "device.hpp"
+#include "launch.hpp"
+
+#include <algorithm>
+
+namespace sgo {
+
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ __forceinline__ int gfreq(int i, int n) { return i < (n + 1) / 2 ? i : i - n; }
+
+// G vector, |G|^2 and membership of the density set D for grid index e of
+// the [z][y][x] layout.
+struct GPoint {
+  double G[3];
+  double g2;
+  bool inD;
+};
+__device__ __forceinline__ GPoint gpoint(const CandDesc& cd, int e) {
+  const int x = e % cd.N1;
+  const int yz = e / cd.N1;
+  const int y = yz % cd.N2;
+  const int z = yz / cd.N2;
+  const int m1 = gfreq(x, cd.N1), m2 = gfreq(y, cd.N2), m3 = gfreq(z, cd.N3);
+  GPoint p;
+  p.G[0] = m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6];
+  p.G[1] = m1 * cd.B[1] + m2 * cd.B[4] + m3 * cd.B[7];
+  p.G[2] = m1 * cd.B[2] + m2 * cd.B[5] + m3 * cd.B[8];
+  p.g2 = p.G[0] * p.G[0] + p.G[1] * p.G[1] + p.G[2] * p.G[2];
+  p.inD = 2 * abs(m1) < cd.N1 && 2 * abs(m2) < cd.N2 && 2 * abs(m3) < cd.N3;
+  return p;
+}
+
+// Local pseudopotential transform v_s(G), G != 0 (Coulomb tail included).
+__device__ __forceinline__ double vloc_ft(const SpeciesDev& s, double g2) {
+  if (s.local_kind == 0) {  // Appelbaum-Hamann form
+    const double a = s.p[0], v1 = s.p[1], v2 = s.p[2];
+    const double e = exp(-g2 / (4.0 * a));
+    return -4.0 * kPi * s.Z / g2 * e +
+           pow(kPi / a, 1.5) * e * (v1 + v2 * (1.5 / a - g2 / (4.0 * a * a)));
+  }
+  const double rl = s.p[0], c1 = s.p[1], c2 = s.p[2];
+  const double e = exp(-0.5 * g2 * rl * rl);
+  return -4.0 * kPi * s.Z / g2 * e +
+         pow(2.0 * kPi, 1.5) * rl * rl * rl * e * (c1 + c2 * (3.0 - g2 * rl * rl));
+}
+// lim_{G->0} [v_s(G) + 4 pi Z / G^2]
+__device__ __forceinline__ double vloc_g0(const SpeciesDev& s) {
+  if (s.local_kind == 0) {
+    const double a = s.p[0];
+    return kPi * s.Z / a + pow(kPi / a, 1.5) * (s.p[1] + 1.5 * s.p[2] / a);
+  }
+  const double rl = s.p[0];
+  return 2.0 * kPi * s.Z * rl * rl + pow(2.0 * kPi, 1.5) * rl * rl * rl * (s.p[1] + 3.0 * s.p[2]);
+}
+
+__device__ __forceinline__ int nblk(const CandDesc& cd) {
+  return min(1024, (cd.ntot + kNT - 1) / kNT);
+}
+
+// ------------------------------------------------------------ full-grid FFT
+// Rows along x (contiguous).
+__global__ void __launch_bounds__(kNT) k_grid_fft_x(const CandDesc* __restrict__ cds, int sign,
+                                                    int rows_per_block) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int N1 = cd.N1, nrows = cd.N2 * cd.N3;
+  const int r0 = blockIdx.x * rows_per_block;
+  if (r0 >= nrows) return;
+  const int nr = min(rows_per_block, nrows - r0);
+  extern __shared__ __align__(16) char smem[];
+  cplx<double>* tw = (cplx<double>*)smem;
+  cplx<double>* A = tw + kMaxFftN;
+  cplx<double>* Bf = A + rows_per_block * N1;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, N1, tid, nthr);
+  cplx<double>* g = cd.zgrid + (size_t)r0 * N1;
+  for (int e = tid; e < nr * N1; e += nthr) A[e] = g[e];
+  __syncthreads();
+  cplx<double>* r = lds_fft(A, Bf, cd.plan[0], nr, 1, N1, tw, sign, tid, nthr);
+  for (int e = tid; e < nr * N1; e += nthr) g[e] = r[e];
+}
+
+// Columns along y (axis 1) or z (axis 2): each block takes a tile of TX
+// consecutive x values, so global accesses stay contiguous in x.
+constexpr int kTX = 16;
+__global__ void __launch_bounds__(kNT) k_grid_fft_yz(const CandDesc* __restrict__ cds, int axis,
+                                                     int sign) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int N1 = cd.N1, N2 = cd.N2, N3 = cd.N3;
+  const int ntx = (N1 + kTX - 1) / kTX;
+  const int other_n = axis == 1 ? N3 : N2;
+  const int tile = blockIdx.x % ntx, other = blockIdx.x / ntx;
+  if (other >= other_n) return;
+  const int x0 = tile * kTX, tx = min(kTX, N1 - x0);
+  const int n = axis == 1 ? N2 : N3;
+  const size_t es = axis == 1 ? (size_t)N1 : (size_t)N1 * N2;
+  const size_t base = axis == 1 ? (size_t)other * N1 * N2 + x0 : (size_t)other * N1 + x0;
+  extern __shared__ __align__(16) char smem[];
+  cplx<double>* tw = (cplx<double>*)smem;
+  cplx<double>* A = tw + kMaxFftN;
+  cplx<double>* Bf = A + kTX * n;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  fill_twiddles(tw, n, tid, nthr);
+  const FftPlan& P = cd.plan[axis];
+  for (int t = tid; t < tx * n; t += nthr) {
+    const int e = t / tx, c = t - e * tx;
+    A[c * n + e] = cd.zgrid[base + e * es + c];
+  }
+  __syncthreads();
+  cplx<double>* r = lds_fft(A, Bf, P, tx, 1, n, tw, sign, tid, nthr);
+  for (int t = tid; t < tx * n; t += nthr) {
+    const int e = t / tx, c = t - e * tx;
+    cd.zgrid[base + e * es + c] = r[c * n + e];
+  }
+}
+
+// --------------------------------------------------------- density / energy
+// rho_out(r) = sum of the band-pair chunks / Omega; accumulates
+// sum|rho_out - rho_in|, E_xc[rho_out] and int V_eff,in rho_out.
+__global__ void __launch_bounds__(kNT) k_density_finalize(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  if ((int)blockIdx.x >= nblk(cd)) return;
+  __shared__ double sh[16 * 3];
+  double v[3] = {0.0, 0.0, 0.0};
+  const double inv_omega = 1.0 / cd.omega;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cd.ntot; e += nblk(cd) * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < cd.ndens_chunk; ++c) s += cd.dens_part[(size_t)c * cd.ntot + e];
+    const double rho = s * inv_omega;
+    cd.rho_out_r[e] = rho;
+    cd.zgrid[e] = {rho, 0.0};
+    v[0] += fabs(rho - cd.rho_in_r[e]);
+    const double rc = fmax(rho, 0.0);
+    double ex, vx;
+    pz81(rc, &ex, &vx);
+    v[1] += rc * ex;
+    v[2] += cd.veff_r[e] * rho;
+  }
+  block_sum<3>(v, sh);
+  double out[3];
+  if (grid_sum_last<3>(v, cd.red_part, &cd.tickets[kTicketGrid], nblk(cd), blockIdx.x, out, sh)) {
+    if (threadIdx.x == 0) {
+      const double w = cd.omega / cd.ntot;
+      cd.scal[S_DRHO] = w * out[0] / fmax(cd.nelec, 1e-30);
+      cd.scal[S_EXC] = w * out[1];
+      cd.scal[S_VRHO] = w * out[2];
+    }
+  }
+}
+
+// After the forward FFT of rho_out: rho_out(G), density residual into the
+// history, Hartree and local energies, and the residual dot products of the
+// Pulay matrix row of this iteration.
+__global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restrict__ cds, int cur,
+                                                         int nvalid) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  if ((int)blockIdx.x >= nblk(cd)) return;
+  __shared__ double sh[16 * 10];
+  const int H = cd.hist_len;
+  double v[10];
+#pragma unroll
+  for (int k = 0; k < 10; ++k) v[k] = 0.0;
+  const double inv_n = 1.0 / cd.ntot;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cd.ntot; e += nblk(cd) * blockDim.x) {
+    const cplx<double> z = cd.zgrid[e];
+    const cplx<double> rg = {z.x * inv_n, z.y * inv_n};
+    cd.rho_out_G[e] = rg;
+    const cplx<double> rin = cd.hist_in[(size_t)cur * cd.ntot + e];
+    const cplx<double> R = {rg.x - rin.x, rg.y - rin.y};
+    cd.hist_res[(size_t)cur * cd.ntot + e] = R;
+    const GPoint p = gpoint(cd, e);
+    if (p.inD) {
+      if (p.g2 > 0.0) v[0] += 4.0 * kPi * (rg.x * rg.x + rg.y * rg.y) / p.g2;
+      const cplx<double> vl = cd.vloc_G[e];
+      v[1] += vl.x * rg.x + vl.y * rg.y;
+    }
+#pragma unroll
+    for (int l = 0; l < kMaxHist; ++l) {
+      if (l < nvalid) {
+        const int slot = (cur - l + H) % H;
+        const cplx<double> Rl = cd.hist_res[(size_t)slot * cd.ntot + e];
+        v[2 + l] += Rl.x * R.x + Rl.y * R.y;
+      }
+    }
+  }
+  block_sum<10>(v, sh);
+  double out[10];
+  if (grid_sum_last<10>(v, cd.red_part, &cd.tickets[kTicketGrid + 1], nblk(cd), blockIdx.x, out,
+                        sh)) {
+    if (threadIdx.x == 0) {
+      cd.scal[S_EH] = 0.5 * cd.omega * out[0];
+      cd.scal[S_ELOC] = cd.omega * out[1];
+      for (int l = 0; l < nvalid; ++l) {
+        const int slot = (cur - l + H) % H;
+        cd.pulay[cur * kMaxHist + slot] = out[2 + l];
+        cd.pulay[slot * kMaxHist + cur] = out[2 + l];
+      }
+    }
+  }
+}
+
+// Pulay coefficients, total free energy, convergence flags (one block per
+// candidate; the work is a few dozen scalars).
+__global__ void k_scf_control(const CandDesc* __restrict__ cds, int cur, int nvalid, int iter,
+                              double tol_e_atom, double tol_rho) {
+  const CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active) return;
+  if (threadIdx.x != 0) return;
+  const int H = cd.hist_len;
+  double* sc = cd.scal;
+  // Pulay: minimise |sum c_l R_l| with sum c_l = 1
+  const int n = nvalid;
+  double A[kMaxHist + 1][kMaxHist + 2];
+  double scale = 0.0;
+  for (int l = 0; l < n; ++l) {
+    const int sl = (cur - l + H) % H;
+    scale = fmax(scale, fabs(cd.pulay[sl * kMaxHist + sl]));
+  }
+  if (!(scale > 0.0)) scale = 1.0;
+  for (int l = 0; l < n; ++l) {
+    const int sl = (cur - l + H) % H;
+    for (int m = 0; m < n; ++m) {
+      const int sm = (cur - m + H) % H;
+      A[l][m] = cd.pulay[sl * kMaxHist + sm] / scale;
+    }
+    A[l][l] += 1e-13;
+    A[l][n] = 1.0;
+    A[l][n + 1] = 0.0;
+  }
+  for (int m = 0; m < n; ++m) A[n][m] = 1.0;
+  A[n][n] = 0.0;
+  A[n][n + 1] = 1.0;
+  const int N = n + 1;
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < N; ++r)
+      if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+    if (piv != k)
+      for (int c = 0; c <= N; ++c) {
+        const double t = A[k][c];
+        A[k][c] = A[piv][c];
+        A[piv][c] = t;
+      }
+    const double d = A[k][k];
+    for (int r = k + 1; r < N; ++r) {
+      const double f = A[r][k] / d;
+      for (int c = k; c <= N; ++c) A[r][c] -= f * A[k][c];
+    }
+  }
+  double x[kMaxHist + 1];
+  for (int k = N - 1; k >= 0; --k) {
+    double s = A[k][N];
+    for (int c = k + 1; c < N; ++c) s -= A[k][c] * x[c];
+    x[k] = s / A[k][k];
+  }
+  bool ok = true;
+  for (int l = 0; l < n; ++l) ok = ok && isfinite(x[l]);
+  for (int l = 0; l < n; ++l) cd.coef[(cur - l + H) % H] = ok ? x[l] : (l == 0 ? 1.0 : 0.0);
+  // energies
+  double ekin = 0.0;
+  for (int i = 0; i < cd.nb; ++i) ekin += cd.occ[i] * cd.bandw[i];
+  const double ekn = sc[S_EBAND] - sc[S_VRHO];
+  const double ent = -cd.sigma * sc[S_ENTROPY];
+  const double etot = ekn + sc[S_ELOC] + sc[S_EH] + sc[S_EXC] + sc[S_EEW] + ent;
+  sc[S_EKIN] = ekin;
+  sc[S_ENL] = ekn - ekin;
+  sc[S_ENTROPY_TERM] = ent;
+  const double de = iter > 0 ? fabs(etot - sc[S_EPREV]) : 1e300;
+  sc[S_DE] = de;
+  sc[S_EPREV] = etot;
+  sc[S_ETOT] = etot;
+  sc[S_ITER] = iter + 1;
+  sc[S_CONV] = (iter > 0 && de < tol_e_atom * cd.nat && sc[S_DRHO] < tol_rho) ? 1.0 : 0.0;
+  if (!isfinite(etot) || !isfinite(sc[S_DRHO])) sc[S_ERR] = 1.0;
+}
+
+// Mixed input density in G space and the potential V(G) = V_loc + V_H on D,
+// packed as V(G) + i rho_in(G) for one inverse transform of both.
+__global__ void __launch_bounds__(kNT) k_mix(const CandDesc* __restrict__ cds, int initial,
+                                             int cur, int nvalid, int next, double alpha,
+                                             double q0) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int H = cd.hist_len;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cd.ntot; e += gridDim.x * blockDim.x) {
+    const GPoint p = gpoint(cd, e);
+    cplx<double> rho;
+    if (initial) {
+      rho = cd.rho0_G[e];
+    } else {
+      const double kk = p.g2 > 0.0 ? p.g2 / (p.g2 + q0 * q0) : 0.0;
+      rho = {0.0, 0.0};
+      for (int l = 0; l < nvalid; ++l) {
+        const int sl = (cur - l + H) % H;
+        const double c = cd.coef[sl];
+        const cplx<double> ri = cd.hist_in[(size_t)sl * cd.ntot + e];
+        const cplx<double> rr = cd.hist_res[(size_t)sl * cd.ntot + e];
+        rho.x += c * (ri.x + alpha * kk * rr.x);
+        rho.y += c * (ri.y + alpha * kk * rr.y);
+      }
+    }
+    cd.hist_in[(size_t)next * cd.ntot + e] = rho;
+    cplx<double> V = {0.0, 0.0};
+    if (p.inD) {
+      V = cd.vloc_G[e];
+      if (p.g2 > 0.0) {
+        V.x += 4.0 * kPi * rho.x / p.g2;
+        V.y += 4.0 * kPi * rho.y / p.g2;
+      }
+    }
+    cd.zgrid[e] = {V.x - rho.y, V.y + rho.x};
+  }
+}
+
+// --------------------------------------------------------------- setup
+// V_loc(G) = (1/Omega) sum_I v_s(|G|) e^{-iG.R_I} and the starting density
+// rho_0(G) = (1/Omega) sum_I Z_I e^{-G^2 w^2/2} e^{-iG.R_I} on D.
+__global__ void __launch_bounds__(kNT) k_setup_grid(const CandDesc* __restrict__ cds,
+                                                    const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const double io = 1.0 / cd.omega;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cd.ntot; e += gridDim.x * blockDim.x) {
+    const GPoint p = gpoint(cd, e);
+    cplx<double> vl = {0.0, 0.0}, r0 = {0.0, 0.0};
+    if (p.inD) {
+      double ztot = 0.0;
+      for (int I = 0; I < cd.nat; ++I) {
+        const SpeciesDev& s = sp[cd.spec[I]];
+        double sn, cs;
+        sincos(-(p.G[0] * cd.pos[3 * I] + p.G[1] * cd.pos[3 * I + 1] + p.G[2] * cd.pos[3 * I + 2]),
+               &sn, &cs);
+        const double v = p.g2 > 0.0 ? vloc_ft(s, p.g2) : vloc_g0(s);
+        vl.x += v * cs;
+        vl.y += v * sn;
+        const double a = s.Z * exp(-0.5 * p.g2 * s.rho0_width * s.rho0_width);
+        r0.x += a * cs;
+        r0.y += a * sn;
+        ztot += s.Z;
+      }
+      if (p.g2 == 0.0) r0.x += cd.nelec - ztot;
+    }
+    cd.vloc_G[e] = {vl.x * io, vl.y * io};
+    cd.rho0_G[e] = {r0.x * io, r0.y * io};
+  }
+}
+
+// Ewald, reciprocal part: S(G) = sum_J Z_J e^{iG.R_J} on the enumerated box
+// and E_recip = (2 pi/Omega) sum_{0<|G|<=gcut} e^{-G^2/4eta^2}/G^2 |S|^2.
+__global__ void __launch_bounds__(kNT) k_ewald_recip(const CandDesc* __restrict__ cds,
+                                                     const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int nb = min(1024, (cd.ew_ng + kNT - 1) / kNT);
+  if ((int)blockIdx.x >= nb) return;
+  __shared__ double sh[16];
+  const int w1 = 2 * cd.ew_m[0] + 1, w2 = 2 * cd.ew_m[1] + 1;
+  const double eta = cd.ew_eta;
+  double v[1] = {0.0};
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cd.ew_ng; t += nb * blockDim.x) {
+    const int m1 = t % w1 - cd.ew_m[0];
+    const int m2 = (t / w1) % w2 - cd.ew_m[1];
+    const int m3 = t / (w1 * w2) - cd.ew_m[2];
+    const double G0 = m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6];
+    const double G1 = m1 * cd.B[1] + m2 * cd.B[4] + m3 * cd.B[7];
+    const double G2 = m1 * cd.B[2] + m2 * cd.B[5] + m3 * cd.B[8];
+    const double g2 = G0 * G0 + G1 * G1 + G2 * G2;
+    cplx<double> S = {0.0, 0.0};
+    if (g2 > 0.0 && g2 <= cd.ew_gcut * cd.ew_gcut) {
+      for (int J = 0; J < cd.nat; ++J) {
+        double sn, cs;
+        sincos(G0 * cd.pos[3 * J] + G1 * cd.pos[3 * J + 1] + G2 * cd.pos[3 * J + 2], &sn, &cs);
+        const double Z = sp[cd.spec[J]].Z;
+        S.x += Z * cs;
+        S.y += Z * sn;
+      }
+      v[0] += exp(-g2 / (4.0 * eta * eta)) / g2 * (S.x * S.x + S.y * S.y);
+    }
+    cd.ewS[t] = S;
+  }
+  block_sum<1>(v, sh);
+  double out[1];
+  if (grid_sum_last<1>(v, cd.red_part, &cd.tickets[kTicketGrid + 2], nb, blockIdx.x, out, sh)) {
+    if (threadIdx.x == 0) cd.scal[S_EWRECIP] = 2.0 * kPi / cd.omega * out[0];
+  }
+}
+
+// Ewald, per atom I: real-space pair sum over images, reciprocal force from
+// S(G); the last block adds self and background terms to the total.
+__global__ void __launch_bounds__(kNT) k_ewald_atom(const CandDesc* __restrict__ cds,
+                                                    const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int I = blockIdx.x;
+  if (I >= cd.nat) return;
+  __shared__ double sh[16 * 4];
+  const double eta = cd.ew_eta;
+  const double ZI = sp[cd.spec[I]].Z;
+  const double RI0 = cd.pos[3 * I], RI1 = cd.pos[3 * I + 1], RI2 = cd.pos[3 * I + 2];
+  const int n1 = 2 * cd.ew_n[0] + 1, n2 = 2 * cd.ew_n[1] + 1;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};  // energy, Fx, Fy, Fz
+  const double rc2 = cd.ew_rcut * cd.ew_rcut;
+  const long total = (long)cd.nat * cd.ew_nimg;
+  for (long t = threadIdx.x; t < total; t += blockDim.x) {
+    const int J = (int)(t / cd.ew_nimg);
+    const int im = (int)(t - (long)J * cd.ew_nimg);
+    const int a = im % n1 - cd.ew_n[0];
+    const int b = (im / n1) % n2 - cd.ew_n[1];
+    const int c = im / (n1 * n2) - cd.ew_n[2];
+    const double d0 = RI0 - cd.pos[3 * J] + a * cd.A[0] + b * cd.A[3] + c * cd.A[6];
+    const double d1 = RI1 - cd.pos[3 * J + 1] + a * cd.A[1] + b * cd.A[4] + c * cd.A[7];
+    const double d2 = RI2 - cd.pos[3 * J + 2] + a * cd.A[2] + b * cd.A[5] + c * cd.A[8];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 < 1e-24 || r2 > rc2) continue;
+    const double r = sqrt(r2);
+    const double ZZ = ZI * sp[cd.spec[J]].Z;
+    const double ec = erfc(eta * r);
+    v[0] += 0.5 * ZZ * ec / r;
+    const double dphi = ec / r2 + 2.0 * eta / sqrt(kPi) * exp(-eta * eta * r2) / r;
+    const double f = ZZ * dphi / r;
+    v[1] += f * d0;
+    v[2] += f * d1;
+    v[3] += f * d2;
+  }
+  const int w1 = 2 * cd.ew_m[0] + 1, w2 = 2 * cd.ew_m[1] + 1;
+  for (int t = threadIdx.x; t < cd.ew_ng; t += blockDim.x) {
+    const int m1 = t % w1 - cd.ew_m[0];
+    const int m2 = (t / w1) % w2 - cd.ew_m[1];
+    const int m3 = t / (w1 * w2) - cd.ew_m[2];
+    const double G0 = m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6];
+    const double G1 = m1 * cd.B[1] + m2 * cd.B[4] + m3 * cd.B[7];
+    const double G2 = m1 * cd.B[2] + m2 * cd.B[5] + m3 * cd.B[8];
+    const double g2 = G0 * G0 + G1 * G1 + G2 * G2;
+    if (!(g2 > 0.0) || g2 > cd.ew_gcut * cd.ew_gcut) continue;
+    const cplx<double> S = cd.ewS[t];
+    double sn, cs;
+    sincos(G0 * RI0 + G1 * RI1 + G2 * RI2, &sn, &cs);
+    // Im[conj(S) e^{iG.R_I}]
+    const double im = S.x * sn - S.y * cs;
+    const double w = 4.0 * kPi / cd.omega * ZI * exp(-g2 / (4.0 * eta * eta)) / g2 * im;
+    v[1] += w * G0;
+    v[2] += w * G1;
+    v[3] += w * G2;
+  }
+  block_sum<4>(v, sh);
+  if (threadIdx.x == 0) {
+    cd.force_ew[3 * I] = v[1];
+    cd.force_ew[3 * I + 1] = v[2];
+    cd.force_ew[3 * I + 2] = v[3];
+  }
+  double e1[1] = {v[0]};
+  double out[1];
+  if (grid_sum_last<1>(e1, cd.red_part + 64, &cd.tickets[kTicketGrid + 3], cd.nat, I, out, sh)) {
+    if (threadIdx.x == 0) {
+      double z2 = 0.0, zs = 0.0;
+      for (int J = 0; J < cd.nat; ++J) {
+        const double Z = sp[cd.spec[J]].Z;
+        z2 += Z * Z;
+        zs += Z;
+      }
+      const double eself = -eta / sqrt(kPi) * z2;
+      const double ebg = -kPi * zs * zs / (2.0 * cd.omega * eta * eta);
+      cd.scal[S_EEW] = out[0] + cd.scal[S_EWRECIP] + eself + ebg;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ forces
+// F_loc,I = sum_{G in D, G != 0} G v_s(|G|) Im[e^{iG.R_I} rho(G)].
+__global__ void __launch_bounds__(kNT) k_force_local(const CandDesc* __restrict__ cds,
+                                                     const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int I = blockIdx.x;
+  if (I >= cd.nat) return;
+  __shared__ double sh[16 * 3];
+  const SpeciesDev& s = sp[cd.spec[I]];
+  const double R0 = cd.pos[3 * I], R1 = cd.pos[3 * I + 1], R2 = cd.pos[3 * I + 2];
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int e = threadIdx.x; e < cd.ntot; e += blockDim.x) {
+    const GPoint p = gpoint(cd, e);
+    if (!p.inD || !(p.g2 > 0.0)) continue;
+    const double vs = vloc_ft(s, p.g2);
+    double sn, cs;
+    sincos(p.G[0] * R0 + p.G[1] * R1 + p.G[2] * R2, &sn, &cs);
+    const cplx<double> r = cd.rho_out_G[e];
+    const double im = vs * (cs * r.y + sn * r.x);
+    v[0] += p.G[0] * im;
+    v[1] += p.G[1] * im;
+    v[2] += p.G[2] * im;
+  }
+  block_sum<3>(v, sh);
+  if (threadIdx.x == 0) {
+    cd.force_part[3 * I] = v[0];
+    cd.force_part[3 * I + 1] = v[1];
+    cd.force_part[3 * I + 2] = v[2];
+  }
+}
+
+// Total force: local + nonlocal (-2 sum_i f_i sum_{p on I} h_p P dP) + Ewald.
+__global__ void k_force_finalize(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active) return;
+  for (int t = threadIdx.x; t < 3 * cd.nat; t += blockDim.x) {
+    const int I = t / 3, a = t - 3 * I;
+    double fnl = 0.0;
+    for (int p = 0; p < cd.nproj; ++p) {
+      if (cd.proj_atom[p] != I) continue;
+      double s = 0.0;
+      for (int i = 0; i < cd.nb; ++i) {
+        const double* w = cd.nlwork + ((size_t)p * cd.nb + i) * 4;
+        s += cd.occ[i] * w[0] * w[1 + a];
+      }
+      fnl += -2.0 * cd.hproj[p] * s;
+    }
+    cd.force_part[3 * cd.nat + t] = fnl;
+    cd.force[t] = cd.force_part[t] + fnl + cd.force_ew[t];
+  }
+}
+
+// ------------------------------------------------------------ occupations
+// Fixed: f = 2 on the lowest nocc bands.  Fermi-Dirac: f = 2/(1+e^{(e-mu)/s})
+// with mu from 200 bisection steps so that sum f = N_el; entropy
+// S = -2 sum [g ln g + (1-g) ln(1-g)], g = f/2.
+__global__ void k_occupations(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active) return;
+  __shared__ double sh[16 * 2];
+  const int n = cd.nb;
+  if (cd.occ_kind == 0) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) cd.occ[i] = i < cd.nocc ? 2.0 : 0.0;
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += (i < cd.nocc ? 2.0 : 0.0) * cd.eps[i];
+    block_sum<1>(v, sh);
+    if (threadIdx.x == 0) {
+      cd.scal[S_EBAND] = v[0];
+      cd.scal[S_ENTROPY] = 0.0;
+      cd.scal[S_MU] = cd.nocc < n ? 0.5 * (cd.eps[cd.nocc - 1] + cd.eps[cd.nocc]) : cd.eps[n - 1];
+    }
+    return;
+  }
+  const double sg = cd.sigma;
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    lo = fmin(lo, cd.eps[i]);
+    hi = fmax(hi, cd.eps[i]);
+  }
+  lo -= 40.0 * sg;
+  hi += 40.0 * sg;
+  for (int it = 0; it < 200; ++it) {
+    const double mu = 0.5 * (lo + hi);
+    double v[1] = {0.0};
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += 2.0 / (1.0 + exp((cd.eps[i] - mu) / sg));
+    block_sum<1>(v, sh);
+    if (v[0] > cd.nelec) hi = mu;
+    else lo = mu;
+  }
+  const double mu = 0.5 * (lo + hi);
+  double v[2] = {0.0, 0.0};
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double f = 2.0 / (1.0 + exp((cd.eps[i] - mu) / sg));
+    cd.occ[i] = f;
+    v[0] += f * cd.eps[i];
+    const double g = fmax(0.5 * f, 1e-300), gm = fmax(1.0 - 0.5 * f, 1e-300);
+    v[1] += g * log(g) + gm * log(gm);
+  }
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0) {
+    cd.scal[S_EBAND] = v[0];
+    cd.scal[S_ENTROPY] = -2.0 * v[1];
+    cd.scal[S_MU] = mu;
+  }
+}
+
+// ------------------------------------------------- FP64 subspace solver
+// mode 1: orthonormalise only:  S = L L^T, M = L^-T.
+// mode 3: orthonormalise + Rayleigh-Ritz:  H' = L^-1 H L^-T = V diag(e) V^T,
+//         M = L^-T V (columns sorted by ascending e), eps = e.
+// New bands are X_new[:, i] = sum_j X[:, j] M[j][i].
+constexpr int kSubNT = 512;
+__global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict__ cds, int mode,
+                                                     int use_lds) {
+  const CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active) return;
+  const int n = cd.nb;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  extern __shared__ __align__(16) char smem[];
+  const bool in_lds = use_lds != 0;
+  double *P0, *P1, *P2, *P3;
+  if (in_lds) {
+    P0 = (double*)smem;
+    P1 = P0 + n * n;
+    P2 = P1 + n * n;
+    P3 = P2 + n * n;
+    for (int e = tid; e < n * n; e += nthr) {
+      P0[e] = cd.S[e];
+      P1[e] = cd.Hs[e];
+    }
+  } else {
+    P0 = cd.S;
+    P1 = cd.Hs;
+    P2 = cd.C;
+    P3 = cd.M;
+  }
+  __shared__ int fail;
+  __shared__ double jc[320], js[320];
+  __shared__ int jp[320], jq[320];
+  __shared__ double sh[16 * 2];
+  __shared__ int rank[640];
+  if (tid == 0) fail = 0;
+  __syncthreads();
+  // Cholesky S = L L^T (lower, in place)
+  for (int k = 0; k < n; ++k) {
+    if (tid == 0) {
+      const double d = P0[k * n + k];
+      if (!(d > 0.0)) fail = 1;
+      else P0[k * n + k] = sqrt(d);
+    }
+    __syncthreads();
+    if (fail) break;
+    const double piv = P0[k * n + k];
+    for (int i = k + 1 + tid; i < n; i += nthr) P0[i * n + k] /= piv;
+    __syncthreads();
+    const int m = n - k - 1;
+    for (int t = tid; t < m * m; t += nthr) {
+      const int i = k + 1 + t / m, j = k + 1 + t % m;
+      if (j <= i) P0[i * n + j] -= P0[i * n + k] * P0[j * n + k];
+    }
+    __syncthreads();
+  }
+  if (fail) {
+    if (tid == 0) cd.scal[S_ERR] = 2.0;
+    for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
+    return;
+  }
+  // W = L^-1 (lower) into P2, column by column
+  for (int j = tid; j < n; j += nthr) {
+    for (int i = 0; i < j; ++i) P2[i * n + j] = 0.0;
+    P2[j * n + j] = 1.0 / P0[j * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += P0[i * n + k] * P2[k * n + j];
+      P2[i * n + j] = -s / P0[i * n + i];
+    }
+  }
+  __syncthreads();
+  if (mode == 1) {
+    // M = W^T
+    if (in_lds) {
+      for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * n + e / n];
+    } else {
+      for (int e = tid; e < n * n; e += nthr) P0[e] = P2[(e % n) * n + e / n];
+      __syncthreads();
+      for (int e = tid; e < n * n; e += nthr) cd.M[e] = P0[e];
+    }
+    return;
+  }
+  // T1 = W H -> P3 ; H' = T1 W^T -> P1 (symmetrised)
+  for (int e = tid; e < n * n; e += nthr) {
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int k = 0; k <= i; ++k) s += P2[i * n + k] * P1[k * n + j];
+    P3[e] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += nthr) {
+    const int i = e / n, j = e % n;
+    double s = 0.0;
+    for (int k = 0; k <= j; ++k) s += P3[i * n + k] * P2[j * n + k];
+    P1[e] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += nthr) {
+    const int i = e / n, j = e % n;
+    if (i < j) {
+      const double a = 0.5 * (P1[i * n + j] + P1[j * n + i]);
+      P1[i * n + j] = a;
+      P1[j * n + i] = a;
+    }
+  }
+  for (int e = tid; e < n * n; e += nthr) P3[e] = (e / n == e % n) ? 1.0 : 0.0;
+  __syncthreads();
+  // cyclic Jacobi, round-robin ordering of disjoint pairs
+  const int n2 = n + (n & 1);
+  const int npair = n2 / 2;
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double v[2] = {0.0, 0.0};
+    for (int e = tid; e < n * n; e += nthr) {
+      const int i = e / n, j = e % n;
+      const double a = P1[e];
+      if (i == j) v[1] += a * a;
+      else v[0] += a * a;
+    }
+    block_sum<2>(v, sh);
+    if (!(v[0] > 1e-30 * v[1])) break;
+    for (int r = 0; r < n2 - 1; ++r) {
+      for (int k = tid; k < npair; k += nthr) {
+        const int a = k == 0 ? 0 : ((r + k - 1) % (n2 - 1)) + 1;
+        const int kb = n2 - 1 - k;
+        const int b = kb == 0 ? 0 : ((r + kb - 1) % (n2 - 1)) + 1;
+        const int p = min(a, b), q = max(a, b);
+        double c = 1.0, s = 0.0;
+        if (q < n) {
+          const double apq = P1[p * n + q];
+          if (fabs(apq) > 1e-300) {
+            const double th = (P1[q * n + q] - P1[p * n + p]) / (2.0 * apq);
+            double t;
+            if (fabs(th) > 1e150) t = 0.5 / th;
+            else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+          }
+        }
+        jc[k] = c;
+        js[k] = s;
+        jp[k] = p;
+        jq[k] = q < n ? q : -1;
+      }
+      __syncthreads();
+      for (int t = tid; t < npair * n; t += nthr) {  // rows p, q
+        const int k = t / n, j = t - k * n;
+        if (jq[k] < 0 || js[k] == 0.0) continue;
+        const int p = jp[k], q = jq[k];
+        const double c = jc[k], s = js[k];
+        const double ap = P1[p * n + j], aq = P1[q * n + j];
+        P1[p * n + j] = c * ap - s * aq;
+        P1[q * n + j] = s * ap + c * aq;
+      }
+      __syncthreads();
+      for (int t = tid; t < npair * n; t += nthr) {  // columns p, q of H' and V
+        const int k = t / n, i = t - k * n;
+        if (jq[k] < 0 || js[k] == 0.0) continue;
+        const int p = jp[k], q = jq[k];
+        const double c = jc[k], s = js[k];
+        const double ap = P1[i * n + p], aq = P1[i * n + q];
+        P1[i * n + p] = c * ap - s * aq;
+        P1[i * n + q] = s * ap + c * aq;
+        const double vp = P3[i * n + p], vq = P3[i * n + q];
+        P3[i * n + p] = c * vp - s * vq;
+        P3[i * n + q] = s * vp + c * vq;
+      }
+      __syncthreads();
+    }
+  }
+  // ranks of the eigenvalues (ascending, ties by index)
+  for (int i = tid; i < n; i += nthr) {
+    const double li = P1[i * n + i];
+    int rnk = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = P1[j * n + j];
+      if (lj < li || (lj == li && j < i)) ++rnk;
+    }
+    rank[i] = rnk;
+  }
+  // Mtmp = W^T V -> P0
+  for (int e = tid; e < n * n; e += nthr) {
+    const int j = e / n, i = e % n;
+    double s = 0.0;
+    for (int k = j; k < n; ++k) s += P2[k * n + j] * P3[k * n + i];
+    P0[e] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < n * n; e += nthr) {
+    const int j = e / n, i = e % n;
+    cd.M[j * n + rank[i]] = P0[e];
+  }
+  for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = P1[i * n + i];
+}
+
+// ---------------------------------------------------------- launch helpers
+void launch_grid_fft(const LaunchCtx& L, int sign) {
+  const BatchGeom& g = L.g;
+  const int rpb = std::max(1, 1024 / g.N1max);
+  const int rows = g.N2max * g.N3max;
+  size_t lds_x = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)rpb * g.N1max);
+  hipLaunchKernelGGL(k_grid_fft_x, dim3((rows + rpb - 1) / rpb, 1, g.ncand), dim3(kNT), lds_x,
+                     L.stream, L.desc, sign, rpb);
+  const int ntx = (g.N1max + kTX - 1) / kTX;
+  size_t lds_y = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)kTX * g.N2max);
+  hipLaunchKernelGGL(k_grid_fft_yz, dim3(ntx * g.N3max, 1, g.ncand), dim3(kNT), lds_y, L.stream,
+                     L.desc, 1, sign);
+  size_t lds_z = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)kTX * g.N3max);
+  hipLaunchKernelGGL(k_grid_fft_yz, dim3(ntx * g.N2max, 1, g.ncand), dim3(kNT), lds_z, L.stream,
+                     L.desc, 2, sign);
+}
+
+static int grid_blocks(const BatchGeom& g) { return std::min(1024, (g.ntot_max + kNT - 1) / kNT); }
+
+void launch_density_finalize(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_density_finalize, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0,
+                     L.stream, L.desc);
+}
+void launch_gspace_residual(const LaunchCtx& L, int cur, int nvalid) {
+  hipLaunchKernelGGL(k_gspace_residual, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0,
+                     L.stream, L.desc, cur, nvalid);
+}
+void launch_scf_control(const LaunchCtx& L, int cur, int nvalid, int iter, double tol_e_atom,
+                        double tol_rho) {
+  hipLaunchKernelGGL(k_scf_control, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, cur, nvalid,
+                     iter, tol_e_atom, tol_rho);
+}
+void launch_mix(const LaunchCtx& L, int initial, int cur, int nvalid, int next, double alpha,
+                double q0) {
+  hipLaunchKernelGGL(k_mix, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
+                     initial, cur, nvalid, next, alpha, q0);
+}
+void launch_setup_grid(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_setup_grid, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc, L.species);
+}
+void launch_ewald(const LaunchCtx& L) {
+  const int nb = std::min(1024, (L.g.ew_ng_max + kNT - 1) / kNT);
+  hipLaunchKernelGGL(k_ewald_recip, dim3(nb, 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
+                     L.species);
+  hipLaunchKernelGGL(k_ewald_atom, dim3(L.g.nat_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc, L.species);
+}
+void launch_force_local(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_force_local, dim3(L.g.nat_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc, L.species);
+}
+void launch_force_finalize(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_force_finalize, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
+}
+void launch_occupations(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_occupations, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
+}
+void launch_subspace(const LaunchCtx& L, int mode) {
+  const int n = L.g.nb_max;
+  const int use_lds = n <= 64 ? 1 : 0;
+  size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * n : 0;
+  hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(kSubNT), lds, L.stream, L.desc, mode,
+                     use_lds);
+}
+
+void configure_wave();
+void configure_kernels() {
+  const int big = 160 * 1024;
+  hipFuncSetAttribute((const void*)k_grid_fft_x, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  hipFuncSetAttribute((const void*)k_grid_fft_yz, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  hipFuncSetAttribute((const void*)k_subspace, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  configure_wave();
+}
+
+}  // namespace sgo

@@ -1,0 +1,757 @@
+// Wavefunction-side kernels, templated on the bulk precision T.
+//
+//  * H|psi> (Algorithm 1, the bold "Calculate H|Psi>" steps): Gamma-point
+//    two-bands-per-FFT packing, sphere-pruned z transforms on the occupied
+//    stick pairs, a fused per-plane kernel (inverse 2-D FFT, multiply by
+//    V_eff(r), forward 2-D FFT) and a gather that unpacks the two bands and
+//    adds the kinetic term; projector products for the nonlocal part.
+//  * density planes (output charge density of the SCF step, Section 2.4).
+//  * split-K Gram products and in-place rotations (the subspace and
+//    projection steps of Algorithm 1), FP64 accumulation.
+//  * per-band CG kernels: residual + preconditioning + CG direction, and the
+//    line minimisation over the angle theta.
+//  * the FP64 subspace solver: Cholesky orthonormalisation and Jacobi
+//    diagonalisation of the subspace Hamiltonian.
+#include "device.hpp"
+#include "launch.hpp"
+
+#include <algorithm>
+
+namespace sgo {
+
+template <typename T>
+__device__ __forceinline__ T* warr(const CandDesc& c, int w) {
+  switch (w) {
+    case W_X: return (T*)c.X;
+    case W_HX: return (T*)c.HX;
+    case W_D: return (T*)c.D;
+    case W_HD: return (T*)c.HD;
+    default: return (T*)c.beta;
+  }
+}
+__device__ __forceinline__ int wrows(const CandDesc& c, int w) { return w == W_BETA ? c.nproj : c.nb; }
+__device__ __forceinline__ double* marr(const CandDesc& c, int m) {
+  switch (m) {
+    case M_S: return c.S;
+    case M_H: return c.Hs;
+    case M_M: return c.M;
+    default: return c.C;
+  }
+}
+
+__device__ __forceinline__ int mirror_stick(int s) { return s == 0 ? 0 : ((s & 1) ? s + 1 : s - 1); }
+
+// ------------------------------------------------------------ z transforms
+// Scatter band pair (2p, 2p+1) of the half sphere into its stick pairs
+// (c_{-G} = conj c_G fills the mirror stick) and inverse-transform along z.
+// Output layout: sticks[pair][z][stick] (z-major, so the plane kernel reads
+// one contiguous row per plane).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_z_inverse(const CandDesc* __restrict__ cds, int src,
+                                                   int sp_chunk) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int pair = blockIdx.y;
+  const int q0 = blockIdx.x * sp_chunk;
+  if (pair >= cd.npair || q0 >= cd.nsp) return;
+  const int q1 = min(q0 + sp_chunk, cd.nsp);
+  const int s0 = q0 == 0 ? 0 : 2 * q0 - 1;
+  const int s1 = 2 * q1 - 1;
+  const int nloc = s1 - s0;
+  const int N3 = cd.N3;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  extern __shared__ __align__(16) char smem[];
+  cplx<T>* tw = (cplx<T>*)smem;
+  cplx<T>* A = tw + kMaxFftN;
+  cplx<T>* Bf = A + nloc * N3;
+  fill_twiddles(tw, N3, tid, nthr);
+  for (int e = tid; e < nloc * N3; e += nthr) A[e] = {(T)0, (T)0};
+  __syncthreads();
+  const T* base = warr<T>(cd, src);
+  const T* xa = base + (size_t)(2 * pair) * cd.K;
+  const bool hasb = 2 * pair + 1 < cd.nb;
+  const T* xb = base + (size_t)(2 * pair + 1) * cd.K;
+  const int g0 = cd.sp_off[q0], g1 = cd.sp_off[q1];
+  for (int g = g0 + tid; g < g1; g += nthr) {
+    const int meta = cd.gmeta[g];
+    const int s = meta & 0xFFFFF, z = meta >> 20;
+    cplx<T> ca = unpack_coef(xa, g);
+    cplx<T> cb = hasb ? unpack_coef(xb, g) : cplx<T>{(T)0, (T)0};
+    A[(s - s0) * N3 + z] = {ca.x - cb.y, ca.y + cb.x};  // c_a + i c_b
+    if (g != 0) {
+      const int sm = mirror_stick(s);
+      const int zm = z == 0 ? 0 : N3 - z;
+      A[(sm - s0) * N3 + zm] = {ca.x + cb.y, cb.x - ca.y};  // conj c_a + i conj c_b
+    }
+  }
+  __syncthreads();
+  cplx<T>* r = lds_fft(A, Bf, cd.plan[2], nloc, 1, N3, tw, +1, tid, nthr);
+  cplx<T>* out = (cplx<T>*)cd.sticks + (size_t)pair * N3 * cd.nst;
+  for (int t = tid; t < nloc * N3; t += nthr) {
+    const int z = t / nloc, s = t - z * nloc;
+    out[(size_t)z * cd.nst + s0 + s] = r[s * N3 + z];
+  }
+}
+
+// Forward z transform of the stick pairs and gather back to the half
+// sphere: split the pair by Hermitian symmetry, scale 1/Ntot, add the
+// kinetic term |G|^2/2 psi, write H psi in the packed layout.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_z_forward(const CandDesc* __restrict__ cds, int src,
+                                                   int dst, int sp_chunk) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int pair = blockIdx.y;
+  const int q0 = blockIdx.x * sp_chunk;
+  if (pair >= cd.npair || q0 >= cd.nsp) return;
+  const int q1 = min(q0 + sp_chunk, cd.nsp);
+  const int s0 = q0 == 0 ? 0 : 2 * q0 - 1;
+  const int s1 = 2 * q1 - 1;
+  const int nloc = s1 - s0;
+  const int N3 = cd.N3;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  extern __shared__ __align__(16) char smem[];
+  cplx<T>* tw = (cplx<T>*)smem;
+  cplx<T>* A = tw + kMaxFftN;
+  cplx<T>* Bf = A + nloc * N3;
+  fill_twiddles(tw, N3, tid, nthr);
+  const cplx<T>* in = (const cplx<T>*)cd.sticks + (size_t)pair * N3 * cd.nst;
+  for (int t = tid; t < nloc * N3; t += nthr) {
+    const int z = t / nloc, s = t - z * nloc;
+    A[s * N3 + z] = in[(size_t)z * cd.nst + s0 + s];
+  }
+  __syncthreads();
+  cplx<T>* r = lds_fft(A, Bf, cd.plan[2], nloc, 1, N3, tw, -1, tid, nthr);
+  const T sc = (T)(1.0 / (double)cd.ntot);
+  const T rt2 = (T)1.41421356237309504880;
+  const T* xsrc = warr<T>(cd, src);
+  T* ydst = warr<T>(cd, dst);
+  const int a = 2 * pair, b = 2 * pair + 1;
+  const bool hasb = b < cd.nb;
+  const T* xa = xsrc + (size_t)a * cd.K;
+  const T* xb = xsrc + (size_t)b * cd.K;
+  T* ya = ydst + (size_t)a * cd.K;
+  T* yb = ydst + (size_t)b * cd.K;
+  const int g0 = cd.sp_off[q0], g1 = cd.sp_off[q1];
+  for (int g = g0 + tid; g < g1; g += nthr) {
+    const int meta = cd.gmeta[g];
+    const int s = meta & 0xFFFFF, z = meta >> 20;
+    const int sm = mirror_stick(s);
+    const int zm = z == 0 ? 0 : N3 - z;
+    cplx<T> W = r[(s - s0) * N3 + z];
+    cplx<T> Wm = r[(sm - s0) * N3 + zm];
+    // (V psi_a)_G = (W_G + conj W_-G)/2 ; (V psi_b)_G = (W_G - conj W_-G)/(2i)
+    cplx<T> va = {(T)0.5 * (W.x + Wm.x) * sc, (T)0.5 * (W.y - Wm.y) * sc};
+    cplx<T> vb = {(T)0.5 * (W.y + Wm.y) * sc, (T)-0.5 * (W.x - Wm.x) * sc};
+    const T kin = (T)cd.kin[g];
+    if (g == 0) {
+      ya[0] = va.x + kin * xa[0];
+      ya[1] = (T)0;
+      if (hasb) {
+        yb[0] = vb.x + kin * xb[0];
+        yb[1] = (T)0;
+      }
+    } else {
+      ya[2 * g] = rt2 * va.x + kin * xa[2 * g];
+      ya[2 * g + 1] = rt2 * va.y + kin * xa[2 * g + 1];
+      if (hasb) {
+        yb[2 * g] = rt2 * vb.x + kin * xb[2 * g];
+        yb[2 * g + 1] = rt2 * vb.y + kin * xb[2 * g + 1];
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------ plane kernels
+// One z-plane of one band pair: gather the stick values, inverse 2-D FFT,
+// multiply by V_eff(r), forward 2-D FFT, scatter back to the sticks.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_plane_hpsi(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int z = blockIdx.x, pair = blockIdx.y;
+  if (z >= cd.N3 || pair >= cd.npair) return;
+  const int N1 = cd.N1, N2 = cd.N2, NP = N1 * N2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  extern __shared__ __align__(16) char smem[];
+  cplx<T>* tw1 = (cplx<T>*)smem;
+  cplx<T>* tw2 = tw1 + kMaxFftN;
+  cplx<T>* A = tw2 + kMaxFftN;
+  cplx<T>* Bf = A + NP;
+  fill_twiddles(tw1, N1, tid, nthr);
+  fill_twiddles(tw2, N2, tid, nthr);
+  for (int e = tid; e < NP; e += nthr) A[e] = {(T)0, (T)0};
+  __syncthreads();
+  cplx<T>* st = (cplx<T>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
+  for (int s = tid; s < cd.nst; s += nthr) {
+    const int xy = cd.stick_xy[s];
+    A[(xy >> 16) * N1 + (xy & 0xFFFF)] = st[s];
+  }
+  __syncthreads();
+  cplx<T>* r = lds_fft(A, Bf, cd.plan[1], N1, N1, 1, tw2, +1, tid, nthr);  // along y
+  cplx<T>* o = r == A ? Bf : A;
+  r = lds_fft(r, o, cd.plan[0], N2, 1, N1, tw1, +1, tid, nthr);            // along x
+  const T* V = (const T*)cd.veff_t + (size_t)z * NP;
+  for (int e = tid; e < NP; e += nthr) {
+    const T v = V[e];
+    r[e].x *= v;
+    r[e].y *= v;
+  }
+  __syncthreads();
+  o = r == A ? Bf : A;
+  r = lds_fft(r, o, cd.plan[0], N2, 1, N1, tw1, -1, tid, nthr);
+  o = r == A ? Bf : A;
+  r = lds_fft(r, o, cd.plan[1], N1, N1, 1, tw2, -1, tid, nthr);
+  for (int s = tid; s < cd.nst; s += nthr) {
+    const int xy = cd.stick_xy[s];
+    st[s] = r[(xy >> 16) * N1 + (xy & 0xFFFF)];
+  }
+}
+
+// Density of one z-plane summed over a chunk of band pairs:
+// part[chunk][z][y][x] = sum_pairs f_a Re(u)^2 + f_b Im(u)^2, u = psi_a + i psi_b
+// (unnormalised transforms; the 1/Omega is applied when chunks are summed).
+constexpr int kDensRegs = 48;
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_plane_density(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int z = blockIdx.x, chunk = blockIdx.y;
+  if (z >= cd.N3 || chunk >= cd.ndens_chunk) return;
+  const int N1 = cd.N1, N2 = cd.N2, NP = N1 * N2;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  extern __shared__ __align__(16) char smem[];
+  cplx<T>* tw1 = (cplx<T>*)smem;
+  cplx<T>* tw2 = tw1 + kMaxFftN;
+  cplx<T>* A = tw2 + kMaxFftN;
+  cplx<T>* Bf = A + NP;
+  fill_twiddles(tw1, N1, tid, nthr);
+  fill_twiddles(tw2, N2, tid, nthr);
+  double acc[kDensRegs];
+#pragma unroll
+  for (int k = 0; k < kDensRegs; ++k) acc[k] = 0.0;
+  const int per = (cd.npair + cd.ndens_chunk - 1) / cd.ndens_chunk;
+  const int p0 = chunk * per, p1 = min(cd.npair, p0 + per);
+  for (int pair = p0; pair < p1; ++pair) {
+    for (int e = tid; e < NP; e += nthr) A[e] = {(T)0, (T)0};
+    __syncthreads();
+    const cplx<T>* st = (const cplx<T>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
+    for (int s = tid; s < cd.nst; s += nthr) {
+      const int xy = cd.stick_xy[s];
+      A[(xy >> 16) * N1 + (xy & 0xFFFF)] = st[s];
+    }
+    __syncthreads();
+    cplx<T>* r = lds_fft(A, Bf, cd.plan[1], N1, N1, 1, tw2, +1, tid, nthr);
+    cplx<T>* o = r == A ? Bf : A;
+    r = lds_fft(r, o, cd.plan[0], N2, 1, N1, tw1, +1, tid, nthr);
+    const double fa = cd.occ[2 * pair];
+    const double fb = 2 * pair + 1 < cd.nb ? cd.occ[2 * pair + 1] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kDensRegs; ++k) {
+      const int e = tid + k * nthr;
+      if (e < NP) {
+        const double ux = (double)r[e].x, uy = (double)r[e].y;
+        acc[k] += fa * ux * ux + fb * uy * uy;
+      }
+    }
+    __syncthreads();
+  }
+  double* out = cd.dens_part + (size_t)chunk * cd.ntot + (size_t)z * NP;
+#pragma unroll
+  for (int k = 0; k < kDensRegs; ++k) {
+    const int e = tid + k * nthr;
+    if (e < NP) out[e] = acc[k];
+  }
+}
+
+// ------------------------------------------------------ split-K Gram product
+// out[i][j] = sum_k A[i][k] B[j][k] (FP64 accumulation) for up to two
+// products per launch.  Each block covers one 64x64 output tile over one K
+// range; the last block of a tile sums the partial tiles in K order.
+constexpr int kGT = 64, kGS = 32;
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, int kc_len,
+                                              int nkc_max, int a0, int b0, int o0, int a1, int b1,
+                                              int o1) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int prod = blockIdx.y;
+  const int wa = prod ? a1 : a0, wb = prod ? b1 : b0, wo = prod ? o1 : o0;
+  const int na = wrows(cd, wa), nbb = wrows(cd, wb);
+  if (na == 0 || nbb == 0) return;
+  const int nti = (na + kGT - 1) / kGT, ntj = (nbb + kGT - 1) / kGT;
+  const int nkc = (cd.K + kc_len - 1) / kc_len;
+  const int kc = blockIdx.x % nkc_max;
+  const int tile = blockIdx.x / nkc_max;
+  if (kc >= nkc || tile >= nti * ntj) return;
+  const int ti = tile / ntj, tj = tile - ti * ntj;
+  const T* Am = warr<T>(cd, wa);
+  const T* Bm = warr<T>(cd, wb);
+  const int K = cd.K;
+  const int k0 = kc * kc_len, k1 = min(K, k0 + kc_len);
+  __shared__ double As[kGT][kGS + 1];
+  __shared__ double Bs[kGT][kGS + 1];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
+  for (int ks = k0; ks < k1; ks += kGS) {
+    for (int e = threadIdx.x; e < kGT * kGS; e += blockDim.x) {
+      const int rr = e / kGS, kk = e - rr * kGS;
+      const int k = ks + kk;
+      const int ia = ti * kGT + rr, jb = tj * kGT + rr;
+      As[rr][kk] = (ia < na && k < k1) ? (double)Am[(size_t)ia * K + k] : 0.0;
+      Bs[rr][kk] = (jb < nbb && k < k1) ? (double)Bm[(size_t)jb * K + k] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < kGS; ++kk) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) av[u] = As[ty + 16 * u][kk];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bv[v] = Bs[tx + 16 * v][kk];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
+    }
+    __syncthreads();
+  }
+  // partial tile -> scratch; last block of this tile reduces in K order
+  const size_t tile_sz = (size_t)kGT * kGT;
+  double* part = cd.red_part + ((size_t)prod * nti * ntj + tile) * nkc * tile_sz;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) part[(size_t)kc * tile_sz + (ty + 16 * u) * kGT + tx + 16 * v] = acc[u][v];
+  __threadfence();
+  __shared__ int is_last;
+  if (threadIdx.x == 0) {
+    unsigned t = atomicAdd(&cd.tickets[prod * nti * ntj + tile], 1u);
+    is_last = (t == (unsigned)(nkc - 1));
+  }
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  double* out = marr(cd, wo);
+  for (int e = threadIdx.x; e < kGT * kGT; e += blockDim.x) {
+    const int rr = e / kGT, cc = e - rr * kGT;
+    const int i = ti * kGT + rr, j = tj * kGT + cc;
+    double s = 0.0;
+    for (int c = 0; c < nkc; ++c) s += load_coherent(part + (size_t)c * tile_sz + e);
+    if (i < na && j < nbb) out[(size_t)i * nbb + j] = s;
+  }
+  if (threadIdx.x == 0) atomicExch(&cd.tickets[prod * nti * ntj + tile], 0u);
+}
+
+// ------------------------------------------------------- rotation products
+// Y[i][k] = alpha Y[i][k] + beta sum_j w_j M[j][i] A[j][k]   (i < nout, j < nin)
+// with w_j = h_j (projector energies) when use_h, else 1.  Each block stages
+// a 32-column slice of A in LDS, so Y may alias A (in-place rotation).
+constexpr int kRC = 32;
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ cds, int y0, int y1,
+                                                  int y2, int a0, int a1, int a2, int mat,
+                                                  double alpha, double beta, int use_h) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int arr = blockIdx.y;
+  const int wy = arr == 0 ? y0 : (arr == 1 ? y1 : y2);
+  const int wa = arr == 0 ? a0 : (arr == 1 ? a1 : a2);
+  const int nin = wrows(cd, wa), nout = wrows(cd, wy);
+  if (nin == 0) return;
+  const int K = cd.K;
+  const int kbase = blockIdx.x * kRC;
+  if (kbase >= K) return;
+  const T* A = warr<T>(cd, wa);
+  T* Y = warr<T>(cd, wy);
+  const double* M = marr(cd, mat);
+  extern __shared__ __align__(16) char smem[];
+  double* As = (double*)smem;  // [nin][kRC]
+  for (int e = threadIdx.x; e < nin * kRC; e += blockDim.x) {
+    const int j = e / kRC, kk = e - j * kRC;
+    const int k = kbase + kk;
+    As[e] = k < K ? (double)A[(size_t)j * K + k] : 0.0;
+  }
+  __syncthreads();
+  const int kk = threadIdx.x % kRC, rg = threadIdx.x / kRC, nrg = blockDim.x / kRC;
+  const int k = kbase + kk;
+  if (k >= K) return;
+  for (int i = rg; i < nout; i += nrg) {
+    double s = 0.0;
+    if (use_h) {
+      for (int j = 0; j < nin; ++j) s = fma(cd.hproj[j] * M[(size_t)j * nout + i], As[j * kRC + kk], s);
+    } else {
+      for (int j = 0; j < nin; ++j) s = fma(M[(size_t)j * nout + i], As[j * kRC + kk], s);
+    }
+    const size_t idx = (size_t)i * K + k;
+    const double yo = alpha != 0.0 ? (double)Y[idx] : 0.0;
+    Y[idx] = (T)(alpha * yo + beta * s);
+  }
+}
+
+// ------------------------------------------------------------- band kernels
+// Teter-Payne-Allan preconditioner K(x), x = (|G|^2/2) / E_kin(band).
+__device__ __forceinline__ double tpa(double x) {
+  const double p = 27.0 + x * (18.0 + x * (12.0 + 8.0 * x));
+  return p / (p + 16.0 * x * x * x * x);
+}
+
+// Residual R = H psi - eps psi, preconditioned g = K R, CG direction
+// D = g + beta D_prev with beta = <g,R>_k / <g,R>_{k-1} (first step: D = g).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_cg_direction(const CandDesc* __restrict__ cds, int first) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int i = blockIdx.x;
+  if (i >= cd.nb) return;
+  __shared__ double sh[16 * 2];
+  const int K = cd.K;
+  const T* x = (const T*)cd.X + (size_t)i * K;
+  const T* hx = (const T*)cd.HX + (size_t)i * K;
+  T* d = (T*)cd.D + (size_t)i * K;
+  double v1[1] = {0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double xv = (double)x[k];
+    v1[0] += cd.kin[k >> 1] * xv * xv;
+  }
+  block_sum<1>(v1, sh);
+  const double ek = fmax(v1[0], 1e-8);
+  const double e = cd.eps[i];
+  double v2[1] = {0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double r = (double)hx[k] - e * (double)x[k];
+    const double g = tpa(cd.kin[k >> 1] / ek) * r;
+    v2[0] += g * r;
+  }
+  block_sum<1>(v2, sh);
+  const double gam = v2[0];
+  double beta = 0.0;
+  if (!first) {
+    const double gp = cd.gam[i];
+    beta = gp > 0.0 ? gam / gp : 0.0;
+  }
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double r = (double)hx[k] - e * (double)x[k];
+    const double g = tpa(cd.kin[k >> 1] / ek) * r;
+    d[k] = (T)(g + (first ? 0.0 : beta * (double)d[k]));
+  }
+  if (threadIdx.x == 0) cd.gam[i] = gam;
+}
+
+// Line minimisation of each band along its (projected) direction d:
+// psi(theta) = x cos(theta) + d/|d| sin(theta), exact minimiser of the 2x2
+// Rayleigh quotient at fixed H; H psi is updated with H d (no extra H apply).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_linemin(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int i = blockIdx.x;
+  if (i >= cd.nb) return;
+  __shared__ double sh[16 * 4];
+  const int K = cd.K;
+  T* x = (T*)cd.X + (size_t)i * K;
+  T* hx = (T*)cd.HX + (size_t)i * K;
+  const T* d = (const T*)cd.D + (size_t)i * K;
+  const T* hd = (const T*)cd.HD + (size_t)i * K;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    const double xv = x[k], hxv = hx[k], dv = d[k], hdv = hd[k];
+    v[0] += xv * hxv;
+    v[1] += xv * hdv;
+    v[2] += dv * hdv;
+    v[3] += dv * dv;
+  }
+  block_sum<4>(v, sh);
+  const double n2 = v[3];
+  if (!(n2 > 0.0)) return;
+  const double inv = 1.0 / sqrt(n2);
+  const double a = v[0], b = v[1] * inv, c = v[2] * inv * inv;
+  const double theta = 0.5 * atan2(-2.0 * b, c - a);
+  double sn, cs;
+  sincos(theta, &sn, &cs);
+  const double sd = sn * inv;
+  for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    x[k] = (T)(cs * (double)x[k] + sd * (double)d[k]);
+    hx[k] = (T)(cs * (double)hx[k] + sd * (double)hd[k]);
+  }
+}
+
+// Kinetic energy of each band: bandw[i] = sum_G |G|^2/2 |c_iG|^2.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_band_kinetic(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int i = blockIdx.x;
+  if (i >= cd.nb) return;
+  __shared__ double sh[16];
+  const T* x = (const T*)cd.X + (size_t)i * cd.K;
+  double v[1] = {0.0};
+  for (int k = threadIdx.x; k < cd.K; k += blockDim.x) {
+    const double xv = x[k];
+    v[0] += cd.kin[k >> 1] * xv * xv;
+  }
+  block_sum<1>(v, sh);
+  if (threadIdx.x == 0) cd.bandw[i] = v[0];
+}
+
+// Counter-based starting wavefunctions: uniform(-1,1) from a 64-bit mix of
+// (seed, candidate, band, index), damped by 1/(1 + |G|^2/2).
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+template <typename T>
+__global__ void k_init_random(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int i = blockIdx.y;
+  if (i >= cd.nb) return;
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < cd.K; k += gridDim.x * blockDim.x) {
+    unsigned long long h = mix64(((unsigned long long)cd.seed << 40) ^
+                                 ((unsigned long long)cd.ncand_index << 32) ^
+                                 ((unsigned long long)i << 20) ^ (unsigned long long)k);
+    h = mix64(h);
+    const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+    const double v = k == 1 ? 0.0 : u / (1.0 + cd.kin[k >> 1]);
+    ((T*)cd.X)[(size_t)i * cd.K + k] = (T)v;
+    ((T*)cd.D)[(size_t)i * cd.K + k] = (T)0;
+  }
+}
+
+// Kleinman-Bylander projectors in packed storage:
+// beta_{Ilm}(G) = p_l(|G|) (-i)^l Y_lm(G^) e^{-i G.R_I} / sqrt(Omega).
+template <typename T>
+__global__ void k_setup_beta(const CandDesc* __restrict__ cds, const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int p = blockIdx.y;
+  if (p >= cd.nproj) return;
+  const int I = cd.proj_atom[p];
+  const int l = cd.proj_lm[p] >> 2, m = cd.proj_lm[p] & 3;
+  const double rl = cd.proj_r[p];
+  const double R0 = cd.pos[3 * I], R1 = cd.pos[3 * I + 1], R2 = cd.pos[3 * I + 2];
+  const double inv_sqrt_omega = 1.0 / sqrt(cd.omega);
+  const double pi = 3.14159265358979323846;
+  T* out = (T*)cd.beta + (size_t)p * cd.K;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < cd.npwh; g += gridDim.x * blockDim.x) {
+    const double m1 = cd.gmill[3 * g], m2 = cd.gmill[3 * g + 1], m3 = cd.gmill[3 * g + 2];
+    const double G0 = m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6];
+    const double G1 = m1 * cd.B[1] + m2 * cd.B[4] + m3 * cd.B[7];
+    const double G2 = m1 * cd.B[2] + m2 * cd.B[5] + m3 * cd.B[8];
+    const double gg = sqrt(G0 * G0 + G1 * G1 + G2 * G2);
+    double val;  // real amplitude before the phase; (-i)^l handled below
+    if (l == 0) {
+      // 4 pi sqrt(pi) r^{3/2} e^{-G^2 r^2/2} / sqrt(Gamma(3/2)) * Y00
+      val = 4.0 * pi * sqrt(pi) * pow(rl, 1.5) * exp(-0.5 * gg * gg * rl * rl) /
+            sqrt(0.5 * sqrt(pi)) * (1.0 / sqrt(4.0 * pi));
+    } else {
+      const double gm = m == 0 ? G0 : (m == 1 ? G1 : G2);
+      // p_1(G) Y_1m = 4 pi sqrt(pi) r^{5/2} G e^{..} / sqrt(Gamma(5/2)) * sqrt(3/4pi) G_m/G
+      val = 4.0 * pi * sqrt(pi) * pow(rl, 2.5) * exp(-0.5 * gg * gg * rl * rl) /
+            sqrt(0.75 * sqrt(pi)) * sqrt(3.0 / (4.0 * pi)) * gm;
+    }
+    val *= inv_sqrt_omega;
+    double sn, cs;
+    sincos(-(G0 * R0 + G1 * R1 + G2 * R2), &sn, &cs);
+    double re = val * cs, im = val * sn;  // val e^{-iG.R}
+    if (l == 1) {  // multiply by -i
+      const double t = re;
+      re = im;
+      im = -t;
+    }
+    if (g == 0) {
+      out[0] = (T)re;
+      out[1] = (T)0;
+    } else {
+      out[2 * g] = (T)(1.41421356237309504880 * re);
+      out[2 * g + 1] = (T)(1.41421356237309504880 * im);
+    }
+  }
+}
+
+// Projections needed by the nonlocal forces, for projector p and band i:
+// P = <beta_p|psi_i>, dP_a = <-i G_a beta_p|psi_i>  (a = x, y, z).
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_force_nonlocal(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int p = blockIdx.x, i = blockIdx.y;
+  if (p >= cd.nproj || i >= cd.nb) return;
+  __shared__ double sh[16 * 4];
+  const T* b = (const T*)cd.beta + (size_t)p * cd.K;
+  const T* x = (const T*)cd.X + (size_t)i * cd.K;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < cd.npwh; g += blockDim.x) {
+    const double br = b[2 * g], bi = b[2 * g + 1], xr = x[2 * g], xi = x[2 * g + 1];
+    v[0] += br * xr + bi * xi;
+    const double m1 = cd.gmill[3 * g], m2 = cd.gmill[3 * g + 1], m3 = cd.gmill[3 * g + 2];
+    const double t = bi * xr - br * xi;  // packed (-i beta) . x per unit G
+    v[1] += (m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6]) * t;
+    v[2] += (m1 * cd.B[1] + m2 * cd.B[4] + m3 * cd.B[7]) * t;
+    v[3] += (m1 * cd.B[2] + m2 * cd.B[5] + m3 * cd.B[8]) * t;
+  }
+  block_sum<4>(v, sh);
+  if (threadIdx.x == 0) {
+    double* o = cd.nlwork + ((size_t)p * cd.nb + i) * 4;
+    o[0] = v[0];
+    o[1] = v[1];
+    o[2] = v[2];
+    o[3] = v[3];
+  }
+}
+
+// V_eff(r) from the inverse transform of V(G) + i rho_in(G): real part is
+// V_loc + V_H, imaginary part the mixed input density.  Adds v_xc.
+template <typename T>
+__global__ void k_potential_finalize(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cd.ntot; e += gridDim.x * blockDim.x) {
+    const cplx<double> z = cd.zgrid[e];
+    const double rho = z.y;
+    double ex, vx;
+    pz81(fmax(rho, 0.0), &ex, &vx);
+    const double v = z.x + vx;
+    cd.rho_in_r[e] = rho;
+    cd.veff_r[e] = v;
+    ((T*)cd.veff_t)[e] = (T)v;
+  }
+}
+
+// ---------------------------------------------------------- launch helpers
+template <typename T>
+static size_t z_lds(const BatchGeom& g) {
+  const int nloc = 2 * g.sp_chunk;
+  return sizeof(cplx<T>) * (kMaxFftN + 2 * (size_t)nloc * g.N3max);
+}
+template <typename T>
+static size_t plane_lds(const BatchGeom& g) {
+  return sizeof(cplx<T>) * (2 * kMaxFftN + 2 * (size_t)g.plane_max);
+}
+
+template <typename T>
+void launch_hpsi(const LaunchCtx& L, int src) {
+  const BatchGeom& g = L.g;
+  const int dst = src == W_X ? W_HX : W_HD;
+  dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
+  hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, g.sp_chunk);
+  dim3 gp(g.N3max, g.npair_max, g.ncand);
+  hipLaunchKernelGGL(k_plane_hpsi<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
+  hipLaunchKernelGGL(k_z_forward<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, dst,
+                     g.sp_chunk);
+  if (g.nproj_max > 0) {
+    int a[1] = {W_BETA}, b[1] = {src}, o[1] = {M_C};
+    launch_gram<T>(L, 1, a, b, o);
+    int y[1] = {dst}, aa[1] = {W_BETA};
+    launch_gemm_acc<T>(L, 1, y, aa, M_C, 1.0, 1.0, 1);
+  }
+}
+
+template <typename T>
+void launch_density(const LaunchCtx& L) {
+  const BatchGeom& g = L.g;
+  dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
+  hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, (int)W_X,
+                     g.sp_chunk);
+  dim3 gp(g.N3max, g.dens_chunks, g.ncand);
+  hipLaunchKernelGGL(k_plane_density<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
+}
+
+template <typename T>
+void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, const int* out) {
+  const BatchGeom& g = L.g;
+  const int rows = std::max(g.nb_max, g.nproj_max);
+  const int nt = (rows + kGT - 1) / kGT;
+  dim3 grid(nt * nt * g.nkc_max, nprod, g.ncand);
+  hipLaunchKernelGGL(k_gram<T>, grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max, a[0],
+                     b[0], out[0], nprod > 1 ? a[1] : 0, nprod > 1 ? b[1] : 0,
+                     nprod > 1 ? out[1] : 0);
+}
+
+template <typename T>
+void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, int mat,
+                     double alpha, double beta, int use_h) {
+  const BatchGeom& g = L.g;
+  const int rows = std::max(g.nb_max, g.nproj_max);
+  dim3 grid((g.K_max + kRC - 1) / kRC, narr, g.ncand);
+  size_t lds = sizeof(double) * (size_t)rows * kRC;
+  hipLaunchKernelGGL(k_gemm_acc<T>, grid, dim3(kNT), lds, L.stream, L.desc, y[0],
+                     narr > 1 ? y[1] : 0, narr > 2 ? y[2] : 0, a[0], narr > 1 ? a[1] : 0,
+                     narr > 2 ? a[2] : 0, mat, alpha, beta, use_h);
+}
+
+template <typename T>
+void launch_cg_direction(const LaunchCtx& L, int first) {
+  hipLaunchKernelGGL(k_cg_direction<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc, first);
+}
+template <typename T>
+void launch_linemin(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_linemin<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
+}
+template <typename T>
+void launch_band_kinetic(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_band_kinetic<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc);
+}
+template <typename T>
+void launch_init_random(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_init_random<T>, dim3(8, L.g.nb_max, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc);
+}
+template <typename T>
+void launch_setup_beta(const LaunchCtx& L) {
+  if (L.g.nproj_max == 0) return;
+  hipLaunchKernelGGL(k_setup_beta<T>, dim3(16, L.g.nproj_max, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc, L.species);
+}
+template <typename T>
+void launch_force_nonlocal(const LaunchCtx& L) {
+  if (L.g.nproj_max == 0) return;
+  hipLaunchKernelGGL(k_force_nonlocal<T>, dim3(L.g.nproj_max, L.g.nb_max, L.g.ncand), dim3(kNT), 0,
+                     L.stream, L.desc);
+}
+template <typename T>
+void launch_potential_finalize(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_potential_finalize<T>, dim3((L.g.ntot_max + kNT - 1) / kNT, 1, L.g.ncand),
+                     dim3(kNT), 0, L.stream, L.desc);
+}
+
+template <typename T>
+static void configure_t() {
+  const int big = 160 * 1024;
+  hipFuncSetAttribute((const void*)k_z_inverse<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  hipFuncSetAttribute((const void*)k_z_forward<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  hipFuncSetAttribute((const void*)k_plane_hpsi<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  hipFuncSetAttribute((const void*)k_plane_density<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      big);
+  hipFuncSetAttribute((const void*)k_gemm_acc<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+}
+void configure_wave() {
+  configure_t<float>();
+  configure_t<double>();
+}
+
+#define SGO_INST(T)                                                                       \
+  template void launch_hpsi<T>(const LaunchCtx&, int);                                    \
+  template void launch_density<T>(const LaunchCtx&);                                      \
+  template void launch_gram<T>(const LaunchCtx&, int, const int*, const int*, const int*); \
+  template void launch_gemm_acc<T>(const LaunchCtx&, int, const int*, const int*, int, double, \
+                                   double, int);                                         \
+  template void launch_cg_direction<T>(const LaunchCtx&, int);                            \
+  template void launch_linemin<T>(const LaunchCtx&);                                      \
+  template void launch_band_kinetic<T>(const LaunchCtx&);                                 \
+  template void launch_init_random<T>(const LaunchCtx&);                                  \
+  template void launch_setup_beta<T>(const LaunchCtx&);                                   \
+  template void launch_force_nonlocal<T>(const LaunchCtx&);                               \
+  template void launch_potential_finalize<T>(const LaunchCtx&);
+SGO_INST(float)
+SGO_INST(double)
+
+}  // namespace sgo

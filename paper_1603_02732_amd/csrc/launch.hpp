@@ -1,0 +1,63 @@
+// Host-side launch wrappers of the HIP kernels (defined in kernels_*.hip).
+#pragma once
+#include "common.hpp"
+
+namespace sgo {
+
+// Which wavefunction-side array a kernel reads or writes.
+enum WArr { W_X = 0, W_HX = 1, W_D = 2, W_HD = 3, W_BETA = 4 };
+// Which FP64 matrix a product writes or reads.
+enum MArr { M_S = 0, M_H = 1, M_M = 2, M_C = 3 };
+
+// Launch geometry shared by all candidates of a batch (maxima over them).
+struct BatchGeom {
+  int ncand;
+  int npair_max, nsp_max, nb_max, nproj_max, nat_max;
+  int N1max, N2max, N3max, ntot_max, plane_max;
+  int K_max;
+  int sp_chunk;      // stick pairs per block of the z kernels
+  int kc_len;        // K range per block of the split-K products
+  int nkc_max;       // number of K ranges
+  int dens_chunks;   // band-pair chunks of the density planes
+  int ew_ng_max;     // reciprocal Ewald vectors enumerated (box size)
+  int ew_nimg_max;
+};
+
+struct LaunchCtx {
+  hipStream_t stream;
+  const CandDesc* desc;      // device array [ncand]
+  const SpeciesDev* species; // device array [kMaxSpecies]
+  BatchGeom g;
+};
+
+template <typename T> void launch_hpsi(const LaunchCtx& L, int src /*W_X or W_D*/);
+template <typename T> void launch_density(const LaunchCtx& L);
+template <typename T> void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b,
+                                       const int* out);
+template <typename T> void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a,
+                                           int mat, double alpha, double beta, int use_h);
+template <typename T> void launch_cg_direction(const LaunchCtx& L, int first);
+template <typename T> void launch_linemin(const LaunchCtx& L);
+template <typename T> void launch_band_kinetic(const LaunchCtx& L);
+template <typename T> void launch_init_random(const LaunchCtx& L);
+template <typename T> void launch_setup_beta(const LaunchCtx& L);
+template <typename T> void launch_force_nonlocal(const LaunchCtx& L);
+template <typename T> void launch_potential_finalize(const LaunchCtx& L);
+void launch_subspace(const LaunchCtx& L, int mode);
+void launch_occupations(const LaunchCtx& L);
+void launch_grid_fft(const LaunchCtx& L, int sign);
+void launch_density_finalize(const LaunchCtx& L);
+void launch_gspace_residual(const LaunchCtx& L, int cur, int nvalid);
+void launch_scf_control(const LaunchCtx& L, int cur, int nvalid, int iter, double tol_e_atom,
+                        double tol_rho);
+void launch_mix(const LaunchCtx& L, int initial, int cur, int nvalid, int next, double alpha,
+                double q0);
+void launch_setup_grid(const LaunchCtx& L);
+void launch_ewald(const LaunchCtx& L);
+void launch_force_local(const LaunchCtx& L);
+void launch_force_finalize(const LaunchCtx& L);
+
+// Enable large dynamic LDS for every kernel (once per process per device).
+void configure_kernels();
+
+}  // namespace sgo
