@@ -21,6 +21,8 @@ Energy terms (Mermin free energy F = E - sigma S for Fermi-Dirac):
   E_ion = Ewald
   S     = -2 sum_i [g ln g + (1-g) ln(1-g)],  g = f_i/2
 """
+import warnings
+
 import numpy as np
 import scipy.linalg
 from scipy.special import expit
@@ -108,7 +110,9 @@ def eigensolve(st, veff, nb, X0=None, dense_max=3000, tol=1e-8, maxiter=400):
                        matmat=lambda R: prec[:, None] * R)
     res = np.inf
     for attempt in range(6):
-        w, V = lobpcg(op, X, largest=False, tol=tol, maxiter=maxiter, M=M)
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            w, V = lobpcg(op, X, largest=False, tol=tol, maxiter=maxiter, M=M)
         order = np.argsort(w)
         w, V = w[order], V[:, order]
         # orthonormalise and Rayleigh-Ritz once more for a clean subspace
@@ -127,7 +131,9 @@ def eigensolve(st, veff, nb, X0=None, dense_max=3000, tol=1e-8, maxiter=400):
 
 def run_scf(system, tol_e=1e-10, tol_rho=1e-9, maxiter=200, mix_alpha=0.5,
             kerker_q0=0.8, history=8, dense_max=3000, verbose=False, setup=None,
-            rho0=None):
+            rho0=None, stop_after=None):
+    """Self-consistent solve.  stop_after=k returns after k iterations
+    without raising (used only to time a bounded sample)."""
     st = setup if setup is not None else Setup(system)
     occ = system["occupation"]
     sigma = float(occ.get("sigma", 0.0))
@@ -139,6 +145,7 @@ def run_scf(system, tol_e=1e-10, tol_rho=1e-9, maxiter=200, mix_alpha=0.5,
     e_prev = None
     X = None
     info = {}
+    trace = []
     for it in range(1, maxiter + 1):
         veff, _ = potentials(st, rho_in)
         eps, C = eigensolve(st, veff, nb, X0=X, dense_max=dense_max)
@@ -150,10 +157,11 @@ def run_scf(system, tol_e=1e-10, tol_rho=1e-9, maxiter=200, mix_alpha=0.5,
         R = rho_out - rho_in
         drho = st.omega / st.ntot * np.abs(R).sum() / max(st.nelec, 1e-30)
         de = abs(e - e_prev) if e_prev is not None else np.inf
+        trace.append((e, de, drho))
         if verbose:
             print("oracle scf %3d  E=%.12f  dE=%.2e  drho=%.2e" % (it, e, de, drho))
-        if de < tol_e and drho < tol_rho:
-            info = {"iterations": it, "drho": drho, "de": de}
+        if (de < tol_e and drho < tol_rho) or (stop_after is not None and it >= stop_after):
+            info = {"iterations": it, "drho": drho, "de": de, "trace": trace}
             break
         e_prev = e
         hist_in.append(rho_in.copy())

@@ -32,6 +32,21 @@ struct Error : std::runtime_error {
 
 static const double kPiH = 3.14159265358979323846;
 
+static int g_lds_limit = 64 * 1024;
+
+void allow_lds(const void* kernel) {
+  hipFuncAttributes a;
+  HIPCHK(hipFuncGetAttributes(&a, kernel));
+  const int dyn = g_lds_limit - (int)a.sharedSizeBytes;
+  if (dyn > 0) HIPCHK(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
+}
+
+void check_launch(const char* name) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    throw Error(SGO_EDEVICE, std::string("launch of ") + name + " failed: " + hipGetErrorString(e));
+}
+
 // --------------------------------------------------------------- utilities
 static bool fft_plan(int n, FftPlan& p) {
   p.n = n;
@@ -117,6 +132,10 @@ class Engine {
     HIPCHK(hipSetDevice(device));
     static bool configured = false;
     if (!configured) {
+      int lim = 0;
+      HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+      g_lds_limit = lim;
+      (void)hipGetLastError();
       configure_kernels();
       configured = true;
     }
@@ -524,7 +543,7 @@ class Engine {
   void check_lds(const BatchGeom& g) {
     const size_t ts = tsize();
     const size_t plane = 2 * ts * (2 * kMaxFftN + 2 * (size_t)g.plane_max);
-    if (plane > 160 * 1024)
+    if (plane > (size_t)g_lds_limit)
       throw Error(SGO_EINVAL, "FFT plane N1*N2 too large for LDS at this precision");
     if (g.plane_max > 48 * kNT) throw Error(SGO_EINVAL, "FFT plane N1*N2 exceeds 12288");
     if (g.nb_max > 640) throw Error(SGO_EINVAL, "nbands exceeds 640");

@@ -786,13 +786,16 @@ void launch_grid_fft(const LaunchCtx& L, int sign) {
   size_t lds_x = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)rpb * g.N1max);
   hipLaunchKernelGGL(k_grid_fft_x, dim3((rows + rpb - 1) / rpb, 1, g.ncand), dim3(kNT), lds_x,
                      L.stream, L.desc, sign, rpb);
+  check_launch("k_grid_fft_x");
   const int ntx = (g.N1max + kTX - 1) / kTX;
   size_t lds_y = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)kTX * g.N2max);
   hipLaunchKernelGGL(k_grid_fft_yz, dim3(ntx * g.N3max, 1, g.ncand), dim3(kNT), lds_y, L.stream,
                      L.desc, 1, sign);
+  check_launch("k_grid_fft_yz");
   size_t lds_z = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)kTX * g.N3max);
   hipLaunchKernelGGL(k_grid_fft_yz, dim3(ntx * g.N2max, 1, g.ncand), dim3(kNT), lds_z, L.stream,
                      L.desc, 2, sign);
+  check_launch("k_grid_fft_yz");
 }
 
 static int grid_blocks(const BatchGeom& g) { return std::min(1024, (g.ntot_max + kNT - 1) / kNT); }
@@ -800,41 +803,51 @@ static int grid_blocks(const BatchGeom& g) { return std::min(1024, (g.ntot_max +
 void launch_density_finalize(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_density_finalize, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0,
                      L.stream, L.desc);
+  check_launch("k_density_finalize");
 }
 void launch_gspace_residual(const LaunchCtx& L, int cur, int nvalid) {
   hipLaunchKernelGGL(k_gspace_residual, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0,
                      L.stream, L.desc, cur, nvalid);
+  check_launch("k_gspace_residual");
 }
 void launch_scf_control(const LaunchCtx& L, int cur, int nvalid, int iter, double tol_e_atom,
                         double tol_rho) {
   hipLaunchKernelGGL(k_scf_control, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, cur, nvalid,
                      iter, tol_e_atom, tol_rho);
+  check_launch("k_scf_control");
 }
 void launch_mix(const LaunchCtx& L, int initial, int cur, int nvalid, int next, double alpha,
                 double q0) {
   hipLaunchKernelGGL(k_mix, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
                      initial, cur, nvalid, next, alpha, q0);
+  check_launch("k_mix");
 }
 void launch_setup_grid(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_setup_grid, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
+  check_launch("k_setup_grid");
 }
 void launch_ewald(const LaunchCtx& L) {
   const int nb = std::min(1024, (L.g.ew_ng_max + kNT - 1) / kNT);
   hipLaunchKernelGGL(k_ewald_recip, dim3(nb, 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
                      L.species);
+  check_launch("k_ewald_recip");
   hipLaunchKernelGGL(k_ewald_atom, dim3(L.g.nat_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
+  check_launch("k_ewald_atom");
 }
 void launch_force_local(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_force_local, dim3(L.g.nat_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
+  check_launch("k_force_local");
 }
 void launch_force_finalize(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_force_finalize, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
+  check_launch("k_force_finalize");
 }
 void launch_occupations(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_occupations, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
+  check_launch("k_occupations");
 }
 void launch_subspace(const LaunchCtx& L, int mode) {
   const int n = L.g.nb_max;
@@ -842,14 +855,14 @@ void launch_subspace(const LaunchCtx& L, int mode) {
   size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * n : 0;
   hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(kSubNT), lds, L.stream, L.desc, mode,
                      use_lds);
+  check_launch("k_subspace");
 }
 
 void configure_wave();
 void configure_kernels() {
-  const int big = 160 * 1024;
-  hipFuncSetAttribute((const void*)k_grid_fft_x, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  hipFuncSetAttribute((const void*)k_grid_fft_yz, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  hipFuncSetAttribute((const void*)k_subspace, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  allow_lds((const void*)k_grid_fft_x);
+  allow_lds((const void*)k_grid_fft_yz);
+  allow_lds((const void*)k_subspace);
   configure_wave();
 }
 

@@ -641,10 +641,13 @@ void launch_hpsi(const LaunchCtx& L, int src) {
   const int dst = src == W_X ? W_HX : W_HD;
   dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
   hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, g.sp_chunk);
+  check_launch("k_z_inverse");
   dim3 gp(g.N3max, g.npair_max, g.ncand);
   hipLaunchKernelGGL(k_plane_hpsi<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
+  check_launch("k_plane_hpsi");
   hipLaunchKernelGGL(k_z_forward<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, dst,
                      g.sp_chunk);
+  check_launch("k_z_forward");
   if (g.nproj_max > 0) {
     int a[1] = {W_BETA}, b[1] = {src}, o[1] = {M_C};
     launch_gram<T>(L, 1, a, b, o);
@@ -659,8 +662,10 @@ void launch_density(const LaunchCtx& L) {
   dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
   hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, (int)W_X,
                      g.sp_chunk);
+  check_launch("k_z_inverse");
   dim3 gp(g.N3max, g.dens_chunks, g.ncand);
   hipLaunchKernelGGL(k_plane_density<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
+  check_launch("k_plane_density");
 }
 
 template <typename T>
@@ -672,6 +677,7 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
   hipLaunchKernelGGL(k_gram<T>, grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max, a[0],
                      b[0], out[0], nprod > 1 ? a[1] : 0, nprod > 1 ? b[1] : 0,
                      nprod > 1 ? out[1] : 0);
+  check_launch("k_gram");
 }
 
 template <typename T>
@@ -684,54 +690,60 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
   hipLaunchKernelGGL(k_gemm_acc<T>, grid, dim3(kNT), lds, L.stream, L.desc, y[0],
                      narr > 1 ? y[1] : 0, narr > 2 ? y[2] : 0, a[0], narr > 1 ? a[1] : 0,
                      narr > 2 ? a[2] : 0, mat, alpha, beta, use_h);
+  check_launch("k_gemm_acc");
 }
 
 template <typename T>
 void launch_cg_direction(const LaunchCtx& L, int first) {
   hipLaunchKernelGGL(k_cg_direction<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, first);
+  check_launch("k_cg_direction");
 }
 template <typename T>
 void launch_linemin(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_linemin<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
+  check_launch("k_linemin");
 }
 template <typename T>
 void launch_band_kinetic(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_band_kinetic<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc);
+  check_launch("k_band_kinetic");
 }
 template <typename T>
 void launch_init_random(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_init_random<T>, dim3(8, L.g.nb_max, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc);
+  check_launch("k_init_random");
 }
 template <typename T>
 void launch_setup_beta(const LaunchCtx& L) {
   if (L.g.nproj_max == 0) return;
   hipLaunchKernelGGL(k_setup_beta<T>, dim3(16, L.g.nproj_max, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
+  check_launch("k_setup_beta");
 }
 template <typename T>
 void launch_force_nonlocal(const LaunchCtx& L) {
   if (L.g.nproj_max == 0) return;
   hipLaunchKernelGGL(k_force_nonlocal<T>, dim3(L.g.nproj_max, L.g.nb_max, L.g.ncand), dim3(kNT), 0,
                      L.stream, L.desc);
+  check_launch("k_force_nonlocal");
 }
 template <typename T>
 void launch_potential_finalize(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_potential_finalize<T>, dim3((L.g.ntot_max + kNT - 1) / kNT, 1, L.g.ncand),
                      dim3(kNT), 0, L.stream, L.desc);
+  check_launch("k_potential_finalize");
 }
 
 template <typename T>
 static void configure_t() {
-  const int big = 160 * 1024;
-  hipFuncSetAttribute((const void*)k_z_inverse<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  hipFuncSetAttribute((const void*)k_z_forward<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  hipFuncSetAttribute((const void*)k_plane_hpsi<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
-  hipFuncSetAttribute((const void*)k_plane_density<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      big);
-  hipFuncSetAttribute((const void*)k_gemm_acc<T>, hipFuncAttributeMaxDynamicSharedMemorySize, big);
+  allow_lds((const void*)k_z_inverse<T>);
+  allow_lds((const void*)k_z_forward<T>);
+  allow_lds((const void*)k_plane_hpsi<T>);
+  allow_lds((const void*)k_plane_density<T>);
+  allow_lds((const void*)k_gemm_acc<T>);
 }
 void configure_wave() {
   configure_t<float>();

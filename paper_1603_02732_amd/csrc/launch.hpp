@@ -59,5 +59,9 @@ void launch_force_finalize(const LaunchCtx& L);
 
 // Enable large dynamic LDS for every kernel (once per process per device).
 void configure_kernels();
+// Raise the dynamic-LDS limit of one kernel to what the device allows.
+void allow_lds(const void* kernel);
+// Report a failed launch by kernel name (throws on the host side).
+void check_launch(const char* name);
 
 }  // namespace sgo

@@ -28,6 +28,7 @@ def golden(system, **kw):
             "mu": r["mu"], "forces": F.tolist(),
             "force_parts": {k: v.tolist() for k, v in parts.items()},
             "iterations": r["info"]["iterations"], "npw": int(r["setup"].npw),
+            "trace": [list(t) for t in r["info"]["trace"]],
             "seconds": time.time() - t0, "system": system}
 
 

@@ -23,8 +23,8 @@ def _sgo():
 
 
 @pytest.mark.parametrize("kind,ecut,grid,prec,nb", [
-    ("sip", 3.0, (12, 10, 14), "fp64", 5),
-    ("sip", 3.0, (12, 10, 14), "fp32", 5),
+    ("sip", 3.0, (12, 10, 15), "fp64", 5),
+    ("sip", 3.0, (12, 10, 15), "fp32", 5),
     ("c", 6.0, (20, 18, 24), "fp64", 9),
     ("si", 8.0, (24, 24, 24), "fp64", 20),
 ])
