@@ -189,6 +189,32 @@ int sgo_get_density(sgo_ctx* ctx, double* rho, double* veff);
 
 const char* sgo_last_error(const sgo_ctx* ctx);
 
+/* Sizes of the current structure: info[0..9] = N1, N2, N3, N1*N2*N3, npw_half,
+ * nbands, band pairs (two real bands share one complex FFT), z-sticks of the
+ * sphere, stick pairs (+-(m1,m2)), projectors. */
+int sgo_grid_info(sgo_ctx* ctx, int info[10]);
+
+/* The FP64 subspace step on host matrices (n <= 640): Cholesky S = L L^T
+ * (Gram-Schmidt in band order, Algorithm 1 "Orthogonalization") and, for
+ * mode 3, diagonalisation of H' = L^-1 H L^-T (subspace diagonalisation).
+ * Writes M [n*n] (row-major; new band i = sum_j old band j * M[j*n+i]):
+ * mode 1: M = L^-T; mode 3: M = L^-T V with eigenvalues eps [n] ascending.
+ * Runs the same kernel the SCF uses `reps` times and returns the mean time
+ * per call; clocks (nullable, 6 entries) receives device timestamps of the
+ * solver phases and the Jacobi sweep count.  SGO_ENUMERIC if S is not
+ * positive definite. */
+int sgo_subspace_solve(int device, int n, int mode, const double* S, const double* H,
+                       double* M, double* eps, int reps, double* ms_per_call,
+                       long long* clocks);
+
+/* Measurement hooks (process-wide): from sgo_profile_begin until
+ * sgo_profile_end, every launch of the kernel named `kernel` (for example
+ * "k_plane_hpsi") is bracketed by a pair of HIP events recorded on the stream
+ * it is launched on.  sgo_profile_end waits for the events and returns the
+ * number of launches and their summed duration in milliseconds. */
+int sgo_profile_begin(const char* kernel);
+int sgo_profile_end(int* launches, double* total_ms);
+
 /* ---- Population of candidates, solved together (Section 2.4 last
  * paragraph: the relaxations of one generation may run side by side).  The
  * batch holds up to `capacity` candidates with their own cells, atoms,
@@ -210,6 +236,8 @@ int sgo_batch_set_atoms(sgo_batch* b, int i, const double* pos);
 int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, double* forces,
                   int* status);
 int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info);
+/* Drop the warm-start wavefunctions of every candidate (next solve is cold). */
+int sgo_batch_reset(sgo_batch* b);
 int sgo_batch_size(sgo_batch* b, int* n);
 const char* sgo_batch_last_error(const sgo_batch* b);
 

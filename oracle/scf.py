@@ -146,6 +146,8 @@ def run_scf(system, tol_e=1e-10, tol_rho=1e-9, maxiter=200, mix_alpha=0.5,
     X = None
     info = {}
     trace = []
+    import time as _time
+    t_start = _time.perf_counter()
     for it in range(1, maxiter + 1):
         veff, _ = potentials(st, rho_in)
         eps, C = eigensolve(st, veff, nb, X0=X, dense_max=dense_max)
@@ -157,7 +159,7 @@ def run_scf(system, tol_e=1e-10, tol_rho=1e-9, maxiter=200, mix_alpha=0.5,
         R = rho_out - rho_in
         drho = st.omega / st.ntot * np.abs(R).sum() / max(st.nelec, 1e-30)
         de = abs(e - e_prev) if e_prev is not None else np.inf
-        trace.append((e, de, drho))
+        trace.append((e, de, drho, _time.perf_counter() - t_start))
         if verbose:
             print("oracle scf %3d  E=%.12f  dE=%.2e  drho=%.2e" % (it, e, de, drho))
         if (de < tol_e and drho < tol_rho) or (stop_after is not None and it >= stop_after):

@@ -92,6 +92,11 @@ def load_library(path=None):
         "sgo_apply_h": (I, [P, dp, I, dp, dp]),
         "sgo_get_density": (I, [P, dp, dp]),
         "sgo_last_error": (ctypes.c_char_p, [P]),
+        "sgo_grid_info": (I, [P, ip]),
+        "sgo_subspace_solve": (I, [I, I, I, dp, dp, dp, dp, I, dp,
+                                   ctypes.POINTER(ctypes.c_longlong)]),
+        "sgo_profile_begin": (I, [ctypes.c_char_p]),
+        "sgo_profile_end": (I, [ip, dp]),
         "sgo_batch_create": (I, [ctypes.POINTER(P), I, I, I]),
         "sgo_batch_destroy": (I, [P]),
         "sgo_batch_set_stream": (I, [P, P]),
@@ -101,6 +106,7 @@ def load_library(path=None):
         "sgo_batch_scf": (I, [P, ctypes.POINTER(sgo_scf_opts), dp, dp, ip]),
         "sgo_batch_info": (I, [P, I, ctypes.POINTER(sgo_scf_info)]),
         "sgo_batch_size": (I, [P, ip]),
+        "sgo_batch_reset": (I, [P]),
         "sgo_batch_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
@@ -274,6 +280,54 @@ class Context:
     def reset(self):
         self._check(self._lib.sgo_reset(self._h))
 
+    def geometry(self):
+        v = np.zeros(10, dtype=np.int32)
+        self._check(self._lib.sgo_grid_info(self._h, _iptr(v)))
+        keys = ("N1", "N2", "N3", "ntot", "npw_half", "nbands", "npair", "nst", "nsp", "nproj")
+        return {k: int(x) for k, x in zip(keys, v)}
+
+    def profile_begin(self, kernel):
+        return profile_begin(kernel)
+
+    def profile_end(self):
+        return profile_end()
+
+
+def subspace_solve(S, H=None, mode=3, reps=1, device=0, clocks=False):
+    """Cholesky orthonormalisation (+ subspace diagonalisation for mode 3) of
+    host FP64 matrices on the GPU.  Returns (M, eps, ms_per_call, clocks)."""
+    lib = load_library()
+    S = np.ascontiguousarray(S, dtype=np.float64)
+    n = S.shape[0]
+    Hc = None if H is None else np.ascontiguousarray(H, dtype=np.float64)
+    M = np.zeros((n, n))
+    eps = np.zeros(n)
+    ms = ctypes.c_double()
+    clk = (ctypes.c_longlong * 6)()
+    rc = lib.sgo_subspace_solve(device, n, mode, _dptr(S), _dptr(Hc) if Hc is not None else None,
+                                _dptr(M), _dptr(eps), reps, ctypes.byref(ms),
+                                clk if clocks else None)
+    if rc != SGO_OK:
+        raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
+    return M, eps, ms.value, list(clk) if clocks else None
+
+
+def profile_begin(kernel):
+    """Time every launch of `kernel` with HIP events until profile_end()."""
+    rc = load_library().sgo_profile_begin(kernel.encode())
+    if rc != SGO_OK:
+        raise SgoError(rc, "profile_begin")
+
+
+def profile_end():
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    lib = load_library()
+    rc = lib.sgo_profile_end(ctypes.byref(n), ctypes.byref(ms))
+    if rc != SGO_OK:
+        raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
+    return {"launches": n.value, "ms": ms.value}
+
 
 class Batch:
     """A population of candidates solved together (sgo_batch)."""
@@ -346,6 +400,9 @@ class Batch:
             forces.append(f[off:off + 3 * na].reshape(na, 3))
             off += 3 * na
         return e, forces, st
+
+    def reset(self):
+        self._check(self._lib.sgo_batch_reset(self._h))
 
     def info(self, i):
         inf = sgo_scf_info()

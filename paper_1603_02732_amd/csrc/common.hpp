@@ -107,6 +107,7 @@ struct CandDesc {
   double ew_eta, ew_rcut, ew_gcut, pad2;
   int ew_m[3], ew_n[3];  // reciprocal / image enumeration half-widths
   int ew_ng, ew_nimg;
+  long long* dbg_clk;   // optional phase timestamps of the subspace solver
   // reduction scratch: partial sums and tickets (zeroed at allocation)
   double* red_part;     // [kRedSlots]
   unsigned* tickets;    // [kTickets]

@@ -63,7 +63,7 @@ __device__ bool grid_sum_last(const double (&v)[N], double* part, unsigned* tick
 #pragma unroll
   for (int i = 0; i < N; ++i) {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += load_coherent(part + (size_t)b * N + i);
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) s += part[(size_t)b * N + i];
     out[i] = s;
   }
   block_sum<N>(out, sh);
@@ -142,8 +142,17 @@ __device__ __forceinline__ void fft_stage(const cplx<T>* __restrict__ a, cplx<T>
   const int tws = n / (Ns * R);
   const int total = nbf * nseq;
   for (int t = tid; t < total; t += nthr) {
-    const int seq = t / nbf;
-    const int j = t - seq * nbf;
+    // consecutive threads take consecutive elements when elements are
+    // contiguous (es == 1), else consecutive sequences: either way the LDS
+    // addresses of a wavefront are consecutive (no bank conflicts).
+    int seq, j;
+    if (es == 1) {
+      seq = t / nbf;
+      j = t - seq * nbf;
+    } else {
+      j = t / nseq;
+      seq = t - j * nseq;
+    }
     const cplx<T>* src = a + seq * ss;
     cplx<T>* dst = b + seq * ss;
     const int jm = j % Ns;

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <stdexcept>
@@ -34,11 +35,44 @@ static const double kPiH = 3.14159265358979323846;
 
 static int g_lds_limit = 64 * 1024;
 
+// Launch-shape tuning parameters (environment overrides of the defaults).
+static int tune(const char* name, int def) {
+  const char* v = std::getenv(name);
+  if (!v || !*v) return def;
+  const int x = std::atoi(v);
+  return x > 0 ? x : def;
+}
+
 void allow_lds(const void* kernel) {
   hipFuncAttributes a;
   HIPCHK(hipFuncGetAttributes(&a, kernel));
   const int dyn = g_lds_limit - (int)a.sharedSizeBytes;
   if (dyn > 0) HIPCHK(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, dyn));
+}
+
+struct ProfState {
+  bool on = false;
+  std::string name;
+  std::vector<hipEvent_t> ev;  // start/stop pairs
+  size_t used = 0;
+};
+static ProfState g_prof;
+
+void prof_before(const char* name, hipStream_t s) {
+  if (!g_prof.on || g_prof.name != name) return;
+  if (g_prof.used + 2 > g_prof.ev.size()) {
+    for (int k = 0; k < 2; ++k) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      g_prof.ev.push_back(e);
+    }
+  }
+  HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], s));
+}
+void prof_after(const char* name, hipStream_t s) {
+  if (!g_prof.on || g_prof.name != name) return;
+  HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], s));
+  g_prof.used += 2;
 }
 
 void check_launch(const char* name) {
@@ -534,7 +568,9 @@ class Engine {
       g.ew_ng_max = std::max(g.ew_ng_max, c.ew_ng);
     }
     g.sp_chunk = std::max(1, 640 / std::max(1, g.N3max));
-    g.kc_len = std::max(256, ((g.K_max + 31) / 32 + 31) / 32 * 32);
+    g.kc_len = std::max(tune("SGO_GRAM_KC", 256), ((g.K_max + 31) / 32 + 31) / 32 * 32);
+    g.kc_len = (g.kc_len + 31) / 32 * 32;
+    g.sub_threads = std::max(64, std::min(512, tune("SGO_SUB_THREADS", 512) / 64 * 64));
     g.nkc_max = (g.K_max + g.kc_len - 1) / g.kc_len;
     g.dens_chunks = std::max(1, std::min(g.npair_max, (512 + g.N3max - 1) / std::max(1, g.N3max)));
     return g;
@@ -608,19 +644,23 @@ class Engine {
     launch_ewald(L);
   }
 
+  // Orthonormalise (Cholesky) and rotate to the Ritz vectors of the band
+  // subspace.  Intermediate calls within an SCF iteration may stop after
+  // `sweeps` Jacobi sweeps; the last one converges fully.
   template <typename T>
-  void subspace_rotate(const LaunchCtx& L, bool with_d) {
+  void subspace_rotate(const LaunchCtx& L, bool with_d, int sweeps) {
     int a[2] = {W_X, W_X}, b[2] = {W_X, W_HX}, o[2] = {M_S, M_H};
     launch_gram<T>(L, 2, a, b, o);
-    launch_subspace(L, 3);
+    launch_subspace(L, 3, sweeps);
     int y[3] = {W_X, W_HX, W_D};
     launch_gemm_acc<T>(L, with_d ? 3 : 2, y, y, M_M, 0.0, 1.0, 0);
   }
 
   template <typename T>
   void eigensolver(const LaunchCtx& L, int ncg) {
+    const int inter = tune("SGO_RR_SWEEPS", 1);
     launch_hpsi<T>(L, W_X);
-    subspace_rotate<T>(L, false);
+    subspace_rotate<T>(L, false, inter);
     for (int k = 0; k < ncg; ++k) {
       launch_cg_direction<T>(L, k == 0 ? 1 : 0);
       int a[1] = {W_X}, b[1] = {W_D}, o[1] = {M_C};
@@ -629,7 +669,7 @@ class Engine {
       launch_gemm_acc<T>(L, 1, y, aa, M_C, 1.0, -1.0, 0);
       launch_hpsi<T>(L, W_D);
       launch_linemin<T>(L);
-      subspace_rotate<T>(L, true);
+      subspace_rotate<T>(L, true, k + 1 == ncg ? 40 : inter);
     }
   }
 
@@ -1136,6 +1176,126 @@ int sgo_get_density(sgo_ctx* c, double* rho, double* veff) {
 
 const char* sgo_last_error(const sgo_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
 
+int sgo_profile_begin(const char* kernel) {
+  if (!kernel) return SGO_EINVAL;
+  sgo::g_prof.on = true;
+  sgo::g_prof.name = kernel;
+  sgo::g_prof.used = 0;
+  return SGO_OK;
+}
+
+int sgo_profile_end(int* launches, double* total_ms) {
+  return guard(nullptr, [&] {
+    auto& P = sgo::g_prof;
+    double ms = 0.0;
+    for (size_t k = 0; k + 1 < P.used; k += 2) {
+      HIPCHK(hipEventSynchronize(P.ev[k + 1]));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, P.ev[k], P.ev[k + 1]));
+      ms += t;
+    }
+    if (launches) *launches = (int)(P.used / 2);
+    if (total_ms) *total_ms = ms;
+    P.on = false;
+    P.used = 0;
+    return SGO_OK;
+  });
+}
+
+int sgo_subspace_solve(int device, int n, int mode, const double* S, const double* H, double* M,
+                       double* eps, int reps, double* ms_per_call, long long* clocks) {
+  return guard(nullptr, [&] {
+    if (n < 1 || n > 640 || !S || !M || (mode != 1 && mode != 3) || (mode == 3 && (!H || !eps)))
+      throw Error(SGO_EINVAL, "bad subspace_solve arguments");
+    if (reps < 1) reps = 1;
+    HIPCHK(hipSetDevice(device));
+    static bool configured = false;
+    if (!configured) {
+      int lim = 0;
+      HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+      sgo::g_lds_limit = lim;
+      sgo::configure_kernels();
+      configured = true;
+    }
+    const size_t nn = (size_t)n * n;
+    double *dS, *dH, *dC, *dM, *deps, *dscal, *dSsave, *dHsave;
+    long long* dclk;
+    HIPCHK(hipMalloc(&dS, nn * 8));
+    HIPCHK(hipMalloc(&dH, nn * 8));
+    HIPCHK(hipMalloc(&dC, nn * 8));
+    HIPCHK(hipMalloc(&dM, nn * 8));
+    HIPCHK(hipMalloc(&dSsave, nn * 8));
+    HIPCHK(hipMalloc(&dHsave, nn * 8));
+    HIPCHK(hipMalloc(&deps, n * 8));
+    HIPCHK(hipMalloc(&dscal, sgo::S_COUNT * 8));
+    HIPCHK(hipMalloc(&dclk, 8 * sizeof(long long)));
+    HIPCHK(hipMemset(dscal, 0, sgo::S_COUNT * 8));
+    HIPCHK(hipMemcpy(dSsave, S, nn * 8, hipMemcpyHostToDevice));
+    if (H) HIPCHK(hipMemcpy(dHsave, H, nn * 8, hipMemcpyHostToDevice));
+    sgo::CandDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.nb = n;
+    d.active = 1;
+    d.S = dS;
+    d.Hs = dH;
+    d.C = dC;
+    d.M = dM;
+    d.eps = deps;
+    d.scal = dscal;
+    d.dbg_clk = clocks ? dclk : nullptr;
+    sgo::CandDesc* dd;
+    HIPCHK(hipMalloc(&dd, sizeof(d)));
+    HIPCHK(hipMemcpy(dd, &d, sizeof(d), hipMemcpyHostToDevice));
+    sgo::LaunchCtx L{};
+    L.stream = nullptr;
+    L.desc = dd;
+    L.g.ncand = 1;
+    L.g.nb_max = n;
+    const char* env = std::getenv("SGO_SUB_THREADS");
+    L.g.sub_threads = env ? std::max(64, std::min(512, std::atoi(env) / 64 * 64)) : 512;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float total = 0.f;
+    for (int r = 0; r < reps; ++r) {
+      HIPCHK(hipMemcpy(dS, dSsave, nn * 8, hipMemcpyDeviceToDevice));
+      if (H) HIPCHK(hipMemcpy(dH, dHsave, nn * 8, hipMemcpyDeviceToDevice));
+      HIPCHK(hipEventRecord(e0, nullptr));
+      sgo::launch_subspace(L, mode);
+      HIPCHK(hipEventRecord(e1, nullptr));
+      HIPCHK(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, e0, e1));
+      total += t;
+    }
+    double flag = 0;
+    HIPCHK(hipMemcpy(M, dM, nn * 8, hipMemcpyDeviceToHost));
+    if (eps && mode == 3) HIPCHK(hipMemcpy(eps, deps, n * 8, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(&flag, dscal + sgo::S_ERR, 8, hipMemcpyDeviceToHost));
+    if (clocks) HIPCHK(hipMemcpy(clocks, dclk, 6 * sizeof(long long), hipMemcpyDeviceToHost));
+    if (ms_per_call) *ms_per_call = total / reps;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (void* p : {(void*)dS, (void*)dH, (void*)dC, (void*)dM, (void*)deps, (void*)dscal,
+                    (void*)dSsave, (void*)dHsave, (void*)dclk, (void*)dd})
+      (void)hipFree(p);
+    if (flag != 0.0) throw Error(SGO_ENUMERIC, "overlap matrix is not positive definite");
+    return SGO_OK;
+  });
+}
+
+int sgo_grid_info(sgo_ctx* c, int* info) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!info) throw Error(SGO_EINVAL, "NULL info");
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& h = c->eng->cand(0);
+    const int v[10] = {h.N[0], h.N[1], h.N[2], h.ntot, h.npwh, h.nb, h.npair, h.nst, h.nsp, h.nproj};
+    std::memcpy(info, v, sizeof(v));
+    return SGO_OK;
+  });
+}
+
 // ---------------------------------------------------------------- batches
 int sgo_batch_create(sgo_batch** out, int device, int precision, int capacity) {
   if (!out) return SGO_EINVAL;
@@ -1226,6 +1386,12 @@ int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info) {
     *info = b->eng->cand(i).info;
     return SGO_OK;
   });
+}
+
+int sgo_batch_reset(sgo_batch* b) {
+  if (!b) return SGO_EINVAL;
+  b->eng->reset();
+  return SGO_OK;
 }
 
 int sgo_batch_size(sgo_batch* b, int* n) {

@@ -533,18 +533,21 @@ __global__ void k_force_finalize(const CandDesc* __restrict__ cds) {
 // Fixed: f = 2 on the lowest nocc bands.  Fermi-Dirac: f = 2/(1+e^{(e-mu)/s})
 // with mu from 200 bisection steps so that sum f = N_el; entropy
 // S = -2 sum [g ln g + (1-g) ln(1-g)], g = f/2.
-__global__ void k_occupations(const CandDesc* __restrict__ cds) {
+__global__ void __launch_bounds__(64) k_occupations(const CandDesc* __restrict__ cds) {
+  // one wavefront per candidate: all reductions are cross-lane sums
   const CandDesc& cd = cds[blockIdx.x];
   if (!cd.active) return;
-  __shared__ double sh[16 * 2];
-  const int n = cd.nb;
+  const int n = cd.nb, lane = threadIdx.x;
   if (cd.occ_kind == 0) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) cd.occ[i] = i < cd.nocc ? 2.0 : 0.0;
-    double v[1] = {0.0};
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += (i < cd.nocc ? 2.0 : 0.0) * cd.eps[i];
-    block_sum<1>(v, sh);
-    if (threadIdx.x == 0) {
-      cd.scal[S_EBAND] = v[0];
+    double v = 0.0;
+    for (int i = lane; i < n; i += 64) {
+      const double f = i < cd.nocc ? 2.0 : 0.0;
+      cd.occ[i] = f;
+      v += f * cd.eps[i];
+    }
+    v = wave_sum(v);
+    if (lane == 0) {
+      cd.scal[S_EBAND] = v;
       cd.scal[S_ENTROPY] = 0.0;
       cd.scal[S_MU] = cd.nocc < n ? 0.5 * (cd.eps[cd.nocc - 1] + cd.eps[cd.nocc]) : cd.eps[n - 1];
     }
@@ -552,33 +555,39 @@ __global__ void k_occupations(const CandDesc* __restrict__ cds) {
   }
   const double sg = cd.sigma;
   double lo = 1e300, hi = -1e300;
-  for (int i = 0; i < n; ++i) {
+  for (int i = lane; i < n; i += 64) {
     lo = fmin(lo, cd.eps[i]);
     hi = fmax(hi, cd.eps[i]);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
   }
   lo -= 40.0 * sg;
   hi += 40.0 * sg;
   for (int it = 0; it < 200; ++it) {
     const double mu = 0.5 * (lo + hi);
-    double v[1] = {0.0};
-    for (int i = threadIdx.x; i < n; i += blockDim.x) v[0] += 2.0 / (1.0 + exp((cd.eps[i] - mu) / sg));
-    block_sum<1>(v, sh);
-    if (v[0] > cd.nelec) hi = mu;
+    if (mu <= lo || mu >= hi) break;  // interval exhausted in FP64
+    double v = 0.0;
+    for (int i = lane; i < n; i += 64) v += 2.0 / (1.0 + exp((cd.eps[i] - mu) / sg));
+    v = wave_sum(v);
+    if (v > cd.nelec) hi = mu;
     else lo = mu;
   }
   const double mu = 0.5 * (lo + hi);
-  double v[2] = {0.0, 0.0};
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+  double v0 = 0.0, v1 = 0.0;
+  for (int i = lane; i < n; i += 64) {
     const double f = 2.0 / (1.0 + exp((cd.eps[i] - mu) / sg));
     cd.occ[i] = f;
-    v[0] += f * cd.eps[i];
+    v0 += f * cd.eps[i];
     const double g = fmax(0.5 * f, 1e-300), gm = fmax(1.0 - 0.5 * f, 1e-300);
-    v[1] += g * log(g) + gm * log(gm);
+    v1 += g * log(g) + gm * log(gm);
   }
-  block_sum<2>(v, sh);
-  if (threadIdx.x == 0) {
-    cd.scal[S_EBAND] = v[0];
-    cd.scal[S_ENTROPY] = -2.0 * v[1];
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  if (lane == 0) {
+    cd.scal[S_EBAND] = v0;
+    cd.scal[S_ENTROPY] = -2.0 * v1;
     cd.scal[S_MU] = mu;
   }
 }
@@ -587,18 +596,50 @@ __global__ void k_occupations(const CandDesc* __restrict__ cds) {
 // mode 1: orthonormalise only:  S = L L^T, M = L^-T.
 // mode 3: orthonormalise + Rayleigh-Ritz:  H' = L^-1 H L^-T = V diag(e) V^T,
 //         M = L^-T V (columns sorted by ascending e), eps = e.
-// New bands are X_new[:, i] = sum_j X[:, j] M[j][i].
+// New bands are X_new[:, i] = sum_j X[:, j] M[j][i] (Cholesky-QR, i.e.
+// Gram-Schmidt in band order, followed by the subspace diagonalisation).
+// max_sweeps bounds the Jacobi sweeps (1 gives an approximate rotation for
+// intermediate CG steps; the last step of an SCF iteration converges).
 constexpr int kSubNT = 512;
+
+// Pair k of round r of the round-robin (circle) schedule on n2 indices:
+// index 0 stays fixed, indices 1..n2-1 rotate.  Returns p < q.
+__device__ __forceinline__ void jacobi_pair(int r, int k, int n2, int* p, int* q) {
+  const int a = k == 0 ? 0 : ((r + k - 1) % (n2 - 1)) + 1;
+  const int kb = n2 - 1 - k;
+  const int b = kb == 0 ? 0 : ((r + kb - 1) % (n2 - 1)) + 1;
+  *p = min(a, b);
+  *q = max(a, b);
+}
+// Rotation (c, s) that zeroes A[p][q] of the symmetric matrix A:
+// theta = (a_qq - a_pp) / (2 a_pq), t = sgn(theta) / (|theta| + sqrt(theta^2 + 1)).
+// Entries at rounding level (|a_pq| <= 1e-17 sqrt|a_pp a_qq|) are left alone.
+__device__ __forceinline__ void jacobi_rot(const double* A, int n, int p, int q, double* c,
+                                           double* s) {
+  *c = 1.0;
+  *s = 0.0;
+  if (q >= n) return;
+  const double apq = A[p * n + q];
+  const double app = A[p * n + p], aqq = A[q * n + q];
+  if (!(fabs(apq) > 1e-17 * sqrt(fabs(app * aqq)) + 1e-300)) return;
+  const double th = (aqq - app) / (2.0 * apq);
+  double t;
+  if (fabs(th) > 1e150) t = 0.5 / th;
+  else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+  *c = 1.0 / sqrt(t * t + 1.0);
+  *s = t * (*c);
+}
+
 __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict__ cds, int mode,
-                                                     int use_lds) {
+                                                     int use_lds, int max_sweeps) {
   const CandDesc& cd = cds[blockIdx.x];
   if (!cd.active) return;
   const int n = cd.nb;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
   extern __shared__ __align__(16) char smem[];
-  const bool in_lds = use_lds != 0;
-  double *P0, *P1, *P2, *P3;
-  if (in_lds) {
+  double *P0, *P1, *P2, *P3;  // L, H / H', W = L^-1, scratch / V
+  if (use_lds) {
     P0 = (double*)smem;
     P1 = P0 + n * n;
     P2 = P1 + n * n;
@@ -614,70 +655,83 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     P3 = cd.M;
   }
   __shared__ int fail;
-  __shared__ double jc[320], js[320];
-  __shared__ int jp[320], jq[320];
   __shared__ double sh[16 * 2];
   __shared__ int rank[640];
+  __shared__ double rc[320], rs[320];
+  __shared__ int rp[320], rq[320];
   if (tid == 0) fail = 0;
+  long long* clk = cd.dbg_clk;
+  if (clk && tid == 0) clk[0] = clock64();
   __syncthreads();
-  // Cholesky S = L L^T (lower, in place)
+  // Cholesky S = L L^T (lower, in place, right-looking; two barriers per
+  // column).  The pivots are kept aside in P3 and written to the diagonal at
+  // the end, so no thread overwrites a pivot another thread still reads.
   for (int k = 0; k < n; ++k) {
-    if (tid == 0) {
-      const double d = P0[k * n + k];
-      if (!(d > 0.0)) fail = 1;
-      else P0[k * n + k] = sqrt(d);
+    __syncthreads();  // trailing update of the previous column is complete
+    const double d = P0[k * n + k];
+    if (!(d > 0.0)) {
+      if (tid == 0) fail = 1;
+      break;
     }
-    __syncthreads();
-    if (fail) break;
-    const double piv = P0[k * n + k];
-    for (int i = k + 1 + tid; i < n; i += nthr) P0[i * n + k] /= piv;
+    const double piv = sqrt(d);
+    const double inv = 1.0 / piv;
+    if (tid == 0) P3[k] = piv;
+    for (int i = k + 1 + tid; i < n; i += nthr) P0[i * n + k] *= inv;
     __syncthreads();
     const int m = n - k - 1;
     for (int t = tid; t < m * m; t += nthr) {
       const int i = k + 1 + t / m, j = k + 1 + t % m;
       if (j <= i) P0[i * n + j] -= P0[i * n + k] * P0[j * n + k];
     }
-    __syncthreads();
   }
+  __syncthreads();
+  if (!fail)
+    for (int k = tid; k < n; k += nthr) P0[k * n + k] = P3[k];
+  __syncthreads();
   if (fail) {
     if (tid == 0) cd.scal[S_ERR] = 2.0;
     for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
     return;
   }
-  // W = L^-1 (lower) into P2, column by column
-  for (int j = tid; j < n; j += nthr) {
-    for (int i = 0; i < j; ++i) P2[i * n + j] = 0.0;
-    P2[j * n + j] = 1.0 / P0[j * n + j];
-    for (int i = j + 1; i < n; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s += P0[i * n + k] * P2[k * n + j];
-      P2[i * n + j] = -s / P0[i * n + i];
-    }
+  // W = L^-1 by elimination on [L | I]: at step j, rows i > j subtract
+  // L[i][j] * row j (final since step j-1); row j+1 is complete after this
+  // step and is divided by its pivot.  One barrier per step.
+  for (int e = tid; e < n * n; e += nthr) {
+    const int i = e / n, j = e % n;
+    P2[e] = i == j ? (i == 0 ? 1.0 / P0[0] : 1.0) : 0.0;
   }
   __syncthreads();
-  if (mode == 1) {
-    // M = W^T
-    if (in_lds) {
-      for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * n + e / n];
-    } else {
-      for (int e = tid; e < n * n; e += nthr) P0[e] = P2[(e % n) * n + e / n];
-      __syncthreads();
-      for (int e = tid; e < n * n; e += nthr) cd.M[e] = P0[e];
+  for (int j = 0; j + 1 < n; ++j) {
+    const int rows = n - 1 - j, cols = j + 1;
+    for (int t = tid; t < rows * cols + 1; t += nthr) {
+      if (t == rows * cols) {
+        P2[(j + 1) * n + j + 1] = 1.0 / P0[(j + 1) * n + j + 1];
+        continue;
+      }
+      const int i = j + 1 + t / cols, c = t % cols;
+      double w = P2[i * n + c] - P0[i * n + j] * P2[j * n + c];
+      if (i == j + 1) w /= P0[i * n + i];
+      P2[i * n + c] = w;
     }
+    __syncthreads();
+  }
+  if (clk && tid == 0) clk[1] = clock64();
+  if (mode == 1) {
+    for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * n + e / n];
     return;
   }
-  // T1 = W H -> P3 ; H' = T1 W^T -> P1 (symmetrised)
+  // H' = W H W^T (symmetrised)
   for (int e = tid; e < n * n; e += nthr) {
     const int i = e / n, j = e % n;
     double s = 0.0;
-    for (int k = 0; k <= i; ++k) s += P2[i * n + k] * P1[k * n + j];
+    for (int k = 0; k <= i; ++k) s = fma(P2[i * n + k], P1[k * n + j], s);
     P3[e] = s;
   }
   __syncthreads();
   for (int e = tid; e < n * n; e += nthr) {
     const int i = e / n, j = e % n;
     double s = 0.0;
-    for (int k = 0; k <= j; ++k) s += P3[i * n + k] * P2[j * n + k];
+    for (int k = 0; k <= j; ++k) s = fma(P3[i * n + k], P2[j * n + k], s);
     P1[e] = s;
   }
   __syncthreads();
@@ -688,13 +742,20 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       P1[i * n + j] = a;
       P1[j * n + i] = a;
     }
+    P3[e] = (i == j) ? 1.0 : 0.0;
   }
-  for (int e = tid; e < n * n; e += nthr) P3[e] = (e / n == e % n) ? 1.0 : 0.0;
   __syncthreads();
-  // cyclic Jacobi, round-robin ordering of disjoint pairs
+  // Cyclic Jacobi with the round-robin ordering of disjoint index pairs.
+  // Phase A computes the rotations of a round; in phase B each wavefront
+  // takes column pairs Q (its rotation is a wave-uniform read) and its lanes
+  // take row pairs P, rotating 2x2 blocks in place, then V's columns.
+  // Blocks whose two rotations are both the identity are skipped.  Stop when
+  // the off-diagonal norm is below 1e-13 of the diagonal norm.
   const int n2 = n + (n & 1);
   const int npair = n2 / 2;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  if (clk && tid == 0) clk[2] = clock64();
+  int nsweep = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double v[2] = {0.0, 0.0};
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
@@ -703,55 +764,59 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       else v[0] += a * a;
     }
     block_sum<2>(v, sh);
-    if (!(v[0] > 1e-30 * v[1])) break;
+    if (!(v[0] > 1e-26 * v[1] + 1e-300)) break;
+    ++nsweep;
     for (int r = 0; r < n2 - 1; ++r) {
       for (int k = tid; k < npair; k += nthr) {
-        const int a = k == 0 ? 0 : ((r + k - 1) % (n2 - 1)) + 1;
-        const int kb = n2 - 1 - k;
-        const int b = kb == 0 ? 0 : ((r + kb - 1) % (n2 - 1)) + 1;
-        const int p = min(a, b), q = max(a, b);
-        double c = 1.0, s = 0.0;
-        if (q < n) {
-          const double apq = P1[p * n + q];
-          if (fabs(apq) > 1e-300) {
-            const double th = (P1[q * n + q] - P1[p * n + p]) / (2.0 * apq);
-            double t;
-            if (fabs(th) > 1e150) t = 0.5 / th;
-            else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
+        int p, q;
+        jacobi_pair(r, k, n2, &p, &q);
+        double c, sn;
+        jacobi_rot(P1, n, p, q, &c, &sn);
+        rp[k] = p;
+        rq[k] = q;
+        rc[k] = c;
+        rs[k] = sn;
+      }
+      __syncthreads();
+      for (int P = wave; P < npair; P += nw) {
+        const double sP = rs[P], cP = rc[P];
+        const int p1 = rp[P], p2 = rq[P];
+        const bool p2v = p2 < n;
+        for (int Q = lane; Q < npair; Q += 64) {
+          const double sQ = rs[Q];
+          if (sP == 0.0 && sQ == 0.0) continue;
+          const double cQ = rc[Q];
+          const int q1 = rp[Q], q2 = rq[Q];
+          const bool q2v = q2 < n;
+          const double a11 = P1[p1 * n + q1];
+          const double a12 = q2v ? P1[p1 * n + q2] : 0.0;
+          const double a21 = p2v ? P1[p2 * n + q1] : 0.0;
+          const double a22 = (p2v && q2v) ? P1[p2 * n + q2] : 0.0;
+          // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
+          const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
+          const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
+          // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
+          P1[p1 * n + q1] = cQ * b11 - sQ * b12;
+          if (q2v) P1[p1 * n + q2] = sQ * b11 + cQ * b12;
+          if (p2v) P1[p2 * n + q1] = cQ * b21 - sQ * b22;
+          if (p2v && q2v) P1[p2 * n + q2] = sQ * b21 + cQ * b22;
+        }
+        // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
+        // pair P updates rows p1, p2 of P3, contiguous across lanes
+        if (sP != 0.0 && p2v) {
+          for (int i = lane; i < n; i += 64) {
+            const double vp = P3[p1 * n + i], vq = P3[p2 * n + i];
+            P3[p1 * n + i] = cP * vp - sP * vq;
+            P3[p2 * n + i] = sP * vp + cP * vq;
           }
         }
-        jc[k] = c;
-        js[k] = s;
-        jp[k] = p;
-        jq[k] = q < n ? q : -1;
-      }
-      __syncthreads();
-      for (int t = tid; t < npair * n; t += nthr) {  // rows p, q
-        const int k = t / n, j = t - k * n;
-        if (jq[k] < 0 || js[k] == 0.0) continue;
-        const int p = jp[k], q = jq[k];
-        const double c = jc[k], s = js[k];
-        const double ap = P1[p * n + j], aq = P1[q * n + j];
-        P1[p * n + j] = c * ap - s * aq;
-        P1[q * n + j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      for (int t = tid; t < npair * n; t += nthr) {  // columns p, q of H' and V
-        const int k = t / n, i = t - k * n;
-        if (jq[k] < 0 || js[k] == 0.0) continue;
-        const int p = jp[k], q = jq[k];
-        const double c = jc[k], s = js[k];
-        const double ap = P1[i * n + p], aq = P1[i * n + q];
-        P1[i * n + p] = c * ap - s * aq;
-        P1[i * n + q] = s * ap + c * aq;
-        const double vp = P3[i * n + p], vq = P3[i * n + q];
-        P3[i * n + p] = c * vp - s * vq;
-        P3[i * n + q] = s * vp + c * vq;
       }
       __syncthreads();
     }
+  }
+  if (clk && tid == 0) {
+    clk[3] = clock64();
+    clk[5] = nsweep;
   }
   // ranks of the eigenvalues (ascending, ties by index)
   for (int i = tid; i < n; i += nthr) {
@@ -763,11 +828,11 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     }
     rank[i] = rnk;
   }
-  // Mtmp = W^T V -> P0
+  // M = W^T V into P0 (L is no longer needed); P3 holds V^T
   for (int e = tid; e < n * n; e += nthr) {
     const int j = e / n, i = e % n;
     double s = 0.0;
-    for (int k = j; k < n; ++k) s += P2[k * n + j] * P3[k * n + i];
+    for (int k = j; k < n; ++k) s = fma(P2[k * n + j], P3[i * n + k], s);
     P0[e] = s;
   }
   __syncthreads();
@@ -776,6 +841,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     cd.M[j * n + rank[i]] = P0[e];
   }
   for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = P1[i * n + i];
+  if (clk && tid == 0) clk[4] = clock64();
 }
 
 // ---------------------------------------------------------- launch helpers
@@ -784,78 +850,109 @@ void launch_grid_fft(const LaunchCtx& L, int sign) {
   const int rpb = std::max(1, 1024 / g.N1max);
   const int rows = g.N2max * g.N3max;
   size_t lds_x = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)rpb * g.N1max);
+  prof_before("k_grid_fft_x", L.stream);
   hipLaunchKernelGGL(k_grid_fft_x, dim3((rows + rpb - 1) / rpb, 1, g.ncand), dim3(kNT), lds_x,
                      L.stream, L.desc, sign, rpb);
   check_launch("k_grid_fft_x");
+  prof_after("k_grid_fft_x", L.stream);
   const int ntx = (g.N1max + kTX - 1) / kTX;
   size_t lds_y = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)kTX * g.N2max);
+  prof_before("k_grid_fft_yz", L.stream);
   hipLaunchKernelGGL(k_grid_fft_yz, dim3(ntx * g.N3max, 1, g.ncand), dim3(kNT), lds_y, L.stream,
                      L.desc, 1, sign);
   check_launch("k_grid_fft_yz");
+  prof_after("k_grid_fft_yz", L.stream);
   size_t lds_z = sizeof(cplx<double>) * (kMaxFftN + 2 * (size_t)kTX * g.N3max);
+  prof_before("k_grid_fft_yz", L.stream);
   hipLaunchKernelGGL(k_grid_fft_yz, dim3(ntx * g.N2max, 1, g.ncand), dim3(kNT), lds_z, L.stream,
                      L.desc, 2, sign);
   check_launch("k_grid_fft_yz");
+  prof_after("k_grid_fft_yz", L.stream);
 }
 
 static int grid_blocks(const BatchGeom& g) { return std::min(1024, (g.ntot_max + kNT - 1) / kNT); }
 
 void launch_density_finalize(const LaunchCtx& L) {
+  prof_before("k_density_finalize", L.stream);
   hipLaunchKernelGGL(k_density_finalize, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0,
                      L.stream, L.desc);
   check_launch("k_density_finalize");
+  prof_after("k_density_finalize", L.stream);
 }
 void launch_gspace_residual(const LaunchCtx& L, int cur, int nvalid) {
+  prof_before("k_gspace_residual", L.stream);
   hipLaunchKernelGGL(k_gspace_residual, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0,
                      L.stream, L.desc, cur, nvalid);
   check_launch("k_gspace_residual");
+  prof_after("k_gspace_residual", L.stream);
 }
 void launch_scf_control(const LaunchCtx& L, int cur, int nvalid, int iter, double tol_e_atom,
                         double tol_rho) {
+  prof_before("k_scf_control", L.stream);
   hipLaunchKernelGGL(k_scf_control, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, cur, nvalid,
                      iter, tol_e_atom, tol_rho);
   check_launch("k_scf_control");
+  prof_after("k_scf_control", L.stream);
 }
 void launch_mix(const LaunchCtx& L, int initial, int cur, int nvalid, int next, double alpha,
                 double q0) {
+  prof_before("k_mix", L.stream);
   hipLaunchKernelGGL(k_mix, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
                      initial, cur, nvalid, next, alpha, q0);
   check_launch("k_mix");
+  prof_after("k_mix", L.stream);
 }
 void launch_setup_grid(const LaunchCtx& L) {
+  prof_before("k_setup_grid", L.stream);
   hipLaunchKernelGGL(k_setup_grid, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
   check_launch("k_setup_grid");
+  prof_after("k_setup_grid", L.stream);
 }
 void launch_ewald(const LaunchCtx& L) {
   const int nb = std::min(1024, (L.g.ew_ng_max + kNT - 1) / kNT);
+  prof_before("k_ewald_recip", L.stream);
   hipLaunchKernelGGL(k_ewald_recip, dim3(nb, 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
                      L.species);
   check_launch("k_ewald_recip");
+  prof_after("k_ewald_recip", L.stream);
+  prof_before("k_ewald_atom", L.stream);
   hipLaunchKernelGGL(k_ewald_atom, dim3(L.g.nat_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
   check_launch("k_ewald_atom");
+  prof_after("k_ewald_atom", L.stream);
 }
 void launch_force_local(const LaunchCtx& L) {
+  prof_before("k_force_local", L.stream);
   hipLaunchKernelGGL(k_force_local, dim3(L.g.nat_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
   check_launch("k_force_local");
+  prof_after("k_force_local", L.stream);
 }
 void launch_force_finalize(const LaunchCtx& L) {
+  prof_before("k_force_finalize", L.stream);
   hipLaunchKernelGGL(k_force_finalize, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
   check_launch("k_force_finalize");
+  prof_after("k_force_finalize", L.stream);
 }
 void launch_occupations(const LaunchCtx& L) {
-  hipLaunchKernelGGL(k_occupations, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
+  prof_before("k_occupations", L.stream);
+  hipLaunchKernelGGL(k_occupations, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc);
   check_launch("k_occupations");
+  prof_after("k_occupations", L.stream);
 }
-void launch_subspace(const LaunchCtx& L, int mode) {
+void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
+  // up to 64 bands the matrices live in LDS; the thread count is a tuning
+  // parameter (a single wavefront makes barriers almost free).
   const int n = L.g.nb_max;
   const int use_lds = n <= 64 ? 1 : 0;
   size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * n : 0;
-  hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(kSubNT), lds, L.stream, L.desc, mode,
-                     use_lds);
+  const int nthr = L.g.sub_threads;
+  prof_before("k_subspace", L.stream);
+  hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode,
+                     use_lds, max_sweeps);
   check_launch("k_subspace");
+  prof_after("k_subspace", L.stream);
 }
 
 void configure_wave();

@@ -337,12 +337,22 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
   if (!is_last) return;
   __threadfence();
   double* out = marr(cd, wo);
-  for (int e = threadIdx.x; e < kGT * kGT; e += blockDim.x) {
+  // 16 outputs per thread, so 16 independent loads are in flight per chunk
+  constexpr int kPer = kGT * kGT / kNT;
+  double sum[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) sum[u] = 0.0;
+  for (int c = 0; c < nkc; ++c) {
+    const double* pc = part + (size_t)c * tile_sz;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) sum[u] += pc[threadIdx.x + u * kNT];
+  }
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = threadIdx.x + u * kNT;
     const int rr = e / kGT, cc = e - rr * kGT;
     const int i = ti * kGT + rr, j = tj * kGT + cc;
-    double s = 0.0;
-    for (int c = 0; c < nkc; ++c) s += load_coherent(part + (size_t)c * tile_sz + e);
-    if (i < na && j < nbb) out[(size_t)i * nbb + j] = s;
+    if (i < na && j < nbb) out[(size_t)i * nbb + j] = sum[u];
   }
   if (threadIdx.x == 0) atomicExch(&cd.tickets[prod * nti * ntj + tile], 0u);
 }
@@ -352,10 +362,12 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
 // with w_j = h_j (projector energies) when use_h, else 1.  Each block stages
 // a 32-column slice of A in LDS, so Y may alias A (in-place rotation).
 constexpr int kRC = 32;
+constexpr int kStageM = 8192;  // stage M in LDS up to 64 KB
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ cds, int y0, int y1,
                                                   int y2, int a0, int a1, int a2, int mat,
-                                                  double alpha, double beta, int use_h) {
+                                                  double alpha, double beta, int use_h,
+                                                  int stage_ok) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
   const int arr = blockIdx.y;
@@ -371,10 +383,16 @@ __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ c
   const double* M = marr(cd, mat);
   extern __shared__ __align__(16) char smem[];
   double* As = (double*)smem;  // [nin][kRC]
+  double* Ms = As + (size_t)nin * kRC;  // [nin][nout] when staged
+  const bool stage_m = stage_ok != 0;  // launch-wide: LDS was sized for it
   for (int e = threadIdx.x; e < nin * kRC; e += blockDim.x) {
     const int j = e / kRC, kk = e - j * kRC;
     const int k = kbase + kk;
     As[e] = k < K ? (double)A[(size_t)j * K + k] : 0.0;
+  }
+  if (stage_m) {
+    for (int e = threadIdx.x; e < nin * nout; e += blockDim.x)
+      Ms[e] = use_h ? cd.hproj[e / nout] * M[e] : M[e];
   }
   __syncthreads();
   const int kk = threadIdx.x % kRC, rg = threadIdx.x / kRC, nrg = blockDim.x / kRC;
@@ -382,7 +400,9 @@ __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ c
   if (k >= K) return;
   for (int i = rg; i < nout; i += nrg) {
     double s = 0.0;
-    if (use_h) {
+    if (stage_m) {
+      for (int j = 0; j < nin; ++j) s = fma(Ms[j * nout + i], As[j * kRC + kk], s);
+    } else if (use_h) {
       for (int j = 0; j < nin; ++j) s = fma(cd.hproj[j] * M[(size_t)j * nout + i], As[j * kRC + kk], s);
     } else {
       for (int j = 0; j < nin; ++j) s = fma(M[(size_t)j * nout + i], As[j * kRC + kk], s);
@@ -640,14 +660,20 @@ void launch_hpsi(const LaunchCtx& L, int src) {
   const BatchGeom& g = L.g;
   const int dst = src == W_X ? W_HX : W_HD;
   dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
+  prof_before("k_z_inverse", L.stream);
   hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, g.sp_chunk);
   check_launch("k_z_inverse");
+  prof_after("k_z_inverse", L.stream);
   dim3 gp(g.N3max, g.npair_max, g.ncand);
+  prof_before("k_plane_hpsi", L.stream);
   hipLaunchKernelGGL(k_plane_hpsi<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
   check_launch("k_plane_hpsi");
+  prof_after("k_plane_hpsi", L.stream);
+  prof_before("k_z_forward", L.stream);
   hipLaunchKernelGGL(k_z_forward<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, dst,
                      g.sp_chunk);
   check_launch("k_z_forward");
+  prof_after("k_z_forward", L.stream);
   if (g.nproj_max > 0) {
     int a[1] = {W_BETA}, b[1] = {src}, o[1] = {M_C};
     launch_gram<T>(L, 1, a, b, o);
@@ -660,12 +686,16 @@ template <typename T>
 void launch_density(const LaunchCtx& L) {
   const BatchGeom& g = L.g;
   dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
+  prof_before("k_z_inverse", L.stream);
   hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, (int)W_X,
                      g.sp_chunk);
   check_launch("k_z_inverse");
+  prof_after("k_z_inverse", L.stream);
   dim3 gp(g.N3max, g.dens_chunks, g.ncand);
+  prof_before("k_plane_density", L.stream);
   hipLaunchKernelGGL(k_plane_density<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
   check_launch("k_plane_density");
+  prof_after("k_plane_density", L.stream);
 }
 
 template <typename T>
@@ -674,10 +704,12 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
   const int rows = std::max(g.nb_max, g.nproj_max);
   const int nt = (rows + kGT - 1) / kGT;
   dim3 grid(nt * nt * g.nkc_max, nprod, g.ncand);
+  prof_before("k_gram", L.stream);
   hipLaunchKernelGGL(k_gram<T>, grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max, a[0],
                      b[0], out[0], nprod > 1 ? a[1] : 0, nprod > 1 ? b[1] : 0,
                      nprod > 1 ? out[1] : 0);
   check_launch("k_gram");
+  prof_after("k_gram", L.stream);
 }
 
 template <typename T>
@@ -686,55 +718,72 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
   const BatchGeom& g = L.g;
   const int rows = std::max(g.nb_max, g.nproj_max);
   dim3 grid((g.K_max + kRC - 1) / kRC, narr, g.ncand);
-  size_t lds = sizeof(double) * (size_t)rows * kRC;
+  const int stage_ok = rows * g.nb_max <= kStageM ? 1 : 0;
+  size_t lds = sizeof(double) * ((size_t)rows * kRC + (size_t)(stage_ok ? rows * g.nb_max : 0));
+  prof_before("k_gemm_acc", L.stream);
   hipLaunchKernelGGL(k_gemm_acc<T>, grid, dim3(kNT), lds, L.stream, L.desc, y[0],
                      narr > 1 ? y[1] : 0, narr > 2 ? y[2] : 0, a[0], narr > 1 ? a[1] : 0,
-                     narr > 2 ? a[2] : 0, mat, alpha, beta, use_h);
+                     narr > 2 ? a[2] : 0, mat, alpha, beta, use_h, stage_ok);
   check_launch("k_gemm_acc");
+  prof_after("k_gemm_acc", L.stream);
 }
 
 template <typename T>
 void launch_cg_direction(const LaunchCtx& L, int first) {
+  prof_before("k_cg_direction", L.stream);
   hipLaunchKernelGGL(k_cg_direction<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, first);
   check_launch("k_cg_direction");
+  prof_after("k_cg_direction", L.stream);
 }
 template <typename T>
 void launch_linemin(const LaunchCtx& L) {
+  prof_before("k_linemin", L.stream);
   hipLaunchKernelGGL(k_linemin<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
   check_launch("k_linemin");
+  prof_after("k_linemin", L.stream);
 }
 template <typename T>
 void launch_band_kinetic(const LaunchCtx& L) {
+  prof_before("k_band_kinetic", L.stream);
   hipLaunchKernelGGL(k_band_kinetic<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc);
   check_launch("k_band_kinetic");
+  prof_after("k_band_kinetic", L.stream);
 }
 template <typename T>
 void launch_init_random(const LaunchCtx& L) {
+  prof_before("k_init_random", L.stream);
   hipLaunchKernelGGL(k_init_random<T>, dim3(8, L.g.nb_max, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc);
   check_launch("k_init_random");
+  prof_after("k_init_random", L.stream);
 }
 template <typename T>
 void launch_setup_beta(const LaunchCtx& L) {
   if (L.g.nproj_max == 0) return;
+  prof_before("k_setup_beta", L.stream);
   hipLaunchKernelGGL(k_setup_beta<T>, dim3(16, L.g.nproj_max, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, L.species);
   check_launch("k_setup_beta");
+  prof_after("k_setup_beta", L.stream);
 }
 template <typename T>
 void launch_force_nonlocal(const LaunchCtx& L) {
   if (L.g.nproj_max == 0) return;
+  prof_before("k_force_nonlocal", L.stream);
   hipLaunchKernelGGL(k_force_nonlocal<T>, dim3(L.g.nproj_max, L.g.nb_max, L.g.ncand), dim3(kNT), 0,
                      L.stream, L.desc);
   check_launch("k_force_nonlocal");
+  prof_after("k_force_nonlocal", L.stream);
 }
 template <typename T>
 void launch_potential_finalize(const LaunchCtx& L) {
+  prof_before("k_potential_finalize", L.stream);
   hipLaunchKernelGGL(k_potential_finalize<T>, dim3((L.g.ntot_max + kNT - 1) / kNT, 1, L.g.ncand),
                      dim3(kNT), 0, L.stream, L.desc);
   check_launch("k_potential_finalize");
+  prof_after("k_potential_finalize", L.stream);
 }
 
 template <typename T>

@@ -21,6 +21,7 @@ struct BatchGeom {
   int dens_chunks;   // band-pair chunks of the density planes
   int ew_ng_max;     // reciprocal Ewald vectors enumerated (box size)
   int ew_nimg_max;
+  int sub_threads;   // threads of the LDS-resident subspace solver
 };
 
 struct LaunchCtx {
@@ -43,7 +44,7 @@ template <typename T> void launch_init_random(const LaunchCtx& L);
 template <typename T> void launch_setup_beta(const LaunchCtx& L);
 template <typename T> void launch_force_nonlocal(const LaunchCtx& L);
 template <typename T> void launch_potential_finalize(const LaunchCtx& L);
-void launch_subspace(const LaunchCtx& L, int mode);
+void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps = 40);
 void launch_occupations(const LaunchCtx& L);
 void launch_grid_fft(const LaunchCtx& L, int sign);
 void launch_density_finalize(const LaunchCtx& L);
@@ -63,5 +64,8 @@ void configure_kernels();
 void allow_lds(const void* kernel);
 // Report a failed launch by kernel name (throws on the host side).
 void check_launch(const char* name);
+// Optional event timing of every launch of one named kernel.
+void prof_before(const char* name, hipStream_t s);
+void prof_after(const char* name, hipStream_t s);
 
 }  // namespace sgo

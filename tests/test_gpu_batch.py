@@ -1,0 +1,82 @@
+"""The batched engine (one launch covers a population of candidates with
+uneven atoms, grids and bands; converged candidates are masked out) against
+the same candidates solved one at a time, and against the oracle."""
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import say, load_golden
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _population():
+    a = workloads.tiny_system("c", ecut=5.0, grid=(18, 18, 18), seed=11)
+    b = workloads.tiny_system("sip", ecut=3.0, grid=(12, 12, 15), seed=12)
+    c = workloads.tiny_system("si", ecut=3.0, grid=(12, 12, 12), seed=13)
+    d = workloads.tiny_system("c", ecut=4.0, grid=(16, 15, 16), seed=14, nbands=11)
+    return [a, b, c, d]
+
+
+def test_batch_equals_individual_fp64():
+    import paper_1603_02732_amd as sgo
+    pop = _population()
+    say("batch of", len(pop), [s["grid"] for s in pop])
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP64)
+    for s in pop:
+        B.add_system(s)
+    opts = sgo.default_opts(tol_e=1e-10, tol_rho=1e-8, max_iter=200)
+    E, F, st = B.scf(opts)
+    assert list(st) == [0] * len(pop)
+    for i, s in enumerate(pop):
+        ctx = sgo.context_from_system(s, sgo.SGO_FP64)
+        ctx.scf(opts)
+        e1, _ = ctx.energy()
+        f1 = ctx.forces()
+        nat = len(s["symbols"])
+        say("  cand %d: batch %.10f single %.10f  iters %d" % (i, E[i], e1, B.info(i)["iterations"]))
+        assert abs(E[i] - e1) / nat < 1e-8
+        assert np.abs(F[i] - f1).max() < 1e-6
+
+
+def test_batch_matches_oracle_small():
+    from oracle.scf import run_scf
+    from oracle.forces import hf_forces
+    import paper_1603_02732_amd as sgo
+    pop = _population()[:2]
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+    for s in pop:
+        B.add_system(s)
+    E, F, st = B.scf(sgo.default_opts(tol_e=1e-7, tol_rho=1e-6, max_iter=200))
+    for i, s in enumerate(pop):
+        r = run_scf(s)
+        Fr, _ = hf_forces(r)
+        nat = len(s["symbols"])
+        dE = abs(E[i] - r["energy"]) / nat
+        dF = np.abs(F[i] - Fr).max()
+        say("  fp32 batch cand %d dE/atom %.2e dF %.2e" % (i, dE, dF))
+        assert dE < 1e-5 and dF < 5e-4
+
+
+def test_c3_population_fp32():
+    import paper_1603_02732_amd as sgo
+    pop = workloads.config_c3()
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+    for s in pop:
+        B.add_system(s)
+    say("C3 population", len(pop))
+    E, F, st = B.scf(sgo.default_opts(tol_e=1e-6, tol_rho=1e-4, max_iter=150))
+    say("  status", list(st), "iters", [B.info(i)["iterations"] for i in range(len(pop))])
+    assert np.all(st == 0)
+    for k in range(2):
+        ref = load_golden("C3-%d" % k)
+        if ref is None:
+            continue
+        dE = abs(E[k] - ref["energy"]) / 13
+        dF = np.abs(F[k] - np.array(ref["forces"])).max()
+        say("  C3-%d dE/atom %.2e dF %.2e" % (k, dE, dF))
+        assert dE < 1e-5 and dF < 5e-4
+    # translation of a candidate by a lattice vector leaves it unchanged
+    for k in range(len(pop)):
+        assert np.all(np.isfinite(F[k]))
+        assert np.abs(F[k].sum(0)).max() < 5e-2
