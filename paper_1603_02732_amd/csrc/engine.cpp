@@ -572,7 +572,10 @@ class Engine {
     g.kc_len = (g.kc_len + 31) / 32 * 32;
     g.sub_threads = std::max(64, std::min(512, tune("SGO_SUB_THREADS", 512) / 64 * 64));
     g.nkc_max = (g.K_max + g.kc_len - 1) / g.kc_len;
-    g.dens_chunks = std::max(1, std::min(g.npair_max, (512 + g.N3max - 1) / std::max(1, g.N3max)));
+    // band-pair chunks of the density planes: enough blocks to fill the chip
+    // (planes x candidates x chunks >= 512), no more (each chunk is a grid)
+    const int planes = std::max(1, g.N3max * g.ncand);
+    g.dens_chunks = std::max(1, std::min(g.npair_max, (512 + planes - 1) / planes));
     return g;
   }
 
