@@ -40,7 +40,7 @@ def parse():
     return ap.parse_args()
 
 
-CANDIDATE_KERNELS = ("k_plane_hpsi", "k_subspace", "k_gram", "k_gemm_acc", "k_z_inverse",
+CANDIDATE_KERNELS = ("k_plane_hpsi", "k_subspace", "k_gram", "k_gram_reduce", "k_gemm_acc", "k_z_inverse",
                      "k_z_forward", "k_cg_direction", "k_linemin", "k_plane_density")
 
 

@@ -48,6 +48,7 @@ struct FftPlan {
 struct CandDesc {
   int N1, N2, N3, ntot;
   int npwh, K, nb, npair;
+  int Kp, pad_kp;   // Kp: row stride of band arrays (K rounded up to 32, zero padded)
   int nsp, nst, nproj, nat;
   int occ_kind, nocc, active, ncand_index;
   double sigma, nelec, omega, pad0;

@@ -75,6 +75,8 @@ void prof_after(const char* name, hipStream_t s) {
   g_prof.used += 2;
 }
 
+void throw_unsupported(const char* what) { throw Error(SGO_EINVAL, what); }
+
 void check_launch(const char* name) {
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess)
@@ -129,7 +131,7 @@ struct HostCand {
   double omega = 0, B[9];
   double nelec = 0;
   int nocc = 0;
-  int npwh = 0, K = 0, nsp = 0, nst = 0, npair = 0, nproj = 0, ntot = 0;
+  int npwh = 0, K = 0, Kp = 0, nsp = 0, nst = 0, npair = 0, nproj = 0, ntot = 0;
   std::vector<int> gmill, gmeta, sp_off, stick_xy, proj_atom, proj_lm;
   std::vector<double> kin, hproj, proj_r;
   FftPlan plan[3];
@@ -356,6 +358,7 @@ class Engine {
     });
     c.npwh = (int)half.size();
     c.K = 2 * c.npwh;
+    c.Kp = (c.K + 31) / 32 * 32;
     if (half.empty() || half[0][1] != 0 || half[0][2] != 0 || half[0][3] != 0)
       throw Error(SGO_EINVAL, "internal: G = 0 must lead the basis");
     c.gmill.resize(3 * c.npwh);
@@ -440,7 +443,7 @@ class Engine {
   void alloc_cand(HostCand& c, const BatchGeom& g) {
     free_cand(c);
     const size_t ts = tsize();
-    const size_t nb = c.nb, K = c.K, nt = c.ntot, nbm = std::max(c.nb, c.nproj);
+    const size_t nb = c.nb, K = c.Kp, nt = c.ntot, nbm = std::max(c.nb, c.nproj);
     const int ntile = (std::max(c.nb, c.nproj) + 63) / 64;
     c.red_doubles = std::max((size_t)kRedSlots, (size_t)2 * ntile * ntile * 32 * 4096);
     c.dens_chunks = g.dens_chunks;
@@ -499,6 +502,7 @@ class Engine {
     d.ntot = c.ntot;
     d.npwh = c.npwh;
     d.K = c.K;
+    d.Kp = c.Kp;
     d.nb = c.nb;
     d.npair = c.npair;
     d.nsp = c.nsp;
@@ -585,7 +589,7 @@ class Engine {
     if (plane > (size_t)g_lds_limit)
       throw Error(SGO_EINVAL, "FFT plane N1*N2 too large for LDS at this precision");
     if (g.plane_max > 48 * kNT) throw Error(SGO_EINVAL, "FFT plane N1*N2 exceeds 12288");
-    if (g.nb_max > 640) throw Error(SGO_EINVAL, "nbands exceeds 640");
+    if (g.nb_max > 320) throw Error(SGO_EINVAL, "nbands exceeds 320");
     if (std::max(g.nb_max, g.nproj_max) > 600) throw Error(SGO_EINVAL, "too many projectors");
   }
 
@@ -779,16 +783,18 @@ class Engine {
     BatchGeom g = prepare(1, kMaxHist);
     LaunchCtx L = ctx(g);
     setup_geometry<T>(L);
-    std::vector<T> v(c.ntot), x((size_t)c.nb * c.K, (T)0);
+    std::vector<T> v(c.ntot), x((size_t)c.nb * c.Kp, (T)0);
     for (int e = 0; e < c.ntot; ++e) v[e] = (T)veff[e];
-    for (size_t e = 0; e < (size_t)nbx * c.K; ++e) x[e] = (T)psi[e];
+    for (int i = 0; i < nbx; ++i)
+      for (int k = 0; k < c.K; ++k) x[(size_t)i * c.Kp + k] = (T)psi[(size_t)i * c.K + k];
     HIPCHK(hipMemcpy(c.d.veff_t, v.data(), c.ntot * sizeof(T), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(c.d.X, x.data(), x.size() * sizeof(T), hipMemcpyHostToDevice));
     launch_hpsi<T>(L, W_X);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(stream_));
     HIPCHK(hipMemcpy(x.data(), c.d.HX, x.size() * sizeof(T), hipMemcpyDeviceToHost));
-    for (size_t e = 0; e < (size_t)nbx * c.K; ++e) hpsi[e] = (double)x[e];
+    for (int i = 0; i < nbx; ++i)
+      for (int k = 0; k < c.K; ++k) hpsi[(size_t)i * c.K + k] = (double)x[(size_t)i * c.Kp + k];
     c.have_psi = false;
     c.have_scf = false;
   }

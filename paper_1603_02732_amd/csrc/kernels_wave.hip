@@ -68,9 +68,9 @@ __global__ void __launch_bounds__(kNT) k_z_inverse(const CandDesc* __restrict__ 
   for (int e = tid; e < nloc * N3; e += nthr) A[e] = {(T)0, (T)0};
   __syncthreads();
   const T* base = warr<T>(cd, src);
-  const T* xa = base + (size_t)(2 * pair) * cd.K;
+  const T* xa = base + (size_t)(2 * pair) * cd.Kp;
   const bool hasb = 2 * pair + 1 < cd.nb;
-  const T* xb = base + (size_t)(2 * pair + 1) * cd.K;
+  const T* xb = base + (size_t)(2 * pair + 1) * cd.Kp;
   const int g0 = cd.sp_off[q0], g1 = cd.sp_off[q1];
   for (int g = g0 + tid; g < g1; g += nthr) {
     const int meta = cd.gmeta[g];
@@ -128,10 +128,10 @@ __global__ void __launch_bounds__(kNT) k_z_forward(const CandDesc* __restrict__ 
   T* ydst = warr<T>(cd, dst);
   const int a = 2 * pair, b = 2 * pair + 1;
   const bool hasb = b < cd.nb;
-  const T* xa = xsrc + (size_t)a * cd.K;
-  const T* xb = xsrc + (size_t)b * cd.K;
-  T* ya = ydst + (size_t)a * cd.K;
-  T* yb = ydst + (size_t)b * cd.K;
+  const T* xa = xsrc + (size_t)a * cd.Kp;
+  const T* xb = xsrc + (size_t)b * cd.Kp;
+  T* ya = ydst + (size_t)a * cd.Kp;
+  T* yb = ydst + (size_t)b * cd.Kp;
   const int g0 = cd.sp_off[q0], g1 = cd.sp_off[q1];
   for (int g = g0 + tid; g < g1; g += nthr) {
     const int meta = cd.gmeta[g];
@@ -264,22 +264,58 @@ __global__ void __launch_bounds__(kNT) k_plane_density(const CandDesc* __restric
   }
 }
 
-// ------------------------------------------------------ split-K Gram product
-// out[i][j] = sum_k A[i][k] B[j][k] (FP64 accumulation) for up to two
-// products per launch.  Each block covers one 64x64 output tile over one K
-// range; the last block of a tile sums the partial tiles in K order.
-constexpr int kGT = 64, kGS = 32;
-template <typename T>
+// ------------------------------------------------ MFMA subspace products
+// FP64 matrix-core products (v_mfma_f64_16x16x4f64): operands are the band
+// arrays converted to FP64 (exact for FP32 data), accumulation in FP64.
+// Fragment layout of one 16x16x4 step, lane l = 16 g + r16 (g = l / 16):
+//   A operand: A[r16][g],  B operand: B[g][r16],  result register r: D[4 r + g][r16].
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void load4(const float* p, bool ok, double* v) {
+  if (ok) {
+    const float4 f = *reinterpret_cast<const float4*>(p);
+    v[0] = f.x;
+    v[1] = f.y;
+    v[2] = f.z;
+    v[3] = f.w;
+  } else {
+    v[0] = v[1] = v[2] = v[3] = 0.0;
+  }
+}
+__device__ __forceinline__ void load4(const double* p, bool ok, double* v) {
+  if (ok) {
+    const double2 a = *reinterpret_cast<const double2*>(p);
+    const double2 b = *reinterpret_cast<const double2*>(p + 2);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = b.x;
+    v[3] = b.y;
+  } else {
+    v[0] = v[1] = v[2] = v[3] = 0.0;
+  }
+}
+
+constexpr int kGT = 64;
+// Split-K Gram product out[i][j] = sum_k A[i][k] B[j][k] for up to two
+// products per launch.  A block covers one (16 TB)^2 output tile over one K
+// range; its four wavefronts take interleaved 16-wide K steps (the loads of
+// the next step are issued before the MFMAs of the current one), each lane
+// loading four consecutive reals of one row (the four MFMAs of a step use
+// one element each, the same k permutation for both operands).  Waves are
+// summed in LDS; each block writes the valid part of its tile to a partial
+// buffer that k_gram_reduce sums in K order.  Rows past the band count are
+// zero.
+template <typename T, int TB>
 __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, int kc_len,
-                                              int nkc_max, int a0, int b0, int o0, int a1, int b1,
-                                              int o1) {
+                                              int nkc_max, int a0, int b0, int a1, int b1) {
+  constexpr int TT = 16 * TB;
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
   const int prod = blockIdx.y;
-  const int wa = prod ? a1 : a0, wb = prod ? b1 : b0, wo = prod ? o1 : o0;
+  const int wa = prod ? a1 : a0, wb = prod ? b1 : b0;
   const int na = wrows(cd, wa), nbb = wrows(cd, wb);
   if (na == 0 || nbb == 0) return;
-  const int nti = (na + kGT - 1) / kGT, ntj = (nbb + kGT - 1) / kGT;
+  const int nti = (na + TT - 1) / TT, ntj = (nbb + TT - 1) / TT;
   const int nkc = (cd.K + kc_len - 1) / kc_len;
   const int kc = blockIdx.x % nkc_max;
   const int tile = blockIdx.x / nkc_max;
@@ -287,87 +323,136 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
   const int ti = tile / ntj, tj = tile - ti * ntj;
   const T* Am = warr<T>(cd, wa);
   const T* Bm = warr<T>(cd, wb);
-  const int K = cd.K;
-  const int k0 = kc * kc_len, k1 = min(K, k0 + kc_len);
-  __shared__ double As[kGT][kGS + 1];
-  __shared__ double Bs[kGT][kGS + 1];
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4];
+  const int Kp = cd.Kp;
+  const int k0 = kc * kc_len, k1 = min(cd.K, k0 + kc_len);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int BI = min(TB, (na - ti * TT + 15) / 16), BJ = min(TB, (nbb - tj * TT + 15) / 16);
+  __shared__ double tileS[TT * TT];
+  for (int e = threadIdx.x; e < TT * TT; e += blockDim.x) tileS[e] = 0.0;
+  dbl4 acc[TB][TB];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int u = 0; u < TB; ++u)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int ks = k0; ks < k1; ks += kGS) {
-    for (int e = threadIdx.x; e < kGT * kGS; e += blockDim.x) {
-      const int rr = e / kGS, kk = e - rr * kGS;
-      const int k = ks + kk;
-      const int ia = ti * kGT + rr, jb = tj * kGT + rr;
-      As[rr][kk] = (ia < na && k < k1) ? (double)Am[(size_t)ia * K + k] : 0.0;
-      Bs[rr][kk] = (jb < nbb && k < k1) ? (double)Bm[(size_t)jb * K + k] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < kGS; ++kk) {
-      double av[4], bv[4];
+    for (int v = 0; v < TB; ++v) acc[u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
+  const T* pa[TB];
+  const T* pb[TB];
+  bool oka[TB], okb[TB];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) av[u] = As[ty + 16 * u][kk];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) bv[v] = Bs[tx + 16 * v][kk];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(av[u], bv[v], acc[u][v]);
-    }
-    __syncthreads();
+  for (int u = 0; u < TB; ++u) {
+    const int ra = ti * TT + u * 16 + r16, rb = tj * TT + u * 16 + r16;
+    oka[u] = u < BI && ra < na;
+    okb[u] = u < BJ && rb < nbb;
+    pa[u] = Am + (size_t)(oka[u] ? ra : 0) * Kp + 4 * g;
+    pb[u] = Bm + (size_t)(okb[u] ? rb : 0) * Kp + 4 * g;
   }
-  // partial tile -> scratch; last block of this tile reduces in K order
-  const size_t tile_sz = (size_t)kGT * kGT;
-  double* part = cd.red_part + ((size_t)prod * nti * ntj + tile) * nkc * tile_sz;
+  double a[TB][4], b[TB][4];
+  int ks = k0 + wave * 16;
+  if (ks < k1) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < TB; ++u) {
+      load4(pa[u] + ks, oka[u], a[u]);
+      load4(pb[u] + ks, okb[u], b[u]);
+    }
+  }
+  while (ks < k1) {
+    const int kn = ks + 64;
+    double an[TB][4], bn[TB][4];
+    if (kn < k1) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) part[(size_t)kc * tile_sz + (ty + 16 * u) * kGT + tx + 16 * v] = acc[u][v];
-  __threadfence();
-  __shared__ int is_last;
-  if (threadIdx.x == 0) {
-    unsigned t = atomicAdd(&cd.tickets[prod * nti * ntj + tile], 1u);
-    is_last = (t == (unsigned)(nkc - 1));
+      for (int u = 0; u < TB; ++u) {
+        load4(pa[u] + kn, oka[u], an[u]);
+        load4(pb[u] + kn, okb[u], bn[u]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int u = 0; u < TB; ++u)
+#pragma unroll
+        for (int v = 0; v < TB; ++v)
+          if (u < BI && v < BJ)
+            acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t], b[v][t], acc[u][v], 0, 0, 0);
+    if (kn < k1) {
+#pragma unroll
+      for (int u = 0; u < TB; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          a[u][t] = an[u][t];
+          b[u][t] = bn[u][t];
+        }
+    }
+    ks = kn;
   }
   __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  double* out = marr(cd, wo);
-  // 16 outputs per thread, so 16 independent loads are in flight per chunk
-  constexpr int kPer = kGT * kGT / kNT;
-  double sum[kPer];
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) sum[u] = 0.0;
-  for (int c = 0; c < nkc; ++c) {
-    const double* pc = part + (size_t)c * tile_sz;
+      for (int u = 0; u < TB; ++u)
 #pragma unroll
-    for (int u = 0; u < kPer; ++u) sum[u] += pc[threadIdx.x + u * kNT];
+        for (int v = 0; v < TB; ++v)
+          if (u < BI && v < BJ)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) tileS[(u * 16 + 4 * r + g) * TT + v * 16 + r16] += acc[u][v][r];
+    }
+    __syncthreads();
   }
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int e = threadIdx.x + u * kNT;
-    const int rr = e / kGT, cc = e - rr * kGT;
-    const int i = ti * kGT + rr, j = tj * kGT + cc;
-    if (i < na && j < nbb) out[(size_t)i * nbb + j] = sum[u];
+  // valid part of the tile -> partial buffer [prod][tile][kc][rows][cols]
+  const int rows = min(TT, na - ti * TT), cols = min(TT, nbb - tj * TT);
+  const size_t tile_sz = (size_t)TT * TT;
+  double* part = cd.red_part + (((size_t)prod * nti * ntj + tile) * nkc + kc) * tile_sz;
+  for (int e = threadIdx.x; e < rows * cols; e += blockDim.x) {
+    const int rr = e / cols, cc = e - rr * cols;
+    part[e] = tileS[rr * TT + cc];
   }
-  if (threadIdx.x == 0) atomicExch(&cd.tickets[prod * nti * ntj + tile], 0u);
 }
 
-// ------------------------------------------------------- rotation products
-// Y[i][k] = alpha Y[i][k] + beta sum_j w_j M[j][i] A[j][k]   (i < nout, j < nin)
-// with w_j = h_j (projector energies) when use_h, else 1.  Each block stages
-// a 32-column slice of A in LDS, so Y may alias A (in-place rotation).
-constexpr int kRC = 32;
-constexpr int kStageM = 8192;  // stage M in LDS up to 64 KB
-template <typename T>
+// Sum of the split-K partial tiles in K order: one thread per output entry.
+template <int TB>
+__global__ void __launch_bounds__(kNT) k_gram_reduce(const CandDesc* __restrict__ cds, int kc_len,
+                                                     int a0, int b0, int o0, int a1, int b1,
+                                                     int o1) {
+  constexpr int TT = 16 * TB;
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int prod = blockIdx.y;
+  const int wa = prod ? a1 : a0, wb = prod ? b1 : b0, wo = prod ? o1 : o0;
+  const int na = wrows(cd, wa), nbb = wrows(cd, wb);
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= na * nbb) return;
+  const int i = e / nbb, j = e - i * nbb;
+  const int nti = (na + TT - 1) / TT, ntj = (nbb + TT - 1) / TT;
+  const int ti = i / TT, tj = j / TT;
+  const int tile = ti * ntj + tj;
+  const int rows = min(TT, na - ti * TT), cols = min(TT, nbb - tj * TT);
+  (void)rows;
+  const int nkc = (cd.K + kc_len - 1) / kc_len;
+  const size_t tile_sz = (size_t)TT * TT;
+  const double* part = cd.red_part + ((size_t)prod * nti * ntj + tile) * nkc * tile_sz +
+                       (i - ti * TT) * cols + (j - tj * TT);
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int c = 0;
+  for (; c + 3 < nkc; c += 4) {
+    s0 += part[(size_t)c * tile_sz];
+    s1 += part[(size_t)(c + 1) * tile_sz];
+    s2 += part[(size_t)(c + 2) * tile_sz];
+    s3 += part[(size_t)(c + 3) * tile_sz];
+  }
+  for (; c < nkc; ++c) s0 += part[(size_t)c * tile_sz];
+  marr(cd, wo)[(size_t)i * nbb + j] = (s0 + s1) + (s2 + s3);
+}
+
+// Band-space product on 64-column slices:
+//   Y[i][k] = alpha Y[i][k] + beta sum_j w_j M[j][i] A[j][k]   (i < nout, j < nin)
+// w_j = h_j (projector energies) when use_h, else 1.  Each block owns all
+// rows of its 64 columns, so Y may alias A (in-place rotation): the block
+// reads every A row of its slice (through LDS, 32 rows at a time) before it
+// writes.  Wave w holds the output rows 16 (w + 4 m) .. +16, m < IBW.
+constexpr int kJC = 32;
+template <typename T, int IBW>
 __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ cds, int y0, int y1,
                                                   int y2, int a0, int a1, int a2, int mat,
-                                                  double alpha, double beta, int use_h,
-                                                  int stage_ok) {
+                                                  double alpha, double beta, int use_h) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
   const int arr = blockIdx.y;
@@ -375,41 +460,78 @@ __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ c
   const int wa = arr == 0 ? a0 : (arr == 1 ? a1 : a2);
   const int nin = wrows(cd, wa), nout = wrows(cd, wy);
   if (nin == 0) return;
-  const int K = cd.K;
-  const int kbase = blockIdx.x * kRC;
-  if (kbase >= K) return;
+  const int Kp = cd.Kp;
+  const int kbase = blockIdx.x * 64;
+  if (kbase >= cd.K) return;
   const T* A = warr<T>(cd, wa);
   T* Y = warr<T>(cd, wy);
   const double* M = marr(cd, mat);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r16 = lane & 15, g = lane >> 4;
+  const int nib = (nout + 15) / 16;
   extern __shared__ __align__(16) char smem[];
-  double* As = (double*)smem;  // [nin][kRC]
-  double* Ms = As + (size_t)nin * kRC;  // [nin][nout] when staged
-  const bool stage_m = stage_ok != 0;  // launch-wide: LDS was sized for it
-  for (int e = threadIdx.x; e < nin * kRC; e += blockDim.x) {
-    const int j = e / kRC, kk = e - j * kRC;
-    const int k = kbase + kk;
-    As[e] = k < K ? (double)A[(size_t)j * K + k] : 0.0;
-  }
-  if (stage_m) {
-    for (int e = threadIdx.x; e < nin * nout; e += blockDim.x)
-      Ms[e] = use_h ? cd.hproj[e / nout] * M[e] : M[e];
-  }
-  __syncthreads();
-  const int kk = threadIdx.x % kRC, rg = threadIdx.x / kRC, nrg = blockDim.x / kRC;
-  const int k = kbase + kk;
-  if (k >= K) return;
-  for (int i = rg; i < nout; i += nrg) {
-    double s = 0.0;
-    if (stage_m) {
-      for (int j = 0; j < nin; ++j) s = fma(Ms[j * nout + i], As[j * kRC + kk], s);
-    } else if (use_h) {
-      for (int j = 0; j < nin; ++j) s = fma(cd.hproj[j] * M[(size_t)j * nout + i], As[j * kRC + kk], s);
-    } else {
-      for (int j = 0; j < nin; ++j) s = fma(M[(size_t)j * nout + i], As[j * kRC + kk], s);
+  double* As = (double*)smem;            // [kJC][64]
+  double* Ms = As + kJC * 64;            // [kJC][nib*16]
+  const int ldm = nib * 16;
+  dbl4 acc[IBW][4];
+#pragma unroll
+  for (int m = 0; m < IBW; ++m)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[m][v] = dbl4{0.0, 0.0, 0.0, 0.0};
+  for (int j0 = 0; j0 < nin; j0 += kJC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kJC * 64; e += blockDim.x) {
+      const int jj = e >> 6, kk = e & 63;
+      const int j = j0 + jj, k = kbase + kk;
+      As[e] = (j < nin && k < Kp) ? (double)A[(size_t)j * Kp + k] : 0.0;
     }
-    const size_t idx = (size_t)i * K + k;
-    const double yo = alpha != 0.0 ? (double)Y[idx] : 0.0;
-    Y[idx] = (T)(alpha * yo + beta * s);
+    for (int e = threadIdx.x; e < kJC * ldm; e += blockDim.x) {
+      const int jj = e / ldm, i = e - jj * ldm;
+      const int j = j0 + jj;
+      double m = 0.0;
+      if (j < nin && i < nout) {
+        m = M[(size_t)j * nout + i];
+        if (use_h) m *= cd.hproj[j];
+      }
+      Ms[e] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j4 = 0; j4 < kJC / 4; ++j4) {
+      const int jr = 4 * j4 + g;
+      double bop[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) bop[v] = As[jr * 64 + v * 16 + r16];
+#pragma unroll
+      for (int m = 0; m < IBW; ++m) {
+        const int ib = wave + 4 * m;
+        if (ib < nib) {
+          const double aop = Ms[jr * ldm + ib * 16 + r16];
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            acc[m][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[v], acc[m][v], 0, 0, 0);
+        }
+      }
+    }
+  }
+  __syncthreads();  // every read of A in this slice precedes the writes
+#pragma unroll
+  for (int m = 0; m < IBW; ++m) {
+    const int ib = wave + 4 * m;
+    if (ib >= nib) continue;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int k = kbase + v * 16 + r16;
+      if (k >= cd.K) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ib * 16 + 4 * r + g;
+        if (i >= nout) continue;
+        const size_t idx = (size_t)i * Kp + k;
+        const double yo = alpha != 0.0 ? (double)Y[idx] : 0.0;
+        Y[idx] = (T)(alpha * yo + beta * acc[m][v][r]);
+      }
+    }
   }
 }
 
@@ -430,9 +552,9 @@ __global__ void __launch_bounds__(kNT) k_cg_direction(const CandDesc* __restrict
   if (i >= cd.nb) return;
   __shared__ double sh[16 * 2];
   const int K = cd.K;
-  const T* x = (const T*)cd.X + (size_t)i * K;
-  const T* hx = (const T*)cd.HX + (size_t)i * K;
-  T* d = (T*)cd.D + (size_t)i * K;
+  const T* x = (const T*)cd.X + (size_t)i * cd.Kp;
+  const T* hx = (const T*)cd.HX + (size_t)i * cd.Kp;
+  T* d = (T*)cd.D + (size_t)i * cd.Kp;
   double v1[1] = {0.0};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double xv = (double)x[k];
@@ -473,10 +595,10 @@ __global__ void __launch_bounds__(kNT) k_linemin(const CandDesc* __restrict__ cd
   if (i >= cd.nb) return;
   __shared__ double sh[16 * 4];
   const int K = cd.K;
-  T* x = (T*)cd.X + (size_t)i * K;
-  T* hx = (T*)cd.HX + (size_t)i * K;
-  const T* d = (const T*)cd.D + (size_t)i * K;
-  const T* hd = (const T*)cd.HD + (size_t)i * K;
+  T* x = (T*)cd.X + (size_t)i * cd.Kp;
+  T* hx = (T*)cd.HX + (size_t)i * cd.Kp;
+  const T* d = (const T*)cd.D + (size_t)i * cd.Kp;
+  const T* hd = (const T*)cd.HD + (size_t)i * cd.Kp;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double xv = x[k], hxv = hx[k], dv = d[k], hdv = hd[k];
@@ -508,7 +630,7 @@ __global__ void __launch_bounds__(kNT) k_band_kinetic(const CandDesc* __restrict
   const int i = blockIdx.x;
   if (i >= cd.nb) return;
   __shared__ double sh[16];
-  const T* x = (const T*)cd.X + (size_t)i * cd.K;
+  const T* x = (const T*)cd.X + (size_t)i * cd.Kp;
   double v[1] = {0.0};
   for (int k = threadIdx.x; k < cd.K; k += blockDim.x) {
     const double xv = x[k];
@@ -539,8 +661,8 @@ __global__ void k_init_random(const CandDesc* __restrict__ cds) {
     h = mix64(h);
     const double u = (double)(h >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
     const double v = k == 1 ? 0.0 : u / (1.0 + cd.kin[k >> 1]);
-    ((T*)cd.X)[(size_t)i * cd.K + k] = (T)v;
-    ((T*)cd.D)[(size_t)i * cd.K + k] = (T)0;
+    ((T*)cd.X)[(size_t)i * cd.Kp + k] = (T)v;
+    ((T*)cd.D)[(size_t)i * cd.Kp + k] = (T)0;
   }
 }
 
@@ -558,7 +680,7 @@ __global__ void k_setup_beta(const CandDesc* __restrict__ cds, const SpeciesDev*
   const double R0 = cd.pos[3 * I], R1 = cd.pos[3 * I + 1], R2 = cd.pos[3 * I + 2];
   const double inv_sqrt_omega = 1.0 / sqrt(cd.omega);
   const double pi = 3.14159265358979323846;
-  T* out = (T*)cd.beta + (size_t)p * cd.K;
+  T* out = (T*)cd.beta + (size_t)p * cd.Kp;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < cd.npwh; g += gridDim.x * blockDim.x) {
     const double m1 = cd.gmill[3 * g], m2 = cd.gmill[3 * g + 1], m3 = cd.gmill[3 * g + 2];
     const double G0 = m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6];
@@ -604,8 +726,8 @@ __global__ void __launch_bounds__(kNT) k_force_nonlocal(const CandDesc* __restri
   const int p = blockIdx.x, i = blockIdx.y;
   if (p >= cd.nproj || i >= cd.nb) return;
   __shared__ double sh[16 * 4];
-  const T* b = (const T*)cd.beta + (size_t)p * cd.K;
-  const T* x = (const T*)cd.X + (size_t)i * cd.K;
+  const T* b = (const T*)cd.beta + (size_t)p * cd.Kp;
+  const T* x = (const T*)cd.X + (size_t)i * cd.Kp;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int g = threadIdx.x; g < cd.npwh; g += blockDim.x) {
     const double br = b[2 * g], bi = b[2 * g + 1], xr = x[2 * g], xi = x[2 * g + 1];
@@ -702,14 +824,31 @@ template <typename T>
 void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, const int* out) {
   const BatchGeom& g = L.g;
   const int rows = std::max(g.nb_max, g.nproj_max);
-  const int nt = (rows + kGT - 1) / kGT;
+  const int a1 = nprod > 1 ? a[1] : 0, b1 = nprod > 1 ? b[1] : 0, o1 = nprod > 1 ? out[1] : 0;
+  // 32x32 tiles when every product fits one (fewer registers, more waves)
+  const int TB = rows <= 32 ? 2 : 4;
+  const int TT = 16 * TB;
+  const int nt = (rows + TT - 1) / TT;
   dim3 grid(nt * nt * g.nkc_max, nprod, g.ncand);
+  dim3 rgrid((rows * rows + kNT - 1) / kNT, nprod, g.ncand);
   prof_before("k_gram", L.stream);
-  hipLaunchKernelGGL(k_gram<T>, grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max, a[0],
-                     b[0], out[0], nprod > 1 ? a[1] : 0, nprod > 1 ? b[1] : 0,
-                     nprod > 1 ? out[1] : 0);
+  if (TB == 2)
+    hipLaunchKernelGGL((k_gram<T, 2>), grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max,
+                       a[0], b[0], a1, b1);
+  else
+    hipLaunchKernelGGL((k_gram<T, 4>), grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max,
+                       a[0], b[0], a1, b1);
   check_launch("k_gram");
   prof_after("k_gram", L.stream);
+  prof_before("k_gram_reduce", L.stream);
+  if (TB == 2)
+    hipLaunchKernelGGL((k_gram_reduce<2>), rgrid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, a[0],
+                       b[0], out[0], a1, b1, o1);
+  else
+    hipLaunchKernelGGL((k_gram_reduce<4>), rgrid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, a[0],
+                       b[0], out[0], a1, b1, o1);
+  check_launch("k_gram_reduce");
+  prof_after("k_gram_reduce", L.stream);
 }
 
 template <typename T>
@@ -717,13 +856,24 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
                      double alpha, double beta, int use_h) {
   const BatchGeom& g = L.g;
   const int rows = std::max(g.nb_max, g.nproj_max);
-  dim3 grid((g.K_max + kRC - 1) / kRC, narr, g.ncand);
-  const int stage_ok = rows * g.nb_max <= kStageM ? 1 : 0;
-  size_t lds = sizeof(double) * ((size_t)rows * kRC + (size_t)(stage_ok ? rows * g.nb_max : 0));
+  const int nib = (g.nb_max + 15) / 16;  // outputs are always band rows
+  dim3 grid((g.K_max + 63) / 64, narr, g.ncand);
+  size_t lds = sizeof(double) * ((size_t)kJC * 64 + (size_t)kJC * nib * 16);
+  (void)rows;
+  const int y1 = narr > 1 ? y[1] : 0, y2 = narr > 2 ? y[2] : 0;
+  const int a1 = narr > 1 ? a[1] : 0, a2 = narr > 2 ? a[2] : 0;
   prof_before("k_gemm_acc", L.stream);
-  hipLaunchKernelGGL(k_gemm_acc<T>, grid, dim3(kNT), lds, L.stream, L.desc, y[0],
-                     narr > 1 ? y[1] : 0, narr > 2 ? y[2] : 0, a[0], narr > 1 ? a[1] : 0,
-                     narr > 2 ? a[2] : 0, mat, alpha, beta, use_h, stage_ok);
+  if (nib <= 4)
+    hipLaunchKernelGGL((k_gemm_acc<T, 1>), grid, dim3(kNT), lds, L.stream, L.desc, y[0], y1, y2,
+                       a[0], a1, a2, mat, alpha, beta, use_h);
+  else if (nib <= 8)
+    hipLaunchKernelGGL((k_gemm_acc<T, 2>), grid, dim3(kNT), lds, L.stream, L.desc, y[0], y1, y2,
+                       a[0], a1, a2, mat, alpha, beta, use_h);
+  else if (nib <= 20)
+    hipLaunchKernelGGL((k_gemm_acc<T, 5>), grid, dim3(kNT), lds, L.stream, L.desc, y[0], y1, y2,
+                       a[0], a1, a2, mat, alpha, beta, use_h);
+  else
+    throw_unsupported("more than 320 bands in the rotation kernel");
   check_launch("k_gemm_acc");
   prof_after("k_gemm_acc", L.stream);
 }
@@ -792,7 +942,9 @@ static void configure_t() {
   allow_lds((const void*)k_z_forward<T>);
   allow_lds((const void*)k_plane_hpsi<T>);
   allow_lds((const void*)k_plane_density<T>);
-  allow_lds((const void*)k_gemm_acc<T>);
+  allow_lds((const void*)k_gemm_acc<T, 1>);
+  allow_lds((const void*)k_gemm_acc<T, 2>);
+  allow_lds((const void*)k_gemm_acc<T, 5>);
 }
 void configure_wave() {
   configure_t<float>();

@@ -64,6 +64,8 @@ void configure_kernels();
 void allow_lds(const void* kernel);
 // Report a failed launch by kernel name (throws on the host side).
 void check_launch(const char* name);
+// Reject a launch shape the kernels do not support (throws on the host side).
+void throw_unsupported(const char* what);
 // Optional event timing of every launch of one named kernel.
 void prof_before(const char* name, hipStream_t s);
 void prof_after(const char* name, hipStream_t s);
