@@ -238,6 +238,14 @@ int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, doub
 int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info);
 /* Drop the warm-start wavefunctions of every candidate (next solve is cold). */
 int sgo_batch_reset(sgo_batch* b);
+/* Read back the state of candidate i after sgo_batch_scf (each pointer may be
+ * NULL): sizes info[10] as in sgo_grid_info; Miller indices [npw_half*3] of
+ * its basis; bands psi [nbands][2*npw_half] in the packed layout described at
+ * sgo_basis_millers (FP64 copies of the stored precision), eigenvalues and
+ * occupations [nbands]; output density rho and input potential veff
+ * [N3][N2][N1]; energy terms. */
+int sgo_batch_get_state(sgo_batch* b, int i, int* info, int* millers, double* psi, double* eig,
+                        double* occ, double* rho, double* veff, sgo_energy_terms* terms);
 int sgo_batch_size(sgo_batch* b, int* n);
 const char* sgo_batch_last_error(const sgo_batch* b);
 

@@ -107,6 +107,8 @@ def load_library(path=None):
         "sgo_batch_info": (I, [P, I, ctypes.POINTER(sgo_scf_info)]),
         "sgo_batch_size": (I, [P, ip]),
         "sgo_batch_reset": (I, [P]),
+        "sgo_batch_get_state": (I, [P, I, ip, ip, dp, dp, dp, dp, dp,
+                                    ctypes.POINTER(sgo_energy_terms)]),
         "sgo_batch_last_error": (ctypes.c_char_p, [P]),
     }
     for name, (res, args) in sig.items():
@@ -202,6 +204,7 @@ class Context:
         p = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
         self._check(self._lib.sgo_set_atoms(self._h, len(s), _iptr(s), _dptr(p)))
         self.natoms = len(s)
+        self.atom_species = s.copy()
 
     def set_cutoff(self, ecut, grid, nbands, occ_kind=SGO_OCC_FIXED, sigma=0.0):
         g = np.ascontiguousarray(grid, dtype=np.int32)
@@ -403,6 +406,27 @@ class Batch:
 
     def reset(self):
         self._check(self._lib.sgo_batch_reset(self._h))
+
+    def state(self, i):
+        """Converged state of candidate i: sizes, Miller indices, packed bands,
+        eigenvalues, occupations, density, V_eff (both [z][y][x]) and energy terms."""
+        info = np.zeros(10, dtype=np.int32)
+        self._check(self._lib.sgo_batch_get_state(self._h, int(i), _iptr(info), None, None, None,
+                                                  None, None, None, None))
+        N1, N2, N3, ntot, nh, nb = (int(x) for x in info[:6])
+        m = np.zeros((nh, 3), dtype=np.int32)
+        psi = np.zeros((nb, 2 * nh))
+        eig = np.zeros(nb)
+        occ = np.zeros(nb)
+        rho = np.zeros(ntot)
+        veff = np.zeros(ntot)
+        t = sgo_energy_terms()
+        self._check(self._lib.sgo_batch_get_state(self._h, int(i), None, _iptr(m), _dptr(psi),
+                                                  _dptr(eig), _dptr(occ), _dptr(rho),
+                                                  _dptr(veff), ctypes.byref(t)))
+        return {"grid": (N1, N2, N3), "millers": m, "psi": psi, "eig": eig, "occ": occ,
+                "rho": rho.reshape(N3, N2, N1), "veff": veff.reshape(N3, N2, N1),
+                "terms": {n: getattr(t, n) for n, _ in sgo_energy_terms._fields_}}
 
     def info(self, i):
         inf = sgo_scf_info()

@@ -850,6 +850,49 @@ class Engine {
   }
   int precision() const { return prec_; }
 
+  // Host copy of candidate i's state (FP64); any pointer may be null.
+  void get_state(int i, int* info, int* millers, double* psi, double* eig, double* occ,
+                 double* rho, double* veff, sgo_energy_terms* t) {
+    HostCand& c = cand(i);
+    if (info) {
+      const int v[10] = {c.N[0], c.N[1], c.N[2], c.ntot, c.npwh, c.nb, c.npair, c.nst, c.nsp, c.nproj};
+      std::memcpy(info, v, sizeof(v));
+    }
+    if (millers) std::memcpy(millers, c.gmill.data(), c.gmill.size() * sizeof(int));
+    if (!(psi || eig || occ || rho || veff || t)) return;
+    require_scf(c);
+    HIPCHK(hipSetDevice(device_));
+    if (psi) {
+      const size_t ts = tsize();
+      std::vector<char> raw((size_t)c.nb * c.Kp * ts);
+      HIPCHK(hipMemcpy(raw.data(), c.d.X, raw.size(), hipMemcpyDeviceToHost));
+      for (int b = 0; b < c.nb; ++b)
+        for (int k = 0; k < c.K; ++k) {
+          const size_t e = (size_t)b * c.Kp + k;
+          psi[(size_t)b * c.K + k] = prec_ == SGO_FP64 ? ((const double*)raw.data())[e]
+                                                       : (double)((const float*)raw.data())[e];
+        }
+    }
+    if (eig) HIPCHK(hipMemcpy(eig, c.d.eps, c.nb * 8, hipMemcpyDeviceToHost));
+    if (occ) HIPCHK(hipMemcpy(occ, c.d.occ, c.nb * 8, hipMemcpyDeviceToHost));
+    if (rho) HIPCHK(hipMemcpy(rho, c.d.rho_out_r, c.ntot * 8, hipMemcpyDeviceToHost));
+    if (veff) HIPCHK(hipMemcpy(veff, c.d.veff_r, c.ntot * 8, hipMemcpyDeviceToHost));
+    if (t) {
+      double s[S_COUNT];
+      HIPCHK(hipMemcpy(s, c.d.scal, S_COUNT * 8, hipMemcpyDeviceToHost));
+      t->total = s[S_ETOT];
+      t->kinetic = s[S_EKIN];
+      t->nonlocal = s[S_ENL];
+      t->local = s[S_ELOC];
+      t->hartree = s[S_EH];
+      t->xc = s[S_EXC];
+      t->ewald = s[S_EEW];
+      t->entropy = s[S_ENTROPY_TERM];
+      t->band = s[S_EBAND];
+      t->fermi = s[S_MU];
+    }
+  }
+
  private:
   int device_, prec_, capacity_;
   hipStream_t stream_ = nullptr;
@@ -1393,6 +1436,15 @@ int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info) {
   return guard(&b->err, [&] {
     if (!info) throw Error(SGO_EINVAL, "NULL info");
     *info = b->eng->cand(i).info;
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_get_state(sgo_batch* b, int i, int* info, int* millers, double* psi, double* eig,
+                        double* occ, double* rho, double* veff, sgo_energy_terms* terms) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    b->eng->get_state(i, info, millers, psi, eig, occ, rho, veff, terms);
     return SGO_OK;
   });
 }

@@ -50,3 +50,48 @@ def load_golden(name):
         return None
     with open(path) as f:
         return json.load(f)
+
+
+def full_coefficients(psi, millers_gpu, oracle_millers):
+    """Packed half-sphere bands (nb, 2*nh) -> full complex coefficients (npw, nb)."""
+    pos, neg = half_to_full_index(millers_gpu, oracle_millers)
+    h = (psi[:, 0::2] + 1j * psi[:, 1::2]) / np.sqrt(2)
+    h[:, 0] = psi[:, 0]
+    C = np.zeros((len(oracle_millers), psi.shape[0]), dtype=complex)
+    C[neg] = np.conj(h.T)
+    C[pos] = h.T
+    return C
+
+
+def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say):
+    """Hand the GPU's converged state (bands, occupations, density, V_eff) to
+    the oracle and recompute, in FP64 with the oracle's own arithmetic: the
+    density from the bands, every energy term, the Hellmann-Feynman forces and
+    the eigen-residual under the oracle's Hamiltonian at V_eff."""
+    from oracle.hamiltonian import Setup
+    from oracle.scf import energy_terms, occupations
+    from oracle.forces import hf_forces
+    st = Setup(system)
+    C = full_coefficients(stt["psi"], stt["millers"], st.millers)
+    f = stt["occ"]
+    rho = np.transpose(stt["rho"], (2, 1, 0))
+    veff = np.transpose(stt["veff"], (2, 1, 0))
+    rho_o = st.density(C, f)
+    d_rho = np.abs(rho_o - rho).max() / np.abs(rho).max()
+    occ = system["occupation"]
+    _, _, S = occupations(stt["eig"], st.nelec, occ)
+    terms = energy_terms(st, C, f, rho, S, float(occ.get("sigma", 0.0)))
+    out = {"density": d_rho}
+    for k in ("kinetic", "nonlocal", "local", "hartree", "xc", "ewald"):
+        out[k] = abs(terms[k] - stt["terms"][k]) / max(1.0, abs(terms[k]))
+    F_o, _ = hf_forces({"setup": st, "rho": rho, "C": C, "occupations": f})
+    out["forces"] = np.abs(F_o - forces).max()
+    HC = st.apply_h(veff, C)
+    res = np.linalg.norm(HC - C * stt["eig"][None, :], axis=0)
+    out["residual_charged"] = res[f > 1e-2].max()
+    say("  oracle check of GPU state: " + "  ".join("%s %.1e" % kv for kv in out.items()))
+    assert d_rho < e_rtol
+    for k in ("kinetic", "nonlocal", "local", "hartree", "xc", "ewald"):
+        assert out[k] < e_rtol, k
+    assert out["forces"] < f_tol
+    return out

@@ -1,0 +1,60 @@
+"""The energy as a torch.autograd.Function: its backward (the library's
+Hellmann-Feynman adjoint) against central finite differences of the same
+energy (h = 1e-3 bohr) and against the oracle's forces."""
+import copy
+
+import numpy as np
+import pytest
+
+from tests.gpu_helpers import say, load_golden
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _sheet_small():
+    lat, pos = workloads.sheet_random(8, 8.0, 8.0, 10.0, 2.4, 21)
+    return workloads.make_system("sheet8", lat, ["C-G"] * 8, pos, 8.0, (24, 24, 30), 20,
+                                 {"kind": "fermi", "sigma": 0.01}, "fp64")
+
+
+def test_autograd_matches_finite_differences_fp64():
+    import torch
+    import paper_1603_02732_amd as sgo
+    from paper_1603_02732_amd.autograd import ScfEnergy
+    s = _sheet_small()
+    ctx = sgo.context_from_system(s, sgo.SGO_FP64)
+    opts = sgo.default_opts(tol_e=1e-12, tol_rho=1e-9, max_iter=300)
+    R = torch.tensor(np.array(s["positions"]), dtype=torch.float64, requires_grad=True)
+    E = ScfEnergy.apply(R, ctx, opts)
+    (g,) = torch.autograd.grad(2.5 * E, R)
+    h = 1e-3
+    for I, a in [(0, 0), (3, 1), (5, 2), (7, 0)]:
+        e = []
+        for sg in (1, -1):
+            Rp = R.detach().clone()
+            Rp[I, a] += sg * h
+            e.append(float(ScfEnergy.apply(Rp, ctx, opts)))
+        fd = 2.5 * (e[0] - e[1]) / (2 * h)
+        say("atom %d axis %d: autograd %.8f  FD %.8f" % (I, a, float(g[I, a]), fd))
+        assert abs(float(g[I, a]) - fd) < 1e-5
+
+
+def test_autograd_fp32_sheet_matches_oracle_forces():
+    import torch
+    import paper_1603_02732_amd as sgo
+    from paper_1603_02732_amd.autograd import ScfEnergy
+    ref = load_golden("C2")
+    if ref is None:
+        pytest.skip("C2 oracle reference not generated")
+    s = workloads.config_c2()
+    ctx = sgo.context_from_system(s, sgo.SGO_FP32)
+    opts = sgo.default_opts(tol_e=1e-8, tol_rho=1e-6, max_iter=200)
+    R = torch.tensor(np.array(s["positions"]), dtype=torch.float64, requires_grad=True)
+    E = ScfEnergy.apply(R, ctx, opts)
+    E.backward()
+    dF = np.abs(-R.grad.numpy() - np.array(ref["forces"])).max()
+    say("C2 fp32 adjoint vs oracle forces: max dF %.2e, dE/atom %.2e"
+        % (dF, abs(float(E) - ref["energy"]) / 24))
+    assert dF < 5e-4
+    assert abs(float(E) - ref["energy"]) / 24 < 1e-5
