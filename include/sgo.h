@@ -207,6 +207,18 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
                        double* M, double* eps, int reps, double* ms_per_call,
                        long long* clocks);
 
+/* Launch-schedule tuning (process-wide; read when a solve starts).  Keys:
+ * "SGO_GRAM_KC" (K range of one split-K Gram block, multiple of 32),
+ * "SGO_SUB_THREADS" (threads of the subspace solver, 64..512),
+ * "SGO_SP_CHUNK" (stick pairs per block of the z transforms),
+ * "SGO_DENS_CHUNKS" (band-pair chunks of the density planes),
+ * "SGO_RR_SWEEPS" (Jacobi sweeps of the intermediate subspace steps).
+ * value <= 0 restores the default (or the environment variable of the same
+ * name).  SGO_EINVAL for an unknown key.  sgo_get_tuning returns the value
+ * set (0 if none). */
+int sgo_set_tuning(const char* key, int value);
+int sgo_get_tuning(const char* key);
+
 /* Measurement hooks (process-wide): from sgo_profile_begin until
  * sgo_profile_end, every launch of the kernel named `kernel` (for example
  * "k_plane_hpsi") is bracketed by a pair of HIP events recorded on the stream

@@ -93,6 +93,8 @@ def load_library(path=None):
         "sgo_get_density": (I, [P, dp, dp]),
         "sgo_last_error": (ctypes.c_char_p, [P]),
         "sgo_grid_info": (I, [P, ip]),
+        "sgo_set_tuning": (I, [ctypes.c_char_p, I]),
+        "sgo_get_tuning": (I, [ctypes.c_char_p]),
         "sgo_subspace_solve": (I, [I, I, I, dp, dp, dp, dp, I, dp,
                                    ctypes.POINTER(ctypes.c_longlong)]),
         "sgo_profile_begin": (I, [ctypes.c_char_p]),
@@ -313,6 +315,17 @@ def subspace_solve(S, H=None, mode=3, reps=1, device=0, clocks=False):
     if rc != SGO_OK:
         raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
     return M, eps, ms.value, list(clk) if clocks else None
+
+
+def set_tuning(key, value):
+    """Set a launch-schedule parameter (see sgo.h); value <= 0 restores the default."""
+    rc = load_library().sgo_set_tuning(key.encode(), int(value))
+    if rc != SGO_OK:
+        raise SgoError(rc, "unknown tuning key %r" % key)
+
+
+def get_tuning(key):
+    return load_library().sgo_get_tuning(key.encode())
 
 
 def profile_begin(kernel):

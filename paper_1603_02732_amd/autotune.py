@@ -1,0 +1,107 @@
+"""Autotuner of the launch schedule.
+
+For a given population (a `Batch` already loaded with its candidates) it
+times a fixed number of SCF iterations of the real workload under each
+candidate value of one schedule parameter at a time (coordinate descent over
+the Gram K range, subspace-solver threads, stick pairs per z block, density
+chunks and graph replay), keeps the fastest, and caches the winning schedule
+in a JSON file keyed by (device architecture, candidate shapes, precision).
+A later call with the same key applies the cached schedule without timing.
+
+Timing uses wall time around complete synchronous solves of `iters`
+iterations (the library synchronises its stream before returning).
+"""
+import hashlib
+import json
+import os
+import time
+
+from . import set_tuning, default_opts, SGO_ENOTCONV
+
+SPACE = {
+    "SGO_GRAM_KC": [256, 512, 1024, 2048],
+    "SGO_SUB_THREADS": [128, 256, 512],
+    "SGO_SP_CHUNK": [4, 8, 13, 20, 32],
+    "SGO_DENS_CHUNKS": [1, 2, 4],
+    "use_graph": [0, 1],
+}
+
+
+def cache_path():
+    return os.environ.get("SGO_AUTOTUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "sgo", "autotune.json"))
+
+
+def key_of(systems, precision, arch="gfx950"):
+    shape = [(tuple(s["grid"]), int(s["nbands"]), len(s["symbols"])) for s in systems]
+    h = hashlib.sha1(json.dumps([arch, precision, shape]).encode()).hexdigest()[:16]
+    return "%s-%s-n%d-%s" % (arch, "fp64" if precision == 0 else "fp32", len(systems), h)
+
+
+def _time(batch, opts, reps=2):
+    best = float("inf")
+    for _ in range(reps):
+        batch.reset()
+        t0 = time.perf_counter()
+        batch.scf(opts)
+        best = min(best, time.perf_counter() - t0)
+    return best
+
+
+def apply(schedule):
+    for k, v in schedule.items():
+        if k != "use_graph":
+            set_tuning(k, v)
+
+
+def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False):
+    """Returns the schedule (dict) and applies it.  `use_graph` in the result
+    is for the caller's solve options."""
+    key = key_of(systems, precision)
+    path = cache_path()
+    cache = {}
+    if use_cache and os.path.exists(path):
+        try:
+            cache = json.load(open(path))
+        except (OSError, ValueError):
+            cache = {}
+    if use_cache and key in cache:
+        apply(cache[key]["schedule"])
+        return dict(cache[key]["schedule"], cached=True)
+    sched = {"SGO_GRAM_KC": 0, "SGO_SUB_THREADS": 0, "SGO_SP_CHUNK": 0, "SGO_DENS_CHUNKS": 0,
+             "use_graph": 1}
+    apply(sched)
+
+    def opts():
+        # a fixed number of iterations: the stop tests can never be met
+        return default_opts(tol_e=-1.0, tol_rho=-1.0, max_iter=iters,
+                            use_graph=sched["use_graph"])
+
+    batch.scf(opts())  # warm-up (allocation, first-touch)
+    base = _time(batch, opts())
+    timings = {"default": base}
+    for name, values in SPACE.items():
+        best_v, best_t = sched[name], base
+        for v in values:
+            trial = dict(sched)
+            trial[name] = v
+            apply(trial)
+            sched_backup = sched
+            sched = trial
+            t = _time(batch, opts())
+            sched = sched_backup
+            timings["%s=%d" % (name, v)] = t
+            if verbose:
+                print("autotune %s=%d: %.2f ms" % (name, v, t * 1e3), flush=True)
+            if t < best_t * 0.98:
+                best_v, best_t = v, t
+        sched[name] = best_v
+        base = best_t
+        apply(sched)
+    out = {"schedule": sched, "seconds_per_%d_iterations" % iters: base, "timings": timings}
+    if use_cache:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        cache[key] = out
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1)
+    return dict(sched, cached=False)

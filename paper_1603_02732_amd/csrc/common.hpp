@@ -109,6 +109,7 @@ struct CandDesc {
   int ew_m[3], ew_n[3];  // reciprocal / image enumeration half-widths
   int ew_ng, ew_nimg;
   long long* dbg_clk;   // optional phase timestamps of the subspace solver
+  int* iter_state;      // SCF iteration counter of the batch (device memory)
   // reduction scratch: partial sums and tickets (zeroed at allocation)
   double* red_part;     // [kRedSlots]
   unsigned* tickets;    // [kTickets]

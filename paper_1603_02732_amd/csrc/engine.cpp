@@ -35,8 +35,12 @@ static const double kPiH = 3.14159265358979323846;
 
 static int g_lds_limit = 64 * 1024;
 
-// Launch-shape tuning parameters (environment overrides of the defaults).
+// Launch-shape tuning parameters: values set through sgo_set_tuning (by the
+// autotuner) take precedence over the environment, then the defaults.
+static std::map<std::string, int> g_tuning;
 static int tune(const char* name, int def) {
+  auto it = g_tuning.find(name);
+  if (it != g_tuning.end() && it->second > 0) return it->second;
   const char* v = std::getenv(name);
   if (!v || !*v) return def;
   const int x = std::atoi(v);
@@ -57,9 +61,10 @@ struct ProfState {
   size_t used = 0;
 };
 static ProfState g_prof;
+static bool g_capturing = false;  // no event records inside a captured graph
 
 void prof_before(const char* name, hipStream_t s) {
-  if (!g_prof.on || g_prof.name != name) return;
+  if (!g_prof.on || g_capturing || g_prof.name != name) return;
   if (g_prof.used + 2 > g_prof.ev.size()) {
     for (int k = 0; k < 2; ++k) {
       hipEvent_t e;
@@ -70,7 +75,7 @@ void prof_before(const char* name, hipStream_t s) {
   HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], s));
 }
 void prof_after(const char* name, hipStream_t s) {
-  if (!g_prof.on || g_prof.name != name) return;
+  if (!g_prof.on || g_capturing || g_prof.name != name) return;
   HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], s));
   g_prof.used += 2;
 }
@@ -177,6 +182,8 @@ class Engine {
     }
     HIPCHK(hipMalloc(&d_species_, sizeof(SpeciesDev) * kMaxSpecies));
     HIPCHK(hipMemset(d_species_, 0, sizeof(SpeciesDev) * kMaxSpecies));
+    HIPCHK(hipMalloc(&d_iter_, 64));
+    HIPCHK(hipMemset(d_iter_, 0, 64));
     species_.resize(kMaxSpecies);
   }
   ~Engine() {
@@ -184,6 +191,8 @@ class Engine {
     for (auto& c : cands_) free_cand(c);
     if (d_species_) (void)hipFree(d_species_);
     if (d_desc_) (void)hipFree(d_desc_);
+    if (d_iter_) (void)hipFree(d_iter_);
+    if (own_stream_) (void)hipStreamDestroy(own_stream_);
   }
 
   void set_stream(void* s) { stream_ = (hipStream_t)s; }
@@ -571,7 +580,12 @@ class Engine {
       g.K_max = std::max(g.K_max, c.K);
       g.ew_ng_max = std::max(g.ew_ng_max, c.ew_ng);
     }
-    g.sp_chunk = std::max(1, 640 / std::max(1, g.N3max));
+    g.sp_chunk = std::max(1, tune("SGO_SP_CHUNK", std::max(1, 640 / std::max(1, g.N3max))));
+    {  // the z kernels hold 2 x (2 sp_chunk) sticks of N3 complex values in LDS
+      const size_t cplx_bytes = 2 * tsize();
+      const int cap = (int)(((size_t)g_lds_limit / cplx_bytes - kMaxFftN) / (4 * (size_t)std::max(1, g.N3max)));
+      g.sp_chunk = std::max(1, std::min(g.sp_chunk, cap));
+    }
     g.kc_len = std::max(tune("SGO_GRAM_KC", 256), ((g.K_max + 31) / 32 + 31) / 32 * 32);
     g.kc_len = (g.kc_len + 31) / 32 * 32;
     g.sub_threads = std::max(64, std::min(512, tune("SGO_SUB_THREADS", 512) / 64 * 64));
@@ -579,7 +593,7 @@ class Engine {
     // band-pair chunks of the density planes: enough blocks to fill the chip
     // (planes x candidates x chunks >= 512), no more (each chunk is a grid)
     const int planes = std::max(1, g.N3max * g.ncand);
-    g.dens_chunks = std::max(1, std::min(g.npair_max, (512 + planes - 1) / planes));
+    g.dens_chunks = std::max(1, std::min(g.npair_max, tune("SGO_DENS_CHUNKS", (512 + planes - 1) / planes)));
     return g;
   }
 
@@ -636,6 +650,7 @@ class Engine {
       }
       c.d.seed = seed;
       c.d.active = 1;
+      c.d.iter_state = d_iter_;
       c.status = SGO_OK;
       c.info = sgo_scf_info{};
       HIPCHK(hipMemsetAsync(c.d.scal, 0, S_COUNT * 8, stream_));
@@ -698,60 +713,114 @@ class Engine {
     HIPCHK(hipStreamSynchronize(stream_));
   }
 
+  // One SCF iteration after the first: mix the previous output into the new
+  // input potential, solve (Algorithm 1), occupations, output density,
+  // residual and Pulay row, energies and convergence flags, advance the
+  // device-side iteration counter.  Captured once into a HIP graph when
+  // opts.use_graph is set.
+  template <typename T>
+  void iteration_body(const LaunchCtx& L, const sgo_scf_opts& o) {
+    launch_mix(L, 0, o.mix_alpha, o.kerker_q0);
+    launch_grid_fft(L, +1);
+    launch_potential_finalize<T>(L);
+    iteration_solve<T>(L, o, o.ncg);
+  }
+  template <typename T>
+  void iteration_solve(const LaunchCtx& L, const sgo_scf_opts& o, int ncg) {
+    eigensolver<T>(L, ncg);
+    launch_occupations(L);
+    launch_band_kinetic<T>(L);
+    launch_density<T>(L);
+    launch_density_finalize(L);
+    launch_grid_fft(L, -1);
+    launch_gspace_residual(L);
+    launch_scf_control(L, o.tol_e, o.tol_rho);
+    launch_iter_set(L, d_iter_, 1, 1);
+  }
+
+  // Read the status block of every active candidate; mask out the converged
+  // and failed ones.  Returns the number still active.
+  int update_active(int it) {
+    std::vector<std::array<double, S_COUNT>> sc;
+    read_scal(sc);
+    bool changed = false;
+    int nactive = 0;
+    for (size_t i = 0; i < cands_.size(); ++i) {
+      HostCand& c = cands_[i];
+      if (!c.d.active) continue;
+      c.info.iterations = it + 1;
+      c.info.de = sc[i][S_DE];
+      c.info.drho = sc[i][S_DRHO];
+      if (sc[i][S_ERR] != 0.0) {
+        c.status = SGO_ENUMERIC;
+        c.d.active = 0;
+        changed = true;
+      } else if (sc[i][S_CONV] != 0.0) {
+        c.info.converged = 1;
+        c.d.active = 0;
+        changed = true;
+      }
+      nactive += c.d.active;
+    }
+    if (changed) upload_desc();
+    return nactive;
+  }
+
   template <typename T>
   int scf_t(const sgo_scf_opts& o) {
     const int hist = std::max(2, std::min(kMaxHist, o.history));
     BatchGeom g = prepare(o.seed, hist);
+    hipStream_t user_stream = stream_;
+    if (o.use_graph && !stream_) {
+      if (!own_stream_) HIPCHK(hipStreamCreateWithFlags(&own_stream_, hipStreamNonBlocking));
+      stream_ = own_stream_;
+    }
+    struct Restore {
+      Engine* e;
+      hipStream_t s;
+      ~Restore() { e->stream_ = s; }
+    } restore{this, user_stream};
     LaunchCtx L = ctx(g);
     bool all_warm = true;
     for (auto& c : cands_) all_warm = all_warm && c.have_psi;
+    launch_iter_set(L, d_iter_, 0, 0);
     setup_geometry<T>(L);
     if (!all_warm) init_wavefunctions<T>(L);
-    launch_mix(L, 1, 0, 0, 0, o.mix_alpha, o.kerker_q0);
+    launch_mix(L, 1, o.mix_alpha, o.kerker_q0);
     launch_grid_fft(L, +1);
     launch_potential_finalize<T>(L);
+    iteration_solve<T>(L, o, all_warm ? o.ncg : o.ncg_first);
     HIPCHK(hipGetLastError());
-    std::vector<std::array<double, S_COUNT>> sc;
-    int nactive = (int)cands_.size();
     int it = 0;
-    for (; it < o.max_iter; ++it) {
-      const int cur = it % hist;
-      const int nvalid = std::min(it + 1, hist - 1);
-      eigensolver<T>(L, (it == 0 && !all_warm) ? o.ncg_first : o.ncg);
-      launch_occupations(L);
-      launch_band_kinetic<T>(L);
-      launch_density<T>(L);
-      launch_density_finalize(L);
-      launch_grid_fft(L, -1);
-      launch_gspace_residual(L, cur, nvalid);
-      launch_scf_control(L, cur, nvalid, it, o.tol_e, o.tol_rho);
-      HIPCHK(hipGetLastError());
-      read_scal(sc);
-      bool changed = false;
-      for (size_t i = 0; i < cands_.size(); ++i) {
-        HostCand& c = cands_[i];
-        if (!c.d.active) continue;
-        c.info.iterations = it + 1;
-        c.info.de = sc[i][S_DE];
-        c.info.drho = sc[i][S_DRHO];
-        if (sc[i][S_ERR] != 0.0) {
-          c.status = SGO_ENUMERIC;
-          c.d.active = 0;
-          changed = true;
-        } else if (sc[i][S_CONV] != 0.0) {
-          c.info.converged = 1;
-          c.d.active = 0;
-          changed = true;
+    int nactive = update_active(it);
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    for (it = 1; it < o.max_iter && nactive > 0; ++it) {
+      if (o.use_graph) {
+        if (!exec) {
+          g_capturing = true;
+          HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
+          try {
+            iteration_body<T>(L, o);
+          } catch (...) {
+            hipGraph_t dummy;
+            (void)hipStreamEndCapture(stream_, &dummy);
+            g_capturing = false;
+            throw;
+          }
+          HIPCHK(hipStreamEndCapture(stream_, &graph));
+          g_capturing = false;
+          HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
         }
+        HIPCHK(hipGraphLaunch(exec, stream_));
+      } else {
+        iteration_body<T>(L, o);
       }
-      nactive = 0;
-      for (auto& c : cands_) nactive += c.d.active;
-      if (changed) upload_desc();
-      if (nactive == 0) break;
-      launch_mix(L, 0, cur, nvalid, (cur + 1) % hist, o.mix_alpha, o.kerker_q0);
-      launch_grid_fft(L, +1);
-      launch_potential_finalize<T>(L);
+      HIPCHK(hipGetLastError());
+      nactive = update_active(it);
     }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
     for (auto& c : cands_) {
       if (c.d.active) c.status = SGO_ENOTCONV;
       c.d.active = 1;
@@ -901,6 +970,8 @@ class Engine {
   std::vector<HostCand> cands_;
   CandDesc* d_desc_ = nullptr;
   size_t desc_cap_ = 0;
+  int* d_iter_ = nullptr;             // SCF iteration counter (device)
+  hipStream_t own_stream_ = nullptr;  // used for graph capture when no stream is set
   bool desc_dirty_ = true;
 };
 
@@ -1334,6 +1405,24 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
     if (flag != 0.0) throw Error(SGO_ENUMERIC, "overlap matrix is not positive definite");
     return SGO_OK;
   });
+}
+
+int sgo_set_tuning(const char* key, int value) {
+  if (!key) return SGO_EINVAL;
+  static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
+                                "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS"};
+  bool ok = false;
+  for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
+  if (!ok) return SGO_EINVAL;
+  if (value <= 0) sgo::g_tuning.erase(key);
+  else sgo::g_tuning[key] = value;
+  return SGO_OK;
+}
+
+int sgo_get_tuning(const char* key) {
+  if (!key) return SGO_EINVAL;
+  auto it = sgo::g_tuning.find(key);
+  return it == sgo::g_tuning.end() ? 0 : it->second;
 }
 
 int sgo_grid_info(sgo_ctx* c, int* info) {

@@ -61,6 +61,20 @@ __device__ __forceinline__ double vloc_g0(const SpeciesDev& s) {
   return 2.0 * kPi * s.Z * rl * rl + pow(2.0 * kPi, 1.5) * rl * rl * rl * (s.p[1] + 3.0 * s.p[2]);
 }
 
+// History slots of SCF iteration `it` (the batch iterates in lockstep; the
+// counter lives in device memory so a captured iteration can be replayed).
+struct IterSlots {
+  int it, cur, nvalid, next;
+};
+__device__ __forceinline__ IterSlots slots_of(int it, int H) {
+  IterSlots s;
+  s.it = it;
+  s.cur = it % H;
+  s.nvalid = min(it + 1, H - 1);
+  s.next = (it + 1) % H;
+  return s;
+}
+
 __device__ __forceinline__ int nblk(const CandDesc& cd) {
   return min(1024, (cd.ntot + kNT - 1) / kNT);
 }
@@ -161,11 +175,12 @@ __global__ void __launch_bounds__(kNT) k_density_finalize(const CandDesc* __rest
 // After the forward FFT of rho_out: rho_out(G), density residual into the
 // history, Hartree and local energies, and the residual dot products of the
 // Pulay matrix row of this iteration.
-__global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restrict__ cds, int cur,
-                                                         int nvalid) {
+__global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restrict__ cds) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
   if ((int)blockIdx.x >= nblk(cd)) return;
+  const IterSlots sl = slots_of(*cd.iter_state, cd.hist_len);
+  const int cur = sl.cur, nvalid = sl.nvalid;
   __shared__ double sh[16 * 10];
   const int H = cd.hist_len;
   double v[10];
@@ -212,11 +227,12 @@ __global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restr
 
 // Pulay coefficients, total free energy, convergence flags (one block per
 // candidate; the work is a few dozen scalars).
-__global__ void k_scf_control(const CandDesc* __restrict__ cds, int cur, int nvalid, int iter,
-                              double tol_e_atom, double tol_rho) {
+__global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_atom, double tol_rho) {
   const CandDesc& cd = cds[blockIdx.x];
   if (!cd.active) return;
   if (threadIdx.x != 0) return;
+  const IterSlots sl = slots_of(*cd.iter_state, cd.hist_len);
+  const int cur = sl.cur, nvalid = sl.nvalid, iter = sl.it;
   const int H = cd.hist_len;
   double* sc = cd.scal;
   // Pulay: minimise |sum c_l R_l| with sum c_l = 1
@@ -288,11 +304,14 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, int cur, int nva
 // Mixed input density in G space and the potential V(G) = V_loc + V_H on D,
 // packed as V(G) + i rho_in(G) for one inverse transform of both.
 __global__ void __launch_bounds__(kNT) k_mix(const CandDesc* __restrict__ cds, int initial,
-                                             int cur, int nvalid, int next, double alpha,
-                                             double q0) {
+                                             double alpha, double q0) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
   const int H = cd.hist_len;
+  // mixes the output of the previous iteration (the counter was advanced
+  // after it) into the input of the current one; the first input is rho_0
+  const IterSlots sl = slots_of(*cd.iter_state - 1, H);
+  const int cur = sl.cur, nvalid = sl.nvalid, next = initial ? 0 : sl.next;
   for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cd.ntot; e += gridDim.x * blockDim.x) {
     const GPoint p = gpoint(cd, e);
     cplx<double> rho;
@@ -844,6 +863,11 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   if (clk && tid == 0) clk[4] = clock64();
 }
 
+// Set or advance the batch's SCF iteration counter (one thread).
+__global__ void k_iter_set(int* state, int value, int add) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *state = add ? *state + value : value;
+}
+
 // ---------------------------------------------------------- launch helpers
 void launch_grid_fft(const LaunchCtx& L, int sign) {
   const BatchGeom& g = L.g;
@@ -879,26 +903,28 @@ void launch_density_finalize(const LaunchCtx& L) {
   check_launch("k_density_finalize");
   prof_after("k_density_finalize", L.stream);
 }
-void launch_gspace_residual(const LaunchCtx& L, int cur, int nvalid) {
+void launch_iter_set(const LaunchCtx& L, int* state, int value, int add) {
+  hipLaunchKernelGGL(k_iter_set, dim3(1), dim3(64), 0, L.stream, state, value, add);
+  check_launch("k_iter_set");
+}
+void launch_gspace_residual(const LaunchCtx& L) {
   prof_before("k_gspace_residual", L.stream);
   hipLaunchKernelGGL(k_gspace_residual, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0,
-                     L.stream, L.desc, cur, nvalid);
+                     L.stream, L.desc);
   check_launch("k_gspace_residual");
   prof_after("k_gspace_residual", L.stream);
 }
-void launch_scf_control(const LaunchCtx& L, int cur, int nvalid, int iter, double tol_e_atom,
-                        double tol_rho) {
+void launch_scf_control(const LaunchCtx& L, double tol_e_atom, double tol_rho) {
   prof_before("k_scf_control", L.stream);
-  hipLaunchKernelGGL(k_scf_control, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, cur, nvalid,
-                     iter, tol_e_atom, tol_rho);
+  hipLaunchKernelGGL(k_scf_control, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, tol_e_atom,
+                     tol_rho);
   check_launch("k_scf_control");
   prof_after("k_scf_control", L.stream);
 }
-void launch_mix(const LaunchCtx& L, int initial, int cur, int nvalid, int next, double alpha,
-                double q0) {
+void launch_mix(const LaunchCtx& L, int initial, double alpha, double q0) {
   prof_before("k_mix", L.stream);
   hipLaunchKernelGGL(k_mix, dim3(grid_blocks(L.g), 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
-                     initial, cur, nvalid, next, alpha, q0);
+                     initial, alpha, q0);
   check_launch("k_mix");
   prof_after("k_mix", L.stream);
 }

@@ -48,11 +48,10 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps = 40);
 void launch_occupations(const LaunchCtx& L);
 void launch_grid_fft(const LaunchCtx& L, int sign);
 void launch_density_finalize(const LaunchCtx& L);
-void launch_gspace_residual(const LaunchCtx& L, int cur, int nvalid);
-void launch_scf_control(const LaunchCtx& L, int cur, int nvalid, int iter, double tol_e_atom,
-                        double tol_rho);
-void launch_mix(const LaunchCtx& L, int initial, int cur, int nvalid, int next, double alpha,
-                double q0);
+void launch_gspace_residual(const LaunchCtx& L);
+void launch_scf_control(const LaunchCtx& L, double tol_e_atom, double tol_rho);
+void launch_iter_set(const LaunchCtx& L, int* state, int value, int add);
+void launch_mix(const LaunchCtx& L, int initial, double alpha, double q0);
 void launch_setup_grid(const LaunchCtx& L);
 void launch_ewald(const LaunchCtx& L);
 void launch_force_local(const LaunchCtx& L);

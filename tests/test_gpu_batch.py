@@ -80,3 +80,28 @@ def test_c3_population_fp32():
     for k in range(len(pop)):
         assert np.all(np.isfinite(F[k]))
         assert np.abs(F[k].sum(0)).max() < 5e-2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_replay_equals_eager(prec):
+    """Every SCF iteration after the first replays one captured HIP graph;
+    results must equal the eagerly launched sequence, call after call."""
+    import paper_1603_02732_amd as sgo
+    p = sgo.SGO_FP64 if prec == "fp64" else sgo.SGO_FP32
+    pop = _population()
+    B = sgo.Batch(len(pop), precision=p)
+    for s in pop:
+        B.add_system(s)
+    kw = dict(tol_e=1e-9, tol_rho=1e-7, max_iter=200)
+    for rep in range(3):
+        B.reset()
+        Ee, Fe, ste = B.scf(sgo.default_opts(use_graph=0, **kw))
+        it_e = [B.info(i)["iterations"] for i in range(len(pop))]
+        B.reset()
+        Eg, Fg, stg = B.scf(sgo.default_opts(use_graph=1, **kw))
+        it_g = [B.info(i)["iterations"] for i in range(len(pop))]
+        dE = np.abs(Ee - Eg).max()
+        dF = max(np.abs(a - b).max() for a, b in zip(Fe, Fg))
+        say("  %s rep %d: graph vs eager dE %.2e dF %.2e iters %s %s" % (prec, rep, dE, dF, it_e, it_g))
+        assert it_e == it_g and list(ste) == list(stg)
+        assert dE == 0.0 and dF == 0.0
