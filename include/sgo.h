@@ -248,6 +248,17 @@ int sgo_batch_set_atoms(sgo_batch* b, int i, const double* pos);
 int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, double* forces,
                   int* status);
 int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info);
+/* Conventional CG relaxation of every candidate, nsteps steps (Section 2.3
+ * names CG among the relaxation options): Polak-Ribiere directions built
+ * from the Hellmann-Feynman forces, a secant line search on F.d (trial step
+ * 0.1 bohr along the largest direction component, capped by twice the
+ * previous step; secant step clamped to [0.1, 4] x trial), two batched
+ * warm-started evaluations per step.  energies [n][nsteps+1] (nullable)
+ * receives the energy before the first and after each step; forces and
+ * positions [sum natoms*3] (nullable) the final ones, status [n] per
+ * candidate.  Returns the worst status. */
+int sgo_batch_relax_cg(sgo_batch* b, int nsteps, const sgo_scf_opts* opts, double* energies,
+                       double* forces, double* positions, int* status);
 /* Drop the warm-start wavefunctions of every candidate (next solve is cold). */
 int sgo_batch_reset(sgo_batch* b);
 /* Read back the state of candidate i after sgo_batch_scf (each pointer may be

@@ -109,6 +109,7 @@ def load_library(path=None):
         "sgo_batch_info": (I, [P, I, ctypes.POINTER(sgo_scf_info)]),
         "sgo_batch_size": (I, [P, ip]),
         "sgo_batch_reset": (I, [P]),
+        "sgo_batch_relax_cg": (I, [P, I, ctypes.POINTER(sgo_scf_opts), dp, dp, dp, ip]),
         "sgo_batch_get_state": (I, [P, I, ip, ip, dp, dp, dp, dp, dp,
                                     ctypes.POINTER(sgo_energy_terms)]),
         "sgo_batch_last_error": (ctypes.c_char_p, [P]),
@@ -440,6 +441,26 @@ class Batch:
         return {"grid": (N1, N2, N3), "millers": m, "psi": psi, "eig": eig, "occ": occ,
                 "rho": rho.reshape(N3, N2, N1), "veff": veff.reshape(N3, N2, N1),
                 "terms": {n: getattr(t, n) for n, _ in sgo_energy_terms._fields_}}
+
+    def relax_cg(self, nsteps, opts=None, **kw):
+        """nsteps CG relaxation steps of every candidate; returns energies
+        (n, nsteps+1), final forces and positions (lists of (natoms, 3)), status."""
+        o = opts if opts is not None else default_opts(**kw)
+        n = len(self.natoms)
+        e = np.zeros((n, nsteps + 1))
+        f = np.zeros(sum(self.natoms) * 3)
+        p = np.zeros(sum(self.natoms) * 3)
+        st = np.zeros(n, dtype=np.int32)
+        rc = self._lib.sgo_batch_relax_cg(self._h, int(nsteps), ctypes.byref(o), _dptr(e), _dptr(f),
+                                          _dptr(p), _iptr(st))
+        if rc not in (SGO_OK, SGO_ENOTCONV, SGO_ENUMERIC):
+            self._check(rc)
+        forces, pos, off = [], [], 0
+        for na in self.natoms:
+            forces.append(f[off:off + 3 * na].reshape(na, 3))
+            pos.append(p[off:off + 3 * na].reshape(na, 3))
+            off += 3 * na
+        return e, forces, pos, st
 
     def info(self, i):
         inf = sgo_scf_info()

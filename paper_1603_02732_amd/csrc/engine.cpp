@@ -845,6 +845,89 @@ class Engine {
     return prec_ == SGO_FP64 ? scf_t<double>(o) : scf_t<float>(o);
   }
 
+  // Conventional CG relaxation of every candidate (Section 2.3 lists it
+  // among the relaxation options): Polak-Ribiere directions and a secant
+  // line search on F.d, two batched evaluations per step, warm-started.
+  //   trial step  alpha1 = 0.1 bohr / max_i |d_i| (capped by the previous step x 2)
+  //   secant      alpha2 = alpha1 s0 / (s0 - s1), s = -F.d, clamped to [0.1, 4] alpha1
+  //   direction   d <- F_new + max(0, F_new.(F_new - F) / F.F) d
+  // energies [n][nsteps+1] records the energy after each accepted step.
+  int relax_cg(int nsteps, const sgo_scf_opts& o, double* energies) {
+    const int n = (int)cands_.size();
+    std::vector<std::vector<double>> x(n), F(n), d(n), x1(n), F1(n);
+    std::vector<double> E(n), alpha_prev(n, 0.0);
+    std::vector<int> status(n, SGO_OK);
+    auto evaluate = [&](std::vector<std::vector<double>>& pos, std::vector<std::vector<double>>& force,
+                        std::vector<double>* en) {
+      for (int i = 0; i < n; ++i) move_atoms(i, pos[i].data());
+      const int rc = scf(o);
+      (void)rc;
+      for (int i = 0; i < n; ++i) {
+        HostCand& c = cands_[i];
+        force[i].resize(3 * c.nat);
+        get(c.d.force, force[i].data(), 3 * c.nat * sizeof(double));
+        if (en) {
+          double s[S_COUNT];
+          get_scal(c, s);
+          (*en)[i] = s[S_ETOT];
+        }
+        if (c.status < status[i]) status[i] = c.status;
+      }
+    };
+    for (int i = 0; i < n; ++i) x[i] = cands_[i].pos;
+    evaluate(x, F, &E);
+    for (int i = 0; i < n; ++i) {
+      d[i] = F[i];
+      if (energies) energies[(size_t)i * (nsteps + 1)] = E[i];
+    }
+    std::vector<double> alpha1(n), s0(n);
+    for (int step = 1; step <= nsteps; ++step) {
+      for (int i = 0; i < n; ++i) {
+        double dmax = 0.0, fd = 0.0;
+        for (size_t k = 0; k < d[i].size(); k += 3) {
+          const double m = std::sqrt(d[i][k] * d[i][k] + d[i][k + 1] * d[i][k + 1] + d[i][k + 2] * d[i][k + 2]);
+          dmax = std::max(dmax, m);
+        }
+        for (size_t k = 0; k < d[i].size(); ++k) fd += F[i][k] * d[i][k];
+        double a = dmax > 0 ? 0.1 / dmax : 0.0;
+        if (alpha_prev[i] > 0) a = std::min(a, 2.0 * alpha_prev[i]);
+        alpha1[i] = a;
+        s0[i] = -fd;
+        x1[i] = x[i];
+        for (size_t k = 0; k < x1[i].size(); ++k) x1[i][k] += a * d[i][k];
+      }
+      evaluate(x1, F1, nullptr);
+      for (int i = 0; i < n; ++i) {
+        double s1 = 0.0;
+        for (size_t k = 0; k < d[i].size(); ++k) s1 -= F1[i][k] * d[i][k];
+        double a2 = (s0[i] - s1) > 0 ? alpha1[i] * s0[i] / (s0[i] - s1) : 4.0 * alpha1[i];
+        a2 = std::max(0.1 * alpha1[i], std::min(4.0 * alpha1[i], a2));
+        alpha_prev[i] = a2;
+        x1[i] = x[i];
+        for (size_t k = 0; k < x1[i].size(); ++k) x1[i][k] += a2 * d[i][k];
+      }
+      evaluate(x1, F1, &E);
+      for (int i = 0; i < n; ++i) {
+        double num = 0.0, den = 0.0;
+        for (size_t k = 0; k < F1[i].size(); ++k) {
+          num += F1[i][k] * (F1[i][k] - F[i][k]);
+          den += F[i][k] * F[i][k];
+        }
+        const double beta = den > 0 ? std::max(0.0, num / den) : 0.0;
+        for (size_t k = 0; k < d[i].size(); ++k) d[i][k] = F1[i][k] + beta * d[i][k];
+        x[i] = x1[i];
+        F[i] = F1[i];
+        if (energies) energies[(size_t)i * (nsteps + 1) + step] = E[i];
+      }
+    }
+    int worst = SGO_OK;
+    for (int i = 0; i < n; ++i) {
+      cands_[i].status = status[i];
+      worst = std::min(worst, status[i]);
+    }
+    return worst;
+  }
+
   template <typename T>
   void apply_h_t(const double* veff, int nbx, const double* psi, double* hpsi) {
     HostCand& c = cands_.at(0);
@@ -1526,6 +1609,26 @@ int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info) {
     if (!info) throw Error(SGO_EINVAL, "NULL info");
     *info = b->eng->cand(i).info;
     return SGO_OK;
+  });
+}
+
+int sgo_batch_relax_cg(sgo_batch* b, int nsteps, const sgo_scf_opts* opts, double* energies,
+                       double* forces, double* positions, int* status) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if (b->eng->size() == 0) throw Error(SGO_ESTATE, "empty batch");
+    if (nsteps < 0) throw Error(SGO_EINVAL, "nsteps must be >= 0");
+    const sgo_scf_opts o = opts_or_default(opts);
+    const int rc = b->eng->relax_cg(nsteps, o, energies);
+    size_t off = 0;
+    for (int i = 0; i < b->eng->size(); ++i) {
+      auto& hc = b->eng->cand(i);
+      if (forces) b->eng->get(hc.d.force, forces + off, 3 * hc.nat * sizeof(double));
+      if (positions) std::memcpy(positions + off, hc.pos.data(), 3 * hc.nat * sizeof(double));
+      off += 3 * hc.nat;
+      if (status) status[i] = hc.status;
+    }
+    return rc;
   });
 }
 

@@ -105,3 +105,25 @@ def test_graph_replay_equals_eager(prec):
         say("  %s rep %d: graph vs eager dE %.2e dF %.2e iters %s %s" % (prec, rep, dE, dF, it_e, it_g))
         assert it_e == it_g and list(ste) == list(stg)
         assert dE == 0.0 and dF == 0.0
+
+
+def test_cg_relaxation_matches_oracle():
+    """Batched CG relaxation (3 steps, two evaluations each) against the
+    oracle's own implementation of the same algorithm on small clusters."""
+    import paper_1603_02732_amd as sgo
+    from oracle.relax import relax_cg
+    pop = [workloads.tiny_system("c", ecut=5.0, grid=(18, 18, 18), seed=31),
+           workloads.tiny_system("c", ecut=5.0, grid=(18, 18, 18), seed=32)]
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP64)
+    for s in pop:
+        B.add_system(s)
+    E, F, X, st = B.relax_cg(3, tol_e=1e-11, tol_rho=1e-9, max_iter=300)
+    assert np.all(st == 0)
+    for i, s in enumerate(pop):
+        Eo, Xo, Fo = relax_cg(s, 3)
+        nat = len(s["symbols"])
+        say("  cand %d energies gpu %s oracle %s" % (i, np.round(E[i], 7), np.round(Eo, 7)))
+        assert np.abs(E[i] - Eo).max() / nat < 1e-6
+        assert Eo[-1] < Eo[0]  # the relaxation lowers the energy overall
+        assert np.abs(X[i] - Xo).max() < 1e-4
+        assert np.abs(F[i] - Fo).max() < 1e-4
