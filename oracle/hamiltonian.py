@@ -31,7 +31,12 @@ class Setup:
         self.nelec = float(system["nelec"])
         self.nbands = int(system["nbands"])
         self.ecut = float(system["ecut"])
-        self.millers = sphere_millers(self.lattice, self.ecut)
+        # a fixed Miller set (system["millers"]) keeps the basis of a strained
+        # cell identical to that of the reference cell
+        if system.get("millers") is not None:
+            self.millers = np.asarray(system["millers"], dtype=int).reshape(-1, 3)
+        else:
+            self.millers = sphere_millers(self.lattice, self.ecut)
         if not check_grid(self.millers, self.grid):
             raise ValueError("grid too small for the wavefunction sphere")
         self.G = self.millers @ self.B
