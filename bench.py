@@ -142,7 +142,12 @@ def main():
     n_eval = a.steps * len(pop)
     value = n_eval / dt
 
-    bound, amount, unit = kernel_model(dominant, geoms, 4)
+    # every launch covers the whole population, but candidates that have
+    # converged return at once: the work of a launch is that of the
+    # candidates still active in it (all candidates have the same shape)
+    bound, amount_all, unit = kernel_model(dominant, geoms, 4)
+    avg_active = prof["cand_launches"] / max(prof["launches"], 1)
+    amount = amount_all / len(geoms) * avg_active
     avg_s = prof["ms"] * 1e-3 / max(prof["launches"], 1)
     if bound == "hbm":
         ach = amount / avg_s / 1e9
@@ -153,6 +158,7 @@ def main():
     roof = {"bound": bound, "kernel": dominant, "achieved": ach, "peak": peak, "unit": unit,
             "frac": ach / peak, "traffic": None, "avg_launch_us": avg_s * 1e6,
             "launches_per_step": prof["launches"] / a.steps,
+            "active_candidates_per_launch": avg_active,
             ("bytes_per_launch" if bound == "hbm" else "flop_per_launch"): amount,
             "share_of_step": {k: round(v, 4) for k, v in shares.items()}}
 

@@ -156,14 +156,26 @@ int sgo_energy(sgo_ctx* ctx, double* etot, sgo_energy_terms* terms);
  * Ewald parts; -dF/dR of the free energy at self-consistency). */
 int sgo_forces(sgo_ctx* ctx, double* forces);
 
-/* Fixed-basis stress tensor [9] after sgo_scf. */
-int sgo_stress(sgo_ctx* ctx, double stress[9]);
+/* Fixed-basis stress after sgo_scf (Appendix A, stress of the plane-wave
+ * functional): sigma_ab = (1/Omega) dF/d eps_ab for the homogeneous strain
+ * r -> (1 + eps) r of cell and atoms together, at the current Miller set and
+ * fixed coefficients and occupations (the Mermin free energy is stationary
+ * in both at self-consistency).  Ha/bohr^3, row-major symmetric [3][3]; a
+ * cell under compression has negative diagonal entries (sigma = -pressure
+ * for an isotropic cell).  parts (nullable) receives [6][3][3]: kinetic,
+ * nonlocal, Hartree, local, exchange-correlation and Ewald contributions,
+ * summing to stress.  Runs the stress kernels on the converged state; the
+ * structure must have been solved (SGO_ESTATE otherwise). */
+int sgo_stress(sgo_ctx* ctx, double stress[9], double* parts);
 
 /* Eigenvalues [nbands] (ascending) and, if occ != NULL, occupations. */
 int sgo_eigenvalues(sgo_ctx* ctx, double* eig, double* occ);
 
 /* Adjoint of the energy: grad_pos = gE * dE/dR = -gE * F  [natoms*3] and,
- * if grad_lattice != NULL, gE * dE/d(lattice) [9] at a fixed Miller set. */
+ * if grad_lattice != NULL, gE * dE/dA [3][3] (A rows = lattice vectors) with
+ * the Cartesian positions as given held fixed and the Miller set of the
+ * current basis held fixed: dE/dA = A^-T (Omega sigma + sum_I R_I F_I^T),
+ * from the stress sigma (sgo_stress) and forces. */
 int sgo_adjoint(sgo_ctx* ctx, double gE, double* grad_pos, double* grad_lattice);
 
 /* Drop the warm-start wavefunctions and density. */
@@ -223,9 +235,11 @@ int sgo_get_tuning(const char* key);
  * sgo_profile_end, every launch of the kernel named `kernel` (for example
  * "k_plane_hpsi") is bracketed by a pair of HIP events recorded on the stream
  * it is launched on.  sgo_profile_end waits for the events and returns the
- * number of launches and their summed duration in milliseconds. */
+ * number of launches, their summed duration in milliseconds and (nullable)
+ * the sum over those launches of the candidates still active in each (a
+ * population launch returns at once for converged candidates). */
 int sgo_profile_begin(const char* kernel);
-int sgo_profile_end(int* launches, double* total_ms);
+int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches);
 
 /* ---- Population of candidates, solved together (Section 2.4 last
  * paragraph: the relaxations of one generation may run side by side).  The
@@ -269,6 +283,9 @@ int sgo_batch_reset(sgo_batch* b);
  * [N3][N2][N1]; energy terms. */
 int sgo_batch_get_state(sgo_batch* b, int i, int* info, int* millers, double* psi, double* eig,
                         double* occ, double* rho, double* veff, sgo_energy_terms* terms);
+/* Fixed-basis stress [n][3][3] of every solved candidate (conventions of
+ * sgo_stress); candidates not yet solved get SGO_ESTATE. */
+int sgo_batch_stress(sgo_batch* b, double* stress);
 int sgo_batch_size(sgo_batch* b, int* n);
 const char* sgo_batch_last_error(const sgo_batch* b);
 

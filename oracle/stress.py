@@ -100,7 +100,7 @@ def stress(res):
                         for b in range(3):
                             dbeta[a, b] = (-0.5 * (a == b) * base
                                            + dq * (-2 * st.G[:, a] * st.G[:, b]))
-                    dP = np.einsum("abg,gn->abn", dbeta.conj(), C)
+                    dP = (dbeta.reshape(9, -1).conj() @ C).reshape(3, 3, -1)
                     Pp = P[col]
                     nl += h * 2 * np.real(np.einsum("n,abn->ab", f * np.conj(Pp), dP))
                     col += 1
@@ -117,7 +117,7 @@ def stress(res):
                                 dbeta[a, b] = (-0.5 * (a == b) * base
                                                + (-1j) * amp * phase * e * dGm
                                                + base * (-0.5 * rl * rl) * (-2 * st.G[:, a] * st.G[:, b]))
-                        dP = np.einsum("abg,gn->abn", dbeta.conj(), C)
+                        dP = (dbeta.reshape(9, -1).conj() @ C).reshape(3, 3, -1)
                         Pp = P[col]
                         nl += h * 2 * np.real(np.einsum("n,abn->ab", f * np.conj(Pp), dP))
                         col += 1

@@ -83,7 +83,7 @@ def load_library(path=None):
         "sgo_scf": (I, [P, ctypes.POINTER(sgo_scf_opts), ctypes.POINTER(sgo_scf_info)]),
         "sgo_energy": (I, [P, dp, ctypes.POINTER(sgo_energy_terms)]),
         "sgo_forces": (I, [P, dp]),
-        "sgo_stress": (I, [P, dp]),
+        "sgo_stress": (I, [P, dp, dp]),
         "sgo_eigenvalues": (I, [P, dp, dp]),
         "sgo_adjoint": (I, [P, D, dp, dp]),
         "sgo_reset": (I, [P]),
@@ -98,7 +98,7 @@ def load_library(path=None):
         "sgo_subspace_solve": (I, [I, I, I, dp, dp, dp, dp, I, dp,
                                    ctypes.POINTER(ctypes.c_longlong)]),
         "sgo_profile_begin": (I, [ctypes.c_char_p]),
-        "sgo_profile_end": (I, [ip, dp]),
+        "sgo_profile_end": (I, [ip, dp, ctypes.POINTER(ctypes.c_longlong)]),
         "sgo_batch_create": (I, [ctypes.POINTER(P), I, I, I]),
         "sgo_batch_destroy": (I, [P]),
         "sgo_batch_set_stream": (I, [P, P]),
@@ -108,6 +108,7 @@ def load_library(path=None):
         "sgo_batch_scf": (I, [P, ctypes.POINTER(sgo_scf_opts), dp, dp, ip]),
         "sgo_batch_info": (I, [P, I, ctypes.POINTER(sgo_scf_info)]),
         "sgo_batch_size": (I, [P, ip]),
+        "sgo_batch_stress": (I, [P, dp]),
         "sgo_batch_reset": (I, [P]),
         "sgo_batch_relax_cg": (I, [P, I, ctypes.POINTER(sgo_scf_opts), dp, dp, dp, ip]),
         "sgo_batch_get_state": (I, [P, I, ip, ip, dp, dp, dp, dp, dp,
@@ -248,10 +249,28 @@ class Context:
         self._check(self._lib.sgo_forces(self._h, _dptr(f)))
         return f
 
-    def adjoint(self, gE=1.0):
+    def adjoint(self, gE=1.0, lattice=False):
+        """gE * dE/dR [natoms, 3]; with lattice=True also gE * dE/dA [3, 3]
+        (Cartesian positions and Miller set fixed)."""
         g = np.zeros((self.natoms, 3))
-        self._check(self._lib.sgo_adjoint(self._h, float(gE), _dptr(g), None))
-        return g
+        if not lattice:
+            self._check(self._lib.sgo_adjoint(self._h, float(gE), _dptr(g), None))
+            return g
+        gl = np.zeros((3, 3))
+        self._check(self._lib.sgo_adjoint(self._h, float(gE), _dptr(g), _dptr(gl)))
+        return g, gl
+
+    def stress(self, parts=False):
+        """Fixed-basis stress [3, 3] (Ha/bohr^3); with parts=True also a dict
+        of the kinetic, nonlocal, hartree, local, xc and ewald parts."""
+        s = np.zeros((3, 3))
+        if not parts:
+            self._check(self._lib.sgo_stress(self._h, _dptr(s), None))
+            return s
+        p = np.zeros((6, 3, 3))
+        self._check(self._lib.sgo_stress(self._h, _dptr(s), _dptr(p)))
+        names = ("kinetic", "nonlocal", "hartree", "local", "xc", "ewald")
+        return s, {n: p[k] for k, n in enumerate(names)}
 
     def eigenvalues(self):
         e = np.zeros(self.nbands)
@@ -339,11 +358,12 @@ def profile_begin(kernel):
 def profile_end():
     n = ctypes.c_int()
     ms = ctypes.c_double()
+    cl = ctypes.c_longlong()
     lib = load_library()
-    rc = lib.sgo_profile_end(ctypes.byref(n), ctypes.byref(ms))
+    rc = lib.sgo_profile_end(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(cl))
     if rc != SGO_OK:
         raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
-    return {"launches": n.value, "ms": ms.value}
+    return {"launches": n.value, "ms": ms.value, "cand_launches": cl.value}
 
 
 class Batch:
@@ -467,6 +487,12 @@ class Batch:
         self._check(self._lib.sgo_batch_info(self._h, int(i), ctypes.byref(inf)))
         return {"iterations": inf.iterations, "converged": bool(inf.converged), "de": inf.de,
                 "drho": inf.drho}
+
+    def stress(self):
+        """Fixed-basis stress [n, 3, 3] of every candidate after scf."""
+        s = np.zeros((len(self.natoms), 3, 3))
+        self._check(self._lib.sgo_batch_stress(self._h, _dptr(s)))
+        return s
 
 
 def context_from_system(system, precision=None, device=0):

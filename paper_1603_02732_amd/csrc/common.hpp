@@ -103,6 +103,8 @@ struct CandDesc {
   double* force_ew;     // [nat*3]
   double* force_part;   // [nat*3*4] local / nonlocal scratch
   double* nlwork;       // [nproj*nb*4]
+  double* stwork;       // stress partial sums, layout in stress_layout()
+  double* stress;       // [9] total, then [6][9] parts (kin, nl, H, loc, xc, Ewald)
   double* scal;         // [S_COUNT]
   cplx<double>* ewS;    // [ew_ng] Ewald structure factors
   double ew_eta, ew_rcut, ew_gcut, pad2;
@@ -118,6 +120,23 @@ struct CandDesc {
 };
 
 constexpr int kRedSlots = 1 << 16;
+
+// Stress partial sums (doubles): per band kinetic [nb][6]; per projector and
+// band (P, Q_xx..Q_xy) [nproj][nb][7]; grid blocks [kStressBlocks][16];
+// per atom Ewald [nat][13].  Voigt order xx yy zz yz xz xy.
+constexpr int kStressBlocks = 256;
+struct StressLayout {
+  size_t kin, nl, grid, ew, total;
+};
+__host__ __device__ inline StressLayout stress_layout(int nb, int nproj, int nat) {
+  StressLayout L;
+  L.kin = 0;
+  L.nl = (size_t)6 * nb;
+  L.grid = L.nl + (size_t)7 * nproj * nb;
+  L.ew = L.grid + (size_t)16 * kStressBlocks;
+  L.total = L.ew + (size_t)13 * nat;
+  return L;
+}
 constexpr int kTickets = 512;
 constexpr int kTicketGrid = 480;  // first ticket not used by the Gram products
 

@@ -35,6 +35,16 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* sh) {
   __syncthreads();
 }
 
+// v[0..5] += w * (G G^T) in Voigt order xx yy zz yz xz xy.
+__device__ __forceinline__ void add_voigt(double* v, double w, const double* G) {
+  v[0] += w * G[0] * G[0];
+  v[1] += w * G[1] * G[1];
+  v[2] += w * G[2] * G[2];
+  v[3] += w * G[1] * G[2];
+  v[4] += w * G[0] * G[2];
+  v[5] += w * G[0] * G[1];
+}
+
 __device__ __forceinline__ double load_coherent(const double* p) {
   unsigned long long u =
       __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p), __ATOMIC_RELAXED,

@@ -57,6 +57,8 @@ void allow_lds(const void* kernel) {
 struct ProfState {
   bool on = false;
   std::string name;
+  int active = 0;          // candidates active in the launches being issued
+  long long cand_launches = 0;  // sum over profiled launches of `active`
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t used = 0;
 };
@@ -78,6 +80,7 @@ void prof_after(const char* name, hipStream_t s) {
   if (!g_prof.on || g_capturing || g_prof.name != name) return;
   HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], s));
   g_prof.used += 2;
+  g_prof.cand_launches += g_prof.active;
 }
 
 void throw_unsupported(const char* what) { throw Error(SGO_EINVAL, what); }
@@ -482,6 +485,8 @@ class Engine {
         {(void**)&d.pos, (size_t)3 * c.nat * 8}, {(void**)&d.spec, (size_t)c.nat * sizeof(int)},
         {(void**)&d.force, (size_t)3 * c.nat * 8}, {(void**)&d.force_ew, (size_t)3 * c.nat * 8},
         {(void**)&d.force_part, (size_t)6 * c.nat * 8}, {(void**)&d.nlwork, (size_t)c.nproj * nb * 4 * 8 + 8},
+        {(void**)&d.stwork, stress_layout(c.nb, c.nproj, c.nat).total * 8},
+        {(void**)&d.stress, (size_t)72 * 8},
         {(void**)&d.scal, S_COUNT * 8}, {(void**)&d.ewS, (size_t)c.ew_ng * 16},
         {(void**)&d.red_part, c.red_doubles * 8}, {(void**)&d.tickets, kTickets * sizeof(unsigned)},
     };
@@ -609,10 +614,13 @@ class Engine {
 
   void upload_desc() {
     std::vector<CandDesc> h(cands_.size());
+    int nact = 0;
     for (size_t i = 0; i < cands_.size(); ++i) {
       h[i] = cands_[i].d;
       h[i].ncand_index = (int)i;
+      nact += h[i].active ? 1 : 0;
     }
+    g_prof.active = nact;
     if (!d_desc_ || desc_cap_ < cands_.size()) {
       if (d_desc_) (void)hipFree(d_desc_);
       HIPCHK(hipMalloc(&d_desc_, sizeof(CandDesc) * cands_.size()));
@@ -838,6 +846,27 @@ class Engine {
     for (auto& c : cands_)
       if (c.status < worst) worst = c.status;
     return worst;
+  }
+
+  // Fixed-basis stress of every candidate that holds a converged state
+  // (others are masked), into each candidate's d.stress.
+  template <typename T>
+  void stress_t() {
+    BatchGeom g = geometry();
+    for (auto& c : cands_) c.d.active = c.have_scf ? 1 : 0;
+    upload_desc();
+    LaunchCtx L = ctx(g);
+    launch_stress_waves<T>(L);
+    launch_stress_grid(L);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    for (auto& c : cands_) c.d.active = 1;
+    upload_desc();
+  }
+  void stress() {
+    HIPCHK(hipSetDevice(device_));
+    if (prec_ == SGO_FP64) stress_t<double>();
+    else stress_t<float>();
   }
 
   int scf(const sgo_scf_opts& o) {
@@ -1295,11 +1324,20 @@ int sgo_forces(sgo_ctx* c, double* forces) {
   });
 }
 
-int sgo_stress(sgo_ctx* c, double stress[9]) {
+int sgo_stress(sgo_ctx* c, double stress[9], double* parts) {
   if (!c) return SGO_EINVAL;
-  return guard(&c->err, [&]() -> int {
-    (void)stress;
-    throw Error(SGO_ESTATE, "stress is not available in this build");
+  return guard(&c->err, [&] {
+    if (!stress) throw Error(SGO_EINVAL, "NULL stress");
+    if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    auto& hc = c->eng->cand(0);
+    c->eng->require_scf(hc);
+    c->eng->stress();
+    double s[63];
+    c->eng->get(hc.d.stress, s, sizeof(s));
+    for (int k = 0; k < 9; ++k) stress[k] = s[k];
+    if (parts)
+      for (int k = 0; k < 54; ++k) parts[k] = s[9 + k];
+    return SGO_OK;
   });
 }
 
@@ -1320,13 +1358,34 @@ int sgo_adjoint(sgo_ctx* c, double gE, double* grad_pos, double* grad_lattice) {
   if (!c) return SGO_EINVAL;
   return guard(&c->err, [&] {
     if (!grad_pos) throw Error(SGO_EINVAL, "NULL grad_pos");
-    if (grad_lattice) throw Error(SGO_ESTATE, "lattice gradient is not available in this build");
     if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
     auto& hc = c->eng->cand(0);
     c->eng->require_scf(hc);
     std::vector<double> f(3 * hc.nat);
     c->eng->get(hc.d.force, f.data(), f.size() * sizeof(double));
     for (size_t k = 0; k < f.size(); ++k) grad_pos[k] = -gE * f[k];
+    if (grad_lattice) {
+      // E(A, R) with Cartesian R held fixed: under r -> (1 + eps) r both A
+      // and R move, so (dE/dA)^T A - sum_I F_I R_I^T = Omega sigma, i.e.
+      // dE/dA = A^-T (Omega sigma + sum_I R_I F_I^T)  (rows of A = a_i).
+      c->eng->stress();
+      double s[9];
+      c->eng->get(hc.d.stress, s, sizeof(s));
+      double M[9];
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          double v = hc.omega * s[3 * a + b];
+          for (int I = 0; I < hc.nat; ++I) v += hc.pos[3 * I + a] * f[3 * I + b];
+          M[3 * a + b] = v;
+        }
+      // A^-T = B / (2 pi) with B the reciprocal rows (b_i . a_j = 2 pi delta_ij)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          double v = 0.0;
+          for (int k = 0; k < 3; ++k) v += hc.B[3 * i + k] * M[3 * k + j];
+          grad_lattice[3 * i + j] = gE * v / (2.0 * sgo::kPiH);
+        }
+    }
     return SGO_OK;
   });
 }
@@ -1387,10 +1446,11 @@ int sgo_profile_begin(const char* kernel) {
   sgo::g_prof.on = true;
   sgo::g_prof.name = kernel;
   sgo::g_prof.used = 0;
+  sgo::g_prof.cand_launches = 0;
   return SGO_OK;
 }
 
-int sgo_profile_end(int* launches, double* total_ms) {
+int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches) {
   return guard(nullptr, [&] {
     auto& P = sgo::g_prof;
     double ms = 0.0;
@@ -1402,8 +1462,10 @@ int sgo_profile_end(int* launches, double* total_ms) {
     }
     if (launches) *launches = (int)(P.used / 2);
     if (total_ms) *total_ms = ms;
+    if (cand_launches) *cand_launches = P.cand_launches;
     P.on = false;
     P.used = 0;
+    P.cand_launches = 0;
     return SGO_OK;
   });
 }
@@ -1645,6 +1707,19 @@ int sgo_batch_reset(sgo_batch* b) {
   if (!b) return SGO_EINVAL;
   b->eng->reset();
   return SGO_OK;
+}
+
+int sgo_batch_stress(sgo_batch* b, double* stress) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if (!stress) throw Error(SGO_EINVAL, "NULL stress");
+    if (b->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    for (int i = 0; i < b->eng->size(); ++i) b->eng->require_scf(b->eng->cand(i));
+    b->eng->stress();
+    for (int i = 0; i < b->eng->size(); ++i)
+      b->eng->get(b->eng->cand(i).d.stress, stress + 9 * i, 9 * sizeof(double));
+    return SGO_OK;
+  });
 }
 
 int sgo_batch_size(sgo_batch* b, int* n) {

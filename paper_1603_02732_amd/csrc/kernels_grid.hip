@@ -548,6 +548,214 @@ __global__ void k_force_finalize(const CandDesc* __restrict__ cds) {
   }
 }
 
+// ------------------------------------------------------------------ stress
+// d v_s / d(G^2) for G != 0, from the transforms in vloc_ft.
+__device__ __forceinline__ double vloc_dq(const SpeciesDev& s, double q) {
+  if (s.local_kind == 0) {
+    const double a = s.p[0], v1 = s.p[1], v2 = s.p[2];
+    const double e = exp(-q / (4.0 * a)), de = -e / (4.0 * a);
+    const double coul = -4.0 * kPi * s.Z * (de / q - e / (q * q));
+    const double A = pow(kPi / a, 1.5);
+    return coul + A * (de * (v1 + v2 * (1.5 / a - q / (4.0 * a * a))) - e * v2 / (4.0 * a * a));
+  }
+  const double rl = s.p[0], c1 = s.p[1], c2 = s.p[2];
+  const double e = exp(-0.5 * q * rl * rl), de = -0.5 * rl * rl * e;
+  const double coul = -4.0 * kPi * s.Z * (de / q - e / (q * q));
+  const double A = pow(2.0 * kPi, 1.5) * rl * rl * rl;
+  return coul + A * (de * (c1 + c2 * (3.0 - q * rl * rl)) - e * c2 * rl * rl);
+}
+
+// Density-side stress sums per block (fixed basis; Omega rho(G) and G.R are
+// strain invariant):
+//   v[0..5]  sum_{D, G!=0} 4 pi |rho(G)|^2 G_a G_b / G^4         (Hartree)
+//   v[6..11] -2 sum_{D, G!=0} sum_I v_I'(G^2) G_a G_b Re(e^{iG.R_I} rho(G))  (local)
+//   v[12]    sum_{D, G!=0} 4 pi |rho(G)|^2 / G^2,  v[13] sum_D Re(conj V_loc(G) rho(G))
+//   v[14]    sum_r (e_xc - v_xc) rho  (LDA volume term)
+__global__ void __launch_bounds__(kNT) k_stress_grid(const CandDesc* __restrict__ cds,
+                                                     const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  __shared__ double sh[16 * 16];
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = 0.0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < cd.ntot; e += stride) {
+    const GPoint p = gpoint(cd, e);
+    if (p.inD) {
+      const cplx<double> r = cd.rho_out_G[e];
+      const cplx<double> vl = cd.vloc_G[e];
+      v[13] += vl.x * r.x + vl.y * r.y;
+      if (p.g2 > 0.0) {
+        const double h = 4.0 * kPi * (r.x * r.x + r.y * r.y) / p.g2;
+        v[12] += h;
+        add_voigt(v, h / p.g2, p.G);
+        double loc = 0.0;
+        for (int I = 0; I < cd.nat; ++I) {
+          double sn, cs;
+          sincos(p.G[0] * cd.pos[3 * I] + p.G[1] * cd.pos[3 * I + 1] + p.G[2] * cd.pos[3 * I + 2],
+                 &sn, &cs);
+          loc += vloc_dq(sp[cd.spec[I]], p.g2) * (cs * r.x - sn * r.y);
+        }
+        add_voigt(v + 6, -2.0 * loc, p.G);
+      }
+    }
+    const double rc = fmax(cd.rho_out_r[e], 0.0);
+    double ex, vx;
+    pz81(rc, &ex, &vx);
+    v[14] += rc * (ex - vx);
+  }
+  block_sum<16>(v, sh);
+  if (threadIdx.x == 0) {
+    double* o = cd.stwork + stress_layout(cd.nb, cd.nproj, cd.nat).grid + (size_t)16 * blockIdx.x;
+    for (int k = 0; k < 16; ++k) o[k] = v[k];
+  }
+}
+
+// Ewald stress sums for atom I: real-space pairs
+//   v[0..5]  (1/2) sum_{J,n} Z_I Z_J phi'(r) d_a d_b / r,  phi = erfc(eta r)/r,
+// and the reciprocal points t = I (mod nat) of the enumerated box
+//   v[6..11] sum_G |S|^2 w(G) 2 G_a G_b (1/(4 eta^2) + 1/G^2),  v[12] sum_G |S|^2 w(G)
+// with w = e^{-G^2/4eta^2}/G^2.
+__global__ void __launch_bounds__(kNT) k_stress_ewald(const CandDesc* __restrict__ cds,
+                                                      const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int I = blockIdx.x;
+  if (I >= cd.nat) return;
+  __shared__ double sh[16 * 13];
+  double v[13];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) v[k] = 0.0;
+  const double eta = cd.ew_eta;
+  const double ZI = sp[cd.spec[I]].Z;
+  const int n1 = 2 * cd.ew_n[0] + 1, n2 = 2 * cd.ew_n[1] + 1;
+  const double rc2 = cd.ew_rcut * cd.ew_rcut;
+  const long total = (long)cd.nat * cd.ew_nimg;
+  for (long t = threadIdx.x; t < total; t += blockDim.x) {
+    const int J = (int)(t / cd.ew_nimg);
+    const int im = (int)(t - (long)J * cd.ew_nimg);
+    const int a = im % n1 - cd.ew_n[0];
+    const int b = (im / n1) % n2 - cd.ew_n[1];
+    const int c = im / (n1 * n2) - cd.ew_n[2];
+    double d[3];
+    d[0] = cd.pos[3 * I] - cd.pos[3 * J] + a * cd.A[0] + b * cd.A[3] + c * cd.A[6];
+    d[1] = cd.pos[3 * I + 1] - cd.pos[3 * J + 1] + a * cd.A[1] + b * cd.A[4] + c * cd.A[7];
+    d[2] = cd.pos[3 * I + 2] - cd.pos[3 * J + 2] + a * cd.A[2] + b * cd.A[5] + c * cd.A[8];
+    const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (r2 < 1e-24 || r2 > rc2) continue;
+    const double r = sqrt(r2);
+    const double dphi = -(erfc(eta * r) / r2 + 2.0 * eta / sqrt(kPi) * exp(-eta * eta * r2) / r);
+    add_voigt(v, 0.5 * ZI * sp[cd.spec[J]].Z * dphi / r, d);
+  }
+  const int w1 = 2 * cd.ew_m[0] + 1, w2 = 2 * cd.ew_m[1] + 1;
+  const double q4 = 1.0 / (4.0 * eta * eta);
+  for (long t = (long)threadIdx.x * cd.nat + I; t < cd.ew_ng; t += (long)blockDim.x * cd.nat) {
+    const int m1 = (int)(t % w1) - cd.ew_m[0];
+    const int m2 = (int)((t / w1) % w2) - cd.ew_m[1];
+    const int m3 = (int)(t / ((long)w1 * w2)) - cd.ew_m[2];
+    double G[3];
+    G[0] = m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6];
+    G[1] = m1 * cd.B[1] + m2 * cd.B[4] + m3 * cd.B[7];
+    G[2] = m1 * cd.B[2] + m2 * cd.B[5] + m3 * cd.B[8];
+    const double g2 = G[0] * G[0] + G[1] * G[1] + G[2] * G[2];
+    if (!(g2 > 0.0) || g2 > cd.ew_gcut * cd.ew_gcut) continue;
+    const cplx<double> S = cd.ewS[t];
+    const double w = exp(-g2 * q4) / g2 * (S.x * S.x + S.y * S.y);
+    v[12] += w;
+    add_voigt(v + 6, 2.0 * w * (q4 + 1.0 / g2), G);
+  }
+  block_sum<13>(v, sh);
+  if (threadIdx.x == 0) {
+    double* o = cd.stwork + stress_layout(cd.nb, cd.nproj, cd.nat).ew + (size_t)13 * I;
+    for (int k = 0; k < 13; ++k) o[k] = v[k];
+  }
+}
+
+// Assemble sigma = (1/Omega) dE/d eps from the partial sums (fixed order, so
+// the result is deterministic).  Writes the symmetric 3x3 total and the
+// kinetic, nonlocal, Hartree, local, xc and Ewald parts.  Nonlocal: with
+// P = <beta|psi> and Q_ab = <G_a G_b beta|psi>, the strain derivative of the
+// projection is dP_ab = -delta_ab P/2 + r_l^2 Q_ab (volume factor and
+// Gaussian radial part), and for l = 1, m: -(delta_mb P_a + delta_ma P_b)/2
+// from G_m (P_a = projection of the same channel's m = a projector);
+// sigma_nl = (2/Omega) sum_i f_i sum_p h_p P dP.
+__global__ void __launch_bounds__(kNT) k_stress_finalize(const CandDesc* __restrict__ cds,
+                                                         const SpeciesDev* __restrict__ sp) {
+  const CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active) return;
+  __shared__ double sh[16 * 16];
+  const StressLayout SL = stress_layout(cd.nb, cd.nproj, cd.nat);
+  const double* w = cd.stwork;
+  const int nb = cd.nb;
+  double a[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) a[k] = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    for (int k = 0; k < 6; ++k) a[k] += cd.occ[i] * w[SL.kin + 6 * (size_t)i + k];
+  const int va[6] = {0, 1, 2, 1, 0, 0}, vb[6] = {0, 1, 2, 2, 2, 1};
+  for (int t = threadIdx.x; t < cd.nproj * nb; t += blockDim.x) {
+    const int p = t / nb, i = t - p * nb;
+    const double f = cd.occ[i];
+    const double* q = w + SL.nl + (size_t)t * 7;
+    const double P = q[0];
+    const int l = cd.proj_lm[p] >> 2, m = cd.proj_lm[p] & 3;
+    const double rl2 = cd.proj_r[p] * cd.proj_r[p];
+    double d[6];
+    for (int k = 0; k < 6; ++k) d[k] = rl2 * q[1 + k] - (k < 3 ? 0.5 * P : 0.0);
+    if (l == 1) {
+      const double* q0 = w + SL.nl + ((size_t)(p - m) * nb + i) * 7;
+      const double Pm[3] = {q0[0], q0[(size_t)7 * nb], q0[(size_t)14 * nb]};
+      for (int k = 0; k < 6; ++k)
+        d[k] -= 0.5 * ((m == vb[k] ? Pm[va[k]] : 0.0) + (m == va[k] ? Pm[vb[k]] : 0.0));
+    }
+    const double c = 2.0 * cd.hproj[p] * f * P;
+    for (int k = 0; k < 6; ++k) a[6 + k] += c * d[k];
+  }
+  block_sum<12>(a, sh);
+  double g[15];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) g[k] = 0.0;
+  for (int b = threadIdx.x; b < kStressBlocks; b += blockDim.x)
+    for (int k = 0; k < 15; ++k) g[k] += w[SL.grid + 16 * (size_t)b + k];
+  block_sum<15>(g, sh);
+  double e[13];
+#pragma unroll
+  for (int k = 0; k < 13; ++k) e[k] = 0.0;
+  for (int I = threadIdx.x; I < cd.nat; I += blockDim.x)
+    for (int k = 0; k < 13; ++k) e[k] += w[SL.ew + 13 * (size_t)I + k];
+  block_sum<13>(e, sh);
+  if (threadIdx.x != 0) return;
+  const double om = cd.omega, eta = cd.ew_eta;
+  double zs = 0.0;
+  for (int J = 0; J < cd.nat; ++J) zs += sp[cd.spec[J]].Z;
+  const double e_recip = 2.0 * kPi / om * e[12];
+  const double e_bg = -kPi * zs * zs / (2.0 * om * eta * eta);
+  double part[6][6];
+  for (int k = 0; k < 6; ++k) {
+    const double dl = k < 3 ? 1.0 : 0.0;
+    part[0][k] = -a[k] / om;
+    part[1][k] = a[6 + k] / om;
+    part[2][k] = g[k] - 0.5 * g[12] * dl;
+    part[3][k] = g[6 + k] / om - g[13] * dl;
+    part[4][k] = g[14] / cd.ntot * dl;
+    part[5][k] = (e[k] + 2.0 * kPi / om * e[6 + k] - (e_recip + e_bg) * dl) / om;
+  }
+  auto put = [&](double* o, const double* s6) {
+    for (int k = 0; k < 6; ++k) {
+      o[3 * va[k] + vb[k]] = s6[k];
+      o[3 * vb[k] + va[k]] = s6[k];
+    }
+  };
+  double tot[6];
+  for (int k = 0; k < 6; ++k) {
+    tot[k] = 0.0;
+    for (int j = 0; j < 6; ++j) tot[k] += part[j][k];
+  }
+  put(cd.stress, tot);
+  for (int j = 0; j < 6; ++j) put(cd.stress + 9 + 9 * j, part[j]);
+}
+
 // ------------------------------------------------------------ occupations
 // Fixed: f = 2 on the lowest nocc bands.  Fermi-Dirac: f = 2/(1+e^{(e-mu)/s})
 // with mu from 200 bisection steps so that sum f = N_el; entropy
@@ -960,6 +1168,23 @@ void launch_force_finalize(const LaunchCtx& L) {
   hipLaunchKernelGGL(k_force_finalize, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
   check_launch("k_force_finalize");
   prof_after("k_force_finalize", L.stream);
+}
+void launch_stress_grid(const LaunchCtx& L) {
+  prof_before("k_stress_grid", L.stream);
+  hipLaunchKernelGGL(k_stress_grid, dim3(kStressBlocks, 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc, L.species);
+  check_launch("k_stress_grid");
+  prof_after("k_stress_grid", L.stream);
+  prof_before("k_stress_ewald", L.stream);
+  hipLaunchKernelGGL(k_stress_ewald, dim3(L.g.nat_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc, L.species);
+  check_launch("k_stress_ewald");
+  prof_after("k_stress_ewald", L.stream);
+  prof_before("k_stress_finalize", L.stream);
+  hipLaunchKernelGGL(k_stress_finalize, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
+                     L.species);
+  check_launch("k_stress_finalize");
+  prof_after("k_stress_finalize", L.stream);
 }
 void launch_occupations(const LaunchCtx& L) {
   prof_before("k_occupations", L.stream);

@@ -748,6 +748,68 @@ __global__ void __launch_bounds__(kNT) k_force_nonlocal(const CandDesc* __restri
   }
 }
 
+// ------------------------------------------------------------------ stress
+// Fixed-basis stress under the strain r -> (1 + eps) r: G.R is invariant and
+// d(G^2)/d eps_ab = -2 G_a G_b.  Wavefunction-side sums for band i:
+// kinetic K_ab = sum_G G_a G_b |c_G|^2 over the full sphere (a packed pair
+// x, y of +-G holds x^2 + y^2 = 2 |c_G|^2).
+__device__ __forceinline__ void gvec_of(const CandDesc& cd, int g, double* G) {
+  const double m1 = cd.gmill[3 * g], m2 = cd.gmill[3 * g + 1], m3 = cd.gmill[3 * g + 2];
+  G[0] = m1 * cd.B[0] + m2 * cd.B[3] + m3 * cd.B[6];
+  G[1] = m1 * cd.B[1] + m2 * cd.B[4] + m3 * cd.B[7];
+  G[2] = m1 * cd.B[2] + m2 * cd.B[5] + m3 * cd.B[8];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_stress_kinetic(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int i = blockIdx.x;
+  if (i >= cd.nb) return;
+  __shared__ double sh[16 * 6];
+  const T* x = (const T*)cd.X + (size_t)i * cd.Kp;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < cd.npwh; g += blockDim.x) {
+    double G[3];
+    gvec_of(cd, g, G);
+    const double a = x[2 * g], b = x[2 * g + 1];
+    add_voigt(v, a * a + b * b, G);
+  }
+  block_sum<6>(v, sh);
+  if (threadIdx.x == 0) {
+    double* o = cd.stwork + stress_layout(cd.nb, cd.nproj, cd.nat).kin + (size_t)6 * i;
+    for (int k = 0; k < 6; ++k) o[k] = v[k];
+  }
+}
+
+// Nonlocal sums for projector p and band i: P = <beta_p|psi_i> and
+// Q_ab = <G_a G_b beta_p|psi_i> (both real at the Gamma point).  The strain
+// derivative of beta (volume factor, radial part through G^2, and the
+// direction factor G_m of l = 1) is assembled from these in the finalize step.
+template <typename T>
+__global__ void __launch_bounds__(kNT) k_stress_nonlocal(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int p = blockIdx.x, i = blockIdx.y;
+  if (p >= cd.nproj || i >= cd.nb) return;
+  __shared__ double sh[16 * 7];
+  const T* b = (const T*)cd.beta + (size_t)p * cd.Kp;
+  const T* x = (const T*)cd.X + (size_t)i * cd.Kp;
+  double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < cd.npwh; g += blockDim.x) {
+    const double d = (double)b[2 * g] * x[2 * g] + (double)b[2 * g + 1] * x[2 * g + 1];
+    v[0] += d;
+    double G[3];
+    gvec_of(cd, g, G);
+    add_voigt(v + 1, d, G);
+  }
+  block_sum<7>(v, sh);
+  if (threadIdx.x == 0) {
+    double* o = cd.stwork + stress_layout(cd.nb, cd.nproj, cd.nat).nl + ((size_t)p * cd.nb + i) * 7;
+    for (int k = 0; k < 7; ++k) o[k] = v[k];
+  }
+}
+
 // V_eff(r) from the inverse transform of V(G) + i rho_in(G): real part is
 // V_loc + V_H, imaginary part the mixed input density.  Adds v_xc.
 template <typename T>
@@ -928,6 +990,20 @@ void launch_force_nonlocal(const LaunchCtx& L) {
   prof_after("k_force_nonlocal", L.stream);
 }
 template <typename T>
+void launch_stress_waves(const LaunchCtx& L) {
+  prof_before("k_stress_kinetic", L.stream);
+  hipLaunchKernelGGL(k_stress_kinetic<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc);
+  check_launch("k_stress_kinetic");
+  prof_after("k_stress_kinetic", L.stream);
+  if (L.g.nproj_max == 0) return;
+  prof_before("k_stress_nonlocal", L.stream);
+  hipLaunchKernelGGL(k_stress_nonlocal<T>, dim3(L.g.nproj_max, L.g.nb_max, L.g.ncand), dim3(kNT),
+                     0, L.stream, L.desc);
+  check_launch("k_stress_nonlocal");
+  prof_after("k_stress_nonlocal", L.stream);
+}
+template <typename T>
 void launch_potential_finalize(const LaunchCtx& L) {
   prof_before("k_potential_finalize", L.stream);
   hipLaunchKernelGGL(k_potential_finalize<T>, dim3((L.g.ntot_max + kNT - 1) / kNT, 1, L.g.ncand),
@@ -963,7 +1039,8 @@ void configure_wave() {
   template void launch_init_random<T>(const LaunchCtx&);                                  \
   template void launch_setup_beta<T>(const LaunchCtx&);                                   \
   template void launch_force_nonlocal<T>(const LaunchCtx&);                               \
-  template void launch_potential_finalize<T>(const LaunchCtx&);
+  template void launch_potential_finalize<T>(const LaunchCtx&);                           \
+  template void launch_stress_waves<T>(const LaunchCtx&);
 SGO_INST(float)
 SGO_INST(double)
 

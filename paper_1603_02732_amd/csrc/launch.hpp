@@ -43,6 +43,7 @@ template <typename T> void launch_band_kinetic(const LaunchCtx& L);
 template <typename T> void launch_init_random(const LaunchCtx& L);
 template <typename T> void launch_setup_beta(const LaunchCtx& L);
 template <typename T> void launch_force_nonlocal(const LaunchCtx& L);
+template <typename T> void launch_stress_waves(const LaunchCtx& L);
 template <typename T> void launch_potential_finalize(const LaunchCtx& L);
 void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps = 40);
 void launch_occupations(const LaunchCtx& L);
@@ -56,6 +57,7 @@ void launch_setup_grid(const LaunchCtx& L);
 void launch_ewald(const LaunchCtx& L);
 void launch_force_local(const LaunchCtx& L);
 void launch_force_finalize(const LaunchCtx& L);
+void launch_stress_grid(const LaunchCtx& L);  // grid, Ewald and finalize kernels
 
 // Enable large dynamic LDS for every kernel (once per process per device).
 void configure_kernels();

@@ -63,7 +63,7 @@ def full_coefficients(psi, millers_gpu, oracle_millers):
     return C
 
 
-def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say):
+def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say, stress=None, s_tol=None):
     """Hand the GPU's converged state (bands, occupations, density, V_eff) to
     the oracle and recompute, in FP64 with the oracle's own arithmetic: the
     density from the bands, every energy term, the Hellmann-Feynman forces and
@@ -76,7 +76,9 @@ def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say):
     f = stt["occ"]
     rho = np.transpose(stt["rho"], (2, 1, 0))
     veff = np.transpose(stt["veff"], (2, 1, 0))
+    say("  oracle check: setup done, %d plane waves" % st.npw)
     rho_o = st.density(C, f)
+    say("  oracle check: density done")
     d_rho = np.abs(rho_o - rho).max() / np.abs(rho).max()
     occ = system["occupation"]
     _, _, S = occupations(stt["eig"], st.nelec, occ)
@@ -84,8 +86,15 @@ def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say):
     out = {"density": d_rho}
     for k in ("kinetic", "nonlocal", "local", "hartree", "xc", "ewald"):
         out[k] = abs(terms[k] - stt["terms"][k]) / max(1.0, abs(terms[k]))
+    say("  oracle check: energy terms done")
     F_o, _ = hf_forces({"setup": st, "rho": rho, "C": C, "occupations": f})
+    say("  oracle check: forces done")
     out["forces"] = np.abs(F_o - forces).max()
+    if stress is not None:
+        from oracle.stress import stress as oracle_stress
+        sig_o, _ = oracle_stress({"setup": st, "rho": rho, "C": C, "occupations": f})
+        out["stress"] = np.abs(sig_o - stress).max()
+        say("  oracle check: stress done")
     HC = st.apply_h(veff, C)
     res = np.linalg.norm(HC - C * stt["eig"][None, :], axis=0)
     out["residual_charged"] = res[f > 1e-2].max()
@@ -94,4 +103,6 @@ def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say):
     for k in ("kinetic", "nonlocal", "local", "hartree", "xc", "ewald"):
         assert out[k] < e_rtol, k
     assert out["forces"] < f_tol
+    if stress is not None:
+        assert out["stress"] < s_tol
     return out

@@ -58,3 +58,33 @@ def test_autograd_fp32_sheet_matches_oracle_forces():
         % (dF, abs(float(E) - ref["energy"]) / 24))
     assert dF < 5e-4
     assert abs(float(E) - ref["energy"]) / 24 < 1e-5
+
+
+def test_autograd_lattice_gradient_matches_finite_differences():
+    """dE/dA from the stress (Cartesian positions fixed) against central
+    differences of the GPU energy over the cell; the step is small enough
+    that no plane wave crosses the cutoff sphere (checked), so the basis of
+    the strained cells is the fixed one the gradient refers to."""
+    import torch
+    import paper_1603_02732_amd as sgo
+    from paper_1603_02732_amd.autograd import ScfEnergy
+    s = workloads.tiny_system("sip", grid=(12, 12, 15))
+    ctx = sgo.context_from_system(s, sgo.SGO_FP64)
+    opts = sgo.default_opts(tol_e=1e-12, tol_rho=1e-10, max_iter=300)
+    R = torch.tensor(np.array(s["positions"]), dtype=torch.float64, requires_grad=True)
+    A = torch.tensor(np.array(s["lattice"]), dtype=torch.float64, requires_grad=True)
+    E = ScfEnergy.apply(R, ctx, opts, A)
+    gR, gA = torch.autograd.grad(1.5 * E, (R, A))
+    npw0 = len(ctx.basis()[0])
+    assert torch.allclose(gR, -1.5 * torch.from_numpy(ctx.forces()))
+    h = 1e-4
+    for (i, j) in [(0, 0), (0, 2), (2, 1)]:
+        e = []
+        for sg in (1, -1):
+            Ap = A.detach().clone()
+            Ap[i, j] += sg * h
+            e.append(float(ScfEnergy.apply(R.detach(), ctx, opts, Ap)))
+            assert len(ctx.basis()[0]) == npw0
+        fd = 1.5 * (e[0] - e[1]) / (2 * h)
+        say("dE/dA[%d,%d]: autograd %.9f  FD %.9f" % (i, j, float(gA[i, j]), fd))
+        assert abs(float(gA[i, j]) - fd) < 2e-6

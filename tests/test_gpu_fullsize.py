@@ -31,3 +31,26 @@ def test_c4_uneven_population_fp32():
         s = pop[i]
         say("candidate %d: %d atoms grid %s bands %d" % (i, nat[i], s["grid"], s["nbands"]))
         oracle_state_check(s, B.state(i), F[i], e_rtol=2e-6, f_tol=5e-4)
+
+
+def test_c5_large_cell_fp32_with_stress():
+    """128-atom Si cell (FFT 108x54x54, 282 bands, s+p projectors): solve to
+    the benchmark gate, then hand the state to the oracle, which recomputes
+    energies, forces and the fixed-basis stress from the same bands and
+    density (the stress here differs from the oracle's only by summation
+    order, so its bound is far below the parity tolerance)."""
+    import time
+    import paper_1603_02732_amd as sgo
+    s = workloads.config_c5()
+    B = sgo.Batch(1, precision=sgo.SGO_FP32)
+    B.add_system(s)
+    t0 = time.perf_counter()
+    E, F, st = B.scf(sgo.default_opts(tol_e=1e-5, tol_rho=1e-3, max_iter=200))
+    sig = B.stress()[0]
+    say("C5: status %d iterations %d  %.2f s  E %.8f" % (st[0], B.info(0)["iterations"],
+                                                         time.perf_counter() - t0, E[0]))
+    say("C5 stress diag (Ha/bohr^3)", np.diag(sig))
+    assert st[0] == 0
+    assert np.abs(F[0].sum(0)).max() < 5e-2
+    assert np.allclose(sig, sig.T)
+    oracle_state_check(s, B.state(0), F[0], e_rtol=2e-6, f_tol=5e-4, stress=sig, s_tol=1e-7)
