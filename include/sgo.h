@@ -224,7 +224,12 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
  * "SGO_SUB_THREADS" (threads of the subspace solver, 64..512),
  * "SGO_SP_CHUNK" (stick pairs per block of the z transforms),
  * "SGO_DENS_CHUNKS" (band-pair chunks of the density planes),
- * "SGO_RR_SWEEPS" (Jacobi sweeps of the intermediate subspace steps).
+ * "SGO_RR_SWEEPS" (Jacobi sweeps of the intermediate subspace steps),
+ * "SGO_PLANE_KERNEL" (FP32 plane transforms: 1 = register-resident line
+ * FFTs, the default where every line length is 2^a 3^b 5^c <= 64;
+ * 2 = LDS Stockham passes, used for FP64 and longer lines),
+ * "SGO_GEMM_KERNEL" (FP32 band products X M: 1 = FP32 MFMA with FP32
+ * accumulation, the default; 2 = FP64 MFMA on the FP32 data).
  * value <= 0 restores the default (or the environment variable of the same
  * name).  SGO_EINVAL for an unknown key.  sgo_get_tuning returns the value
  * set (0 if none). */

@@ -51,6 +51,7 @@ struct CandDesc {
   int Kp, pad_kp;   // Kp: row stride of band arrays (K rounded up to 32, zero padded)
   int nsp, nst, nproj, nat;
   int occ_kind, nocc, active, ncand_index;
+  int pl_nx, pl_nxl, pl_sx, pl_pad;  // active x columns of the planes (register FFT kernels)
   double sigma, nelec, omega, pad0;
   double A[9];
   double B[9];

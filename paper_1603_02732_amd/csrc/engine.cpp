@@ -141,6 +141,7 @@ struct HostCand {
   int nocc = 0;
   int npwh = 0, K = 0, Kp = 0, nsp = 0, nst = 0, npair = 0, nproj = 0, ntot = 0;
   std::vector<int> gmill, gmeta, sp_off, stick_xy, proj_atom, proj_lm;
+  int pl_nx = 0, pl_nxl = 0, pl_sx = 1;  // active plane columns (register FFT kernels)
   std::vector<double> kin, hproj, proj_r;
   FftPlan plan[3];
   double ew_eta = 0, ew_rcut = 0, ew_gcut = 0;
@@ -391,11 +392,17 @@ class Engine {
     }
     for (int q = 0; q < c.nsp; ++q) c.sp_off[q + 1] += c.sp_off[q];
     c.stick_xy.resize(c.nst);
+    int m1max = 0;
     for (int s = 0; s < c.nst; ++s) {
       const int i1 = ((sticks[s].first % c.N[0]) + c.N[0]) % c.N[0];
       const int i2 = ((sticks[s].second % c.N[1]) + c.N[1]) % c.N[1];
       c.stick_xy[s] = i1 | (i2 << 16);
+      m1max = std::max(m1max, std::abs(sticks[s].first));
     }
+    // active x columns of the planes: x <= m1max and x >= N1 - m1max
+    c.pl_nx = std::min(2 * m1max + 1, c.N[0]);
+    c.pl_nxl = c.pl_nx == c.N[0] ? c.N[0] : m1max + 1;
+    c.pl_sx = c.pl_nx | 1;
     // electrons, occupations
     c.nelec = 0;
     for (int I = 0; I < c.nat; ++I) c.nelec += species_[c.spec[I]].d.Z;
@@ -523,6 +530,9 @@ class Engine {
     d.nst = c.nst;
     d.nproj = c.nproj;
     d.nat = c.nat;
+    d.pl_nx = c.pl_nx;
+    d.pl_nxl = c.pl_nxl;
+    d.pl_sx = c.pl_sx;
     d.occ_kind = c.occ_kind;
     d.nocc = c.nocc;
     d.active = 1;
@@ -584,6 +594,7 @@ class Engine {
       g.plane_max = std::max(g.plane_max, c.N[0] * c.N[1]);
       g.K_max = std::max(g.K_max, c.K);
       g.ew_ng_max = std::max(g.ew_ng_max, c.ew_ng);
+      g.pl_sx_max = std::max(g.pl_sx_max, c.pl_sx);
     }
     g.sp_chunk = std::max(1, tune("SGO_SP_CHUNK", std::max(1, 640 / std::max(1, g.N3max))));
     {  // the z kernels hold 2 x (2 sp_chunk) sticks of N3 complex values in LDS
@@ -595,10 +606,20 @@ class Engine {
     g.kc_len = (g.kc_len + 31) / 32 * 32;
     g.sub_threads = std::max(64, std::min(512, tune("SGO_SUB_THREADS", 512) / 64 * 64));
     g.nkc_max = (g.K_max + g.kc_len - 1) / g.kc_len;
+    // FP32 register-FFT plane kernels when every line length is supported
+    // and the compact plane (plus the density accumulator) fits the LDS
+    g.plane_reg = tsize() == 4 && tune("SGO_PLANE_KERNEL", 1) == 1 ? 1 : 0;
+    for (auto& c : cands_)
+      if (!plane_reg_length_ok(c.N[0]) || !plane_reg_length_ok(c.N[1])) g.plane_reg = 0;
+    if (plane_reg_lds(g, true) > (size_t)g_lds_limit) g.plane_reg = 0;
+    g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
     // band-pair chunks of the density planes: enough blocks to fill the chip
-    // (planes x candidates x chunks >= 512), no more (each chunk is a grid)
+    // (planes x candidates x chunks >= 512 blocks of 4 waves, or 4096
+    // one-wave blocks for the register-FFT kernel), no more (each chunk is a
+    // grid of partial sums)
     const int planes = std::max(1, g.N3max * g.ncand);
-    g.dens_chunks = std::max(1, std::min(g.npair_max, tune("SGO_DENS_CHUNKS", (512 + planes - 1) / planes)));
+    const int want = g.plane_reg ? 4096 : 512;
+    g.dens_chunks = std::max(1, std::min(g.npair_max, tune("SGO_DENS_CHUNKS", (want + planes - 1) / planes)));
     return g;
   }
 
@@ -1555,7 +1576,8 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
 int sgo_set_tuning(const char* key, int value) {
   if (!key) return SGO_EINVAL;
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
-                                "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS"};
+                                "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
+                                "SGO_GEMM_KERNEL"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;

@@ -1212,6 +1212,7 @@ void configure_kernels() {
   allow_lds((const void*)k_grid_fft_yz);
   allow_lds((const void*)k_subspace);
   configure_wave();
+  configure_plane_kernels();
 }
 
 }  // namespace sgo

@@ -1,0 +1,290 @@
+// FP32 plane kernels of the band FFTs with register-resident line transforms
+// (Algorithm 1 "Calculate H|psi>": the local-potential product in real
+// space; Section 2.4: the output density).  One wavefront takes one z-plane
+// of one band pair.  The plane lives in LDS only over its active x columns
+// (the projection of the wavefunction sphere, |m1| <= m1max, stored
+// compactly with an odd row stride so that both the column-wise and the
+// row-wise accesses are free of bank conflicts).  Each lane transforms a
+// whole line in registers (fft_reg.hpp):
+//   y pass   one lane per active column (the other columns are zero),
+//   x pass   one lane per row: inverse transform, times V_eff, forward
+//            transform, keeping only the active columns,
+//   y pass   forward, then the stick values are gathered.
+// The y and x phases are dispatched on N2 and N1 separately, so the kernel
+// carries one instantiation per supported length and axis, not per pair.
+#include "device.hpp"
+#include "fft_reg.hpp"
+#include "launch.hpp"
+
+namespace sgo {
+
+#define SGO_LINE_SIZES(X) \
+  X(8) X(9) X(10) X(12) X(15) X(16) X(18) X(20) X(24) X(25) X(27) X(30) X(32) X(36) X(40) X(45) \
+  X(48) X(50) X(54) X(60) X(64)
+
+bool plane_reg_length_ok(int n) {
+  switch (n) {
+#define SGO_CASE(N) \
+  case N:           \
+    return true;
+    SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+    default:
+      return false;
+  }
+}
+
+struct PlaneLds {
+  cplx<float>* Q;  // [N2][sx], active columns only
+  int sx;          // row stride (odd, >= nx)
+  int nx, nxl;     // active columns: x < nxl and x >= N1 - (nx - nxl)
+};
+
+__device__ __forceinline__ int col_of_x(const PlaneLds& p, int N1, int x) {
+  return x < p.nxl ? x : x - (N1 - p.nx);
+}
+
+template <int N2, int S>
+__device__ __forceinline__ void column_pass(const PlaneLds& p, int lane) {
+  if (lane >= p.nx) return;
+  cplx<float> v[N2], w[N2];
+#pragma unroll
+  for (int k = 0; k < N2; ++k) v[k] = p.Q[k * p.sx + lane];
+  freg::fft<float, S, N2>(v, w);
+#pragma unroll
+  for (int k = 0; k < N2; ++k) p.Q[k * p.sx + lane] = w[k];
+}
+
+template <int S>
+__device__ __forceinline__ void column_pass_rt(const PlaneLds& p, int N2, int lane) {
+  switch (N2) {
+#define SGO_CASE(N)              \
+  case N:                        \
+    column_pass<N, S>(p, lane); \
+    break;
+    SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+    default:
+      break;
+  }
+}
+
+// Row y of the plane into registers (zeros outside the active columns).
+template <int N1>
+__device__ __forceinline__ void load_row(const PlaneLds& p, int y, cplx<float> (&v)[N1]) {
+  const int hi0 = N1 - (p.nx - p.nxl);
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const bool act = k < p.nxl || k >= hi0;
+    const int c = act ? (k < p.nxl ? k : k - hi0 + p.nxl) : 0;
+    const cplx<float> q = p.Q[y * p.sx + c];
+    v[k] = act ? q : cplx<float>{0.f, 0.f};
+  }
+}
+
+template <int N1>
+__device__ __forceinline__ void load_vrow(const float* __restrict__ V, float (&r)[N1]) {
+  if constexpr (N1 % 4 == 0) {
+#pragma unroll
+    for (int k = 0; k < N1 / 4; ++k) {
+      const float4 q = reinterpret_cast<const float4*>(V)[k];
+      r[4 * k] = q.x;
+      r[4 * k + 1] = q.y;
+      r[4 * k + 2] = q.z;
+      r[4 * k + 3] = q.w;
+    }
+  } else if constexpr (N1 % 2 == 0) {
+#pragma unroll
+    for (int k = 0; k < N1 / 2; ++k) {
+      const float2 q = reinterpret_cast<const float2*>(V)[k];
+      r[2 * k] = q.x;
+      r[2 * k + 1] = q.y;
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < N1; ++k) r[k] = V[k];
+  }
+}
+
+// x pass of H psi for row y: inverse transform, V_eff product, forward
+// transform; the active columns are written back.
+template <int N1>
+__device__ __forceinline__ void row_pass_hpsi(const PlaneLds& p, int y, const float* __restrict__ V) {
+  cplx<float> v[N1], w[N1];
+  load_row<N1>(p, y, v);
+  freg::fft<float, +1, N1>(v, w);
+  float vr[N1];
+  load_vrow<N1>(V, vr);
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    w[k].x *= vr[k];
+    w[k].y *= vr[k];
+  }
+  freg::fft<float, -1, N1>(w, v);
+  const int hi0 = N1 - (p.nx - p.nxl);
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    if (k < p.nxl) p.Q[y * p.sx + k] = v[k];
+    else if (k >= hi0) p.Q[y * p.sx + k - hi0 + p.nxl] = v[k];
+  }
+}
+
+__device__ __forceinline__ PlaneLds plane_of(const CandDesc& cd, cplx<float>* base) {
+  PlaneLds p;
+  p.Q = base;
+  p.nx = cd.pl_nx;
+  p.nxl = cd.pl_nxl;
+  p.sx = cd.pl_sx;
+  return p;
+}
+
+// Sticks of plane (pair, z) into the compact plane (zeros elsewhere).
+__device__ __forceinline__ void scatter_sticks(const CandDesc& cd, const PlaneLds& p,
+                                               const cplx<float>* __restrict__ st, int lane) {
+  const int n = cd.N2 * p.sx;
+  for (int e = lane; e < n; e += 64) p.Q[e] = {0.f, 0.f};
+  __syncthreads();
+  for (int s = lane; s < cd.nst; s += 64) {
+    const int xy = cd.stick_xy[s];
+    p.Q[(xy >> 16) * p.sx + col_of_x(p, cd.N1, xy & 0xFFFF)] = st[s];
+  }
+  __syncthreads();
+}
+
+// H psi, local part, of one plane of one band pair: sticks are read, and
+// overwritten by the forward transform of V_eff times the inverse transform.
+__global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int z = blockIdx.x, pair = blockIdx.y;
+  if (z >= cd.N3 || pair >= cd.npair) return;
+  extern __shared__ __align__(16) char smem[];
+  PlaneLds p = plane_of(cd, (cplx<float>*)smem);
+  const int lane = threadIdx.x;
+  cplx<float>* st = (cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
+  scatter_sticks(cd, p, st, lane);
+  column_pass_rt<+1>(p, cd.N2, lane);
+  __syncthreads();
+  // strides re-declared opaque between phases: per-line offsets are then
+  // recomputed in each phase instead of being held across all of them
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  if (lane < cd.N2) {
+    const float* V = (const float*)cd.veff_t + ((size_t)z * cd.N2 + lane) * cd.N1;
+    switch (cd.N1) {
+#define SGO_CASE(N)                       \
+  case N:                                 \
+    row_pass_hpsi<N>(p, lane, V);         \
+    break;
+      SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+      default:
+        break;
+    }
+  }
+  __syncthreads();
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  column_pass_rt<-1>(p, cd.N2, lane);
+  __syncthreads();
+  for (int s = lane; s < cd.nst; s += 64) {
+    const int xy = cd.stick_xy[s];
+    st[s] = p.Q[(xy >> 16) * p.sx + col_of_x(p, cd.N1, xy & 0xFFFF)];
+  }
+}
+
+// Density of one plane summed over a chunk of band pairs,
+// part[chunk][z][y][x] = sum_pairs f_a Re(u)^2 + f_b Im(u)^2 (u = psi_a + i psi_b,
+// unnormalised), accumulated in FP64 in LDS (row stride N1 | 1).
+template <int N1>
+__device__ __forceinline__ void row_pass_density(const PlaneLds& p, int y, double* acc, double fa,
+                                                 double fb) {
+  cplx<float> v[N1], w[N1];
+  load_row<N1>(p, y, v);
+  freg::fft<float, +1, N1>(v, w);
+  // this pair's contribution, then the FP64 accumulation in groups of 8 (a
+  // scheduling fence per group keeps the accumulator loads from all being
+  // hoisted at once)
+  const float fa32 = (float)fa, fb32 = (float)fb;
+  double* a = acc + y * (N1 | 1);
+  freg::static_for<0, (N1 + 7) / 8>([&](auto q) {
+    constexpr int K0 = 8 * decltype(q)::value;
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = K0; k < (K0 + 8 < N1 ? K0 + 8 : N1); ++k)
+      a[k] += (double)(fa32 * w[k].x * w[k].x + fb32 * w[k].y * w[k].y);
+  });
+}
+
+__global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int z = blockIdx.x, chunk = blockIdx.y;
+  if (z >= cd.N3 || chunk >= cd.ndens_chunk) return;
+  extern __shared__ __align__(16) char smem[];
+  const PlaneLds p_outer = plane_of(cd, (cplx<float>*)smem);
+  double* acc = (double*)(smem + (size_t)cd.N2 * p_outer.sx * sizeof(cplx<float>));
+  const int lane = threadIdx.x;
+  const int N1 = cd.N1, N2 = cd.N2, ar = N1 | 1;
+  for (int e = lane; e < N2 * ar; e += 64) acc[e] = 0.0;
+  const int per = (cd.npair + cd.ndens_chunk - 1) / cd.ndens_chunk;
+  const int p0 = chunk * per, p1 = min(cd.npair, p0 + per);
+  for (int pair = p0; pair < p1; ++pair) {
+    // the plane strides are re-declared opaque in every iteration, so the
+    // per-line offsets of all line lengths are not hoisted out of the loop
+    // (they would exhaust the scalar registers)
+    PlaneLds p = p_outer;
+    asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+    const cplx<float>* st = (const cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
+    scatter_sticks(cd, p, st, lane);
+    column_pass_rt<+1>(p, N2, lane);
+    __syncthreads();
+    const double fa = cd.occ[2 * pair];
+    const double fb = 2 * pair + 1 < cd.nb ? cd.occ[2 * pair + 1] : 0.0;
+    if (lane < N2) {
+      switch (N1) {
+#define SGO_CASE(N)                                   \
+  case N:                                             \
+    row_pass_density<N>(p, lane, acc, fa, fb);        \
+    break;
+        SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+        default:
+          break;
+      }
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  double* out = cd.dens_part + (size_t)chunk * cd.ntot + (size_t)z * N1 * N2;
+  for (int e = lane; e < N1 * N2; e += 64) out[e] = acc[(e / N1) * ar + e % N1];
+}
+
+size_t plane_reg_lds(const BatchGeom& g, bool density) {
+  size_t b = (size_t)g.N2max * g.pl_sx_max * sizeof(cplx<float>);
+  if (density) b += (size_t)g.N2max * (g.N1max | 1) * sizeof(double);
+  return b;
+}
+
+void launch_plane_hpsi_reg(const LaunchCtx& L) {
+  const BatchGeom& g = L.g;
+  dim3 gp(g.N3max, g.npair_max, g.ncand);
+  prof_before("k_plane_hpsi", L.stream);
+  hipLaunchKernelGGL(k_plane_hpsi_reg, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
+  check_launch("k_plane_hpsi");
+  prof_after("k_plane_hpsi", L.stream);
+}
+
+void launch_plane_density_reg(const LaunchCtx& L) {
+  const BatchGeom& g = L.g;
+  dim3 gp(g.N3max, g.dens_chunks, g.ncand);
+  prof_before("k_plane_density", L.stream);
+  hipLaunchKernelGGL(k_plane_density_reg, gp, dim3(64), plane_reg_lds(g, true), L.stream, L.desc);
+  check_launch("k_plane_density");
+  prof_after("k_plane_density", L.stream);
+}
+
+void configure_plane_kernels() {
+  allow_lds((const void*)k_plane_hpsi_reg);
+  allow_lds((const void*)k_plane_density_reg);
+}
+
+}  // namespace sgo

@@ -15,6 +15,8 @@
 #include "device.hpp"
 #include "launch.hpp"
 
+#include <type_traits>
+
 #include <algorithm>
 
 namespace sgo {
@@ -535,6 +537,83 @@ __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ c
   }
 }
 
+// FP32 band products on MFMA (FP32 bulk path):
+//   Y[i][k] = alpha Y[i][k] + beta sum_j M'[j][i] A[j][k],  M' = M or h_j M,
+// with v_mfma_f32_16x16x4f32 and FP32 accumulation.  One wavefront per
+// 64-column slice of every output row; the A slice (nin x 64) is staged in
+// LDS before any store, so Y may alias A (in-place rotation).  Column n of
+// MFMA tile c is k = k0 + 4n + c: a lane's float4 of a band row is then its
+// B operand for the four column tiles, and each result row leaves as one
+// float4 per lane.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cds, int y0, int y1,
+                                                 int y2, int a0, int a1, int a2, int mat, float alpha,
+                                                 float beta, int use_h) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int arr = blockIdx.y;
+  const int wy = arr == 0 ? y0 : (arr == 1 ? y1 : y2);
+  const int wa = arr == 0 ? a0 : (arr == 1 ? a1 : a2);
+  const int nin = wrows(cd, wa), nout = wrows(cd, wy);
+  if (nin == 0) return;
+  const int Kp = cd.Kp;
+  const int k0 = blockIdx.x * 64;
+  if (k0 >= cd.K) return;
+  const float* A = warr<float>(cd, wa);
+  float* Y = warr<float>(cd, wy);
+  const double* M = marr(cd, mat);
+  const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+  const int kc = k0 + 4 * n;          // first of this lane's four columns
+  const bool kin = kc < Kp;           // Kp is a multiple of 32: all four or none
+  extern __shared__ __align__(16) char smem[];
+  float4* As = (float4*)smem;         // [nin][16] float4 = [nin][64] floats
+  for (int j = g; j < nin; j += 4)
+    As[j * 16 + n] = kin ? *(const float4*)(A + (size_t)j * Kp + kc) : make_float4(0.f, 0.f, 0.f, 0.f);
+  __syncthreads();
+  for (int i0 = 0; i0 < nout; i0 += 64) {
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int j0 = 0; j0 < nin; j0 += 4) {
+      const int j = j0 + g;
+      const float4 b = j < nin ? As[j * 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+      const double hj = (use_h && j < nin) ? cd.hproj[j] : 1.0;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (i0 + 16 * t >= nout) break;
+        const int i = i0 + 16 * t + n;
+        const float a = (j < nin && i < nout) ? (float)(hj * M[(size_t)j * nout + i]) : 0.f;
+        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.x, acc[t][0], 0, 0, 0);
+        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.y, acc[t][1], 0, 0, 0);
+        acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.z, acc[t][2], 0, 0, 0);
+        acc[t][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.w, acc[t][3], 0, 0, 0);
+      }
+    }
+    if (!kin) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + 16 * t + 4 * g + r;
+        if (i >= nout) continue;
+        float4* yp = (float4*)(Y + (size_t)i * Kp + kc);
+        float4 o = make_float4(beta * acc[t][0][r], beta * acc[t][1][r], beta * acc[t][2][r],
+                               beta * acc[t][3][r]);
+        if (alpha != 0.f) {
+          const float4 q = *yp;
+          o.x += alpha * q.x;
+          o.y += alpha * q.y;
+          o.z += alpha * q.z;
+          o.w += alpha * q.w;
+        }
+        *yp = o;
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------- band kernels
 // Teter-Payne-Allan preconditioner K(x), x = (|G|^2/2) / E_kin(band).
 __device__ __forceinline__ double tpa(double x) {
@@ -848,11 +927,15 @@ void launch_hpsi(const LaunchCtx& L, int src) {
   hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, g.sp_chunk);
   check_launch("k_z_inverse");
   prof_after("k_z_inverse", L.stream);
-  dim3 gp(g.N3max, g.npair_max, g.ncand);
-  prof_before("k_plane_hpsi", L.stream);
-  hipLaunchKernelGGL(k_plane_hpsi<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
-  check_launch("k_plane_hpsi");
-  prof_after("k_plane_hpsi", L.stream);
+  if (std::is_same<T, float>::value && g.plane_reg) {
+    launch_plane_hpsi_reg(L);
+  } else {
+    dim3 gp(g.N3max, g.npair_max, g.ncand);
+    prof_before("k_plane_hpsi", L.stream);
+    hipLaunchKernelGGL(k_plane_hpsi<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
+    check_launch("k_plane_hpsi");
+    prof_after("k_plane_hpsi", L.stream);
+  }
   prof_before("k_z_forward", L.stream);
   hipLaunchKernelGGL(k_z_forward<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, dst,
                      g.sp_chunk);
@@ -875,11 +958,15 @@ void launch_density(const LaunchCtx& L) {
                      g.sp_chunk);
   check_launch("k_z_inverse");
   prof_after("k_z_inverse", L.stream);
-  dim3 gp(g.N3max, g.dens_chunks, g.ncand);
-  prof_before("k_plane_density", L.stream);
-  hipLaunchKernelGGL(k_plane_density<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
-  check_launch("k_plane_density");
-  prof_after("k_plane_density", L.stream);
+  if (std::is_same<T, float>::value && g.plane_reg) {
+    launch_plane_density_reg(L);
+  } else {
+    dim3 gp(g.N3max, g.dens_chunks, g.ncand);
+    prof_before("k_plane_density", L.stream);
+    hipLaunchKernelGGL(k_plane_density<T>, gp, dim3(kNT), plane_lds<T>(g), L.stream, L.desc);
+    check_launch("k_plane_density");
+    prof_after("k_plane_density", L.stream);
+  }
 }
 
 template <typename T>
@@ -924,6 +1011,18 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
   (void)rows;
   const int y1 = narr > 1 ? y[1] : 0, y2 = narr > 2 ? y[2] : 0;
   const int a1 = narr > 1 ? a[1] : 0, a2 = narr > 2 ? a[2] : 0;
+  int nin_max = 0;
+  for (int q = 0; q < narr; ++q) nin_max = std::max(nin_max, a[q] == W_BETA ? g.nproj_max : g.nb_max);
+  const size_t lds32 = (size_t)nin_max * 64 * sizeof(float);
+  if (std::is_same<T, float>::value && lds32 <= 65536 && g.gemm_f32) {
+    prof_before("k_gemm_acc", L.stream);
+    hipLaunchKernelGGL(k_gemm_f32, dim3((g.K_max + 63) / 64, narr, g.ncand), dim3(64), lds32,
+                       L.stream, L.desc, y[0], y1, y2, a[0], a1, a2, mat, (float)alpha,
+                       (float)beta, use_h);
+    check_launch("k_gemm_acc");
+    prof_after("k_gemm_acc", L.stream);
+    return;
+  }
   prof_before("k_gemm_acc", L.stream);
   if (nib <= 4)
     hipLaunchKernelGGL((k_gemm_acc<T, 1>), grid, dim3(kNT), lds, L.stream, L.desc, y[0], y1, y2,
@@ -1023,6 +1122,7 @@ static void configure_t() {
   allow_lds((const void*)k_gemm_acc<T, 5>);
 }
 void configure_wave() {
+  allow_lds((const void*)k_gemm_f32);
   configure_t<float>();
   configure_t<double>();
 }

@@ -14,6 +14,9 @@ struct BatchGeom {
   int ncand;
   int npair_max, nsp_max, nb_max, nproj_max, nat_max;
   int N1max, N2max, N3max, ntot_max, plane_max;
+  int plane_reg;   // 1: FP32 register-FFT plane kernels for every candidate
+  int pl_sx_max;   // largest compact plane row stride
+  int gemm_f32;    // 1: FP32-MFMA band products in the FP32 path
   int K_max;
   int sp_chunk;      // stick pairs per block of the z kernels
   int kc_len;        // K range per block of the split-K products
@@ -61,6 +64,12 @@ void launch_stress_grid(const LaunchCtx& L);  // grid, Ewald and finalize kernel
 
 // Enable large dynamic LDS for every kernel (once per process per device).
 void configure_kernels();
+// Register-FFT plane kernels (FP32, line lengths 2^a 3^b 5^c up to 64).
+bool plane_reg_length_ok(int n);
+size_t plane_reg_lds(const BatchGeom& g, bool density);
+void launch_plane_hpsi_reg(const LaunchCtx& L);
+void launch_plane_density_reg(const LaunchCtx& L);
+void configure_plane_kernels();
 // Raise the dynamic-LDS limit of one kernel to what the device allows.
 void allow_lds(const void* kernel);
 // Report a failed launch by kernel name (throws on the host side).
