@@ -116,6 +116,15 @@ def main():
     for _ in range(a.warmup):
         step()
     sync()
+    if have_torch:
+        # a plain device copy of known size (read 64 MiB, write 64 MiB): the
+        # reference that scales hardware byte counters (FETCH_SIZE,
+        # WRITE_SIZE) of a profiled run to bytes
+        src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.add(src, 0.0, out=dst)
+        sync()
+        del src, dst
     shares = {}
     t0 = time.perf_counter()
     step()

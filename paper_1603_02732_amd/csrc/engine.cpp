@@ -196,6 +196,8 @@ class Engine {
     if (d_species_) (void)hipFree(d_species_);
     if (d_desc_) (void)hipFree(d_desc_);
     if (d_iter_) (void)hipFree(d_iter_);
+    if (d_scal_all_) (void)hipFree(d_scal_all_);
+    if (h_scal_all_) (void)hipHostFree(h_scal_all_);
     if (own_stream_) (void)hipStreamDestroy(own_stream_);
   }
 
@@ -734,12 +736,27 @@ class Engine {
     launch_gemm_acc<T>(L, 1, y, y, M_M, 0.0, 1.0, 0);
   }
 
+  // Status scalars of every candidate: one gather kernel and one copy into
+  // pinned host memory.
   void read_scal(std::vector<std::array<double, S_COUNT>>& out) {
-    out.resize(cands_.size());
-    for (size_t i = 0; i < cands_.size(); ++i)
-      HIPCHK(hipMemcpyAsync(out[i].data(), cands_[i].d.scal, S_COUNT * 8, hipMemcpyDeviceToHost,
-                            stream_));
+    const size_t n = cands_.size();
+    out.resize(n);
+    if (scal_cap_ < n) {
+      if (d_scal_all_) (void)hipFree(d_scal_all_);
+      if (h_scal_all_) (void)hipHostFree(h_scal_all_);
+      d_scal_all_ = nullptr;
+      h_scal_all_ = nullptr;
+      scal_cap_ = 0;
+      HIPCHK(hipMalloc(&d_scal_all_, n * S_COUNT * 8));
+      HIPCHK(hipHostMalloc((void**)&h_scal_all_, n * S_COUNT * 8, hipHostMallocDefault));
+      scal_cap_ = n;
+    }
+    LaunchCtx L = ctx(BatchGeom{});
+    L.g.ncand = (int)n;
+    launch_gather_scal(L, d_scal_all_);
+    HIPCHK(hipMemcpyAsync(h_scal_all_, d_scal_all_, n * S_COUNT * 8, hipMemcpyDeviceToHost, stream_));
     HIPCHK(hipStreamSynchronize(stream_));
+    for (size_t i = 0; i < n; ++i) std::memcpy(out[i].data(), h_scal_all_ + i * S_COUNT, S_COUNT * 8);
   }
 
   // One SCF iteration after the first: mix the previous output into the new
@@ -1104,6 +1121,9 @@ class Engine {
   CandDesc* d_desc_ = nullptr;
   size_t desc_cap_ = 0;
   int* d_iter_ = nullptr;             // SCF iteration counter (device)
+  double* d_scal_all_ = nullptr;      // [ncand][S_COUNT] gathered status scalars (device)
+  double* h_scal_all_ = nullptr;      // pinned host copy
+  size_t scal_cap_ = 0;
   hipStream_t own_stream_ = nullptr;  // used for graph capture when no stream is set
   bool desc_dirty_ = true;
 };

@@ -78,6 +78,9 @@ __device__ __forceinline__ IterSlots slots_of(int it, int H) {
 __device__ __forceinline__ int nblk(const CandDesc& cd) {
   return min(1024, (cd.ntot + kNT - 1) / kNT);
 }
+// partial-sum regions of the per-iteration grid kernels in red_part
+constexpr int kPartDens = 0;      // [nblk][3]  density_finalize
+constexpr int kPartRes = 4096;    // [nblk][10] gspace_residual
 
 // ------------------------------------------------------------ full-grid FFT
 // Rows along x (contiguous).
@@ -161,15 +164,9 @@ __global__ void __launch_bounds__(kNT) k_density_finalize(const CandDesc* __rest
     v[2] += cd.veff_r[e] * rho;
   }
   block_sum<3>(v, sh);
-  double out[3];
-  if (grid_sum_last<3>(v, cd.red_part, &cd.tickets[kTicketGrid], nblk(cd), blockIdx.x, out, sh)) {
-    if (threadIdx.x == 0) {
-      const double w = cd.omega / cd.ntot;
-      cd.scal[S_DRHO] = w * out[0] / fmax(cd.nelec, 1e-30);
-      cd.scal[S_EXC] = w * out[1];
-      cd.scal[S_VRHO] = w * out[2];
-    }
-  }
+  // per-block partial sums; k_scf_control adds them up in a fixed order
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) cd.red_part[kPartDens + 3 * blockIdx.x + k] = v[k];
 }
 
 // After the forward FFT of rho_out: rho_out(G), density residual into the
@@ -210,19 +207,8 @@ __global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restr
     }
   }
   block_sum<10>(v, sh);
-  double out[10];
-  if (grid_sum_last<10>(v, cd.red_part, &cd.tickets[kTicketGrid + 1], nblk(cd), blockIdx.x, out,
-                        sh)) {
-    if (threadIdx.x == 0) {
-      cd.scal[S_EH] = 0.5 * cd.omega * out[0];
-      cd.scal[S_ELOC] = cd.omega * out[1];
-      for (int l = 0; l < nvalid; ++l) {
-        const int slot = (cur - l + H) % H;
-        cd.pulay[cur * kMaxHist + slot] = out[2 + l];
-        cd.pulay[slot * kMaxHist + cur] = out[2 + l];
-      }
-    }
-  }
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 10; ++k) cd.red_part[kPartRes + 10 * blockIdx.x + k] = v[k];
 }
 
 // Pulay coefficients, total free energy, convergence flags (one block per
@@ -230,11 +216,38 @@ __global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restr
 __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_atom, double tol_rho) {
   const CandDesc& cd = cds[blockIdx.x];
   if (!cd.active) return;
-  if (threadIdx.x != 0) return;
   const IterSlots sl = slots_of(*cd.iter_state, cd.hist_len);
   const int cur = sl.cur, nvalid = sl.nvalid, iter = sl.it;
   const int H = cd.hist_len;
   double* sc = cd.scal;
+  {
+    // block partials of k_density_finalize and k_gspace_residual, summed in
+    // a fixed order (one wavefront: lane-strided, then the cross-lane tree)
+    const int nbk = nblk(cd);
+    double v[13];
+#pragma unroll
+    for (int k = 0; k < 13; ++k) v[k] = 0.0;
+    for (int b = threadIdx.x; b < nbk; b += 64) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) v[k] += cd.red_part[kPartDens + 3 * b + k];
+#pragma unroll
+      for (int k = 0; k < 10; ++k) v[3 + k] += cd.red_part[kPartRes + 10 * b + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 13; ++k) v[k] = wave_sum(v[k]);
+    if (threadIdx.x != 0) return;
+    const double w = cd.omega / cd.ntot;
+    sc[S_DRHO] = w * v[0] / fmax(cd.nelec, 1e-30);
+    sc[S_EXC] = w * v[1];
+    sc[S_VRHO] = w * v[2];
+    sc[S_EH] = 0.5 * cd.omega * v[3];
+    sc[S_ELOC] = cd.omega * v[4];
+    for (int l = 0; l < nvalid; ++l) {
+      const int slot = (cur - l + H) % H;
+      cd.pulay[cur * kMaxHist + slot] = v[5 + l];
+      cd.pulay[slot * kMaxHist + cur] = v[5 + l];
+    }
+  }
   // Pulay: minimise |sum c_l R_l| with sum c_l = 1
   const int n = nvalid;
   double A[kMaxHist + 1][kMaxHist + 2];
@@ -1121,6 +1134,15 @@ void launch_gspace_residual(const LaunchCtx& L) {
                      L.stream, L.desc);
   check_launch("k_gspace_residual");
   prof_after("k_gspace_residual", L.stream);
+}
+// Status scalars of every candidate into one array (one host copy per read).
+__global__ void k_gather_scal(const CandDesc* __restrict__ cds, double* __restrict__ out) {
+  const CandDesc& cd = cds[blockIdx.x];
+  for (int k = threadIdx.x; k < S_COUNT; k += blockDim.x) out[(size_t)blockIdx.x * S_COUNT + k] = cd.scal[k];
+}
+void launch_gather_scal(const LaunchCtx& L, double* out) {
+  hipLaunchKernelGGL(k_gather_scal, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, out);
+  check_launch("k_gather_scal");
 }
 void launch_scf_control(const LaunchCtx& L, double tol_e_atom, double tol_rho) {
   prof_before("k_scf_control", L.stream);

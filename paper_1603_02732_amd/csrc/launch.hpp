@@ -60,7 +60,8 @@ void launch_setup_grid(const LaunchCtx& L);
 void launch_ewald(const LaunchCtx& L);
 void launch_force_local(const LaunchCtx& L);
 void launch_force_finalize(const LaunchCtx& L);
-void launch_stress_grid(const LaunchCtx& L);  // grid, Ewald and finalize kernels
+void launch_stress_grid(const LaunchCtx& L);
+void launch_gather_scal(const LaunchCtx& L, double* out);  // [ncand][S_COUNT]  // grid, Ewald and finalize kernels
 
 // Enable large dynamic LDS for every kernel (once per process per device).
 void configure_kernels();
