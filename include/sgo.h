@@ -87,7 +87,10 @@ typedef struct {
   double tol_e;      /* |E_k - E_{k-1}| stop, Ha per atom (default 1e-5) */
   double tol_rho;    /* Omega/Ntot sum|rho_out - rho_in| / N_el stop (default 1e-4) */
   double mix_alpha;  /* Pulay/Kerker mixing weight (default 0.5) */
-  double kerker_q0;  /* Kerker wavevector, bohr^-1 (default 0.8) */
+  double kerker_q0;  /* Kerker wavevector, bohr^-1 (default 0.8, robust for
+                        dense cells; isolated clusters in a vacuum box converge
+                        in fewer iterations with weak damping, e.g. 0.3 with
+                        mix_alpha 0.3) */
   int history;       /* Pulay history length, 2..8 (default 8) */
   unsigned seed;     /* seed of the starting wavefunctions (default 1) */
   int use_graph;     /* capture one SCF iteration in a HIP graph (default 0) */

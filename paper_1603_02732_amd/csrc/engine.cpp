@@ -612,7 +612,9 @@ class Engine {
     // and the compact plane (plus the density accumulator) fits the LDS
     g.plane_reg = tsize() == 4 && tune("SGO_PLANE_KERNEL", 1) == 1 ? 1 : 0;
     for (auto& c : cands_)
-      if (!plane_reg_length_ok(c.N[0]) || !plane_reg_length_ok(c.N[1])) g.plane_reg = 0;
+      if (!plane_reg_length_ok(c.N[0]) || !plane_reg_length_ok(c.N[1]) ||
+          !plane_reg_length_ok(c.N[2]))
+        g.plane_reg = 0;
     if (plane_reg_lds(g, true) > (size_t)g_lds_limit) g.plane_reg = 0;
     g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
     // band-pair chunks of the density planes: enough blocks to fill the chip

@@ -258,6 +258,175 @@ __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __r
   for (int e = lane; e < N1 * N2; e += 64) out[e] = acc[(e / N1) * ar + e % N1];
 }
 
+// ------------------------------------------------------------ z transforms
+// Register-FFT z passes (FP32): one wavefront per chunk of up to 32 stick
+// pairs (at most 64 sticks) of one band pair.  The band coefficients are
+// scattered into an LDS tile [stick][z] (row stride N3 | 1) with coalesced
+// reads of the half sphere, each lane transforms one stick along z in
+// registers, and the sticks buffer [pair][z][stick] is written (or read) one
+// 64-stick row per z.
+constexpr int kZPairs = 32;
+__device__ __forceinline__ int mirror_stick_r(int s) { return s == 0 ? 0 : ((s & 1) ? s + 1 : s - 1); }
+
+template <int N3>
+__device__ __forceinline__ void zline_inv(const cplx<float>* __restrict__ row, cplx<float>* out, int nst) {
+  cplx<float> v[N3], w[N3];
+#pragma unroll
+  for (int k = 0; k < N3; ++k) v[k] = row[k];
+  freg::fft<float, +1, N3>(v, w);
+#pragma unroll
+  for (int k = 0; k < N3; ++k) out[(size_t)k * nst] = w[k];
+}
+template <int N3>
+__device__ __forceinline__ void zline_fwd(const cplx<float>* __restrict__ in, int nst, cplx<float>* row) {
+  cplx<float> v[N3], w[N3];
+#pragma unroll
+  for (int k = 0; k < N3; ++k) v[k] = in[(size_t)k * nst];
+  freg::fft<float, -1, N3>(v, w);
+#pragma unroll
+  for (int k = 0; k < N3; ++k) row[k] = w[k];
+}
+
+struct ZChunk {
+  int q0, q1, s0, nloc;
+};
+__device__ __forceinline__ ZChunk zchunk(const CandDesc& cd, int c) {
+  ZChunk z;
+  z.q0 = c * kZPairs;
+  z.q1 = min(z.q0 + kZPairs, cd.nsp);
+  z.s0 = z.q0 == 0 ? 0 : 2 * z.q0 - 1;
+  z.nloc = 2 * z.q1 - 1 - z.s0;
+  return z;
+}
+
+__global__ void __launch_bounds__(64, 2) k_z_inverse_reg(const CandDesc* __restrict__ cds, int src) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int pair = blockIdx.y;
+  if (pair >= cd.npair || (int)blockIdx.x * kZPairs >= cd.nsp) return;
+  const ZChunk ch = zchunk(cd, blockIdx.x);
+  const int N3 = cd.N3, S = N3 | 1, lane = threadIdx.x;
+  extern __shared__ __align__(16) char smem[];
+  cplx<float>* A = (cplx<float>*)smem;
+  for (int e = lane; e < ch.nloc * S; e += 64) A[e] = {0.f, 0.f};
+  __syncthreads();
+  const float* base = (const float*)(src == W_X ? cd.X : (src == W_D ? cd.D : cd.HX));
+  const float* xa = base + (size_t)(2 * pair) * cd.Kp;
+  const bool hasb = 2 * pair + 1 < cd.nb;
+  const float* xb = base + (size_t)(2 * pair + 1) * cd.Kp;
+  const int g0 = cd.sp_off[ch.q0], g1 = cd.sp_off[ch.q1];
+  for (int g = g0 + lane; g < g1; g += 64) {
+    const int meta = cd.gmeta[g];
+    const int st = meta & 0xFFFFF, z = meta >> 20;
+    const cplx<float> ca = unpack_coef(xa, g);
+    const cplx<float> cb = hasb ? unpack_coef(xb, g) : cplx<float>{0.f, 0.f};
+    A[(st - ch.s0) * S + z] = {ca.x - cb.y, ca.y + cb.x};  // c_a + i c_b
+    if (g != 0) {
+      const int sm = mirror_stick_r(st);
+      const int zm = z == 0 ? 0 : N3 - z;
+      A[(sm - ch.s0) * S + zm] = {ca.x + cb.y, cb.x - ca.y};  // conj c_a + i conj c_b
+    }
+  }
+  __syncthreads();
+  if (lane < ch.nloc) {
+    cplx<float>* out = (cplx<float>*)cd.sticks + (size_t)pair * N3 * cd.nst + ch.s0 + lane;
+    switch (N3) {
+#define SGO_CASE(N)                                  \
+  case N:                                            \
+    zline_inv<N>(A + lane * S, out, cd.nst);         \
+    break;
+      SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+      default:
+        break;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64, 2) k_z_forward_reg(const CandDesc* __restrict__ cds, int src,
+                                                         int dst) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int pair = blockIdx.y;
+  if (pair >= cd.npair || (int)blockIdx.x * kZPairs >= cd.nsp) return;
+  const ZChunk ch = zchunk(cd, blockIdx.x);
+  const int N3 = cd.N3, S = N3 | 1, lane = threadIdx.x;
+  extern __shared__ __align__(16) char smem[];
+  cplx<float>* A = (cplx<float>*)smem;
+  if (lane < ch.nloc) {
+    const cplx<float>* in = (const cplx<float>*)cd.sticks + (size_t)pair * N3 * cd.nst + ch.s0 + lane;
+    switch (N3) {
+#define SGO_CASE(N)                                  \
+  case N:                                            \
+    zline_fwd<N>(in, cd.nst, A + lane * S);          \
+    break;
+      SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+      default:
+        break;
+    }
+  }
+  __syncthreads();
+  const float sc = (float)(1.0 / (double)cd.ntot);
+  const float rt2 = 1.41421356237309504880f;
+  const float* xsrc = (const float*)(src == W_X ? cd.X : (src == W_D ? cd.D : cd.HX));
+  float* ydst = (float*)(dst == W_HX ? cd.HX : cd.HD);
+  const int a = 2 * pair, b = 2 * pair + 1;
+  const bool hasb = b < cd.nb;
+  const float* xa = xsrc + (size_t)a * cd.Kp;
+  const float* xb = xsrc + (size_t)b * cd.Kp;
+  float* ya = ydst + (size_t)a * cd.Kp;
+  float* yb = ydst + (size_t)b * cd.Kp;
+  const int g0 = cd.sp_off[ch.q0], g1 = cd.sp_off[ch.q1];
+  for (int g = g0 + lane; g < g1; g += 64) {
+    const int meta = cd.gmeta[g];
+    const int st = meta & 0xFFFFF, z = meta >> 20;
+    const int sm = mirror_stick_r(st);
+    const int zm = z == 0 ? 0 : N3 - z;
+    const cplx<float> W = A[(st - ch.s0) * S + z];
+    const cplx<float> Wm = A[(sm - ch.s0) * S + zm];
+    // (V psi_a)_G = (W_G + conj W_-G)/2 ; (V psi_b)_G = (W_G - conj W_-G)/(2i)
+    const cplx<float> va = {0.5f * (W.x + Wm.x) * sc, 0.5f * (W.y - Wm.y) * sc};
+    const cplx<float> vb = {0.5f * (W.y + Wm.y) * sc, -0.5f * (W.x - Wm.x) * sc};
+    const float kin = (float)cd.kin[g];
+    if (g == 0) {
+      ya[0] = va.x + kin * xa[0];
+      ya[1] = 0.f;
+      if (hasb) {
+        yb[0] = vb.x + kin * xb[0];
+        yb[1] = 0.f;
+      }
+    } else {
+      ya[2 * g] = rt2 * va.x + kin * xa[2 * g];
+      ya[2 * g + 1] = rt2 * va.y + kin * xa[2 * g + 1];
+      if (hasb) {
+        yb[2 * g] = rt2 * vb.x + kin * xb[2 * g];
+        yb[2 * g + 1] = rt2 * vb.y + kin * xb[2 * g + 1];
+      }
+    }
+  }
+}
+
+size_t z_reg_lds(const BatchGeom& g) {
+  return (size_t)2 * kZPairs * (g.N3max | 1) * sizeof(cplx<float>);
+}
+void launch_z_inverse_reg(const LaunchCtx& L, int src) {
+  const BatchGeom& g = L.g;
+  dim3 gz((g.nsp_max + kZPairs - 1) / kZPairs, g.npair_max, g.ncand);
+  prof_before("k_z_inverse", L.stream);
+  hipLaunchKernelGGL(k_z_inverse_reg, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src);
+  check_launch("k_z_inverse");
+  prof_after("k_z_inverse", L.stream);
+}
+void launch_z_forward_reg(const LaunchCtx& L, int src, int dst) {
+  const BatchGeom& g = L.g;
+  dim3 gz((g.nsp_max + kZPairs - 1) / kZPairs, g.npair_max, g.ncand);
+  prof_before("k_z_forward", L.stream);
+  hipLaunchKernelGGL(k_z_forward_reg, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src, dst);
+  check_launch("k_z_forward");
+  prof_after("k_z_forward", L.stream);
+}
+
 size_t plane_reg_lds(const BatchGeom& g, bool density) {
   size_t b = (size_t)g.N2max * g.pl_sx_max * sizeof(cplx<float>);
   if (density) b += (size_t)g.N2max * (g.N1max | 1) * sizeof(double);
@@ -285,6 +454,8 @@ void launch_plane_density_reg(const LaunchCtx& L) {
 void configure_plane_kernels() {
   allow_lds((const void*)k_plane_hpsi_reg);
   allow_lds((const void*)k_plane_density_reg);
+  allow_lds((const void*)k_z_inverse_reg);
+  allow_lds((const void*)k_z_forward_reg);
 }
 
 }  // namespace sgo

@@ -922,11 +922,17 @@ template <typename T>
 void launch_hpsi(const LaunchCtx& L, int src) {
   const BatchGeom& g = L.g;
   const int dst = src == W_X ? W_HX : W_HD;
+  const bool reg = std::is_same<T, float>::value && g.plane_reg;
   dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
-  prof_before("k_z_inverse", L.stream);
-  hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, g.sp_chunk);
-  check_launch("k_z_inverse");
-  prof_after("k_z_inverse", L.stream);
+  if (reg) {
+    launch_z_inverse_reg(L, src);
+  } else {
+    prof_before("k_z_inverse", L.stream);
+    hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src,
+                       g.sp_chunk);
+    check_launch("k_z_inverse");
+    prof_after("k_z_inverse", L.stream);
+  }
   if (std::is_same<T, float>::value && g.plane_reg) {
     launch_plane_hpsi_reg(L);
   } else {
@@ -936,11 +942,15 @@ void launch_hpsi(const LaunchCtx& L, int src) {
     check_launch("k_plane_hpsi");
     prof_after("k_plane_hpsi", L.stream);
   }
-  prof_before("k_z_forward", L.stream);
-  hipLaunchKernelGGL(k_z_forward<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, dst,
-                     g.sp_chunk);
-  check_launch("k_z_forward");
-  prof_after("k_z_forward", L.stream);
+  if (reg) {
+    launch_z_forward_reg(L, src, dst);
+  } else {
+    prof_before("k_z_forward", L.stream);
+    hipLaunchKernelGGL(k_z_forward<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, src, dst,
+                       g.sp_chunk);
+    check_launch("k_z_forward");
+    prof_after("k_z_forward", L.stream);
+  }
   if (g.nproj_max > 0) {
     int a[1] = {W_BETA}, b[1] = {src}, o[1] = {M_C};
     launch_gram<T>(L, 1, a, b, o);
@@ -953,11 +963,15 @@ template <typename T>
 void launch_density(const LaunchCtx& L) {
   const BatchGeom& g = L.g;
   dim3 gz((g.nsp_max + g.sp_chunk - 1) / g.sp_chunk, g.npair_max, g.ncand);
-  prof_before("k_z_inverse", L.stream);
-  hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, (int)W_X,
-                     g.sp_chunk);
-  check_launch("k_z_inverse");
-  prof_after("k_z_inverse", L.stream);
+  if (std::is_same<T, float>::value && g.plane_reg) {
+    launch_z_inverse_reg(L, (int)W_X);
+  } else {
+    prof_before("k_z_inverse", L.stream);
+    hipLaunchKernelGGL(k_z_inverse<T>, gz, dim3(kNT), z_lds<T>(g), L.stream, L.desc, (int)W_X,
+                       g.sp_chunk);
+    check_launch("k_z_inverse");
+    prof_after("k_z_inverse", L.stream);
+  }
   if (std::is_same<T, float>::value && g.plane_reg) {
     launch_plane_density_reg(L);
   } else {

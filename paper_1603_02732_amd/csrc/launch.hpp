@@ -70,6 +70,8 @@ bool plane_reg_length_ok(int n);
 size_t plane_reg_lds(const BatchGeom& g, bool density);
 void launch_plane_hpsi_reg(const LaunchCtx& L);
 void launch_plane_density_reg(const LaunchCtx& L);
+void launch_z_inverse_reg(const LaunchCtx& L, int src);
+void launch_z_forward_reg(const LaunchCtx& L, int src, int dst);
 void configure_plane_kernels();
 // Raise the dynamic-LDS limit of one kernel to what the device allows.
 void allow_lds(const void* kernel);
