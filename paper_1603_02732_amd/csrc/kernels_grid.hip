@@ -876,7 +876,6 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   if (!cd.active) return;
   const int n = cd.nb;
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int lane = tid & 63, wave = tid >> 6, nw = (nthr + 63) >> 6;
   extern __shared__ __align__(16) char smem[];
   double *P0, *P1, *P2, *P3;  // L, H / H', W = L^-1, scratch / V
   if (use_lds) {
@@ -986,9 +985,9 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   }
   __syncthreads();
   // Cyclic Jacobi with the round-robin ordering of disjoint index pairs.
-  // Phase A computes the rotations of a round; in phase B each wavefront
-  // takes column pairs Q (its rotation is a wave-uniform read) and its lanes
-  // take row pairs P, rotating 2x2 blocks in place, then V's columns.
+  // Phase A computes the rotations of a round; in phase B the threads take
+  // the (row pair, column pair) 2x2 blocks, rotating them in place, then
+  // V's columns.
   // Blocks whose two rotations are both the identity are skipped.  Stop when
   // the off-diagonal norm is below 1e-13 of the diagonal norm.
   const int n2 = n + (n & 1);
@@ -1018,38 +1017,39 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
         rs[k] = sn;
       }
       __syncthreads();
-      for (int P = wave; P < npair; P += nw) {
-        const double sP = rs[P], cP = rc[P];
+      // every (row pair P, column pair Q) block of the round over all
+      // threads (consecutive threads take consecutive Q of one P)
+      for (int t = tid; t < npair * npair; t += nthr) {
+        const int P = t / npair, Q = t - P * npair;
+        const double sP = rs[P], sQ = rs[Q];
+        if (sP == 0.0 && sQ == 0.0) continue;
+        const double cP = rc[P], cQ = rc[Q];
+        const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
+        const bool p2v = p2 < n, q2v = q2 < n;
+        const double a11 = P1[p1 * n + q1];
+        const double a12 = q2v ? P1[p1 * n + q2] : 0.0;
+        const double a21 = p2v ? P1[p2 * n + q1] : 0.0;
+        const double a22 = (p2v && q2v) ? P1[p2 * n + q2] : 0.0;
+        // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
+        const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
+        const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
+        // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
+        P1[p1 * n + q1] = cQ * b11 - sQ * b12;
+        if (q2v) P1[p1 * n + q2] = sQ * b11 + cQ * b12;
+        if (p2v) P1[p2 * n + q1] = cQ * b21 - sQ * b22;
+        if (p2v && q2v) P1[p2 * n + q2] = sQ * b21 + cQ * b22;
+      }
+      // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
+      // pair P updates rows p1, p2 of P3 (consecutive threads, consecutive i)
+      for (int t = tid; t < npair * n; t += nthr) {
+        const int P = t / n, i = t - P * n;
+        const double sP = rs[P];
         const int p1 = rp[P], p2 = rq[P];
-        const bool p2v = p2 < n;
-        for (int Q = lane; Q < npair; Q += 64) {
-          const double sQ = rs[Q];
-          if (sP == 0.0 && sQ == 0.0) continue;
-          const double cQ = rc[Q];
-          const int q1 = rp[Q], q2 = rq[Q];
-          const bool q2v = q2 < n;
-          const double a11 = P1[p1 * n + q1];
-          const double a12 = q2v ? P1[p1 * n + q2] : 0.0;
-          const double a21 = p2v ? P1[p2 * n + q1] : 0.0;
-          const double a22 = (p2v && q2v) ? P1[p2 * n + q2] : 0.0;
-          // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
-          const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
-          const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
-          // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
-          P1[p1 * n + q1] = cQ * b11 - sQ * b12;
-          if (q2v) P1[p1 * n + q2] = sQ * b11 + cQ * b12;
-          if (p2v) P1[p2 * n + q1] = cQ * b21 - sQ * b22;
-          if (p2v && q2v) P1[p2 * n + q2] = sQ * b21 + cQ * b22;
-        }
-        // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
-        // pair P updates rows p1, p2 of P3, contiguous across lanes
-        if (sP != 0.0 && p2v) {
-          for (int i = lane; i < n; i += 64) {
-            const double vp = P3[p1 * n + i], vq = P3[p2 * n + i];
-            P3[p1 * n + i] = cP * vp - sP * vq;
-            P3[p2 * n + i] = sP * vp + cP * vq;
-          }
-        }
+        if (sP == 0.0 || p2 >= n) continue;
+        const double cP = rc[P];
+        const double vp = P3[p1 * n + i], vq = P3[p2 * n + i];
+        P3[p1 * n + i] = cP * vp - sP * vq;
+        P3[p2 * n + i] = sP * vp + cP * vq;
       }
       __syncthreads();
     }

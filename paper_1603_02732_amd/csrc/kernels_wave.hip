@@ -701,6 +701,135 @@ __global__ void __launch_bounds__(kNT) k_linemin(const CandDesc* __restrict__ cd
   }
 }
 
+// FP32 variants of the CG direction and the line minimisation that read each
+// band array once: one 512-thread block per band holds the band's values in
+// float4 registers (J per thread and array, Kp <= 2048 J) between the
+// reductions and the update.
+constexpr int kBandNT = 512;
+template <int J>
+__device__ __forceinline__ void load_band4(const float* __restrict__ a, int Kp, float4 (&r)[J]) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = threadIdx.x + kBandNT * j;
+    r[j] = 4 * c < Kp ? reinterpret_cast<const float4*>(a)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+template <int J>
+__device__ __forceinline__ void store_band4(float* __restrict__ a, int Kp, const float4 (&r)[J]) {
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = threadIdx.x + kBandNT * j;
+    if (4 * c < Kp) reinterpret_cast<float4*>(a)[c] = r[j];
+  }
+}
+
+template <int J>
+__global__ void __launch_bounds__(kBandNT) k_linemin_r(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int i = blockIdx.x;
+  if (i >= cd.nb) return;
+  __shared__ double sh[16 * 4];
+  const int Kp = cd.Kp;
+  float* x = (float*)cd.X + (size_t)i * Kp;
+  float* hx = (float*)cd.HX + (size_t)i * Kp;
+  const float* d = (const float*)cd.D + (size_t)i * Kp;
+  const float* hd = (const float*)cd.HD + (size_t)i * Kp;
+  float4 X[J], HX[J], D[J], HD[J];
+  load_band4<J>(x, Kp, X);
+  load_band4<J>(hx, Kp, HX);
+  load_band4<J>(d, Kp, D);
+  load_band4<J>(hd, Kp, HD);
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    v[0] += (double)X[j].x * HX[j].x + (double)X[j].y * HX[j].y + (double)X[j].z * HX[j].z +
+            (double)X[j].w * HX[j].w;
+    v[1] += (double)X[j].x * HD[j].x + (double)X[j].y * HD[j].y + (double)X[j].z * HD[j].z +
+            (double)X[j].w * HD[j].w;
+    v[2] += (double)D[j].x * HD[j].x + (double)D[j].y * HD[j].y + (double)D[j].z * HD[j].z +
+            (double)D[j].w * HD[j].w;
+    v[3] += (double)D[j].x * D[j].x + (double)D[j].y * D[j].y + (double)D[j].z * D[j].z +
+            (double)D[j].w * D[j].w;
+  }
+  block_sum<4>(v, sh);
+  const double n2 = v[3];
+  if (!(n2 > 0.0)) return;
+  const double inv = 1.0 / sqrt(n2);
+  const double a = v[0], b = v[1] * inv, c = v[2] * inv * inv;
+  const double theta = 0.5 * atan2(-2.0 * b, c - a);
+  double sn, cs;
+  sincos(theta, &sn, &cs);
+  const float c32 = (float)cs, s32 = (float)(sn * inv);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    X[j] = make_float4(c32 * X[j].x + s32 * D[j].x, c32 * X[j].y + s32 * D[j].y,
+                       c32 * X[j].z + s32 * D[j].z, c32 * X[j].w + s32 * D[j].w);
+    HX[j] = make_float4(c32 * HX[j].x + s32 * HD[j].x, c32 * HX[j].y + s32 * HD[j].y,
+                        c32 * HX[j].z + s32 * HD[j].z, c32 * HX[j].w + s32 * HD[j].w);
+  }
+  store_band4<J>(x, Kp, X);
+  store_band4<J>(hx, Kp, HX);
+}
+
+template <int J>
+__global__ void __launch_bounds__(kBandNT) k_cg_direction_r(const CandDesc* __restrict__ cds, int first) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int i = blockIdx.x;
+  if (i >= cd.nb) return;
+  __shared__ double sh[16];
+  const int Kp = cd.Kp, npwh = cd.npwh;
+  const float* x = (const float*)cd.X + (size_t)i * Kp;
+  const float* hx = (const float*)cd.HX + (size_t)i * Kp;
+  float* d = (float*)cd.D + (size_t)i * Kp;
+  float4 X[J], R[J];
+  float2 KN[J];  // |G|^2/2 of the two coefficients of each float4
+  load_band4<J>(x, Kp, X);
+  load_band4<J>(hx, Kp, R);
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int c = threadIdx.x + kBandNT * j;
+    KN[j].x = 2 * c < npwh ? (float)cd.kin[2 * c] : 0.f;
+    KN[j].y = 2 * c + 1 < npwh ? (float)cd.kin[2 * c + 1] : 0.f;
+  }
+  double v[1] = {0.0};
+#pragma unroll
+  for (int j = 0; j < J; ++j)
+    v[0] += (double)KN[j].x * ((double)X[j].x * X[j].x + (double)X[j].y * X[j].y) +
+            (double)KN[j].y * ((double)X[j].z * X[j].z + (double)X[j].w * X[j].w);
+  block_sum<1>(v, sh);
+  const double ek = fmax(v[0], 1e-8);
+  const float e = (float)cd.eps[i];
+  const float iek = (float)(1.0 / ek);
+  double w[1] = {0.0};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    // residual r = H x - e x, preconditioned g = K(|G|^2/2 / ek) r
+    R[j] = make_float4(R[j].x - e * X[j].x, R[j].y - e * X[j].y, R[j].z - e * X[j].z,
+                       R[j].w - e * X[j].w);
+    const float ka = (float)tpa((double)(KN[j].x * iek)), kb = (float)tpa((double)(KN[j].y * iek));
+    w[0] += (double)ka * ((double)R[j].x * R[j].x + (double)R[j].y * R[j].y) +
+            (double)kb * ((double)R[j].z * R[j].z + (double)R[j].w * R[j].w);
+    R[j] = make_float4(ka * R[j].x, ka * R[j].y, kb * R[j].z, kb * R[j].w);
+  }
+  block_sum<1>(w, sh);
+  const double gam = w[0];
+  float beta = 0.f;
+  if (!first) {
+    const double gp = cd.gam[i];
+    beta = gp > 0.0 ? (float)(gam / gp) : 0.f;
+    float4 D[J];
+    load_band4<J>(d, Kp, D);
+#pragma unroll
+    for (int j = 0; j < J; ++j)
+      R[j] = make_float4(R[j].x + beta * D[j].x, R[j].y + beta * D[j].y, R[j].z + beta * D[j].z,
+                         R[j].w + beta * D[j].w);
+  }
+  store_band4<J>(d, Kp, R);
+  if (threadIdx.x == 0) cd.gam[i] = gam;
+}
+
 // Kinetic energy of each band: bandw[i] = sum_G |G|^2/2 |c_iG|^2.
 template <typename T>
 __global__ void __launch_bounds__(kNT) k_band_kinetic(const CandDesc* __restrict__ cds) {
@@ -1053,8 +1182,30 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
   prof_after("k_gemm_acc", L.stream);
 }
 
+// J = float4 per thread and band array of the one-pass FP32 band kernels
+// (0: Kp too large, the multi-pass kernels are used)
+static int band_j(const BatchGeom& g) {
+  int kp = 0;
+  kp = (g.K_max + 31) / 32 * 32;
+  if (kp <= 4 * kBandNT * 4) return 4;
+  if (kp <= 4 * kBandNT * 8) return 8;
+  if (kp <= 4 * kBandNT * 12) return 12;
+  return 0;
+}
+
 template <typename T>
 void launch_cg_direction(const LaunchCtx& L, int first) {
+  const int J = std::is_same<T, float>::value ? band_j(L.g) : 0;
+  if (J) {
+    prof_before("k_cg_direction", L.stream);
+    const dim3 gr(L.g.nb_max, 1, L.g.ncand);
+    if (J == 4) hipLaunchKernelGGL(k_cg_direction_r<4>, gr, dim3(kBandNT), 0, L.stream, L.desc, first);
+    else if (J == 8) hipLaunchKernelGGL(k_cg_direction_r<8>, gr, dim3(kBandNT), 0, L.stream, L.desc, first);
+    else hipLaunchKernelGGL(k_cg_direction_r<12>, gr, dim3(kBandNT), 0, L.stream, L.desc, first);
+    check_launch("k_cg_direction");
+    prof_after("k_cg_direction", L.stream);
+    return;
+  }
   prof_before("k_cg_direction", L.stream);
   hipLaunchKernelGGL(k_cg_direction<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream,
                      L.desc, first);
@@ -1063,6 +1214,17 @@ void launch_cg_direction(const LaunchCtx& L, int first) {
 }
 template <typename T>
 void launch_linemin(const LaunchCtx& L) {
+  const int J = std::is_same<T, float>::value ? band_j(L.g) : 0;
+  if (J) {
+    prof_before("k_linemin", L.stream);
+    const dim3 gr(L.g.nb_max, 1, L.g.ncand);
+    if (J == 4) hipLaunchKernelGGL(k_linemin_r<4>, gr, dim3(kBandNT), 0, L.stream, L.desc);
+    else if (J == 8) hipLaunchKernelGGL(k_linemin_r<8>, gr, dim3(kBandNT), 0, L.stream, L.desc);
+    else hipLaunchKernelGGL(k_linemin_r<12>, gr, dim3(kBandNT), 0, L.stream, L.desc);
+    check_launch("k_linemin");
+    prof_after("k_linemin", L.stream);
+    return;
+  }
   prof_before("k_linemin", L.stream);
   hipLaunchKernelGGL(k_linemin<T>, dim3(L.g.nb_max, 1, L.g.ncand), dim3(kNT), 0, L.stream, L.desc);
   check_launch("k_linemin");
