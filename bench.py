@@ -30,6 +30,84 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 
+COUNTERS = os.path.join(ROOT, "profiles", "c3_population_hbm_counters.txt")
+# profiling-hook names of the kernels as rocprofv3 reports them
+HOOK_OF = {"k_gemm_f32": "k_gemm_acc", "k_plane_hpsi_reg": "k_plane_hpsi",
+           "k_plane_density_reg": "k_plane_density", "k_z_inverse_reg": "k_z_inverse",
+           "k_z_forward_reg": "k_z_forward", "k_linemin_r": "k_linemin",
+           "k_cg_direction_r": "k_cg_direction"}
+
+
+def kernel_digest():
+    """SHA-256 over the kernel sources (a counter summary is valid only for
+    the kernels it was taken on)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1603_02732_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def summarize_counters(fetch_csv, write_csv):
+    """Per-kernel HBM bytes per dispatch from two rocprofv3 --pmc runs of the
+    bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
+    the same counter reads for the calibration copy (torch add of 64 MiB:
+    reads 64 MiB, writes 64 MiB).  Prints the summary text."""
+    import collections
+    import csv
+
+    def load(p):
+        agg = collections.defaultdict(lambda: [0, 0.0])
+        for r in csv.DictReader(open(p)):
+            n = r["Kernel_Name"]
+            a = agg[n]
+            a[0] += 1
+            a[1] += float(r["Counter_Value"])
+        return agg
+    f, w = load(fetch_csv), load(write_csv)
+    cal = [k for k in f if "CUDAFunctorOnSelf_add<float>" in k]
+    if len(cal) != 1:
+        raise SystemExit("calibration copy kernel not found in the counter run")
+    known = 64 * 1024.0  # KiB
+    ff = known / (f[cal[0]][1] / f[cal[0]][0])
+    fw = known / (w[cal[0]][1] / w[cal[0]][0])
+    print("kernel_digest %s" % kernel_digest())
+    print("calibration fetch_factor %.4f write_factor %.4f (copy of 64 MiB: FETCH_SIZE %.1f KiB, "
+          "WRITE_SIZE %.1f KiB per dispatch)" % (ff, fw, f[cal[0]][1] / f[cal[0]][0],
+                                                w[cal[0]][1] / w[cal[0]][0]))
+    print("%-24s %9s %14s %14s %16s" % ("kernel", "dispatches", "FETCH_KiB/disp", "WRITE_KiB/disp",
+                                        "bytes/disp(scaled)"))
+    for k in sorted(f, key=lambda k: -f[k][1]):
+        if not k.startswith(("sgo::", "void sgo::")):
+            continue
+        base = k.replace("void ", "").replace("sgo::", "").split("(")[0].split("<")[0]
+        hook = HOOK_OF.get(base, base)
+        fk = f[k][1] / f[k][0]
+        wk = w[k][1] / w[k][0] if k in w else 0.0
+        print("%-24s %9d %14.1f %14.1f %16.0f" % (hook, f[k][0], fk, wk, (ff * fk + fw * wk) * 1024))
+
+
+def counters_traffic(hook):
+    """Scaled HBM bytes per dispatch of `hook` from the committed counter
+    summary, or None if absent or taken on other kernel sources."""
+    if not os.path.exists(COUNTERS):
+        return None
+    lines = open(COUNTERS).read().splitlines()
+    dig = [ln.split()[1] for ln in lines if ln.startswith("kernel_digest")]
+    if not dig or dig[0] != kernel_digest():
+        return None
+    for ln in lines:
+        parts = ln.split()
+        if len(parts) == 5 and parts[0] == hook:
+            try:
+                return float(parts[4])
+            except ValueError:
+                return None
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -37,6 +115,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the HBM counter summary of two rocprofv3 --pmc runs and exit")
     return ap.parse_args()
 
 
@@ -82,6 +162,9 @@ def kernel_model(name, geoms, tsize):
 
 def main():
     a = parse()
+    if a.summarize_counters:
+        summarize_counters(*a.summarize_counters)
+        return
     if a.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported by this build "
               "(candidates are independent and would shard one population slice per GPU)"
@@ -172,8 +255,9 @@ def main():
     else:
         ach = amount / avg_s / 1e12
         peak = FP64_PEAK_TFLOPS
+    traffic = counters_traffic(dominant) if bound == "hbm" else None
     roof = {"bound": bound, "kernel": dominant, "achieved": ach, "peak": peak, "unit": unit,
-            "frac": ach / peak, "traffic": None, "avg_launch_us": avg_s * 1e6,
+            "frac": ach / peak, "traffic": traffic, "avg_launch_us": avg_s * 1e6,
             "launches_per_step": prof["launches"] / a.steps,
             "active_candidates_per_launch": avg_active,
             ("bytes_per_launch" if bound == "hbm" else "flop_per_launch"): amount,
