@@ -54,8 +54,14 @@ enum {
 /* Arithmetic of the bulk wavefunction work (FFTs, H*psi, projector and
  * subspace products).  The subspace Cholesky and diagonalisation, the Ewald
  * sum, the density/potential grid work and every energy sum are FP64 in all
- * modes. */
-enum { SGO_FP64 = 0, SGO_FP32 = 1 };
+ * modes.  SGO_FP32_BF16PROJ is SGO_FP32 with the Kleinman-Bylander projector
+ * products of H*psi (P = beta^T psi, H psi += beta (h P)) on BF16 MFMA with
+ * FP32 accumulation; every operand is split into two BF16 parts (hi + lo)
+ * and a product is hi*hi + hi*lo + lo*hi (a single BF16 rounding moves the
+ * cluster-population energy by ~5e-5 Ha/atom; the split keeps it within
+ * the FP32 form's tolerance).  Forces and stress keep FP32 projections with
+ * FP64 sums. */
+enum { SGO_FP64 = 0, SGO_FP32 = 1, SGO_FP32_BF16PROJ = 2 };
 
 enum { SGO_LOCAL_AH = 0, SGO_LOCAL_GAUSS = 1 };
 enum { SGO_OCC_FIXED = 0, SGO_OCC_FERMI = 1 };
@@ -119,7 +125,8 @@ void sgo_default_opts(sgo_scf_opts* opts);
 /* Version string of the library (static storage). */
 const char* sgo_version(void);
 
-/* Create a handle on HIP device `device` with precision SGO_FP64/SGO_FP32.
+/* Create a handle on HIP device `device` with precision SGO_FP64, SGO_FP32
+ * or SGO_FP32_BF16PROJ.
  * *out receives the handle (caller destroys it with sgo_destroy). */
 int sgo_create(sgo_ctx** out, int device, int precision);
 int sgo_destroy(sgo_ctx* ctx);

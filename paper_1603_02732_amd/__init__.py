@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsgo.so")
 
 SGO_OK, SGO_EINVAL, SGO_ENOMEM, SGO_EDEVICE, SGO_ENOTCONV, SGO_ENUMERIC, SGO_ESTATE = \
     0, -1, -2, -3, -4, -5, -6
-SGO_FP64, SGO_FP32 = 0, 1
+SGO_FP64, SGO_FP32, SGO_FP32_BF16PROJ = 0, 1, 2
 SGO_LOCAL_AH, SGO_LOCAL_GAUSS = 0, 1
 SGO_OCC_FIXED, SGO_OCC_FERMI = 0, 1
 _STATUS = {0: "SGO_OK", -1: "SGO_EINVAL", -2: "SGO_ENOMEM", -3: "SGO_EDEVICE",

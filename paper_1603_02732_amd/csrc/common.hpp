@@ -52,6 +52,7 @@ struct CandDesc {
   int nsp, nst, nproj, nat;
   int occ_kind, nocc, active, ncand_index;
   int pl_nx, pl_nxl, pl_sx, pl_pad;  // active x columns of the planes (register FFT kernels)
+  int np16, pad_np;     // nproj rounded up to 16 (BF16 projector tiles)
   double sigma, nelec, omega, pad0;
   double A[9];
   double B[9];
@@ -64,6 +65,8 @@ struct CandDesc {
   void* sticks;   // cplx<T> [npair][N3][nst]
   void* veff_t;   // T [N3][N2][N1]
   void* beta;     // T [nproj][K]
+  void* beta16;   // bfloat16 [2][np16][Kp] hi, lo parts (FP32_BF16PROJ form only)
+  void* betaT16;  // bfloat16 [2][Kp][np16]
   const double* kin;     // [npwh]
   const int* gmeta;      // [npwh] stick | z << 20
   const int* sp_off;     // [nsp + 1]

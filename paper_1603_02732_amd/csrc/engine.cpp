@@ -169,7 +169,8 @@ class Engine {
  public:
   Engine(int device, int precision, int capacity)
       : device_(device), prec_(precision), capacity_(capacity) {
-    if (precision != SGO_FP64 && precision != SGO_FP32) throw Error(SGO_EINVAL, "bad precision");
+    if (precision != SGO_FP64 && precision != SGO_FP32 && precision != SGO_FP32_BF16PROJ)
+      throw Error(SGO_EINVAL, "bad precision");
     if (capacity < 1) throw Error(SGO_EINVAL, "capacity must be >= 1");
     int ndev = 0;
     HIPCHK(hipGetDeviceCount(&ndev));
@@ -465,6 +466,7 @@ class Engine {
     free_cand(c);
     const size_t ts = tsize();
     const size_t nb = c.nb, K = c.Kp, nt = c.ntot, nbm = std::max(c.nb, c.nproj);
+    const size_t np16 = (size_t)(c.nproj + 15) / 16 * 16;
     const int ntile = (std::max(c.nb, c.nproj) + 63) / 64;
     c.red_doubles = std::max((size_t)kRedSlots, (size_t)2 * ntile * ntile * 32 * 4096);
     c.dens_chunks = g.dens_chunks;
@@ -478,6 +480,8 @@ class Engine {
         {&d.X, nb * K * ts}, {&d.HX, nb * K * ts}, {&d.D, nb * K * ts}, {&d.HD, nb * K * ts},
         {&d.sticks, (size_t)c.npair * c.N[2] * c.nst * 2 * ts}, {&d.veff_t, nt * ts},
         {&d.beta, (size_t)c.nproj * K * ts + 256},
+        {&d.beta16, prec_ == SGO_FP32_BF16PROJ ? (size_t)2 * np16 * K * 2 + 256 : 0},
+        {&d.betaT16, prec_ == SGO_FP32_BF16PROJ ? (size_t)2 * np16 * K * 2 + 256 : 0},
         {(void**)&d.kin, c.npwh * sizeof(double)}, {(void**)&d.gmeta, c.npwh * sizeof(int)},
         {(void**)&d.sp_off, (c.nsp + 1) * sizeof(int)}, {(void**)&d.stick_xy, c.nst * sizeof(int)},
         {(void**)&d.gmill, 3 * c.npwh * sizeof(int)},
@@ -532,6 +536,7 @@ class Engine {
     d.nst = c.nst;
     d.nproj = c.nproj;
     d.nat = c.nat;
+    d.np16 = (c.nproj + 15) / 16 * 16;
     d.pl_nx = c.pl_nx;
     d.pl_nxl = c.pl_nxl;
     d.pl_sx = c.pl_sx;
@@ -617,6 +622,13 @@ class Engine {
         g.plane_reg = 0;
     if (plane_reg_lds(g, true) > (size_t)g_lds_limit) g.plane_reg = 0;
     g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
+    g.bf16proj = prec_ == SGO_FP32_BF16PROJ ? 1 : 0;
+    g.red_min_bytes = (size_t)-1;
+    for (auto& c : cands_) {
+      const int ntile = (std::max(c.nb, c.nproj) + 63) / 64;
+      const size_t rd = std::max((size_t)kRedSlots, (size_t)2 * ntile * ntile * 32 * 4096);
+      g.red_min_bytes = std::min(g.red_min_bytes, rd * 8);
+    }
     // band-pair chunks of the density planes: enough blocks to fill the chip
     // (planes x candidates x chunks >= 512 blocks of 4 waves, or 4096
     // one-wave blocks for the register-FFT kernel), no more (each chunk is a

@@ -1080,7 +1080,9 @@ void launch_hpsi(const LaunchCtx& L, int src) {
     check_launch("k_z_forward");
     prof_after("k_z_forward", L.stream);
   }
-  if (g.nproj_max > 0) {
+  if (g.nproj_max > 0 && std::is_same<T, float>::value && g.bf16proj) {
+    launch_proj_bf16(L, src, dst);
+  } else if (g.nproj_max > 0) {
     int a[1] = {W_BETA}, b[1] = {src}, o[1] = {M_C};
     launch_gram<T>(L, 1, a, b, o);
     int y[1] = {dst}, aa[1] = {W_BETA};
@@ -1254,6 +1256,7 @@ void launch_setup_beta(const LaunchCtx& L) {
                      L.desc, L.species);
   check_launch("k_setup_beta");
   prof_after("k_setup_beta", L.stream);
+  if (std::is_same<T, float>::value && L.g.bf16proj) launch_beta_bf16(L);
 }
 template <typename T>
 void launch_force_nonlocal(const LaunchCtx& L) {

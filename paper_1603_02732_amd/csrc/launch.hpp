@@ -17,6 +17,8 @@ struct BatchGeom {
   int plane_reg;   // 1: FP32 register-FFT plane kernels for every candidate
   int pl_sx_max;   // largest compact plane row stride
   int gemm_f32;    // 1: FP32-MFMA band products in the FP32 path
+  int bf16proj;    // 1: projector products with BF16 inputs (FP32_BF16PROJ form)
+  size_t red_min_bytes;  // smallest reduction scratch of any candidate
   int K_max;
   int sp_chunk;      // stick pairs per block of the z kernels
   int kc_len;        // K range per block of the split-K products
@@ -73,6 +75,9 @@ void launch_plane_density_reg(const LaunchCtx& L);
 void launch_z_inverse_reg(const LaunchCtx& L, int src);
 void launch_z_forward_reg(const LaunchCtx& L, int src, int dst);
 void configure_plane_kernels();
+// BF16-input projector products (FP32_BF16PROJ form).
+void launch_beta_bf16(const LaunchCtx& L);
+void launch_proj_bf16(const LaunchCtx& L, int src, int dst);
 // Raise the dynamic-LDS limit of one kernel to what the device allows.
 void allow_lds(const void* kernel);
 // Report a failed launch by kernel name (throws on the host side).

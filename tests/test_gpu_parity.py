@@ -119,3 +119,56 @@ def test_c2_fp32_matches_oracle():
     info = ctx.scf(tol_e=1e-8, tol_rho=1e-6, max_iter=200)
     say("  info", info)
     _compare(ctx, ref, 24, "fp32")
+
+
+@pytest.mark.parametrize("kind,ecut,grid,nb", [("sip", 3.0, (12, 10, 15), 8), ("c", 6.0, (20, 18, 24), 9)])
+def test_apply_h_bf16_projectors(kind, ecut, grid, nb):
+    """BF16-input projector products with every operand split into two BF16
+    parts (~2^-17 relative per product): elementwise within 2e-5 of
+    max|H psi| (the FP32 local part contributes ~2e-6), Rayleigh quotients
+    <psi_i|H|psi_i> within 1e-5 relative of the oracle's."""
+    from oracle.hamiltonian import Setup
+    sgo = _sgo()
+    s = workloads.tiny_system(kind, ecut=ecut, grid=grid, nbands=max(nb, 20 if kind != "c" else 10))
+    say("apply_h bf16 projectors", kind, grid, nb)
+    ctx = sgo.context_from_system(s, sgo.SGO_FP32_BF16PROJ)
+    st = Setup(s)
+    gm, nproj = ctx.basis()
+    assert nproj == st.beta.shape[1] and nproj > 0
+    pos, neg = half_to_full_index(gm, st.millers)
+    C = random_real_function_coeffs(st.npw, nb, pos, neg, seed=7)
+    rng = np.random.default_rng(11)
+    V = rng.standard_normal(st.grid)
+    HC = st.apply_h(V, C)
+    ref = pack(HC, pos)
+    psi = pack(C, pos)
+    got = ctx.apply_h(np.transpose(V, (2, 1, 0)), psi)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    rq_ref = np.real(np.einsum("gi,gi->i", C.conj(), HC))
+    rq = np.einsum("ik,ik->i", psi, got)
+    rq_err = np.abs(rq - rq_ref).max() / np.abs(rq_ref).max()
+    say("  elementwise rel err %.2e  Rayleigh quotient rel err %.2e" % (err, rq_err))
+    assert err < 2e-5
+    assert rq_err < 1e-5
+
+
+def test_c3_bf16_projectors_match_oracle():
+    """The C3 candidates with stored oracle results, solved in the
+    FP32_BF16PROJ form: energy and forces within the FP32 form's tolerances."""
+    sgo = _sgo()
+    refs = [load_golden("C3-%d" % k) for k in (0, 1)]
+    if any(r is None for r in refs):
+        pytest.skip("C3 oracle references not generated")
+    pop = workloads.config_c3(2)
+    B = sgo.Batch(2, precision=sgo.SGO_FP32_BF16PROJ)
+    for s in pop:
+        B.add_system(s)
+    E, F, st = B.scf(sgo.default_opts(tol_e=1e-6, tol_rho=1e-4, max_iter=150, mix_alpha=0.3,
+                                      kerker_q0=0.3))
+    assert np.all(st == 0)
+    for k in (0, 1):
+        dE = abs(E[k] - refs[k]["energy"]) / 13
+        dF = np.abs(F[k] - np.array(refs[k]["forces"])).max()
+        say("  C3-%d bf16 projectors: dE/atom %.2e  max dF %.2e" % (k, dE, dF))
+        assert dE <= E_TOL["fp32"]
+        assert dF <= F_TOL["fp32"]
