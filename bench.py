@@ -184,6 +184,8 @@ def main():
             torch.cuda.synchronize()
 
     pop = workloads.config_c3()
+    from paper_1603_02732_amd import autotune
+    schedule = autotune.lookup(pop, sgo.SGO_FP32)  # tuned launch schedule, if one is stored
     B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
     if have_torch:
         B.set_stream(torch.cuda.current_stream().cuda_stream)
@@ -191,7 +193,9 @@ def main():
         B.add_system(s)
     # isolated clusters in a vacuum box: weak Kerker damping (the library
     # default, q0 = 0.8 with alpha = 0.5, is tuned for dense cells)
-    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=150, **CLUSTER_MIXING)
+    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=150,
+                            use_graph=int(schedule["use_graph"]) if schedule else 0,
+                            **CLUSTER_MIXING)
     geoms = []
     for s in pop[:1]:
         c = sgo.context_from_system(s, sgo.SGO_FP32)
@@ -275,6 +279,7 @@ def main():
     plain = None
     if not a.no_plain:
         plain = plain_runs(sgo, workloads, sync)
+        plain["C3_batched_fp32_bf16proj"] = bf16proj_run(sgo, pop, opts, sync)
 
     cpu = None
     if not a.no_cpu:
@@ -291,16 +296,45 @@ def main():
                       "candidates_per_step": len(pop), "all_converged": status_ok,
                       "scf_gate": {"dE_per_atom": 1e-5, "density_residual": RHO_GATE},
                       "mixing": dict(CLUSTER_MIXING, history=8, kind="Pulay+Kerker"),
+                      "launch_schedule": schedule or "library defaults",
                       "dE_per_atom_vs_oracle": gates, "max_dF_vs_oracle": fgates},
            "plain": plain, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 
+def bf16proj_run(sgo, pop, opts, sync, steps=2):
+    """The same batched population in the FP32_BF16PROJ form (projector
+    products on BF16 MFMA), with its energy error against the oracle."""
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP32_BF16PROJ)
+    for s in pop:
+        B.add_system(s)
+    B.reset()
+    B.scf(opts)
+    sync()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        B.reset()
+        E, F, st = B.scf(opts)
+    sync()
+    dt = (time.perf_counter() - t0) / steps
+    gates = []
+    for k in range(len(pop)):
+        p = os.path.join(ROOT, "tests", "golden", "C3-%d.json" % k)
+        if os.path.exists(p):
+            gates.append(abs(E[k] - json.load(open(p))["energy"]) / 13)
+    B.close()
+    return {"evals_per_s": len(pop) / dt, "ms_per_step": dt * 1e3,
+            "all_converged": bool((st == 0).all()), "dE_per_atom_vs_oracle": gates}
+
+
 def plain_runs(sgo, workloads, sync):
-    """Plain path: one structure per solve (C2 sheet, and one C3 cluster)."""
+    """Plain path: one structure per solve (C2 sheet and one C3 cluster in
+    FP32, the same cluster in FP64)."""
     out = {}
-    for name, system in (("C2_sheet", workloads.config_c2()), ("C3_cluster", workloads.config_c3(1)[0])):
-        ctx = sgo.context_from_system(system, sgo.SGO_FP32)
+    for name, system, prec in (("C2_sheet", workloads.config_c2(), sgo.SGO_FP32),
+                               ("C3_cluster", workloads.config_c3(1)[0], sgo.SGO_FP32),
+                               ("C3_cluster_fp64", workloads.config_c3(1)[0], sgo.SGO_FP64)):
+        ctx = sgo.context_from_system(system, prec)
         opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=150, **CLUSTER_MIXING)
 
         def step():

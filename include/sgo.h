@@ -135,6 +135,17 @@ int sgo_destroy(sgo_ctx* ctx);
  * current PyTorch stream); NULL selects the null stream. */
 int sgo_set_stream(sgo_ctx* ctx, void* hip_stream);
 
+/* Device memory of the structures (one arena per structure: bands, sticks,
+ * grids, history; the bulk of the footprint) from the caller's allocator,
+ * e.g. a framework's caching allocator: alloc(bytes, user) returns device
+ * memory of `bytes` on the handle's device (256-byte aligned) or NULL;
+ * dealloc(ptr, user) releases it (called after the device has finished with
+ * it).  Both NULL restores hipMalloc/hipFree.  Arenas of the previous
+ * allocator are released at once (the next solve starts cold).  Small
+ * descriptor and status buffers stay with the library. */
+int sgo_set_allocator(sgo_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
+                      void (*dealloc)(void* ptr, void* user), void* user);
+
 /* Register species `id` (0 <= id < 16).  Copies *sp. */
 int sgo_set_species(sgo_ctx* ctx, int id, const sgo_species* sp);
 
@@ -149,6 +160,10 @@ int sgo_set_atoms(sgo_ctx* ctx, int natoms, const int* species, const double* po
 /* Plane-wave cutoff (Ha), FFT grid fft[3] (each N_i must hold the sphere:
  * N_i >= 2 max|m_i| + 1, and factor into 2, 3, 5; at most 128) and the
  * number of bands (must hold the electrons for fixed occupations).
+ * fft = {0, 0, 0} (or any zero entry) selects the smallest 2^a 3^b 5^c length
+ * with spacing |a_i|/N_i <= 0.375 bohr that holds the sphere; nbands = 0
+ * selects the even ceil(1.2 N_occ) (N_occ = ceil(N_el / 2)).  sgo_grid_info
+ * reports what was chosen.
  * Occupations: SGO_OCC_FIXED (2 per band, lowest first) or SGO_OCC_FERMI
  * with smearing width sigma (Ha). */
 int sgo_set_cutoff(sgo_ctx* ctx, double ecut, const int fft[3], int nbands,
@@ -264,6 +279,9 @@ int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches);
 int sgo_batch_create(sgo_batch** out, int device, int precision, int capacity);
 int sgo_batch_destroy(sgo_batch* b);
 int sgo_batch_set_stream(sgo_batch* b, void* hip_stream);
+/* Caller allocator for the candidates' arenas (as sgo_set_allocator). */
+int sgo_batch_set_allocator(sgo_batch* b, void* (*alloc)(size_t bytes, void* user),
+                            void (*dealloc)(void* ptr, void* user), void* user);
 int sgo_batch_set_species(sgo_batch* b, int id, const sgo_species* sp);
 /* Append a candidate; *index_out receives its index (add order). */
 int sgo_batch_add(sgo_batch* b, const double lattice[9], int natoms, const int* species,

@@ -58,6 +58,43 @@ class sgo_energy_terms(ctypes.Structure):
 _lib = None
 
 
+# caller allocator hooks: void* alloc(size_t bytes, void* user); void dealloc(void* p, void* user)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class TorchArenas:
+    """Allocator hooks that take the structures' device arenas from PyTorch's
+    caching allocator (uint8 tensors kept alive until the library frees them).
+    Keep the object alive as long as the handle uses it."""
+
+    def __init__(self, device=0):
+        import torch
+        self._torch = torch
+        self.device = device
+        self.live = {}
+        self.error = None
+        # initialise PyTorch's device state here, not inside a callback
+        torch.zeros(1, device="cuda:%d" % device)
+        self.alloc = ALLOC_FN(self._alloc)
+        self.free = FREE_FN(self._free)
+
+    def _alloc(self, nbytes, user):
+        # an exception must not cross the C boundary: NULL reports failure
+        try:
+            t = self._torch.empty(int(nbytes) + 256, dtype=self._torch.uint8,
+                                  device="cuda:%d" % self.device)
+        except Exception as e:  # out of memory, no device
+            self.error = e
+            return None
+        p = (t.data_ptr() + 255) // 256 * 256
+        self.live[p] = t
+        return p
+
+    def _free(self, p, user):
+        self.live.pop(p, None)
+
+
 def load_library(path=None):
     """Load libsgo.so (raises OSError if it is not built)."""
     global _lib
@@ -66,6 +103,15 @@ def load_library(path=None):
     p = path or LIB_PATH
     if not os.path.exists(p):
         raise OSError("libsgo.so not built; run python -m paper_1603_02732_amd.build")
+    # One HIP runtime per process: PyTorch carries its own copy of the HIP
+    # runtime under the same soname, and whichever is loaded first serves
+    # both.  Loading PyTorch's first (when it is installed) lets tensors,
+    # streams and allocator hooks be shared with this library in any import
+    # order; importing torch does not initialise a device.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(p)
     P, I, D, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
     dp = ctypes.POINTER(ctypes.c_double)
@@ -108,6 +154,8 @@ def load_library(path=None):
         "sgo_batch_scf": (I, [P, ctypes.POINTER(sgo_scf_opts), dp, dp, ip]),
         "sgo_batch_info": (I, [P, I, ctypes.POINTER(sgo_scf_info)]),
         "sgo_batch_size": (I, [P, ip]),
+        "sgo_set_allocator": (I, [P, ALLOC_FN, FREE_FN, P]),
+        "sgo_batch_set_allocator": (I, [P, ALLOC_FN, FREE_FN, P]),
         "sgo_batch_stress": (I, [P, dp]),
         "sgo_batch_reset": (I, [P]),
         "sgo_batch_relax_cg": (I, [P, I, ctypes.POINTER(sgo_scf_opts), dp, dp, dp, ip]),
@@ -198,6 +246,15 @@ class Context:
     def set_species(self, sid, params):
         sp = make_species(params)
         self._check(self._lib.sgo_set_species(self._h, sid, ctypes.byref(sp)))
+
+    def set_allocator(self, hooks):
+        """Route the arena allocations through `hooks` (e.g. TorchArenas());
+        None restores hipMalloc."""
+        self._hooks = hooks
+        if hooks is None:
+            self._check(self._lib.sgo_set_allocator(self._h, ALLOC_FN(), FREE_FN(), None))
+        else:
+            self._check(self._lib.sgo_set_allocator(self._h, hooks.alloc, hooks.free, None))
 
     def set_cell(self, lattice):
         a = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
@@ -394,6 +451,14 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def set_allocator(self, hooks):
+        """Route the candidates' arena allocations through `hooks`."""
+        self._hooks = hooks
+        if hooks is None:
+            self._check(self._lib.sgo_batch_set_allocator(self._h, ALLOC_FN(), FREE_FN(), None))
+        else:
+            self._check(self._lib.sgo_batch_set_allocator(self._h, hooks.alloc, hooks.free, None))
 
     def set_stream(self, stream_ptr):
         self._check(self._lib.sgo_batch_set_stream(self._h, ctypes.c_void_p(stream_ptr)))

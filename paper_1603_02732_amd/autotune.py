@@ -19,12 +19,19 @@ import time
 from . import set_tuning, default_opts, SGO_ENOTCONV
 
 SPACE = {
+    "SGO_PLANE_KERNEL": [1, 2],
+    "SGO_GEMM_KERNEL": [1, 2],
     "SGO_GRAM_KC": [256, 512, 1024, 2048],
     "SGO_SUB_THREADS": [128, 256, 512],
     "SGO_SP_CHUNK": [4, 8, 13, 20, 32],
-    "SGO_DENS_CHUNKS": [1, 2, 4],
+    "SGO_DENS_CHUNKS": [1, 2, 4, 8],
     "use_graph": [0, 1],
 }
+# schedules tuned for the standard workloads, shipped with the package and
+# consulted when the user cache has no entry (python -m
+# paper_1603_02732_amd.autotune --write-table regenerates it on the device)
+TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedules.json")
+PRECISION_NAME = {0: "fp64", 1: "fp32", 2: "fp32bf16proj"}
 
 
 def cache_path():
@@ -35,7 +42,7 @@ def cache_path():
 def key_of(systems, precision, arch="gfx950"):
     shape = [(tuple(s["grid"]), int(s["nbands"]), len(s["symbols"])) for s in systems]
     h = hashlib.sha1(json.dumps([arch, precision, shape]).encode()).hexdigest()[:16]
-    return "%s-%s-n%d-%s" % (arch, "fp64" if precision == 0 else "fp32", len(systems), h)
+    return "%s-%s-n%d-%s" % (arch, PRECISION_NAME.get(precision, str(precision)), len(systems), h)
 
 
 def _time(batch, opts, reps=2):
@@ -54,22 +61,38 @@ def apply(schedule):
             set_tuning(k, v)
 
 
-def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False):
+def _load(path):
+    if os.path.exists(path):
+        try:
+            return json.load(open(path))
+        except (OSError, ValueError):
+            return {}
+    return {}
+
+
+def lookup(systems, precision):
+    """The cached (user cache, then package table) schedule for this
+    population, applied, or None."""
+    key = key_of(systems, precision)
+    for path in (cache_path(), TABLE):
+        entry = _load(path).get(key)
+        if entry:
+            apply(entry["schedule"])
+            return dict(entry["schedule"], cached=True, source=os.path.basename(path))
+    return None
+
+
+def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False, path=None):
     """Returns the schedule (dict) and applies it.  `use_graph` in the result
     is for the caller's solve options."""
     key = key_of(systems, precision)
-    path = cache_path()
-    cache = {}
-    if use_cache and os.path.exists(path):
-        try:
-            cache = json.load(open(path))
-        except (OSError, ValueError):
-            cache = {}
+    path = path or cache_path()
+    cache = _load(path) if use_cache else {}
     if use_cache and key in cache:
         apply(cache[key]["schedule"])
         return dict(cache[key]["schedule"], cached=True)
-    sched = {"SGO_GRAM_KC": 0, "SGO_SUB_THREADS": 0, "SGO_SP_CHUNK": 0, "SGO_DENS_CHUNKS": 0,
-             "use_graph": 1}
+    sched = {"SGO_PLANE_KERNEL": 0, "SGO_GEMM_KERNEL": 0, "SGO_GRAM_KC": 0, "SGO_SUB_THREADS": 0,
+             "SGO_SP_CHUNK": 0, "SGO_DENS_CHUNKS": 0, "use_graph": 1}
     apply(sched)
 
     def opts():
@@ -105,3 +128,32 @@ def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False):
         with open(path, "w") as f:
             json.dump(cache, f, indent=1)
     return dict(sched, cached=False)
+
+
+def _main():
+    """Tune the standard populations on this device and write the table."""
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--write-table", action="store_true",
+                    help="write the package table (or --table-path) instead of the user cache")
+    ap.add_argument("--table-path", default=TABLE)
+    ap.add_argument("--iters", type=int, default=4)
+    a = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import workloads
+    from . import Batch, SGO_FP32
+    out = {}
+    for name, pop in (("C3", workloads.config_c3()),):
+        B = Batch(len(pop), precision=SGO_FP32)
+        for s in pop:
+            B.add_system(s)
+        res = autotune(B, pop, SGO_FP32, iters=a.iters, use_cache=True, verbose=True,
+                       path=a.table_path if a.write_table else None)
+        print(name, res, flush=True)
+        out[name] = res
+    return out
+
+
+if __name__ == "__main__":
+    _main()

@@ -142,6 +142,7 @@ struct HostCand {
   int npwh = 0, K = 0, Kp = 0, nsp = 0, nst = 0, npair = 0, nproj = 0, ntot = 0;
   std::vector<int> gmill, gmeta, sp_off, stick_xy, proj_atom, proj_lm;
   int pl_nx = 0, pl_nxl = 0, pl_sx = 1;  // active plane columns (register FFT kernels)
+  int N_req[3] = {0, 0, 0}, nb_req = 0;  // as requested (0: automatic)
   std::vector<double> kin, hproj, proj_r;
   FftPlan plan[3];
   double ew_eta = 0, ew_rcut = 0, ew_gcut = 0;
@@ -249,7 +250,8 @@ class Engine {
     if (!lat || !spec || !pos || !fft) throw Error(SGO_EINVAL, "NULL argument");
     if (nat <= 0) throw Error(SGO_EINVAL, "natoms must be positive");
     if (!(ecut > 0)) throw Error(SGO_EINVAL, "ecut must be positive");
-    if (nb <= 0) throw Error(SGO_EINVAL, "nbands must be positive");
+    if (nb < 0) throw Error(SGO_EINVAL, "nbands must be positive (or 0: automatic)");
+    if (fft[0] < 0 || fft[1] < 0 || fft[2] < 0) throw Error(SGO_EINVAL, "negative FFT length");
     if (occ_kind != SGO_OCC_FIXED && occ_kind != SGO_OCC_FERMI)
       throw Error(SGO_EINVAL, "unknown occupation kind");
     if (occ_kind == SGO_OCC_FERMI && !(sigma > 0)) throw Error(SGO_EINVAL, "sigma must be > 0");
@@ -265,8 +267,8 @@ class Engine {
     c.pos.assign(pos, pos + 3 * nat);
     check_distances(c);
     c.ecut = ecut;
-    for (int k = 0; k < 3; ++k) c.N[k] = fft[k];
-    c.nb = nb;
+    for (int k = 0; k < 3; ++k) c.N[k] = c.N_req[k] = fft[k];
+    c.nb = c.nb_req = nb;
     c.occ_kind = occ_kind;
     c.sigma = sigma;
     c.built = false;
@@ -324,6 +326,17 @@ class Engine {
           }
         }
     for (int i = 0; i < 3; ++i) {
+      if (c.N_req[i] == 0) {
+        // automatic grid: smallest 2^a 3^b 5^c >= max(|a_i| / 0.375, 2 m_max + 1)
+        const double an = std::sqrt(c.A[3 * i] * c.A[3 * i] + c.A[3 * i + 1] * c.A[3 * i + 1] +
+                                    c.A[3 * i + 2] * c.A[3 * i + 2]);
+        const int want = std::max((int)std::ceil(an / 0.375 - 1e-9), 2 * mabs[i] + 1);
+        int n = want;
+        FftPlan tmp;
+        while (n <= kMaxFftN && !fft_plan(n, tmp)) ++n;
+        if (n > kMaxFftN) throw Error(SGO_EINVAL, "automatic FFT grid exceeds 128 points");
+        c.N[i] = n;
+      }
       if (c.N[i] < 2 * mabs[i] + 1)
         throw Error(SGO_EINVAL, "FFT grid too small for the wavefunction sphere");
       if (!fft_plan(c.N[i], c.plan[i]))
@@ -409,6 +422,15 @@ class Engine {
     // electrons, occupations
     c.nelec = 0;
     for (int I = 0; I < c.nat; ++I) c.nelec += species_[c.spec[I]].d.Z;
+    if (c.nb_req == 0) {
+      // automatic band count: even ceil(1.2 N_occ)
+      const int nocc = (int)std::ceil(0.5 * c.nelec - 1e-9);
+      int nb = (int)std::ceil(1.2 * nocc - 1e-9);
+      if (nb % 2) ++nb;
+      c.nb = std::max(nb, nocc + 1);
+    } else {
+      c.nb = c.nb_req;
+    }
     if (c.occ_kind == SGO_OCC_FIXED) {
       const double h = 0.5 * c.nelec;
       c.nocc = (int)std::llround(h);
@@ -506,7 +528,10 @@ class Engine {
     size_t total = 0;
     for (auto& it : items) total += (it.bytes + 255) / 256 * 256;
     HIPCHK(hipSetDevice(device_));
-    if (hipMalloc(&c.mem, total) != hipSuccess) {
+    if (alloc_fn_) {
+      c.mem = (char*)alloc_fn_(total, alloc_user_);
+      if (!c.mem) throw Error(SGO_ENOMEM, "device allocation failed (caller allocator)");
+    } else if (hipMalloc(&c.mem, total) != hipSuccess) {
       c.mem = nullptr;
       throw Error(SGO_ENOMEM, "device allocation failed");
     }
@@ -579,7 +604,12 @@ class Engine {
   void free_cand(HostCand& c) {
     if (c.mem) {
       (void)hipSetDevice(device_);
-      (void)hipFree(c.mem);
+      if (free_fn_) {
+        (void)hipDeviceSynchronize();  // the caller's allocator may reuse it at once
+        free_fn_(c.mem, alloc_user_);
+      } else {
+        (void)hipFree(c.mem);
+      }
     }
     c.mem = nullptr;
     c.built = false;
@@ -1082,6 +1112,12 @@ class Engine {
     }
   }
   int precision() const { return prec_; }
+  void set_allocator(void* (*a)(size_t, void*), void (*f)(void*, void*), void* user) {
+    for (auto& c : cands_) free_cand(c);  // arenas of the previous allocator
+    alloc_fn_ = a;
+    free_fn_ = f;
+    alloc_user_ = user;
+  }
 
   // Host copy of candidate i's state (FP64); any pointer may be null.
   void get_state(int i, int* info, int* millers, double* psi, double* eig, double* occ,
@@ -1136,6 +1172,9 @@ class Engine {
   size_t desc_cap_ = 0;
   int* d_iter_ = nullptr;             // SCF iteration counter (device)
   double* d_scal_all_ = nullptr;      // [ncand][S_COUNT] gathered status scalars (device)
+  void* (*alloc_fn_)(size_t, void*) = nullptr;  // caller's device allocator (arenas)
+  void (*free_fn_)(void*, void*) = nullptr;
+  void* alloc_user_ = nullptr;
   double* h_scal_all_ = nullptr;      // pinned host copy
   size_t scal_cap_ = 0;
   hipStream_t own_stream_ = nullptr;  // used for graph capture when no stream is set
@@ -1297,6 +1336,28 @@ int sgo_set_atoms(sgo_ctx* c, int natoms, const int* species, const double* pos)
       c->atoms = oa;
       throw;
     }
+    return SGO_OK;
+  });
+}
+
+int sgo_set_allocator(sgo_ctx* c, void* (*alloc)(size_t, void*), void (*dealloc)(void*, void*),
+                      void* user) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if ((alloc == nullptr) != (dealloc == nullptr))
+      throw Error(SGO_EINVAL, "give both allocator hooks or neither");
+    c->eng->set_allocator(alloc, dealloc, user);
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_set_allocator(sgo_batch* b, void* (*alloc)(size_t, void*),
+                            void (*dealloc)(void*, void*), void* user) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if ((alloc == nullptr) != (dealloc == nullptr))
+      throw Error(SGO_EINVAL, "give both allocator hooks or neither");
+    b->eng->set_allocator(alloc, dealloc, user);
     return SGO_OK;
   });
 }
