@@ -254,7 +254,10 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
  * FFTs, the default where every line length is 2^a 3^b 5^c <= 64;
  * 2 = LDS Stockham passes, used for FP64 and longer lines),
  * "SGO_GEMM_KERNEL" (FP32 band products X M: 1 = FP32 MFMA with FP32
- * accumulation, the default; 2 = FP64 MFMA on the FP32 data).
+ * accumulation, the default; 2 = FP64 MFMA on the FP32 data),
+ * "SGO_GRAM_KERNEL" (FP32 Gram products S, H, C: 1 = FP64 MFMA, each product
+ * exact, the default; 2 = FP32 MFMA with FP32 sums over each wavefront's
+ * K share (at most SGO_GRAM_KC/4 terms) and FP64 sums of those).
  * value <= 0 restores the default (or the environment variable of the same
  * name).  SGO_EINVAL for an unknown key.  sgo_get_tuning returns the value
  * set (0 if none). */

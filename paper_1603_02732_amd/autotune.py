@@ -21,6 +21,7 @@ from . import set_tuning, default_opts, SGO_ENOTCONV
 SPACE = {
     "SGO_PLANE_KERNEL": [1, 2],
     "SGO_GEMM_KERNEL": [1, 2],
+    "SGO_GRAM_KERNEL": [1, 2],
     "SGO_GRAM_KC": [256, 512, 1024, 2048],
     "SGO_SUB_THREADS": [128, 256, 512],
     "SGO_SP_CHUNK": [4, 8, 13, 20, 32],
@@ -91,7 +92,7 @@ def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False, 
     if use_cache and key in cache:
         apply(cache[key]["schedule"])
         return dict(cache[key]["schedule"], cached=True)
-    sched = {"SGO_PLANE_KERNEL": 0, "SGO_GEMM_KERNEL": 0, "SGO_GRAM_KC": 0, "SGO_SUB_THREADS": 0,
+    sched = {"SGO_PLANE_KERNEL": 0, "SGO_GEMM_KERNEL": 0, "SGO_GRAM_KERNEL": 0, "SGO_GRAM_KC": 0, "SGO_SUB_THREADS": 0,
              "SGO_SP_CHUNK": 0, "SGO_DENS_CHUNKS": 0, "use_graph": 1}
     apply(sched)
 

@@ -652,6 +652,7 @@ class Engine {
         g.plane_reg = 0;
     if (plane_reg_lds(g, true) > (size_t)g_lds_limit) g.plane_reg = 0;
     g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
+    g.gram_f32 = tsize() == 4 && tune("SGO_GRAM_KERNEL", 1) == 2 ? 1 : 0;
     g.bf16proj = prec_ == SGO_FP32_BF16PROJ ? 1 : 0;
     g.red_min_bytes = (size_t)-1;
     for (auto& c : cands_) {
@@ -1672,7 +1673,7 @@ int sgo_set_tuning(const char* key, int value) {
   if (!key) return SGO_EINVAL;
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
                                 "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
-                                "SGO_GEMM_KERNEL"};
+                                "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;

@@ -297,6 +297,19 @@ __device__ __forceinline__ void load4(const double* p, bool ok, double* v) {
   }
 }
 
+__device__ __forceinline__ void load4(const float* p, bool ok, float* v) {
+  if (ok) {
+    const float4 a = *reinterpret_cast<const float4*>(p);
+    v[0] = a.x;
+    v[1] = a.y;
+    v[2] = a.z;
+    v[3] = a.w;
+  } else {
+    v[0] = v[1] = v[2] = v[3] = 0.f;
+  }
+}
+typedef float gfloatx4 __attribute__((ext_vector_type(4)));
+
 constexpr int kGT = 64;
 // Split-K Gram product out[i][j] = sum_k A[i][k] B[j][k] for up to two
 // products per launch.  A block covers one (16 TB)^2 output tile over one K
@@ -306,10 +319,14 @@ constexpr int kGT = 64;
 // one element each, the same k permutation for both operands).  Waves are
 // summed in LDS; each block writes the valid part of its tile to a partial
 // buffer that k_gram_reduce sums in K order.  Rows past the band count are
-// zero.
-template <typename T, int TB>
+// zero.  F32 = true (FP32 data only): FP32 MFMA with FP32 accumulation over
+// each wavefront's share of the K range (at most kc_len/4 terms); the waves,
+// blocks and K ranges are still summed in FP64.
+template <typename T, int TB, bool F32 = false>
 __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, int kc_len,
                                               int nkc_max, int a0, int b0, int a1, int b1) {
+  using AT = typename std::conditional<F32, float, double>::type;
+  using ACC = typename std::conditional<F32, gfloatx4, dbl4>::type;
   constexpr int TT = 16 * TB;
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
@@ -332,11 +349,11 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
   const int BI = min(TB, (na - ti * TT + 15) / 16), BJ = min(TB, (nbb - tj * TT + 15) / 16);
   __shared__ double tileS[TT * TT];
   for (int e = threadIdx.x; e < TT * TT; e += blockDim.x) tileS[e] = 0.0;
-  dbl4 acc[TB][TB];
+  ACC acc[TB][TB];
 #pragma unroll
   for (int u = 0; u < TB; ++u)
 #pragma unroll
-    for (int v = 0; v < TB; ++v) acc[u][v] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < TB; ++v) acc[u][v] = ACC{0, 0, 0, 0};
   const T* pa[TB];
   const T* pb[TB];
   bool oka[TB], okb[TB];
@@ -348,7 +365,7 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
     pa[u] = Am + (size_t)(oka[u] ? ra : 0) * Kp + 4 * g;
     pb[u] = Bm + (size_t)(okb[u] ? rb : 0) * Kp + 4 * g;
   }
-  double a[TB][4], b[TB][4];
+  AT a[TB][4], b[TB][4];
   int ks = k0 + wave * 16;
   if (ks < k1) {
 #pragma unroll
@@ -359,7 +376,7 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
   }
   while (ks < k1) {
     const int kn = ks + 64;
-    double an[TB][4], bn[TB][4];
+    AT an[TB][4], bn[TB][4];
     if (kn < k1) {
 #pragma unroll
       for (int u = 0; u < TB; ++u) {
@@ -373,8 +390,12 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
       for (int u = 0; u < TB; ++u)
 #pragma unroll
         for (int v = 0; v < TB; ++v)
-          if (u < BI && v < BJ)
-            acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t], b[v][t], acc[u][v], 0, 0, 0);
+          if (u < BI && v < BJ) {
+            if constexpr (F32)
+              acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][t], b[v][t], acc[u][v], 0, 0, 0);
+            else
+              acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t], b[v][t], acc[u][v], 0, 0, 0);
+          }
     if (kn < k1) {
 #pragma unroll
       for (int u = 0; u < TB; ++u)
@@ -395,7 +416,11 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
         for (int v = 0; v < TB; ++v)
           if (u < BI && v < BJ)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) tileS[(u * 16 + 4 * r + g) * TT + v * 16 + r16] += acc[u][v][r];
+            for (int r = 0; r < 4; ++r) {
+              // result register r: row 4r + g (f64 16x16x4), row 4g + r (f32 16x16x4)
+              const int row = F32 ? 4 * g + r : 4 * r + g;
+              tileS[(u * 16 + row) * TT + v * 16 + r16] += (double)acc[u][v][r];
+            }
     }
     __syncthreads();
   }
@@ -1126,6 +1151,19 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
   dim3 grid(nt * nt * g.nkc_max, nprod, g.ncand);
   dim3 rgrid((rows * rows + kNT - 1) / kNT, nprod, g.ncand);
   prof_before("k_gram", L.stream);
+  if constexpr (std::is_same<T, float>::value) {
+    if (g.gram_f32) {
+      if (TB == 2)
+        hipLaunchKernelGGL((k_gram<float, 2, true>), grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len,
+                           g.nkc_max, a[0], b[0], a1, b1);
+      else
+        hipLaunchKernelGGL((k_gram<float, 4, true>), grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len,
+                           g.nkc_max, a[0], b[0], a1, b1);
+      check_launch("k_gram");
+      prof_after("k_gram", L.stream);
+      goto reduce;
+    }
+  }
   if (TB == 2)
     hipLaunchKernelGGL((k_gram<T, 2>), grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max,
                        a[0], b[0], a1, b1);
@@ -1134,6 +1172,7 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
                        a[0], b[0], a1, b1);
   check_launch("k_gram");
   prof_after("k_gram", L.stream);
+reduce:
   prof_before("k_gram_reduce", L.stream);
   if (TB == 2)
     hipLaunchKernelGGL((k_gram_reduce<2>), rgrid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, a[0],

@@ -172,3 +172,30 @@ def test_c3_bf16_projectors_match_oracle():
         say("  C3-%d bf16 projectors: dE/atom %.2e  max dF %.2e" % (k, dE, dF))
         assert dE <= E_TOL["fp32"]
         assert dF <= F_TOL["fp32"]
+
+
+def test_c3_fp32_gram_variant_matches_oracle():
+    """The FP32-MFMA Gram products (FP32 sums over each wavefront's K share,
+    FP64 across shares): the C3 candidates with stored oracle results stay
+    within the FP32 form's energy and force tolerances."""
+    sgo = _sgo()
+    refs = [load_golden("C3-%d" % k) for k in (0, 1)]
+    if any(r is None for r in refs):
+        pytest.skip("C3 oracle references not generated")
+    sgo.set_tuning("SGO_GRAM_KERNEL", 2)
+    try:
+        pop = workloads.config_c3(2)
+        B = sgo.Batch(2, precision=sgo.SGO_FP32)
+        for s in pop:
+            B.add_system(s)
+        E, F, st = B.scf(sgo.default_opts(tol_e=1e-6, tol_rho=1e-4, max_iter=150, mix_alpha=0.3,
+                                          kerker_q0=0.3))
+        assert np.all(st == 0)
+        for k in (0, 1):
+            dE = abs(E[k] - refs[k]["energy"]) / 13
+            dF = np.abs(F[k] - np.array(refs[k]["forces"])).max()
+            say("  C3-%d FP32 Gram products: dE/atom %.2e  max dF %.2e" % (k, dE, dF))
+            assert dE <= E_TOL["fp32"]
+            assert dF <= F_TOL["fp32"]
+    finally:
+        sgo.set_tuning("SGO_GRAM_KERNEL", 0)
