@@ -93,7 +93,7 @@ def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False, 
         apply(cache[key]["schedule"])
         return dict(cache[key]["schedule"], cached=True)
     sched = {"SGO_PLANE_KERNEL": 0, "SGO_GEMM_KERNEL": 0, "SGO_GRAM_KERNEL": 0, "SGO_GRAM_KC": 0, "SGO_SUB_THREADS": 0,
-             "SGO_SP_CHUNK": 0, "SGO_DENS_CHUNKS": 0, "use_graph": 1}
+             "SGO_SP_CHUNK": 0, "SGO_DENS_CHUNKS": 0, "use_graph": 0}
     apply(sched)
 
     def opts():
