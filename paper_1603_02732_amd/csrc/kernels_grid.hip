@@ -854,6 +854,17 @@ __device__ __forceinline__ void jacobi_pair(int r, int k, int n2, int* p, int* q
 // Rotation (c, s) that zeroes A[p][q] of the symmetric matrix A:
 // theta = (a_qq - a_pp) / (2 a_pq), t = sgn(theta) / (|theta| + sqrt(theta^2 + 1)).
 // Entries at rounding level (|a_pq| <= 1e-17 sqrt|a_pp a_qq|) are left alone.
+// 1/x and 1/sqrt(x) from the hardware approximations refined by one Newton
+// step (about 1 ulp; the rotation only has to be orthogonal to rounding, and
+// c^2 + s^2 = 1 holds by construction below).
+__device__ __forceinline__ double rcp_nr(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  const double r = __builtin_amdgcn_rsq(x);
+  return r * fma(-0.5 * x * r, r, 1.5);
+}
 __device__ __forceinline__ void jacobi_rot(const double* A, int n, int p, int q, double* c,
                                            double* s) {
   *c = 1.0;
@@ -861,13 +872,20 @@ __device__ __forceinline__ void jacobi_rot(const double* A, int n, int p, int q,
   if (q >= n) return;
   const double apq = A[p * n + q];
   const double app = A[p * n + p], aqq = A[q * n + q];
-  if (!(fabs(apq) > 1e-17 * sqrt(fabs(app * aqq)) + 1e-300)) return;
-  const double th = (aqq - app) / (2.0 * apq);
+  // skip entries at rounding level: |a_pq|^2 <= 1e-34 |a_pp a_qq|
+  if (!(apq * apq > 1e-34 * fabs(app * aqq) + 1e-300)) return;
+  const double th = 0.5 * (aqq - app) * rcp_nr(apq);
   double t;
-  if (fabs(th) > 1e150) t = 0.5 / th;
-  else t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-  *c = 1.0 / sqrt(t * t + 1.0);
-  *s = t * (*c);
+  if (fabs(th) > 1e150) {
+    t = 0.5 * rcp_nr(th);
+  } else {
+    const double h = fma(th, th, 1.0);
+    const double r = h * rsq_nr(h);  // sqrt(th^2 + 1)
+    t = (th >= 0.0 ? 1.0 : -1.0) * rcp_nr(fabs(th) + r);
+  }
+  const double cc = rsq_nr(fma(t, t, 1.0));
+  *c = cc;
+  *s = t * cc;
 }
 
 __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict__ cds, int mode,
