@@ -144,9 +144,19 @@ __device__ __forceinline__ void scatter_sticks(const CandDesc& cd, const PlaneLd
   const int n = cd.N2 * p.sx;
   for (int e = lane; e < n; e += 64) p.Q[e] = {0.f, 0.f};
   __syncthreads();
-  for (int s = lane; s < cd.nst; s += 64) {
-    const int xy = cd.stick_xy[s];
-    p.Q[(xy >> 16) * p.sx + col_of_x(p, cd.N1, xy & 0xFFFF)] = st[s];
+  // batches of 4 sticks per lane: loads first, then the LDS stores
+  for (int s0 = lane; s0 < cd.nst; s0 += 256) {
+    int xy[4];
+    cplx<float> v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + 64 * u;
+      xy[u] = s < cd.nst ? cd.stick_xy[s] : 0;
+      v[u] = s < cd.nst ? st[s] : cplx<float>{0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (s0 + 64 * u < cd.nst) p.Q[(xy[u] >> 16) * p.sx + col_of_x(p, cd.N1, xy[u] & 0xFFFF)] = v[u];
   }
   __syncthreads();
 }
@@ -185,9 +195,14 @@ __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __rest
   asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
   column_pass_rt<-1>(p, cd.N2, lane);
   __syncthreads();
-  for (int s = lane; s < cd.nst; s += 64) {
-    const int xy = cd.stick_xy[s];
-    st[s] = p.Q[(xy >> 16) * p.sx + col_of_x(p, cd.N1, xy & 0xFFFF)];
+  for (int s0 = lane; s0 < cd.nst; s0 += 256) {
+    int xy[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xy[u] = s0 + 64 * u < cd.nst ? cd.stick_xy[s0 + 64 * u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (s0 + 64 * u < cd.nst)
+        st[s0 + 64 * u] = p.Q[(xy[u] >> 16) * p.sx + col_of_x(p, cd.N1, xy[u] & 0xFFFF)];
   }
 }
 
@@ -315,16 +330,29 @@ __global__ void __launch_bounds__(64, 2) k_z_inverse_reg(const CandDesc* __restr
   const bool hasb = 2 * pair + 1 < cd.nb;
   const float* xb = base + (size_t)(2 * pair + 1) * cd.Kp;
   const int g0 = cd.sp_off[ch.q0], g1 = cd.sp_off[ch.q1];
-  for (int g = g0 + lane; g < g1; g += 64) {
-    const int meta = cd.gmeta[g];
-    const int st = meta & 0xFFFFF, z = meta >> 20;
-    const cplx<float> ca = unpack_coef(xa, g);
-    const cplx<float> cb = hasb ? unpack_coef(xb, g) : cplx<float>{0.f, 0.f};
-    A[(st - ch.s0) * S + z] = {ca.x - cb.y, ca.y + cb.x};  // c_a + i c_b
-    if (g != 0) {
-      const int sm = mirror_stick_r(st);
-      const int zm = z == 0 ? 0 : N3 - z;
-      A[(sm - ch.s0) * S + zm] = {ca.x + cb.y, cb.x - ca.y};  // conj c_a + i conj c_b
+  // batches of 4 coefficients per lane: loads first, then the LDS stores
+  for (int gb = g0 + lane; gb < g1; gb += 256) {
+    int meta[4];
+    cplx<float> ca[4], cb[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int g = gb + 64 * u;
+      const bool ok = g < g1;
+      meta[u] = ok ? cd.gmeta[g] : 0;
+      ca[u] = ok ? unpack_coef(xa, g) : cplx<float>{0.f, 0.f};
+      cb[u] = (ok && hasb) ? unpack_coef(xb, g) : cplx<float>{0.f, 0.f};
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int g = gb + 64 * u;
+      if (g >= g1) continue;
+      const int st = meta[u] & 0xFFFFF, z = meta[u] >> 20;
+      A[(st - ch.s0) * S + z] = {ca[u].x - cb[u].y, ca[u].y + cb[u].x};  // c_a + i c_b
+      if (g != 0) {
+        const int sm = mirror_stick_r(st);
+        const int zm = z == 0 ? 0 : N3 - z;
+        A[(sm - ch.s0) * S + zm] = {ca[u].x + cb[u].y, cb[u].x - ca[u].y};  // conj c_a + i conj c_b
+      }
     }
   }
   __syncthreads();
@@ -378,30 +406,39 @@ __global__ void __launch_bounds__(64, 2) k_z_forward_reg(const CandDesc* __restr
   float* ya = ydst + (size_t)a * cd.Kp;
   float* yb = ydst + (size_t)b * cd.Kp;
   const int g0 = cd.sp_off[ch.q0], g1 = cd.sp_off[ch.q1];
-  for (int g = g0 + lane; g < g1; g += 64) {
-    const int meta = cd.gmeta[g];
-    const int st = meta & 0xFFFFF, z = meta >> 20;
-    const int sm = mirror_stick_r(st);
-    const int zm = z == 0 ? 0 : N3 - z;
-    const cplx<float> W = A[(st - ch.s0) * S + z];
-    const cplx<float> Wm = A[(sm - ch.s0) * S + zm];
-    // (V psi_a)_G = (W_G + conj W_-G)/2 ; (V psi_b)_G = (W_G - conj W_-G)/(2i)
-    const cplx<float> va = {0.5f * (W.x + Wm.x) * sc, 0.5f * (W.y - Wm.y) * sc};
-    const cplx<float> vb = {0.5f * (W.y + Wm.y) * sc, -0.5f * (W.x - Wm.x) * sc};
-    const float kin = (float)cd.kin[g];
-    if (g == 0) {
-      ya[0] = va.x + kin * xa[0];
-      ya[1] = 0.f;
-      if (hasb) {
-        yb[0] = vb.x + kin * xb[0];
-        yb[1] = 0.f;
-      }
-    } else {
-      ya[2 * g] = rt2 * va.x + kin * xa[2 * g];
-      ya[2 * g + 1] = rt2 * va.y + kin * xa[2 * g + 1];
-      if (hasb) {
-        yb[2 * g] = rt2 * vb.x + kin * xb[2 * g];
-        yb[2 * g + 1] = rt2 * vb.y + kin * xb[2 * g + 1];
+  // batches of 4 coefficients per lane: all loads of a batch before its stores
+  for (int gb = g0 + lane; gb < g1; gb += 256) {
+    int meta[4];
+    float kin[4];
+    float2 xav[4], xbv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int g = gb + 64 * u;
+      const bool ok = g < g1;
+      meta[u] = ok ? cd.gmeta[g] : 0;
+      kin[u] = ok ? (float)cd.kin[g] : 0.f;
+      xav[u] = ok ? *(const float2*)(xa + 2 * g) : make_float2(0.f, 0.f);
+      xbv[u] = (ok && hasb) ? *(const float2*)(xb + 2 * g) : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int g = gb + 64 * u;
+      if (g >= g1) continue;
+      const int st = meta[u] & 0xFFFFF, z = meta[u] >> 20;
+      const int sm = mirror_stick_r(st);
+      const int zm = z == 0 ? 0 : N3 - z;
+      const cplx<float> W = A[(st - ch.s0) * S + z];
+      const cplx<float> Wm = A[(sm - ch.s0) * S + zm];
+      // (V psi_a)_G = (W_G + conj W_-G)/2 ; (V psi_b)_G = (W_G - conj W_-G)/(2i)
+      const cplx<float> va = {0.5f * (W.x + Wm.x) * sc, 0.5f * (W.y - Wm.y) * sc};
+      const cplx<float> vb = {0.5f * (W.y + Wm.y) * sc, -0.5f * (W.x - Wm.x) * sc};
+      if (g == 0) {
+        *(float2*)ya = make_float2(va.x + kin[u] * xav[u].x, 0.f);
+        if (hasb) *(float2*)yb = make_float2(vb.x + kin[u] * xbv[u].x, 0.f);
+      } else {
+        *(float2*)(ya + 2 * g) = make_float2(rt2 * va.x + kin[u] * xav[u].x, rt2 * va.y + kin[u] * xav[u].y);
+        if (hasb)
+          *(float2*)(yb + 2 * g) = make_float2(rt2 * vb.x + kin[u] * xbv[u].x, rt2 * vb.y + kin[u] * xbv[u].y);
       }
     }
   }

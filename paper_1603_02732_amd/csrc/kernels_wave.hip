@@ -592,8 +592,22 @@ __global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cd
   const bool kin = kc < Kp;           // Kp is a multiple of 32: all four or none
   extern __shared__ __align__(16) char smem[];
   float4* As = (float4*)smem;         // [nin][16] float4 = [nin][64] floats
-  for (int j = g; j < nin; j += 4)
-    As[j * 16 + n] = kin ? *(const float4*)(A + (size_t)j * Kp + kc) : make_float4(0.f, 0.f, 0.f, 0.f);
+  // staged in batches of 8 rows per lane: the loads of a batch are all in
+  // flight before the first store (one memory latency per batch)
+  for (int jb = g; jb < nin; jb += 32) {
+    float4 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + 4 * u;
+      v[u] = (kin && j < nin) ? *(const float4*)(A + (size_t)j * Kp + kc)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = jb + 4 * u;
+      if (j < nin) As[j * 16 + n] = v[u];
+    }
+  }
   __syncthreads();
   for (int i0 = 0; i0 < nout; i0 += 64) {
     floatx4 acc[4][4];
