@@ -282,6 +282,8 @@ def main():
     if not a.no_plain:
         plain = plain_runs(sgo, workloads, sync)
         plain["C3_batched_fp32_bf16proj"] = bf16proj_run(sgo, pop, opts, sync)
+        plain["C4_uneven_population_batched"] = c4_run(sgo, workloads, sync)
+        plain["C5_large_cell"] = c5_run(sgo, workloads, sync)
 
     cpu = None
     if not a.no_cpu:
@@ -302,6 +304,54 @@ def main():
                       "dE_per_atom_vs_oracle": gates, "max_dF_vs_oracle": fgates},
            "plain": plain, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def c5_run(sgo, workloads, sync):
+    """The 128-atom Si cell (FFT 108x54x54, 282 bands, s+p projectors): one
+    cold solve with forces, then the fixed-basis stress."""
+    s = workloads.config_c5()
+    ctx = sgo.context_from_system(s, sgo.SGO_FP32)
+    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=200)
+    ctx.scf(opts)  # warm-up (allocation)
+    sync()
+    ctx.reset()
+    t0 = time.perf_counter()
+    info = ctx.scf(opts)
+    ctx.forces()
+    sync()
+    t1 = time.perf_counter()
+    sigma = ctx.stress()
+    sync()
+    t2 = time.perf_counter()
+    ctx.close()
+    return {"evals_per_s": 1.0 / (t1 - t0), "ms_per_eval": (t1 - t0) * 1e3,
+            "scf_iterations": info["iterations"], "stress_ms": (t2 - t1) * 1e3,
+            "pressure_GPa": float(-sigma.trace() / 3 * 29421.02648438959)}
+
+
+def c4_run(sgo, workloads, sync):
+    """The uneven population (64 candidates of 8-40 atoms, grids 32^3-64^3,
+    one batched solve, cold start) with the library's default solver settings
+    (dense cells)."""
+    import numpy as np
+    pop = workloads.config_c4()
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+    for s in pop:
+        B.add_system(s)
+    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=300)
+    B.reset()
+    B.scf(opts)
+    sync()
+    B.reset()
+    t0 = time.perf_counter()
+    E, F, st = B.scf(opts)
+    sync()
+    dt = time.perf_counter() - t0
+    its = [B.info(i)["iterations"] for i in range(len(pop))]
+    B.close()
+    return {"evals_per_s": len(pop) / dt, "ms_per_solve": dt * 1e3,
+            "all_converged": bool((st == 0).all()), "scf_iterations_max": max(its),
+            "scf_iterations_mean": float(np.mean(its))}
 
 
 def bf16proj_run(sgo, pop, opts, sync, steps=2):

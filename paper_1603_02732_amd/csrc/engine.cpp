@@ -654,6 +654,7 @@ class Engine {
     g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
     g.gram_f32 = tsize() == 4 && tune("SGO_GRAM_KERNEL", 1) == 2 ? 1 : 0;
     g.bf16proj = prec_ == SGO_FP32_BF16PROJ ? 1 : 0;
+    g.lds_limit = (size_t)g_lds_limit;
     g.red_min_bytes = (size_t)-1;
     for (auto& c : cands_) {
       const int ntile = (std::max(c.nb, c.nproj) + 63) / 64;

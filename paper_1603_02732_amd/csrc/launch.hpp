@@ -20,6 +20,7 @@ struct BatchGeom {
   int gram_f32;    // 1: FP32-MFMA Gram products (FP64 sums of the K ranges)
   int bf16proj;    // 1: projector products with BF16 inputs (FP32_BF16PROJ form)
   size_t red_min_bytes;  // smallest reduction scratch of any candidate
+  size_t lds_limit;      // dynamic LDS a kernel may use (device limit minus static use)
   int K_max;
   int sp_chunk;      // stick pairs per block of the z kernels
   int kc_len;        // K range per block of the split-K products
