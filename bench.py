@@ -153,8 +153,8 @@ def kernel_model(name, geoms, tsize):
             b += sticks + 2 * nb * K * tsize
         elif name == "k_gram":
             b += 2 * nb * K * tsize
-        elif name == "k_gemm_acc":
-            b += 2 * nb * K * tsize
+        elif name == "k_gemm_acc":  # per coefficient row moved (see below)
+            b += K * tsize
         elif name in ("k_cg_direction", "k_linemin"):
             b += 4 * nb * K * tsize
         elif name == "k_subspace":
@@ -254,6 +254,12 @@ def main():
     bound, amount_all, unit = kernel_model(dominant, geoms, 4)
     avg_active = prof["cand_launches"] / max(prof["launches"], 1)
     amount = amount_all / len(geoms) * avg_active
+    if dominant == "k_gemm_acc":
+        # the band rotation reads and writes a call-dependent number of rows
+        # (2 per band for the in-place rotation of X, HX and D, 3 for the
+        # accumulation D -= X C, band + projector rows for the nonlocal
+        # apply): the library counts them per launch
+        amount = amount_all / len(geoms) * prof["cand_rows"] / max(prof["launches"], 1)
     avg_s = prof["ms"] * 1e-3 / max(prof["launches"], 1)
     if bound == "hbm":
         ach = amount / avg_s / 1e9
@@ -266,6 +272,8 @@ def main():
             "frac": ach / peak, "traffic": traffic, "avg_launch_us": avg_s * 1e6,
             "launches_per_step": prof["launches"] / a.steps,
             "active_candidates_per_launch": avg_active,
+            "rows_per_candidate_launch": (prof["cand_rows"] / max(prof["cand_launches"], 1)
+                                          if dominant == "k_gemm_acc" else None),
             ("bytes_per_launch" if bound == "hbm" else "flop_per_launch"): amount,
             "share_of_step": {k: round(v, 4) for k, v in shares.items()}}
 
@@ -284,6 +292,7 @@ def main():
         plain["C3_batched_fp32_bf16proj"] = bf16proj_run(sgo, pop, opts, sync)
         plain["C4_uneven_population_batched"] = c4_run(sgo, workloads, sync)
         plain["C5_large_cell"] = c5_run(sgo, workloads, sync)
+        plain["C3_de_generation"] = de_run(sgo, pop, opts, sync)
 
     cpu = None
     if not a.no_cpu:
@@ -304,6 +313,35 @@ def main():
                       "dE_per_atom_vs_oracle": gates, "max_dF_vs_oracle": fgates},
            "plain": plain, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def de_run(sgo, pop, opts, sync, relax_steps=5):
+    """One differential-evolution generation of the C3 population: triangle
+    mutation (Eq. 2), plane cut-and-splice, distance check, 5 batched CG
+    steps per child (11 batched solves) and greedy selection.  The parents
+    are the population as generated, their energies from one batched solve."""
+    import numpy as np
+    from workloads.search import de_draws
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+    for s in pop:
+        B.add_system(s)
+    parents = [np.asarray(s["positions"], dtype=float) for s in pop]
+    E0, _, _ = B.scf(opts)
+    draws = de_draws(len(pop), 8, seed=2024, radius=(2.0, 4.0), offset_scale=0.5)
+    d = sgo.de_opts(crossover=sgo.SGO_DE_PLANE, relax_steps=relax_steps, dmin=2.0, attempts=8)
+    sync()
+    t0 = time.perf_counter()
+    res = B.de_generation(parents, E0, draws, de=d, opts=opts)
+    sync()
+    dt = time.perf_counter() - t0
+    B.close()
+    evals = len(pop) * (2 * relax_steps + 1)
+    return {"ms_per_generation": dt * 1e3, "evals_per_s": evals / dt,
+            "candidates": len(pop), "relax_steps": relax_steps,
+            "children_accepted_by_checks": int((res["attempt_used"] >= 0).sum()),
+            "children_selected": int(res["take"].sum()),
+            "all_converged": bool((res["status"] == 0).all()),
+            "best_energy_before": float(np.min(E0)), "best_energy_after": float(np.min(res["e_survivor"]))}
 
 
 def c5_run(sgo, workloads, sync):

@@ -270,9 +270,14 @@ int sgo_get_tuning(const char* key);
  * it is launched on.  sgo_profile_end waits for the events and returns the
  * number of launches, their summed duration in milliseconds and (nullable)
  * the sum over those launches of the candidates still active in each (a
- * population launch returns at once for converged candidates). */
+ * population launch returns at once for converged candidates).  For kernels
+ * whose traffic depends on the call (the band rotation / accumulation
+ * k_gemm_acc), `cand_rows` (nullable) returns the sum over the launches of
+ * active candidates times the coefficient rows of length K one candidate's
+ * share reads or writes (0 for kernels that do not state it). */
 int sgo_profile_begin(const char* kernel);
-int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches);
+int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches,
+                    long long* cand_rows);
 
 /* ---- Population of candidates, solved together (Section 2.4 last
  * paragraph: the relaxations of one generation may run side by side).  The
@@ -323,6 +328,112 @@ int sgo_batch_get_state(sgo_batch* b, int i, int* info, int* millers, double* ps
  * sgo_stress); candidates not yet solved get SGO_ESTATE. */
 int sgo_batch_stress(sgo_batch* b, double* stress);
 int sgo_batch_size(sgo_batch* b, int* n);
+
+/* ---- Structure-search operators (Section 2.2: initialisation with distance
+ * checks, mutation, cut-and-splice crossover, greedy selection).  Host code,
+ * no device work.  Structures are Cartesian positions [natoms][3] in bohr in
+ * one fixed cell; every random number is an argument, so equal draws give
+ * equal results.  Outputs are caller-owned. */
+enum { SGO_DE_TRIANGLE = 0, SGO_DE_CLASSIC = 1 };
+enum { SGO_DE_PLANE = 0, SGO_DE_SPHERE = 1 };
+
+/* Mutant from three donors x1..x3 (ncoord doubles each) with fitness values
+ * f1..f3.  SGO_DE_TRIANGLE: Eq. 2, v = (x1+x2+x3)/3 + (p2-p1)(x1-x2) +
+ * (p3-p2)(x2-x3) + (p1-p3)(x3-x1), p_k = |f_k| / (|f1|+|f2|+|f3|) (1/3 each
+ * when all are zero).  SGO_DE_CLASSIC: Eq. 1, v = x3 + F (x1 - x2).
+ * SGO_EINVAL for an unknown scheme or NULL arrays. */
+int sgo_de_mutate(int ncoord, const double* x1, const double* x2, const double* x3, double f1,
+                  double f2, double f3, int scheme, double F, double* v);
+
+/* Plane cut-and-splice (Section 2.2, Fig. 2a).  Parents p1, p2 [natoms][3]
+ * share the species array `species` [natoms].  The child takes P1's atoms
+ * strictly on the +n side of the plane through P1's centroid and P2's atoms
+ * on the other side of (or on) the plane through P2's centroid, translated
+ * by centroid(P1) - centroid(P2).  If the per-species counts differ from
+ * P1's, n turns about `axis` (made orthogonal to n) to the first angle in
+ * [0, 2 pi) that gives them; theta (nullable) receives that angle.  Child
+ * slot order: for each species, P1's atoms (ascending index) fill its slots
+ * first, then P2's.  source (nullable) [natoms][2] = (parent 0/1, atom
+ * index) of each child atom.  SGO_ENUMERIC when no angle gives P1's
+ * composition; SGO_EINVAL for a zero normal or an axis parallel to it. */
+int sgo_de_cross_plane(int natoms, const int* species, const double* p1, const double* p2,
+                       const double normal[3], const double axis[3], double* child, int* source,
+                       double* theta);
+
+/* Sphere cut-and-splice (Section 2.2, Fig. 2b).  Spheres of `radius` about
+ * each parent's centroid + offset.  The child takes P2's atoms inside its
+ * sphere (translated as above) and, per species, the atoms of P1 farthest
+ * from its sphere centre that complete P1's count.  Slot order and source as
+ * for the plane scheme. */
+int sgo_de_cross_sphere(int natoms, const int* species, const double* p1, const double* p2,
+                        const double offset[3], double radius, double* child, int* source);
+
+/* Smallest interatomic distance (minimum image over the 27 neighbouring
+ * cells; +inf for fewer than two atoms). */
+int sgo_de_min_distance(const double lattice[9], int natoms, const double* pos, double* dmin);
+
+/* Structure similarity: mean absolute difference of the sorted
+ * pair-distance lists (bohr; 0 for identical structures up to permutation,
+ * translation and rotation when no distance wraps). */
+int sgo_de_similarity(const double lattice[9], int natoms, const double* pa, const double* pb,
+                      double* s);
+
+/* Random initial structure (Section 2.2, population initialisation).
+ * region 0: whole cell, fractional (u1,u2,u3); 1: ball of radius params[0]
+ * about the cell centre, r = R u1^(1/3), cos(polar) = 2u2-1, azimuth 2 pi u3;
+ * 2: slab, fractional x = u1, y = u2 and z within params[0] bohr of the
+ * middle plane.  Each trial atom consumes three of the `nuniform` uniforms
+ * in [0,1); a trial closer than dmin (minimum image) to a placed atom is
+ * dropped.  *used (nullable) = uniforms consumed.  SGO_ENUMERIC when they
+ * run out before natoms atoms are placed. */
+int sgo_de_init_positions(const double lattice[9], int natoms, int region, const double* params,
+                          double dmin, const double* uniforms, int nuniform, double* pos,
+                          int* used);
+
+/* Greedy selection: take[i] = 1 when the child converged (child_status NULL
+ * or SGO_OK) and e_child[i] < e_parent[i]. */
+int sgo_de_select(int n, const double* e_parent, const double* e_child, const int* child_status,
+                  int* take);
+
+/* One generation on a population batch: for each target i, mutant from the
+ * donors of its first acceptable draw, crossover with the target (P1 = the
+ * mutant, P2 = the target), child rejected when closer than dmin or, with
+ * sim_tol > 0, less than sim_tol from any parent; then relax_steps batched CG
+ * steps (sgo_batch_relax_cg) of every child and greedy selection.  A target
+ * whose draws are all rejected relaxes its own structure instead. */
+typedef struct {
+  int mutation;       /* SGO_DE_TRIANGLE or SGO_DE_CLASSIC */
+  int crossover;      /* SGO_DE_PLANE or SGO_DE_SPHERE */
+  double F;           /* Eq. 1 scale (classic mutation) */
+  int fitness_shift;  /* 1: fitness = E - min E of the parents (lower energy,
+                         larger weight in Eq. 2); 0: fitness = E */
+  int relax_steps;    /* CG steps per child, >= 0 */
+  double dmin;        /* bohr */
+  double sim_tol;     /* bohr; 0 disables the similarity check */
+  int attempts;       /* draws per target, >= 1 */
+} sgo_de_opts;
+
+typedef struct {      /* random numbers of one attempt for one target */
+  int r[3];           /* donor indices, distinct and different from the target */
+  double normal[3];   /* plane scheme */
+  double axis[3];
+  double offset[3];   /* sphere scheme */
+  double radius;
+} sgo_de_draw;
+
+/* parents [sum natoms*3] and e_parent [n] describe the current generation in
+ * the batch's add order (every candidate must share one species array and
+ * cell); draws [n][attempts].  Outputs (each nullable): trial [sum natoms*3]
+ * the children before relaxation, attempt_used [n] (-1: no draw accepted),
+ * e_trial [n] the relaxed children's energies, survivors [sum natoms*3] and
+ * e_survivor [n] the next generation, take [n] the selection, status [n].
+ * The batch's candidates are left at the survivors' positions.  SGO_EINVAL
+ * for invalid draws or options; otherwise the worst relaxation status. */
+int sgo_batch_de_generation(sgo_batch* b, const sgo_de_opts* de, const sgo_scf_opts* opts,
+                            const double* parents, const double* e_parent,
+                            const sgo_de_draw* draws, double* trial, int* attempt_used,
+                            double* e_trial, double* survivors, double* e_survivor, int* take,
+                            int* status);
 const char* sgo_batch_last_error(const sgo_batch* b);
 
 #ifdef __cplusplus

@@ -20,6 +20,8 @@ SGO_OK, SGO_EINVAL, SGO_ENOMEM, SGO_EDEVICE, SGO_ENOTCONV, SGO_ENUMERIC, SGO_EST
 SGO_FP64, SGO_FP32, SGO_FP32_BF16PROJ = 0, 1, 2
 SGO_LOCAL_AH, SGO_LOCAL_GAUSS = 0, 1
 SGO_OCC_FIXED, SGO_OCC_FERMI = 0, 1
+SGO_DE_TRIANGLE, SGO_DE_CLASSIC = 0, 1
+SGO_DE_PLANE, SGO_DE_SPHERE = 0, 1
 _STATUS = {0: "SGO_OK", -1: "SGO_EINVAL", -2: "SGO_ENOMEM", -3: "SGO_EDEVICE",
            -4: "SGO_ENOTCONV", -5: "SGO_ENUMERIC", -6: "SGO_ESTATE"}
 
@@ -61,6 +63,18 @@ _lib = None
 # caller allocator hooks: void* alloc(size_t bytes, void* user); void dealloc(void* p, void* user)
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class sgo_de_opts(ctypes.Structure):
+    _fields_ = [("mutation", ctypes.c_int), ("crossover", ctypes.c_int), ("F", ctypes.c_double),
+                ("fitness_shift", ctypes.c_int), ("relax_steps", ctypes.c_int),
+                ("dmin", ctypes.c_double), ("sim_tol", ctypes.c_double), ("attempts", ctypes.c_int)]
+
+
+class sgo_de_draw(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int * 3), ("normal", ctypes.c_double * 3),
+                ("axis", ctypes.c_double * 3), ("offset", ctypes.c_double * 3),
+                ("radius", ctypes.c_double)]
 
 
 class TorchArenas:
@@ -144,7 +158,8 @@ def load_library(path=None):
         "sgo_subspace_solve": (I, [I, I, I, dp, dp, dp, dp, I, dp,
                                    ctypes.POINTER(ctypes.c_longlong)]),
         "sgo_profile_begin": (I, [ctypes.c_char_p]),
-        "sgo_profile_end": (I, [ip, dp, ctypes.POINTER(ctypes.c_longlong)]),
+        "sgo_profile_end": (I, [ip, dp, ctypes.POINTER(ctypes.c_longlong),
+                             ctypes.POINTER(ctypes.c_longlong)]),
         "sgo_batch_create": (I, [ctypes.POINTER(P), I, I, I]),
         "sgo_batch_destroy": (I, [P]),
         "sgo_batch_set_stream": (I, [P, P]),
@@ -162,6 +177,16 @@ def load_library(path=None):
         "sgo_batch_get_state": (I, [P, I, ip, ip, dp, dp, dp, dp, dp,
                                     ctypes.POINTER(sgo_energy_terms)]),
         "sgo_batch_last_error": (ctypes.c_char_p, [P]),
+        "sgo_de_mutate": (I, [I, dp, dp, dp, D, D, D, I, D, dp]),
+        "sgo_de_cross_plane": (I, [I, ip, dp, dp, dp, dp, dp, ip, dp]),
+        "sgo_de_cross_sphere": (I, [I, ip, dp, dp, dp, D, dp, ip]),
+        "sgo_de_min_distance": (I, [dp, I, dp, dp]),
+        "sgo_de_similarity": (I, [dp, I, dp, dp, dp]),
+        "sgo_de_init_positions": (I, [dp, I, I, dp, D, dp, I, dp, ip]),
+        "sgo_de_select": (I, [I, dp, dp, ip, ip]),
+        "sgo_batch_de_generation": (I, [P, ctypes.POINTER(sgo_de_opts),
+                                        ctypes.POINTER(sgo_scf_opts), dp, dp,
+                                        ctypes.POINTER(sgo_de_draw), dp, ip, dp, dp, dp, ip, ip]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -416,11 +441,136 @@ def profile_end():
     n = ctypes.c_int()
     ms = ctypes.c_double()
     cl = ctypes.c_longlong()
+    cr = ctypes.c_longlong()
     lib = load_library()
-    rc = lib.sgo_profile_end(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(cl))
+    rc = lib.sgo_profile_end(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(cl), ctypes.byref(cr))
     if rc != SGO_OK:
         raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
-    return {"launches": n.value, "ms": ms.value, "cand_launches": cl.value}
+    return {"launches": n.value, "ms": ms.value, "cand_launches": cl.value, "cand_rows": cr.value}
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a if shape is None else a.reshape(shape)
+
+
+def de_mutate(x1, x2, x3, f, scheme=SGO_DE_TRIANGLE, F=0.5):
+    """Mutant of three donor structures (Eq. 2 triangle, or Eq. 1)."""
+    x1, x2, x3 = _f64(x1), _f64(x2), _f64(x3)
+    v = np.zeros_like(x1)
+    rc = load_library().sgo_de_mutate(x1.size, _dptr(x1), _dptr(x2), _dptr(x3), float(f[0]),
+                                      float(f[1]), float(f[2]), int(scheme), float(F), _dptr(v))
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_mutate")
+    return v
+
+
+def de_cross_plane(p1, p2, species, normal, axis):
+    """Plane cut-and-splice: (child, source [natoms, 2], theta) or None when
+    no orientation gives P1's composition."""
+    p1, p2 = _f64(p1), _f64(p2)
+    n = p1.shape[0]
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    child = np.zeros((n, 3))
+    src = np.zeros((n, 2), dtype=np.int32)
+    th = ctypes.c_double()
+    rc = load_library().sgo_de_cross_plane(n, _iptr(sp), _dptr(p1), _dptr(p2),
+                                           _dptr(_f64(normal)), _dptr(_f64(axis)), _dptr(child),
+                                           _iptr(src), ctypes.byref(th))
+    if rc == SGO_ENUMERIC:
+        return None
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_cross_plane")
+    return child, src, th.value
+
+
+def de_cross_sphere(p1, p2, species, offset, radius):
+    """Sphere cut-and-splice: (child, source [natoms, 2])."""
+    p1, p2 = _f64(p1), _f64(p2)
+    n = p1.shape[0]
+    sp = np.ascontiguousarray(species, dtype=np.int32)
+    child = np.zeros((n, 3))
+    src = np.zeros((n, 2), dtype=np.int32)
+    rc = load_library().sgo_de_cross_sphere(n, _iptr(sp), _dptr(p1), _dptr(p2),
+                                            _dptr(_f64(offset)), float(radius), _dptr(child),
+                                            _iptr(src))
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_cross_sphere")
+    return child, src
+
+
+def de_min_distance(lattice, pos):
+    pos = _f64(pos)
+    d = ctypes.c_double()
+    rc = load_library().sgo_de_min_distance(_dptr(_f64(lattice, 9)), pos.shape[0], _dptr(pos),
+                                            ctypes.byref(d))
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_min_distance")
+    return d.value
+
+
+def de_similarity(lattice, pa, pb):
+    pa, pb = _f64(pa), _f64(pb)
+    d = ctypes.c_double()
+    rc = load_library().sgo_de_similarity(_dptr(_f64(lattice, 9)), pa.shape[0], _dptr(pa),
+                                          _dptr(pb), ctypes.byref(d))
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_similarity")
+    return d.value
+
+
+def de_init_positions(lattice, natoms, region, params, dmin, uniforms):
+    """Random placement; (positions [natoms, 3], uniforms used) or None when
+    the uniforms run out."""
+    u = _f64(uniforms)
+    par = _f64(list(params) + [0.0])
+    pos = np.zeros((natoms, 3))
+    used = ctypes.c_int()
+    rc = load_library().sgo_de_init_positions(_dptr(_f64(lattice, 9)), int(natoms), int(region),
+                                              _dptr(par), float(dmin), _dptr(u), u.size,
+                                              _dptr(pos), ctypes.byref(used))
+    if rc == SGO_ENUMERIC:
+        return None
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_init_positions")
+    return pos, used.value
+
+
+def de_select(e_parent, e_child, child_status=None):
+    ep, ec = _f64(e_parent), _f64(e_child)
+    take = np.zeros(ep.size, dtype=np.int32)
+    st = None if child_status is None else np.ascontiguousarray(child_status, dtype=np.int32)
+    rc = load_library().sgo_de_select(ep.size, _dptr(ep), _dptr(ec),
+                                      None if st is None else _iptr(st), _iptr(take))
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_select")
+    return take
+
+
+def de_opts(mutation=SGO_DE_TRIANGLE, crossover=SGO_DE_PLANE, F=0.5, fitness_shift=1,
+            relax_steps=5, dmin=2.0, sim_tol=0.0, attempts=4):
+    o = sgo_de_opts()
+    o.mutation, o.crossover, o.F, o.fitness_shift = mutation, crossover, F, fitness_shift
+    o.relax_steps, o.dmin, o.sim_tol, o.attempts = relax_steps, dmin, sim_tol, attempts
+    return o
+
+
+def de_draws(d):
+    """sgo_de_draw array [n * attempts] from a dict of arrays: r [n, a, 3],
+    normal, axis, offset [n, a, 3], radius [n, a]."""
+    r = np.asarray(d["r"])
+    n, a = r.shape[:2]
+    arr = (sgo_de_draw * (n * a))()
+    for i in range(n):
+        for k in range(a):
+            e = arr[i * a + k]
+            for c in range(3):
+                e.r[c] = int(r[i, k, c])
+                e.normal[c] = float(d["normal"][i][k][c])
+                e.axis[c] = float(d["axis"][i][k][c])
+                e.offset[c] = float(d["offset"][i][k][c])
+            e.radius = float(d["radius"][i][k])
+    return arr
 
 
 class Batch:
@@ -546,6 +696,42 @@ class Batch:
             pos.append(p[off:off + 3 * na].reshape(na, 3))
             off += 3 * na
         return e, forces, pos, st
+
+    def de_generation(self, parents, e_parent, draws, de=None, opts=None, **kw):
+        """One differential-evolution generation over the batch (mutation,
+        crossover, checks, relax_steps batched CG steps, greedy selection).
+        parents: list of (natoms, 3); draws: dict as for de_draws().  Returns
+        a dict with trial, attempt_used, e_trial, survivors, e_survivor, take,
+        status."""
+        o = opts if opts is not None else default_opts(**kw)
+        d = de if de is not None else de_opts()
+        n = len(self.natoms)
+        P = np.ascontiguousarray(np.concatenate([np.asarray(p, dtype=np.float64).reshape(-1)
+                                                 for p in parents]))
+        ep = _f64(e_parent)
+        dr = de_draws(draws)
+        trial = np.zeros_like(P)
+        surv = np.zeros_like(P)
+        used = np.zeros(n, dtype=np.int32)
+        et = np.zeros(n)
+        es = np.zeros(n)
+        take = np.zeros(n, dtype=np.int32)
+        st = np.zeros(n, dtype=np.int32)
+        rc = self._lib.sgo_batch_de_generation(self._h, ctypes.byref(d), ctypes.byref(o), _dptr(P),
+                                               _dptr(ep), dr, _dptr(trial), _iptr(used),
+                                               _dptr(et), _dptr(surv), _dptr(es), _iptr(take),
+                                               _iptr(st))
+        if rc not in (SGO_OK, SGO_ENOTCONV, SGO_ENUMERIC):
+            self._check(rc)
+
+        def split(a):
+            out, off = [], 0
+            for na in self.natoms:
+                out.append(a[off:off + 3 * na].reshape(na, 3))
+                off += 3 * na
+            return out
+        return {"trial": split(trial), "attempt_used": used, "e_trial": et,
+                "survivors": split(surv), "e_survivor": es, "take": take, "status": st}
 
     def info(self, i):
         inf = sgo_scf_info()

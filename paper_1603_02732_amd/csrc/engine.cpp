@@ -15,6 +15,7 @@
 
 #include "../../include/sgo.h"
 #include "common.hpp"
+#include "de.hpp"
 #include "launch.hpp"
 
 namespace sgo {
@@ -59,6 +60,7 @@ struct ProfState {
   std::string name;
   int active = 0;          // candidates active in the launches being issued
   long long cand_launches = 0;  // sum over profiled launches of `active`
+  long long cand_rows = 0;      // sum over profiled launches of `active` x row passes
   std::vector<hipEvent_t> ev;  // start/stop pairs
   size_t used = 0;
 };
@@ -76,11 +78,12 @@ void prof_before(const char* name, hipStream_t s) {
   }
   HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], s));
 }
-void prof_after(const char* name, hipStream_t s) {
+void prof_after(const char* name, hipStream_t s, long long rows) {
   if (!g_prof.on || g_capturing || g_prof.name != name) return;
   HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], s));
   g_prof.used += 2;
   g_prof.cand_launches += g_prof.active;
+  g_prof.cand_rows += (long long)g_prof.active * rows;
 }
 
 void throw_unsupported(const char* what) { throw Error(SGO_EINVAL, what); }
@@ -1565,10 +1568,12 @@ int sgo_profile_begin(const char* kernel) {
   sgo::g_prof.name = kernel;
   sgo::g_prof.used = 0;
   sgo::g_prof.cand_launches = 0;
+  sgo::g_prof.cand_rows = 0;
   return SGO_OK;
 }
 
-int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches) {
+int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches,
+                    long long* cand_rows) {
   return guard(nullptr, [&] {
     auto& P = sgo::g_prof;
     double ms = 0.0;
@@ -1581,9 +1586,11 @@ int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches) {
     if (launches) *launches = (int)(P.used / 2);
     if (total_ms) *total_ms = ms;
     if (cand_launches) *cand_launches = P.cand_launches;
+    if (cand_rows) *cand_rows = P.cand_rows;
     P.on = false;
     P.used = 0;
     P.cand_launches = 0;
+    P.cand_rows = 0;
     return SGO_OK;
   });
 }
@@ -1848,5 +1855,94 @@ int sgo_batch_size(sgo_batch* b, int* n) {
 }
 
 const char* sgo_batch_last_error(const sgo_batch* b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+int sgo_batch_de_generation(sgo_batch* b, const sgo_de_opts* de, const sgo_scf_opts* opts,
+                            const double* parents, const double* e_parent,
+                            const sgo_de_draw* draws, double* trial, int* attempt_used,
+                            double* e_trial, double* survivors, double* e_survivor, int* take,
+                            int* status) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if (!de || !parents || !e_parent || !draws) throw Error(SGO_EINVAL, "NULL argument");
+    sgo::Engine& eng = *b->eng;
+    const int n = eng.size();
+    if (n < 4) throw Error(SGO_EINVAL, "a generation needs at least 4 candidates");
+    if ((de->mutation != SGO_DE_TRIANGLE && de->mutation != SGO_DE_CLASSIC) ||
+        (de->crossover != SGO_DE_PLANE && de->crossover != SGO_DE_SPHERE) ||
+        de->relax_steps < 0 || de->attempts < 1 || !(de->dmin >= 0) || !(de->sim_tol >= 0))
+      throw Error(SGO_EINVAL, "invalid generation options");
+    const sgo::HostCand& c0 = eng.cand(0);
+    const int nat = c0.nat, nc = 3 * nat;
+    for (int i = 1; i < n; ++i) {
+      const sgo::HostCand& c = eng.cand(i);
+      if (c.nat != nat || c.spec != c0.spec || !std::equal(c.A, c.A + 9, c0.A))
+        throw Error(SGO_EINVAL, "the candidates of a generation share one species array and cell");
+    }
+    const int na = de->attempts;
+    for (int i = 0; i < n; ++i)
+      for (int a = 0; a < na; ++a) {
+        const int* r = draws[(size_t)i * na + a].r;
+        for (int k = 0; k < 3; ++k)
+          if (r[k] < 0 || r[k] >= n || r[k] == i || r[k] == r[(k + 1) % 3])
+            throw Error(SGO_EINVAL, "donors must be distinct candidates other than the target");
+      }
+    double emin = e_parent[0];
+    for (int i = 1; i < n; ++i) emin = std::min(emin, e_parent[i]);
+    std::vector<double> f(n);
+    for (int i = 0; i < n; ++i) f[i] = e_parent[i] - (de->fitness_shift ? emin : 0.0);
+    auto P = [&](int i) { return parents + (size_t)i * nc; };
+    std::vector<double> tr((size_t)n * nc), v(nc), child(nc);
+    std::vector<int> used(n, -1);
+    for (int i = 0; i < n; ++i) {
+      for (int a = 0; a < na && used[i] < 0; ++a) {
+        const sgo_de_draw& d = draws[(size_t)i * na + a];
+        sgo::de::mutate(nc, P(d.r[0]), P(d.r[1]), P(d.r[2]), f[d.r[0]], f[d.r[1]], f[d.r[2]],
+                        de->mutation == SGO_DE_CLASSIC, de->F, v.data());
+        const int rc = de->crossover == SGO_DE_PLANE
+                           ? sgo::de::cross_plane(nat, c0.spec.data(), v.data(), P(i), d.normal,
+                                                  d.axis, child.data(), nullptr, nullptr)
+                           : sgo::de::cross_sphere(nat, c0.spec.data(), v.data(), P(i), d.offset,
+                                                   d.radius, child.data(), nullptr);
+        if (rc == SGO_EINVAL) throw Error(SGO_EINVAL, "invalid crossover draw");
+        if (rc != SGO_OK) continue;
+        if (sgo::de::min_distance(c0.A, nat, child.data()) < de->dmin) continue;
+        bool alike = false;
+        for (int j = 0; j < n && de->sim_tol > 0 && !alike; ++j)
+          alike = sgo::de::similarity(c0.A, nat, child.data(), P(j)) < de->sim_tol;
+        if (alike) continue;
+        std::copy(child.begin(), child.end(), tr.begin() + (size_t)i * nc);
+        used[i] = a;
+      }
+      if (used[i] < 0) std::copy(P(i), P(i) + nc, tr.begin() + (size_t)i * nc);
+    }
+    for (int i = 0; i < n; ++i) eng.move_atoms(i, tr.data() + (size_t)i * nc);
+    const int ns = de->relax_steps;
+    std::vector<double> en((size_t)n * (ns + 1));
+    const sgo_scf_opts o = opts_or_default(opts);
+    const int rc = eng.relax_cg(ns, o, en.data());
+    int worst = SGO_OK;
+    std::vector<double> keep(nc);
+    for (int i = 0; i < n; ++i) {
+      const sgo::HostCand& c = eng.cand(i);
+      const double et = en[(size_t)i * (ns + 1) + ns];
+      const int ok = (c.status == SGO_OK && et < e_parent[i]) ? 1 : 0;
+      if (ok)
+        std::copy(c.pos.begin(), c.pos.end(), keep.begin());
+      else
+        std::copy(P(i), P(i) + nc, keep.begin());
+      if (trial) std::copy(tr.begin() + (size_t)i * nc, tr.begin() + (size_t)(i + 1) * nc, trial + (size_t)i * nc);
+      if (attempt_used) attempt_used[i] = used[i];
+      if (e_trial) e_trial[i] = et;
+      if (take) take[i] = ok;
+      if (status) status[i] = c.status;
+      if (e_survivor) e_survivor[i] = ok ? et : e_parent[i];
+      if (survivors) std::copy(keep.begin(), keep.end(), survivors + (size_t)i * nc);
+      if (c.status < worst) worst = c.status;
+      eng.move_atoms(i, keep.data());  // the batch keeps the survivors (warm start from the child)
+    }
+    (void)rc;
+    return worst;
+  });
+}
 
 }  // extern "C"

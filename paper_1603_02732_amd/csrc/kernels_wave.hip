@@ -1210,7 +1210,12 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
   const int y1 = narr > 1 ? y[1] : 0, y2 = narr > 2 ? y[2] : 0;
   const int a1 = narr > 1 ? a[1] : 0, a2 = narr > 2 ? a[2] : 0;
   int nin_max = 0;
-  for (int q = 0; q < narr; ++q) nin_max = std::max(nin_max, a[q] == W_BETA ? g.nproj_max : g.nb_max);
+  long long rows_moved = 0;  // per candidate: A read, Y written, Y read when alpha != 0
+  for (int q = 0; q < narr; ++q) {
+    const int nin = a[q] == W_BETA ? g.nproj_max : g.nb_max;
+    nin_max = std::max(nin_max, nin);
+    rows_moved += nin + (alpha != 0.0 ? 2 : 1) * g.nb_max;
+  }
   const size_t lds32 = (size_t)nin_max * 64 * sizeof(float);
   if (std::is_same<T, float>::value && lds32 <= 65536 && g.gemm_f32) {
     prof_before("k_gemm_acc", L.stream);
@@ -1218,7 +1223,7 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
                        L.stream, L.desc, y[0], y1, y2, a[0], a1, a2, mat, (float)alpha,
                        (float)beta, use_h);
     check_launch("k_gemm_acc");
-    prof_after("k_gemm_acc", L.stream);
+    prof_after("k_gemm_acc", L.stream, rows_moved);
     return;
   }
   prof_before("k_gemm_acc", L.stream);
@@ -1234,7 +1239,7 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
   else
     throw_unsupported("more than 320 bands in the rotation kernel");
   check_launch("k_gemm_acc");
-  prof_after("k_gemm_acc", L.stream);
+  prof_after("k_gemm_acc", L.stream, rows_moved);
 }
 
 // J = float4 per thread and band array of the one-pass FP32 band kernels

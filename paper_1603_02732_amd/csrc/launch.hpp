@@ -88,6 +88,8 @@ void check_launch(const char* name);
 void throw_unsupported(const char* what);
 // Optional event timing of every launch of one named kernel.
 void prof_before(const char* name, hipStream_t s);
-void prof_after(const char* name, hipStream_t s);
+// `rows`: coefficient rows (band or projector rows of length K) that one
+// candidate's share of the launch reads or writes, where a launcher states it
+void prof_after(const char* name, hipStream_t s, long long rows = 0);
 
 }  // namespace sgo
