@@ -390,6 +390,11 @@ int sgo_de_init_positions(const double lattice[9], int natoms, int region, const
                           double dmin, const double* uniforms, int nuniform, double* pos,
                           int* used);
 
+/* Perturbed cell for a new individual (Section 2.2, population
+ * initialisation): lattice vector k scaled by 1 + delta (2 u[k] - 1).
+ * SGO_EINVAL for NULL arrays or delta < 0. */
+int sgo_de_jitter_cell(const double lattice[9], double delta, const double u[3], double out[9]);
+
 /* Greedy selection: take[i] = 1 when the child converged (child_status NULL
  * or SGO_OK) and e_child[i] < e_parent[i]. */
 int sgo_de_select(int n, const double* e_parent, const double* e_child, const int* child_status,

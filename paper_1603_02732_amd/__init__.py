@@ -184,6 +184,7 @@ def load_library(path=None):
         "sgo_de_similarity": (I, [dp, I, dp, dp, dp]),
         "sgo_de_init_positions": (I, [dp, I, I, dp, D, dp, I, dp, ip]),
         "sgo_de_select": (I, [I, dp, dp, ip, ip]),
+        "sgo_de_jitter_cell": (I, [dp, D, dp, dp]),
         "sgo_batch_de_generation": (I, [P, ctypes.POINTER(sgo_de_opts),
                                         ctypes.POINTER(sgo_scf_opts), dp, dp,
                                         ctypes.POINTER(sgo_de_draw), dp, ip, dp, dp, dp, ip, ip]),
@@ -534,6 +535,16 @@ def de_init_positions(lattice, natoms, region, params, dmin, uniforms):
     if rc != SGO_OK:
         raise SgoError(rc, "de_init_positions")
     return pos, used.value
+
+
+def de_jitter_cell(lattice, delta, u3):
+    """Lattice vectors scaled by 1 + delta (2 u_k - 1)."""
+    out = np.zeros(9)
+    rc = load_library().sgo_de_jitter_cell(_dptr(_f64(lattice, 9)), float(delta),
+                                           _dptr(_f64(u3)), _dptr(out))
+    if rc != SGO_OK:
+        raise SgoError(rc, "de_jitter_cell")
+    return out.reshape(3, 3)
 
 
 def de_select(e_parent, e_child, child_status=None):

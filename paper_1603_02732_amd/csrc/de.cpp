@@ -306,6 +306,15 @@ int sgo_de_init_positions(const double lattice[9], int natoms, int region, const
                                  used);
 }
 
+int sgo_de_jitter_cell(const double lattice[9], double delta, const double u[3], double out[9]) {
+  if (!lattice || !u || !out || !(delta >= 0)) return SGO_EINVAL;
+  for (int k = 0; k < 3; ++k) {
+    const double f = 1.0 + delta * (2.0 * u[k] - 1.0);
+    for (int c = 0; c < 3; ++c) out[3 * k + c] = lattice[3 * k + c] * f;
+  }
+  return SGO_OK;
+}
+
 int sgo_de_select(int n, const double* e_parent, const double* e_child, const int* child_status,
                   int* take) {
   if (n < 0 || (n > 0 && (!e_parent || !e_child || !take))) return SGO_EINVAL;

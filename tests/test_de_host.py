@@ -90,6 +90,14 @@ def test_init_parity(region, params, dmin):
     assert sgo.de_init_positions(A, 40, 1, [1.0], 2.0, u[:60]) is None
 
 
+def test_jitter_parity():
+    rng = np.random.default_rng(16)
+    A = np.array([[10.0, 0, 0], [3.0, 9.0, 0], [1.0, 2.0, 11.0]])
+    for trial in range(5):
+        u = rng.random(3)
+        assert np.abs(sgo.de_jitter_cell(A, 0.05, u) - de.jitter_cell(A, 0.05, u)).max() < TOL
+
+
 def test_select_parity():
     rng = np.random.default_rng(15)
     ep = rng.normal(size=50)
