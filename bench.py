@@ -293,6 +293,7 @@ def main():
         plain["C4_uneven_population_batched"] = c4_run(sgo, workloads, sync)
         plain["C5_large_cell"] = c5_run(sgo, workloads, sync)
         plain["C3_de_generation"] = de_run(sgo, pop, opts, sync)
+        plain["C3_relax_cg_vs_pcg"] = relax_run(sgo, pop, opts, sync)
 
     cpu = None
     if not a.no_cpu:
@@ -313,6 +314,33 @@ def main():
                       "dE_per_atom_vs_oracle": gates, "max_dF_vs_oracle": fgates},
            "plain": plain, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def relax_run(sgo, pop, opts, sync, steps=5):
+    """The C3 population relaxed by 5 steps of plain CG and, from the same
+    start, 5 steps of force-fitted PCG (two batched solves per step each)."""
+    import numpy as np
+    out = {}
+    for name in ("cg", "pcg"):
+        B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+        for s in pop:
+            B.add_system(s)
+        B.scf(opts)  # warm-up and allocation
+        B.reset()
+        sync()
+        t0 = time.perf_counter()
+        if name == "cg":
+            E, F, X, st = B.relax_cg(steps, opts=opts)
+        else:
+            E, F, X, prm, st = B.relax_pcg(steps, refit=1, opts=opts)
+        sync()
+        dt = time.perf_counter() - t0
+        B.close()
+        out[name] = {"ms_per_step": dt / steps * 1e3,
+                     "mean_energy_drop_per_atom": float(np.mean(E[:, 0] - E[:, -1]) / 13),
+                     "mean_max_force_after": float(np.mean([np.abs(f).max() for f in F])),
+                     "all_converged": bool((st == 0).all())}
+    return out
 
 
 def de_run(sgo, pop, opts, sync, relax_steps=5):

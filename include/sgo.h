@@ -257,7 +257,10 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
  * accumulation, the default; 2 = FP64 MFMA on the FP32 data),
  * "SGO_GRAM_KERNEL" (FP32 Gram products S, H, C: 1 = FP64 MFMA, each product
  * exact, the default; 2 = FP32 MFMA with FP32 sums over each wavefront's
- * K share (at most SGO_GRAM_KC/4 terms) and FP64 sums of those).
+ * K share (at most SGO_GRAM_KC/4 terms) and FP64 sums of those),
+ * "SGO_PCG_TRIAL" (cap of the PCG trial step on the largest atom
+ * displacement, milli-bohr, default 100), "SGO_PCG_FLOOR" (eigenvalue floor
+ * of the PCG preconditioner, thousandths of max|tau|, default 100).
  * value <= 0 restores the default (or the environment variable of the same
  * name).  SGO_EINVAL for an unknown key.  sgo_get_tuning returns the value
  * set (0 if none). */
@@ -314,6 +317,42 @@ int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info);
  * candidate.  Returns the worst status. */
 int sgo_batch_relax_cg(sgo_batch* b, int nsteps, const sgo_scf_opts* opts, double* energies,
                        double* forces, double* positions, int* status);
+/* Preconditioned CG relaxation (Section 2.3, the PCG option): a Morse pair
+ * force field E = sum_{i<j} D [(1 - e^{-a (r - r0)})^2 - 1] is fitted to
+ * every (positions, forces) sample of the candidate's relaxation so far
+ * (sgo_ff_fit), its Hessian inverted over the modes with non-zero eigenvalue
+ * (sgo_ff_preconditioner) gives P, and the CG directions become
+ * d = P F + beta d with beta = max(0, F_new.P(F_new - F) / F.P F).  Trial
+ * step min(1, 0.1 bohr / max_atom |d|), capped by twice the previous step,
+ * then the secant step of sgo_batch_relax_cg; two batched evaluations per
+ * step.  P is rebuilt every `refit` steps (0: only at the start).  Outputs
+ * as sgo_batch_relax_cg; params (nullable) [n][3] = the last fit (D, a, r0)
+ * of each candidate. */
+int sgo_batch_relax_pcg(sgo_batch* b, int nsteps, int refit, const sgo_scf_opts* opts,
+                        double* energies, double* forces, double* positions, double* params,
+                        int* status);
+
+/* Force-field pieces of the PCG preconditioner (host code).  params =
+ * {D (Ha), a (1/bohr), r0 (bohr)}; pairs by minimum image over the 27
+ * neighbouring cells.  sgo_ff_morse: energy and forces (each nullable).
+ * sgo_ff_hessian: analytic Hessian [3n][3n] (row-major, coordinate 3I + k).
+ * sgo_ff_fit: least-squares fit of the forces of nsamples geometries
+ * (pos, forces [nsamples][natoms][3]): D is the linear optimum for each
+ * (a, r0), taken from a 51 x 41 grid (a = 0.5 ... 3.0, r0 = 0.80 ... 1.60
+ * of the smallest sampled distance) and refined by a compass search inside
+ * that box (30 step halvings); defaults (0.1, 1.0, smallest distance) when no grid point gives
+ * D > 0.  sgo_ff_preconditioner: P [m][m] = sum over eigenpairs (tau, v) of
+ * H with |tau| > 1e-6 max|tau| of v v^T / max(|tau|, 0.1 max|tau|): the
+ * translations (tau = 0) are dropped and negative curvature counts by its
+ * magnitude, so P is positive semi-definite. */
+int sgo_ff_morse(const double lattice[9], int natoms, const double* pos, const double params[3],
+                 double* energy, double* forces);
+int sgo_ff_hessian(const double lattice[9], int natoms, const double* pos, const double params[3],
+                   double* H);
+int sgo_ff_fit(const double lattice[9], int natoms, int nsamples, const double* pos,
+               const double* forces, double params[3]);
+int sgo_ff_preconditioner(int m, const double* H, double* P);
+
 /* Drop the warm-start wavefunctions of every candidate (next solve is cold). */
 int sgo_batch_reset(sgo_batch* b);
 /* Read back the state of candidate i after sgo_batch_scf (each pointer may be

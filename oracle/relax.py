@@ -40,7 +40,7 @@ def relax_cg(system, nsteps, **kw):
         s0 = -np.sum(F * d)
         _, F1 = evaluate(system, x + a1 * d, **kw)
         s1 = -np.sum(F1 * d)
-        a2 = a1 * s0 / (s0 - s1) if s0 - s1 > 0 else 4 * a1
+        a2 = a1 * s0 / (s0 - s1) if s1 - s0 > 0 else 4 * a1
         a2 = min(4 * a1, max(0.1 * a1, a2))
         alpha_prev = a2
         x = x + a2 * d

@@ -185,6 +185,11 @@ def load_library(path=None):
         "sgo_de_init_positions": (I, [dp, I, I, dp, D, dp, I, dp, ip]),
         "sgo_de_select": (I, [I, dp, dp, ip, ip]),
         "sgo_de_jitter_cell": (I, [dp, D, dp, dp]),
+        "sgo_batch_relax_pcg": (I, [P, I, I, ctypes.POINTER(sgo_scf_opts), dp, dp, dp, dp, ip]),
+        "sgo_ff_morse": (I, [dp, I, dp, dp, dp, dp]),
+        "sgo_ff_hessian": (I, [dp, I, dp, dp, dp]),
+        "sgo_ff_fit": (I, [dp, I, I, dp, dp, dp]),
+        "sgo_ff_preconditioner": (I, [I, dp, dp]),
         "sgo_batch_de_generation": (I, [P, ctypes.POINTER(sgo_de_opts),
                                         ctypes.POINTER(sgo_scf_opts), dp, dp,
                                         ctypes.POINTER(sgo_de_draw), dp, ip, dp, dp, dp, ip, ip]),
@@ -558,6 +563,50 @@ def de_select(e_parent, e_child, child_status=None):
     return take
 
 
+def ff_morse(lattice, pos, params):
+    """Morse pair energy and forces (the PCG preconditioner's force field)."""
+    pos = _f64(pos)
+    e = ctypes.c_double()
+    F = np.zeros_like(pos)
+    rc = load_library().sgo_ff_morse(_dptr(_f64(lattice, 9)), pos.shape[0], _dptr(pos),
+                                     _dptr(_f64(params)), ctypes.byref(e), _dptr(F))
+    if rc != SGO_OK:
+        raise SgoError(rc, "ff_morse")
+    return e.value, F
+
+
+def ff_hessian(lattice, pos, params):
+    pos = _f64(pos)
+    m = pos.size
+    H = np.zeros((m, m))
+    rc = load_library().sgo_ff_hessian(_dptr(_f64(lattice, 9)), pos.shape[0], _dptr(pos),
+                                       _dptr(_f64(params)), _dptr(H))
+    if rc != SGO_OK:
+        raise SgoError(rc, "ff_hessian")
+    return H
+
+
+def ff_fit(lattice, positions, forces):
+    """(D, a, r0) fitted to lists of [natoms, 3] positions and forces."""
+    X = np.ascontiguousarray(np.stack([np.asarray(p, dtype=np.float64) for p in positions]))
+    F = np.ascontiguousarray(np.stack([np.asarray(f, dtype=np.float64) for f in forces]))
+    prm = np.zeros(3)
+    rc = load_library().sgo_ff_fit(_dptr(_f64(lattice, 9)), X.shape[1], X.shape[0], _dptr(X),
+                                   _dptr(F), _dptr(prm))
+    if rc != SGO_OK:
+        raise SgoError(rc, "ff_fit")
+    return prm
+
+
+def ff_preconditioner(H):
+    H = _f64(H)
+    P = np.zeros_like(H)
+    rc = load_library().sgo_ff_preconditioner(H.shape[0], _dptr(H), _dptr(P))
+    if rc != SGO_OK:
+        raise SgoError(rc, "ff_preconditioner")
+    return P
+
+
 def de_opts(mutation=SGO_DE_TRIANGLE, crossover=SGO_DE_PLANE, F=0.5, fitness_shift=1,
             relax_steps=5, dmin=2.0, sim_tol=0.0, attempts=4):
     o = sgo_de_opts()
@@ -743,6 +792,28 @@ class Batch:
             return out
         return {"trial": split(trial), "attempt_used": used, "e_trial": et,
                 "survivors": split(surv), "e_survivor": es, "take": take, "status": st}
+
+    def relax_pcg(self, nsteps, refit=1, opts=None, **kw):
+        """nsteps force-fitted PCG relaxation steps of every candidate; returns
+        energies (n, nsteps+1), final forces and positions (lists of
+        (natoms, 3)), the last force-field fits (n, 3) and status."""
+        o = opts if opts is not None else default_opts(**kw)
+        n = len(self.natoms)
+        e = np.zeros((n, nsteps + 1))
+        f = np.zeros(sum(self.natoms) * 3)
+        p = np.zeros(sum(self.natoms) * 3)
+        prm = np.zeros((n, 3))
+        st = np.zeros(n, dtype=np.int32)
+        rc = self._lib.sgo_batch_relax_pcg(self._h, int(nsteps), int(refit), ctypes.byref(o),
+                                           _dptr(e), _dptr(f), _dptr(p), _dptr(prm), _iptr(st))
+        if rc not in (SGO_OK, SGO_ENOTCONV, SGO_ENUMERIC):
+            self._check(rc)
+        forces, pos, off = [], [], 0
+        for na in self.natoms:
+            forces.append(f[off:off + 3 * na].reshape(na, 3))
+            pos.append(p[off:off + 3 * na].reshape(na, 3))
+            off += 3 * na
+        return e, forces, pos, prm, st
 
     def info(self, i):
         inf = sgo_scf_info()

@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgo.so")
 SOURCES = ["kernels_wave.hip", "kernels_grid.hip", "kernels_plane.hip", "kernels_proj.hip", "engine.cpp",
-           "de.cpp"]
+           "de.cpp", "pcg.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

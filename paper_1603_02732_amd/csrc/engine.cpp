@@ -8,15 +8,18 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/sgo.h"
 #include "common.hpp"
 #include "de.hpp"
 #include "launch.hpp"
+#include "pcg.hpp"
 
 namespace sgo {
 
@@ -969,7 +972,62 @@ class Engine {
   //   direction   d <- F_new + max(0, F_new.(F_new - F) / F.F) d
   // energies [n][nsteps+1] records the energy after each accepted step.
   int relax_cg(int nsteps, const sgo_scf_opts& o, double* energies) {
+    return relax(nsteps, o, energies, -1, nullptr);
+  }
+
+  // PCG (Section 2.3): the same secant line search along d = P F + beta d,
+  // beta = max(0, F_new.P(F_new - F) / F.P F), trial step min(1, 0.1 bohr /
+  // max_atom |d|) capped by twice the previous step; P is the inverse Hessian
+  // of a Morse force field fitted to every (positions, forces) sample of the
+  // candidate's relaxation, rebuilt every `refit` steps (0: only at the
+  // start).  params (nullable) [n][3] receives the last fit.
+  int relax_pcg(int nsteps, const sgo_scf_opts& o, double* energies, int refit, double* params) {
+    return relax(nsteps, o, energies, refit, params);
+  }
+
+  int relax(int nsteps, const sgo_scf_opts& o, double* energies, int refit, double* params) {
     const int n = (int)cands_.size();
+    const bool pcg = refit >= 0;
+    std::vector<std::vector<double>> P(n), samp_x(n), samp_f(n);
+    std::vector<std::array<double, 3>> prm(n);
+    const double trial_cap = tune("SGO_PCG_TRIAL", 100) * 1e-3;  // bohr
+    const double floor = tune("SGO_PCG_FLOOR", 100) * 1e-3;       // of max|tau|
+    auto build_P = [&](int i, const std::vector<double>& xi) {
+      const HostCand& c = cands_[i];
+      const int m = 3 * c.nat;
+      ff::fit(c.A, c.nat, (int)(samp_x[i].size() / m), samp_x[i].data(), samp_f[i].data(),
+              prm[i].data());
+      std::vector<double> H((size_t)m * m);
+      ff::morse_hessian(c.A, c.nat, xi.data(), prm[i].data(), H.data());
+      P[i].resize((size_t)m * m);
+      ff::preconditioner(m, H.data(), P[i].data(), floor);
+    };
+    // the fits of different candidates are independent: spread them over host threads
+    auto build_all = [&](const std::vector<std::vector<double>>& xs) {
+      const int nt = std::max(1, std::min(n, (int)std::thread::hardware_concurrency()));
+      std::vector<std::thread> pool;
+      std::vector<std::exception_ptr> err(nt);
+      for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+          try {
+            for (int i = t; i < n; i += nt) build_P(i, xs[i]);
+          } catch (...) {
+            err[t] = std::current_exception();
+          }
+        });
+      for (auto& th : pool) th.join();
+      for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+    };
+    auto apply_P = [&](int i, const std::vector<double>& f, std::vector<double>& out) {
+      const size_t m = f.size();
+      out.assign(m, 0.0);
+      for (size_t k = 0; k < m; ++k) {
+        double acc = 0.0;
+        for (size_t l = 0; l < m; ++l) acc += P[i][k * m + l] * f[l];
+        out[k] = acc;
+      }
+    };
     std::vector<std::vector<double>> x(n), F(n), d(n), x1(n), F1(n);
     std::vector<double> E(n), alpha_prev(n, 0.0);
     std::vector<int> status(n, SGO_OK);
@@ -992,8 +1050,19 @@ class Engine {
     };
     for (int i = 0; i < n; ++i) x[i] = cands_[i].pos;
     evaluate(x, F, &E);
+    std::vector<double> pf, pg;
+    if (pcg) {
+      for (int i = 0; i < n; ++i) {
+        samp_x[i] = x[i];
+        samp_f[i] = F[i];
+      }
+      build_all(x);
+    }
     for (int i = 0; i < n; ++i) {
-      d[i] = F[i];
+      if (pcg)
+        apply_P(i, F[i], d[i]);
+      else
+        d[i] = F[i];
       if (energies) energies[(size_t)i * (nsteps + 1)] = E[i];
     }
     std::vector<double> alpha1(n), s0(n);
@@ -1005,7 +1074,7 @@ class Engine {
           dmax = std::max(dmax, m);
         }
         for (size_t k = 0; k < d[i].size(); ++k) fd += F[i][k] * d[i][k];
-        double a = dmax > 0 ? 0.1 / dmax : 0.0;
+        double a = dmax > 0 ? (pcg ? std::min(1.0, trial_cap / dmax) : 0.1 / dmax) : 0.0;
         if (alpha_prev[i] > 0) a = std::min(a, 2.0 * alpha_prev[i]);
         alpha1[i] = a;
         s0[i] = -fd;
@@ -1016,21 +1085,39 @@ class Engine {
       for (int i = 0; i < n; ++i) {
         double s1 = 0.0;
         for (size_t k = 0; k < d[i].size(); ++k) s1 -= F1[i][k] * d[i][k];
-        double a2 = (s0[i] - s1) > 0 ? alpha1[i] * s0[i] / (s0[i] - s1) : 4.0 * alpha1[i];
+        double a2 = (s1 - s0[i]) > 0 ? alpha1[i] * s0[i] / (s0[i] - s1) : 4.0 * alpha1[i];
         a2 = std::max(0.1 * alpha1[i], std::min(4.0 * alpha1[i], a2));
         alpha_prev[i] = a2;
         x1[i] = x[i];
         for (size_t k = 0; k < x1[i].size(); ++k) x1[i][k] += a2 * d[i][k];
       }
       evaluate(x1, F1, &E);
+      if (pcg) {
+        for (int i = 0; i < n; ++i) {
+          samp_x[i].insert(samp_x[i].end(), x1[i].begin(), x1[i].end());
+          samp_f[i].insert(samp_f[i].end(), F1[i].begin(), F1[i].end());
+        }
+        if (refit > 0 && step % refit == 0) build_all(x1);
+      }
       for (int i = 0; i < n; ++i) {
         double num = 0.0, den = 0.0;
-        for (size_t k = 0; k < F1[i].size(); ++k) {
-          num += F1[i][k] * (F1[i][k] - F[i][k]);
-          den += F[i][k] * F[i][k];
+        if (pcg) {
+          apply_P(i, F1[i], pg);
+          apply_P(i, F[i], pf);
+          for (size_t k = 0; k < F1[i].size(); ++k) {
+            num += F1[i][k] * (pg[k] - pf[k]);
+            den += F[i][k] * pf[k];
+          }
+          const double beta = den > 0 ? std::max(0.0, num / den) : 0.0;
+          for (size_t k = 0; k < d[i].size(); ++k) d[i][k] = pg[k] + beta * d[i][k];
+        } else {
+          for (size_t k = 0; k < F1[i].size(); ++k) {
+            num += F1[i][k] * (F1[i][k] - F[i][k]);
+            den += F[i][k] * F[i][k];
+          }
+          const double beta = den > 0 ? std::max(0.0, num / den) : 0.0;
+          for (size_t k = 0; k < d[i].size(); ++k) d[i][k] = F1[i][k] + beta * d[i][k];
         }
-        const double beta = den > 0 ? std::max(0.0, num / den) : 0.0;
-        for (size_t k = 0; k < d[i].size(); ++k) d[i][k] = F1[i][k] + beta * d[i][k];
         x[i] = x1[i];
         F[i] = F1[i];
         if (energies) energies[(size_t)i * (nsteps + 1) + step] = E[i];
@@ -1040,6 +1127,8 @@ class Engine {
     for (int i = 0; i < n; ++i) {
       cands_[i].status = status[i];
       worst = std::min(worst, status[i]);
+      if (pcg && params)
+        for (int k = 0; k < 3; ++k) params[3 * i + k] = prm[i][k];
     }
     return worst;
   }
@@ -1681,7 +1770,8 @@ int sgo_set_tuning(const char* key, int value) {
   if (!key) return SGO_EINVAL;
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
                                 "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
-                                "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL"};
+                                "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL", "SGO_PCG_TRIAL",
+                                "SGO_PCG_FLOOR"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;
@@ -1818,6 +1908,54 @@ int sgo_batch_relax_cg(sgo_batch* b, int nsteps, const sgo_scf_opts* opts, doubl
     }
     return rc;
   });
+}
+
+int sgo_batch_relax_pcg(sgo_batch* b, int nsteps, int refit, const sgo_scf_opts* opts,
+                        double* energies, double* forces, double* positions, double* params,
+                        int* status) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if (b->eng->size() == 0) throw Error(SGO_ESTATE, "empty batch");
+    if (nsteps < 0 || refit < 0) throw Error(SGO_EINVAL, "nsteps and refit must be >= 0");
+    const sgo_scf_opts o = opts_or_default(opts);
+    const int rc = b->eng->relax_pcg(nsteps, o, energies, refit, params);
+    size_t off = 0;
+    for (int i = 0; i < b->eng->size(); ++i) {
+      auto& hc = b->eng->cand(i);
+      if (forces) b->eng->get(hc.d.force, forces + off, 3 * hc.nat * sizeof(double));
+      if (positions) std::memcpy(positions + off, hc.pos.data(), 3 * hc.nat * sizeof(double));
+      off += 3 * hc.nat;
+      if (status) status[i] = hc.status;
+    }
+    return rc;
+  });
+}
+
+int sgo_ff_morse(const double lattice[9], int natoms, const double* pos, const double params[3],
+                 double* energy, double* forces) {
+  if (!lattice || natoms < 1 || !pos || !params) return SGO_EINVAL;
+  sgo::ff::morse(lattice, natoms, pos, params, energy, forces);
+  return SGO_OK;
+}
+
+int sgo_ff_hessian(const double lattice[9], int natoms, const double* pos, const double params[3],
+                   double* H) {
+  if (!lattice || natoms < 1 || !pos || !params || !H) return SGO_EINVAL;
+  sgo::ff::morse_hessian(lattice, natoms, pos, params, H);
+  return SGO_OK;
+}
+
+int sgo_ff_fit(const double lattice[9], int natoms, int nsamples, const double* pos,
+               const double* forces, double params[3]) {
+  if (!lattice || natoms < 2 || nsamples < 1 || !pos || !forces || !params) return SGO_EINVAL;
+  sgo::ff::fit(lattice, natoms, nsamples, pos, forces, params);
+  return SGO_OK;
+}
+
+int sgo_ff_preconditioner(int m, const double* H, double* P) {
+  if (m < 1 || !H || !P) return SGO_EINVAL;
+  sgo::ff::preconditioner(m, H, P);
+  return SGO_OK;
 }
 
 int sgo_batch_get_state(sgo_batch* b, int i, int* info, int* millers, double* psi, double* eig,
