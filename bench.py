@@ -19,6 +19,7 @@ Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -28,6 +29,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+# FP32 vector arithmetic without packed FP32 instructions (the build turns
+# them off): 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz; the published
+# 157.3 TFLOP/s counts the packed form
+FP32_ALU_PEAK_TFLOPS = 78.6
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "c3_population_hbm_counters.txt")
@@ -134,34 +139,71 @@ CANDIDATE_KERNELS = ("k_plane_hpsi", "k_subspace", "k_gram", "k_gram_reduce", "k
                      "k_z_forward", "k_cg_direction", "k_linemin", "k_plane_density")
 
 
-def kernel_model(name, geoms, tsize):
-    """Algorithmic work of one launch of `name` over the whole population:
+def kernel_model(name, g, tsize):
+    """Algorithmic work of one candidate's share of a launch of `name`:
     (bound, amount, unit).  Bytes count each array the method must read or
-    write once; FP64 flops for the latency-bound subspace solver."""
-    b = 0.0
-    for g in geoms:
-        npair, nst, N3, ntot, K, nb = g["npair"], g["nst"], g["N3"], g["ntot"], \
-            2 * g["npw_half"], g["nbands"]
-        sticks = npair * N3 * nst * 2 * tsize
-        if name == "k_plane_hpsi":
-            b += 2 * sticks + ntot * tsize
-        elif name == "k_plane_density":
-            b += sticks + ntot * 8
-        elif name == "k_z_inverse":
-            b += nb * K * tsize + sticks
-        elif name == "k_z_forward":
-            b += sticks + 2 * nb * K * tsize
-        elif name == "k_gram":
-            b += 2 * nb * K * tsize
-        elif name == "k_gemm_acc":  # per coefficient row moved (see below)
-            b += K * tsize
-        elif name in ("k_cg_direction", "k_linemin"):
-            b += 4 * nb * K * tsize
-        elif name == "k_subspace":
-            b += (2.0 / 3.0 + 2.0) * nb ** 3 * 2  # Cholesky + inverse + congruence
+    write once; for k_gemm_acc and k_gram the amount is per coefficient row
+    of length K (the library reports the rows a launch moves); FP64 flops for
+    the latency-bound subspace solver."""
+    npair, nst, N3, ntot, K, nb = g["npair"], g["nst"], g["N3"], g["ntot"], \
+        2 * g["npw_half"], g["nbands"]
+    sticks = npair * N3 * nst * 2 * tsize
+    if name == "k_plane_hpsi":
+        return "hbm", 2 * sticks + ntot * tsize, "GB/s"
+    if name == "k_plane_density":
+        return "hbm", sticks + ntot * 8, "GB/s"
+    if name == "k_z_inverse":
+        return "hbm", nb * K * tsize + sticks, "GB/s"
+    if name == "k_z_forward":
+        return "hbm", sticks + 2 * nb * K * tsize, "GB/s"
+    if name in ("k_gram", "k_gemm_acc"):
+        return "hbm", K * tsize, "GB/s"
+    if name == "k_cg_direction":
+        return "hbm", 4 * nb * K * tsize, "GB/s"  # X, HX, D_prev read, D written
+    if name == "k_linemin":
+        return "hbm", 6 * nb * K * tsize, "GB/s"  # X, HX, D, HD read, X, HX written
+    if name == "k_gram_reduce":
+        return "hbm", 0.0, "GB/s"
     if name == "k_subspace":
-        return "alu", b, "TFLOP/s"
-    return "hbm", b, "GB/s"
+        return "alu", (2.0 / 3.0 + 2.0) * nb ** 3 * 2, "TFLOP/s"  # Cholesky + inverse + congruence
+    raise KeyError(name)
+
+
+def active_x_columns(sgo, system):
+    """Active x columns of the plane pass: 2 max|m1| + 1 over the sphere."""
+    import numpy as np
+    c = sgo.context_from_system(system, sgo.SGO_FP32)
+    m, _ = c.basis()
+    c.close()
+    return int(min(2 * np.abs(m[:, 0]).max() + 1, system["grid"][0]))
+
+
+def fft_flops(n):
+    """Conventional flop count of a complex FFT of length n (5 n log2 n)."""
+    return 5.0 * n * math.log2(n)
+
+
+def plane_alu_flops(name, g, nxa):
+    """FP32 flops of one candidate's plane pass: per band pair and z-plane,
+    y transforms over the nxa active x columns and x transforms over all N2
+    rows (both directions for H psi, with the V_eff product; the inverse only
+    for the density, with f_a Re^2 + f_b Im^2)."""
+    N1, N2, N3, npair = g["N1"], g["N2"], g["N3"], g["npair"]
+    one = nxa * fft_flops(N2) + N2 * fft_flops(N1)
+    if name == "k_plane_hpsi":
+        per = 2 * one + 2 * N1 * N2
+    else:
+        per = one + 4 * N1 * N2
+    return npair * N3 * per
+
+
+def kernel_amount(name, g, prof, tsize=4):
+    """Algorithmic amount per launch, averaged over the profiled launches."""
+    bound, per, unit = kernel_model(name, g, tsize)
+    n = max(prof["launches"], 1)
+    if name in ("k_gram", "k_gemm_acc"):
+        return bound, per * prof["cand_rows"] / n, unit
+    return bound, per * prof["cand_launches"] / n, unit
 
 
 def main():
@@ -227,11 +269,13 @@ def main():
     step()
     sync()
     t_one = time.perf_counter() - t0
+    kprof = {}
     for k in CANDIDATE_KERNELS:
         sgo.profile_begin(k)
         step()
         sync()
-        shares[k] = sgo.profile_end()["ms"] * 1e-3 / t_one
+        kprof[k] = sgo.profile_end()
+        shares[k] = kprof[k]["ms"] * 1e-3 / t_one
     dominant = max(shares, key=shares.get)
 
     # timed region: K batched steps, dominant kernel bracketed by HIP events
@@ -251,15 +295,12 @@ def main():
     # every launch covers the whole population, but candidates that have
     # converged return at once: the work of a launch is that of the
     # candidates still active in it (all candidates have the same shape)
-    bound, amount_all, unit = kernel_model(dominant, geoms, 4)
+    # the band rotation and the Gram products read and write a call-dependent
+    # number of rows (2 per band for the in-place rotation of X, HX and D, 3
+    # for the accumulation D -= X C, band + projector rows for the nonlocal
+    # apply): the library counts them per launch
+    bound, amount, unit = kernel_amount(dominant, geoms[0], prof)
     avg_active = prof["cand_launches"] / max(prof["launches"], 1)
-    amount = amount_all / len(geoms) * avg_active
-    if dominant == "k_gemm_acc":
-        # the band rotation reads and writes a call-dependent number of rows
-        # (2 per band for the in-place rotation of X, HX and D, 3 for the
-        # accumulation D -= X C, band + projector rows for the nonlocal
-        # apply): the library counts them per launch
-        amount = amount_all / len(geoms) * prof["cand_rows"] / max(prof["launches"], 1)
     avg_s = prof["ms"] * 1e-3 / max(prof["launches"], 1)
     if bound == "hbm":
         ach = amount / avg_s / 1e9
@@ -273,9 +314,32 @@ def main():
             "launches_per_step": prof["launches"] / a.steps,
             "active_candidates_per_launch": avg_active,
             "rows_per_candidate_launch": (prof["cand_rows"] / max(prof["cand_launches"], 1)
-                                          if dominant == "k_gemm_acc" else None),
+                                          if dominant in ("k_gemm_acc", "k_gram") else None),
             ("bytes_per_launch" if bound == "hbm" else "flop_per_launch"): amount,
             "share_of_step": {k: round(v, 4) for k, v in shares.items()}}
+
+    # every candidate kernel against its bound, from its own profiled step
+    nxa = active_x_columns(sgo, pop[0])
+    table = {}
+    for k in CANDIDATE_KERNELS:
+        p = kprof[k]
+        if p["launches"] == 0:
+            continue
+        kb, amt, ku = kernel_amount(k, geoms[0], p)
+        avg = p["ms"] * 1e-3 / p["launches"]
+        row = {"share_of_step": round(shares[k], 4), "launches": p["launches"],
+               "avg_launch_us": round(avg * 1e6, 2)}
+        if kb == "hbm" and amt > 0:
+            row.update({"bound": "hbm", "achieved_GBps": round(amt / avg / 1e9, 1),
+                        "frac_of_hbm_peak": round(amt / avg / 1e9 / HBM_PEAK_GBS, 3)})
+        elif kb == "alu":
+            row.update({"bound": "latency (FP64 flops)", "achieved_TFLOPs": round(amt / avg / 1e12, 4)})
+        if k in ("k_plane_hpsi", "k_plane_density"):
+            fl = plane_alu_flops(k, geoms[0], nxa) * p["cand_launches"] / p["launches"]
+            row.update({"bound": "alu", "alu_TFLOPs": round(fl / avg / 1e12, 2),
+                        "frac_of_fp32_alu_peak": round(fl / avg / 1e12 / FP32_ALU_PEAK_TFLOPS, 3)})
+        table[k] = row
+    roof["kernels"] = table
 
     # parity gate on the candidates that have a stored oracle result
     gates, fgates = [], []
@@ -293,7 +357,7 @@ def main():
         plain["C4_uneven_population_batched"] = c4_run(sgo, workloads, sync)
         plain["C5_large_cell"] = c5_run(sgo, workloads, sync)
         plain["C3_de_generation"] = de_run(sgo, pop, opts, sync)
-        plain["C3_relax_cg_vs_pcg"] = relax_run(sgo, pop, opts, sync)
+        plain["C3_relax_cg_pcg_cls"] = relax_run(sgo, pop, opts, sync)
 
     cpu = None
     if not a.no_cpu:
@@ -318,10 +382,11 @@ def main():
 
 def relax_run(sgo, pop, opts, sync, steps=5):
     """The C3 population relaxed by 5 steps of plain CG and, from the same
-    start, 5 steps of force-fitted PCG (two batched solves per step each)."""
+    start, 5 steps of force-fitted PCG and of the curved line search (two
+    batched solves per step each)."""
     import numpy as np
     out = {}
-    for name in ("cg", "pcg"):
+    for name in ("cg", "pcg", "cls"):
         B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
         for s in pop:
             B.add_system(s)
@@ -331,8 +396,10 @@ def relax_run(sgo, pop, opts, sync, steps=5):
         t0 = time.perf_counter()
         if name == "cg":
             E, F, X, st = B.relax_cg(steps, opts=opts)
-        else:
+        elif name == "pcg":
             E, F, X, prm, st = B.relax_pcg(steps, refit=1, opts=opts)
+        else:
+            E, F, X, prm, st = B.relax_cls(steps, opts=opts)
         sync()
         dt = time.perf_counter() - t0
         B.close()

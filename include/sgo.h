@@ -332,6 +332,18 @@ int sgo_batch_relax_pcg(sgo_batch* b, int nsteps, int refit, const sgo_scf_opts*
                         double* energies, double* forces, double* positions, double* params,
                         int* status);
 
+/* Curved line search relaxation (Section 2.3, the CLS option; the paper
+ * gives its outline only, these steps re-derive it).  Before every step the
+ * Morse field of sgo_batch_relax_pcg is refitted to all samples, and its
+ * steepest-descent path from the current structure (sgo_ff_guided_curve) is
+ * the guided curve x(s); the DFT energy is minimised along the curve with
+ * the secant step on g(s) = -F(x(s)).x'(s): trial s1 = min(curve length,
+ * 0.3 bohr, twice the previous step), secant s2 clamped to [0.1, 4] s1 and
+ * to the curve's end.  Two batched evaluations per step.  Outputs as
+ * sgo_batch_relax_pcg. */
+int sgo_batch_relax_cls(sgo_batch* b, int nsteps, const sgo_scf_opts* opts, double* energies,
+                        double* forces, double* positions, double* params, int* status);
+
 /* Force-field pieces of the PCG preconditioner (host code).  params =
  * {D (Ha), a (1/bohr), r0 (bohr)}; pairs by minimum image over the 27
  * neighbouring cells.  sgo_ff_morse: energy and forces (each nullable).
@@ -352,6 +364,14 @@ int sgo_ff_hessian(const double lattice[9], int natoms, const double* pos, const
 int sgo_ff_fit(const double lattice[9], int natoms, int nsamples, const double* pos,
                const double* forces, double params[3]);
 int sgo_ff_preconditioner(int m, const double* H, double* P);
+/* Guided curve of the CLS relaxation: nodes x_0 = x0, x_{k+1} = x_k +
+ * 0.02 F(x_k) / max_atom |F(x_k)| (the steepest-descent path of the Morse
+ * field, the most-forced atom moving 0.02 bohr per node) until
+ * max_atom |F| < 1e-3 Ha/bohr or 200 steps.  nodes [max_nodes][natoms][3];
+ * *nnodes = number written (at most 201).  SGO_EINVAL when max_nodes is too
+ * small. */
+int sgo_ff_guided_curve(const double lattice[9], int natoms, const double params[3],
+                        const double* x0, int max_nodes, double* nodes, int* nnodes);
 
 /* Drop the warm-start wavefunctions of every candidate (next solve is cold). */
 int sgo_batch_reset(sgo_batch* b);

@@ -190,6 +190,8 @@ def load_library(path=None):
         "sgo_ff_hessian": (I, [dp, I, dp, dp, dp]),
         "sgo_ff_fit": (I, [dp, I, I, dp, dp, dp]),
         "sgo_ff_preconditioner": (I, [I, dp, dp]),
+        "sgo_ff_guided_curve": (I, [dp, I, dp, dp, I, dp, ip]),
+        "sgo_batch_relax_cls": (I, [P, I, ctypes.POINTER(sgo_scf_opts), dp, dp, dp, dp, ip]),
         "sgo_batch_de_generation": (I, [P, ctypes.POINTER(sgo_de_opts),
                                         ctypes.POINTER(sgo_scf_opts), dp, dp,
                                         ctypes.POINTER(sgo_de_draw), dp, ip, dp, dp, dp, ip, ip]),
@@ -607,6 +609,19 @@ def ff_preconditioner(H):
     return P
 
 
+def ff_guided_curve(lattice, pos, params):
+    """Nodes [K, natoms, 3] of the CLS guided curve."""
+    pos = _f64(pos)
+    nodes = np.zeros((201,) + pos.shape)
+    k = ctypes.c_int()
+    rc = load_library().sgo_ff_guided_curve(_dptr(_f64(lattice, 9)), pos.shape[0],
+                                            _dptr(_f64(params)), _dptr(pos), 201, _dptr(nodes),
+                                            ctypes.byref(k))
+    if rc != SGO_OK:
+        raise SgoError(rc, "ff_guided_curve")
+    return nodes[:k.value].copy()
+
+
 def de_opts(mutation=SGO_DE_TRIANGLE, crossover=SGO_DE_PLANE, F=0.5, fitness_shift=1,
             relax_steps=5, dmin=2.0, sim_tol=0.0, attempts=4):
     o = sgo_de_opts()
@@ -806,6 +821,28 @@ class Batch:
         st = np.zeros(n, dtype=np.int32)
         rc = self._lib.sgo_batch_relax_pcg(self._h, int(nsteps), int(refit), ctypes.byref(o),
                                            _dptr(e), _dptr(f), _dptr(p), _dptr(prm), _iptr(st))
+        if rc not in (SGO_OK, SGO_ENOTCONV, SGO_ENUMERIC):
+            self._check(rc)
+        forces, pos, off = [], [], 0
+        for na in self.natoms:
+            forces.append(f[off:off + 3 * na].reshape(na, 3))
+            pos.append(p[off:off + 3 * na].reshape(na, 3))
+            off += 3 * na
+        return e, forces, pos, prm, st
+
+    def relax_cls(self, nsteps, opts=None, **kw):
+        """nsteps curved-line-search relaxation steps of every candidate;
+        returns energies (n, nsteps+1), final forces and positions, the last
+        force-field fits (n, 3) and status."""
+        o = opts if opts is not None else default_opts(**kw)
+        n = len(self.natoms)
+        e = np.zeros((n, nsteps + 1))
+        f = np.zeros(sum(self.natoms) * 3)
+        p = np.zeros(sum(self.natoms) * 3)
+        prm = np.zeros((n, 3))
+        st = np.zeros(n, dtype=np.int32)
+        rc = self._lib.sgo_batch_relax_cls(self._h, int(nsteps), ctypes.byref(o), _dptr(e), _dptr(f),
+                                           _dptr(p), _dptr(prm), _iptr(st))
         if rc not in (SGO_OK, SGO_ENOTCONV, SGO_ENUMERIC):
             self._check(rc)
         forces, pos, off = [], [], 0

@@ -985,6 +985,136 @@ class Engine {
     return relax(nsteps, o, energies, refit, params);
   }
 
+  // CLS (Section 2.3, re-derived): before every step the Morse field is
+  // refitted to all samples; its steepest-descent path from the current
+  // structure (steps moving the most-forced atom by h = 0.02 bohr, until
+  // max|F_FF| < 1e-3 or 200 steps) is the guided curve x(s), s = path
+  // parameter in bohr of largest displacement; the DFT energy is minimised
+  // along it with the secant step on g(s) = -F(x(s)).x'(s): trial
+  // s1 = min(s_end, 0.3, 2 s_prev), s2 clamped to [0.1, 4] s1 and s_end.
+  int relax_cls(int nsteps, const sgo_scf_opts& o, double* energies, double* params) {
+    const int n = (int)cands_.size();
+    const double h = 0.02, ftol = 1e-3, s_cap = 0.3;
+    const int kmax = 200;
+    std::vector<std::vector<double>> x(n), F(n), x1(n), F1(n), nodes(n), samp_x(n), samp_f(n);
+    std::vector<std::array<double, 3>> prm(n);
+    std::vector<double> E(n), s_prev(n, 0.0), s1(n), s_end(n), g0(n);
+    std::vector<int> status(n, SGO_OK);
+    auto evaluate = [&](std::vector<std::vector<double>>& pos, std::vector<std::vector<double>>& force,
+                        std::vector<double>* en) {
+      for (int i = 0; i < n; ++i) move_atoms(i, pos[i].data());
+      (void)scf(o);
+      for (int i = 0; i < n; ++i) {
+        HostCand& c = cands_[i];
+        force[i].resize(3 * c.nat);
+        get(c.d.force, force[i].data(), 3 * c.nat * sizeof(double));
+        if (en) {
+          double sc[S_COUNT];
+          get_scal(c, sc);
+          (*en)[i] = sc[S_ETOT];
+        }
+        if (c.status < status[i]) status[i] = c.status;
+      }
+    };
+    // x(s) on candidate i's polyline and the tangent of the segment holding s
+    auto point = [&](int i, double s, std::vector<double>& out, std::vector<double>* tang) {
+      const size_t m = x[i].size();
+      const int K = (int)(nodes[i].size() / m) - 1;
+      int k = (int)std::floor(s / h);
+      k = std::max(0, std::min(k, K - 1));
+      const double t = s / h - k;
+      const double* a = nodes[i].data() + (size_t)k * m;
+      const double* b = a + m;
+      out.resize(m);
+      for (size_t c = 0; c < m; ++c) out[c] = a[c] + t * (b[c] - a[c]);
+      if (tang) {
+        tang->resize(m);
+        for (size_t c = 0; c < m; ++c) (*tang)[c] = (b[c] - a[c]) / h;
+      }
+    };
+    auto build_curves = [&]() {
+      const int nt = std::max(1, std::min(n, (int)std::thread::hardware_concurrency()));
+      std::vector<std::thread> pool;
+      std::vector<std::exception_ptr> err(nt);
+      for (int t = 0; t < nt; ++t)
+        pool.emplace_back([&, t] {
+          try {
+            for (int i = t; i < n; i += nt) {
+              const HostCand& c = cands_[i];
+              const int m = 3 * c.nat;
+              ff::fit(c.A, c.nat, (int)(samp_x[i].size() / m), samp_x[i].data(),
+                      samp_f[i].data(), prm[i].data());
+              ff::guided_curve(c.A, c.nat, prm[i].data(), x[i].data(), h, ftol, kmax, nodes[i]);
+              if ((int)nodes[i].size() == m) {  // field at rest: one step along the DFT forces
+                double fm = 0.0;
+                for (int I = 0; I < c.nat; ++I)
+                  fm = std::max(fm, std::sqrt(F[i][3 * I] * F[i][3 * I] + F[i][3 * I + 1] * F[i][3 * I + 1] +
+                                              F[i][3 * I + 2] * F[i][3 * I + 2]));
+                for (int q = 0; q < m; ++q) nodes[i].push_back(x[i][q] + (fm > 0 ? h * F[i][q] / fm : 0.0));
+              }
+            }
+          } catch (...) {
+            err[t] = std::current_exception();
+          }
+        });
+      for (auto& th : pool) th.join();
+      for (auto& e : err)
+        if (e) std::rethrow_exception(e);
+    };
+    for (int i = 0; i < n; ++i) x[i] = cands_[i].pos;
+    evaluate(x, F, &E);
+    for (int i = 0; i < n; ++i) {
+      samp_x[i] = x[i];
+      samp_f[i] = F[i];
+      if (energies) energies[(size_t)i * (nsteps + 1)] = E[i];
+    }
+    std::vector<double> tang;
+    for (int step = 1; step <= nsteps; ++step) {
+      build_curves();
+      for (int i = 0; i < n; ++i) {
+        const size_t m = x[i].size();
+        s_end[i] = h * (double)(nodes[i].size() / m - 1);
+        std::vector<double> p0;
+        point(i, 0.0, p0, &tang);
+        double g = 0.0;
+        for (size_t c = 0; c < m; ++c) g -= F[i][c] * tang[c];
+        g0[i] = g;
+        double s = std::min(s_end[i], s_cap);
+        if (s_prev[i] > 0) s = std::min(s, 2.0 * s_prev[i]);
+        s1[i] = s;
+        point(i, s, x1[i], nullptr);
+      }
+      evaluate(x1, F1, nullptr);
+      for (int i = 0; i < n; ++i) {
+        std::vector<double> p1;
+        point(i, s1[i], p1, &tang);
+        double g1 = 0.0;
+        for (size_t c = 0; c < tang.size(); ++c) g1 -= F1[i][c] * tang[c];
+        double s2 = (g1 - g0[i]) > 0 ? s1[i] * g0[i] / (g0[i] - g1) : 4.0 * s1[i];
+        s2 = std::max(0.1 * s1[i], std::min(4.0 * s1[i], s2));
+        s2 = std::min(s2, s_end[i]);
+        s_prev[i] = s2;
+        point(i, s2, x1[i], nullptr);
+      }
+      evaluate(x1, F1, &E);
+      for (int i = 0; i < n; ++i) {
+        x[i] = x1[i];
+        F[i] = F1[i];
+        samp_x[i].insert(samp_x[i].end(), x[i].begin(), x[i].end());
+        samp_f[i].insert(samp_f[i].end(), F[i].begin(), F[i].end());
+        if (energies) energies[(size_t)i * (nsteps + 1) + step] = E[i];
+      }
+    }
+    int worst = SGO_OK;
+    for (int i = 0; i < n; ++i) {
+      cands_[i].status = status[i];
+      worst = std::min(worst, status[i]);
+      if (params)
+        for (int k = 0; k < 3; ++k) params[3 * i + k] = prm[i][k];
+    }
+    return worst;
+  }
+
   int relax(int nsteps, const sgo_scf_opts& o, double* energies, int refit, double* params) {
     const int n = (int)cands_.size();
     const bool pcg = refit >= 0;
@@ -1929,6 +2059,39 @@ int sgo_batch_relax_pcg(sgo_batch* b, int nsteps, int refit, const sgo_scf_opts*
     }
     return rc;
   });
+}
+
+int sgo_batch_relax_cls(sgo_batch* b, int nsteps, const sgo_scf_opts* opts, double* energies,
+                        double* forces, double* positions, double* params, int* status) {
+  if (!b) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    if (b->eng->size() == 0) throw Error(SGO_ESTATE, "empty batch");
+    if (nsteps < 0) throw Error(SGO_EINVAL, "nsteps must be >= 0");
+    const sgo_scf_opts o = opts_or_default(opts);
+    const int rc = b->eng->relax_cls(nsteps, o, energies, params);
+    size_t off = 0;
+    for (int i = 0; i < b->eng->size(); ++i) {
+      auto& hc = b->eng->cand(i);
+      if (forces) b->eng->get(hc.d.force, forces + off, 3 * hc.nat * sizeof(double));
+      if (positions) std::memcpy(positions + off, hc.pos.data(), 3 * hc.nat * sizeof(double));
+      off += 3 * hc.nat;
+      if (status) status[i] = hc.status;
+    }
+    return rc;
+  });
+}
+
+int sgo_ff_guided_curve(const double lattice[9], int natoms, const double params[3],
+                        const double* x0, int max_nodes, double* nodes, int* nnodes) {
+  if (!lattice || natoms < 1 || !params || !x0 || !nodes || !nnodes || max_nodes < 1)
+    return SGO_EINVAL;
+  std::vector<double> v;
+  sgo::ff::guided_curve(lattice, natoms, params, x0, 0.02, 1e-3, 200, v);
+  const int K = (int)(v.size() / (3 * natoms));
+  if (K > max_nodes) return SGO_EINVAL;
+  std::memcpy(nodes, v.data(), v.size() * sizeof(double));
+  *nnodes = K;
+  return SGO_OK;
 }
 
 int sgo_ff_morse(const double lattice[9], int natoms, const double* pos, const double params[3],

@@ -322,6 +322,8 @@ constexpr int kGT = 64;
 // zero.  F32 = true (FP32 data only): FP32 MFMA with FP32 accumulation over
 // each wavefront's share of the K range (at most kc_len/4 terms); the waves,
 // blocks and K ranges are still summed in FP64.
+constexpr int kGramDepth = 2;  // 16-wide K steps in flight per wave (FP32 data)
+
 template <typename T, int TB, bool F32 = false>
 __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, int kc_len,
                                               int nkc_max, int a0, int b0, int a1, int b1) {
@@ -365,45 +367,61 @@ __global__ void __launch_bounds__(kNT) k_gram(const CandDesc* __restrict__ cds, 
     pa[u] = Am + (size_t)(oka[u] ? ra : 0) * Kp + 4 * g;
     pb[u] = Bm + (size_t)(okb[u] ? rb : 0) * Kp + 4 * g;
   }
-  AT a[TB][4], b[TB][4];
+  // Each wave takes the 16-wide K steps ks, ks + 64, ... of the chunk; kGramDepth
+  // of them per iteration, with the loads of the next kGramDepth issued before
+  // the MFMAs of the current ones (more loads in flight per wave).
+  constexpr int D = sizeof(T) == 4 ? kGramDepth : 1;  // FP64 data: registers bound
+  T a[D][TB][4], b[D][TB][4];  // storage type; widened at the MFMA
   int ks = k0 + wave * 16;
-  if (ks < k1) {
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    const int kk = ks + 64 * d;
 #pragma unroll
     for (int u = 0; u < TB; ++u) {
-      load4(pa[u] + ks, oka[u], a[u]);
-      load4(pb[u] + ks, okb[u], b[u]);
+      load4(pa[u] + kk, oka[u] && kk < k1, a[d][u]);
+      load4(pb[u] + kk, okb[u] && kk < k1, b[d][u]);
     }
   }
   while (ks < k1) {
-    const int kn = ks + 64;
-    AT an[TB][4], bn[TB][4];
+    const int kn = ks + 64 * D;
+    T an[D][TB][4], bn[D][TB][4];
     if (kn < k1) {
 #pragma unroll
-      for (int u = 0; u < TB; ++u) {
-        load4(pa[u] + kn, oka[u], an[u]);
-        load4(pb[u] + kn, okb[u], bn[u]);
+      for (int d = 0; d < D; ++d) {
+        const int kk = kn + 64 * d;
+#pragma unroll
+        for (int u = 0; u < TB; ++u) {
+          load4(pa[u] + kk, oka[u] && kk < k1, an[d][u]);
+          load4(pb[u] + kk, okb[u] && kk < k1, bn[d][u]);
+        }
       }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int d = 0; d < D; ++d) {
+      if (ks + 64 * d >= k1) break;
 #pragma unroll
-      for (int u = 0; u < TB; ++u)
+      for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int v = 0; v < TB; ++v)
-          if (u < BI && v < BJ) {
-            if constexpr (F32)
-              acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][t], b[v][t], acc[u][v], 0, 0, 0);
-            else
-              acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][t], b[v][t], acc[u][v], 0, 0, 0);
-          }
+        for (int u = 0; u < TB; ++u)
+#pragma unroll
+          for (int v = 0; v < TB; ++v)
+            if (u < BI && v < BJ) {
+              if constexpr (F32)
+                acc[u][v] = __builtin_amdgcn_mfma_f32_16x16x4f32((AT)a[d][u][t], (AT)b[d][v][t], acc[u][v], 0, 0, 0);
+              else
+                acc[u][v] = __builtin_amdgcn_mfma_f64_16x16x4f64((AT)a[d][u][t], (AT)b[d][v][t], acc[u][v], 0, 0, 0);
+            }
+    }
     if (kn < k1) {
 #pragma unroll
-      for (int u = 0; u < TB; ++u)
+      for (int d = 0; d < D; ++d)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-          a[u][t] = an[u][t];
-          b[u][t] = bn[u][t];
-        }
+        for (int u = 0; u < TB; ++u)
+#pragma unroll
+          for (int t = 0; t < 4; ++t) {
+            a[d][u][t] = an[d][u][t];
+            b[d][u][t] = bn[d][u][t];
+          }
     }
     ks = kn;
   }
@@ -1158,6 +1176,19 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
   const BatchGeom& g = L.g;
   const int rows = std::max(g.nb_max, g.nproj_max);
   const int a1 = nprod > 1 ? a[1] : 0, b1 = nprod > 1 ? b[1] : 0, o1 = nprod > 1 ? out[1] : 0;
+  // rows read per candidate: each distinct operand array once
+  long long rows_read = 0;
+  {
+    int seen[4], ns = 0;
+    const int ops[4] = {a[0], b[0], a1, b1};
+    for (int q = 0; q < 2 * nprod; ++q) {
+      bool dup = false;
+      for (int t = 0; t < ns; ++t) dup = dup || seen[t] == ops[q];
+      if (dup) continue;
+      seen[ns++] = ops[q];
+      rows_read += ops[q] == W_BETA ? g.nproj_max : g.nb_max;
+    }
+  }
   // 32x32 tiles when every product fits one (fewer registers, more waves)
   const int TB = rows <= 32 ? 2 : 4;
   const int TT = 16 * TB;
@@ -1174,7 +1205,7 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
         hipLaunchKernelGGL((k_gram<float, 4, true>), grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len,
                            g.nkc_max, a[0], b[0], a1, b1);
       check_launch("k_gram");
-      prof_after("k_gram", L.stream);
+      prof_after("k_gram", L.stream, rows_read);
       goto reduce;
     }
   }
@@ -1185,7 +1216,7 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
     hipLaunchKernelGGL((k_gram<T, 4>), grid, dim3(kNT), 0, L.stream, L.desc, g.kc_len, g.nkc_max,
                        a[0], b[0], a1, b1);
   check_launch("k_gram");
-  prof_after("k_gram", L.stream);
+  prof_after("k_gram", L.stream, rows_read);
 reduce:
   prof_before("k_gram_reduce", L.stream);
   if (TB == 2)

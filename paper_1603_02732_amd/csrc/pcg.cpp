@@ -231,6 +231,23 @@ void fit(const double* A, int n, int ns, const double* pos, const double* forces
   prm[2] = r0;
 }
 
+void guided_curve(const double* A, int n, const double* prm, const double* x0, double h,
+                  double ftol, int kmax, std::vector<double>& nodes) {
+  const int m = 3 * n;
+  std::vector<double> x(x0, x0 + m), F(m);
+  nodes.assign(x.begin(), x.end());
+  for (int k = 0; k < kmax; ++k) {
+    morse(A, n, x.data(), prm, nullptr, F.data());
+    double fm = 0.0;
+    for (int I = 0; I < n; ++I)
+      fm = std::max(fm, std::sqrt(F[3 * I] * F[3 * I] + F[3 * I + 1] * F[3 * I + 1] +
+                                  F[3 * I + 2] * F[3 * I + 2]));
+    if (fm < ftol) break;
+    for (int c = 0; c < m; ++c) x[c] += h * F[c] / fm;
+    nodes.insert(nodes.end(), x.begin(), x.end());
+  }
+}
+
 void preconditioner(int m, const double* H, double* P, double floor) {
   std::vector<double> Aw(H, H + (size_t)m * m), w, V;
   jacobi_eigen(m, Aw, w, V);

@@ -4,6 +4,8 @@
 // eigenvalue.  Sizes are a few hundred coordinates at most.
 #pragma once
 
+#include <vector>
+
 namespace sgo {
 namespace ff {
 
@@ -17,6 +19,11 @@ void morse_hessian(const double* lattice, int natoms, const double* pos, const d
 // Fit of {D, a, r0} to nsamples (positions, forces) pairs, each [natoms][3].
 void fit(const double* lattice, int natoms, int nsamples, const double* pos, const double* forces,
          double* params);
+// Guided curve of the CLS relaxation: nodes of the steepest-descent path of
+// the fitted energy from x0, x_{k+1} = x_k + h F(x_k) / max_atom |F(x_k)|,
+// until max_atom |F| < ftol or kmax steps.  nodes receives (K+1) * 3n values.
+void guided_curve(const double* lattice, int natoms, const double* params, const double* x0,
+                  double h, double ftol, int kmax, std::vector<double>& nodes);
 // P = sum over modes with |tau| > 1e-6 max|tau| of v v^T / max(|tau|, floor max|tau|).
 void preconditioner(int m, const double* H, double* P, double floor = 0.1);
 

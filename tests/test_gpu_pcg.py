@@ -1,5 +1,6 @@
-"""Force-fitted PCG relaxation (Section 2.3) on the batched evaluator
-against the oracle's own implementation of the same algorithm."""
+"""Force-fitted PCG and curved-line-search relaxations (Section 2.3) on the
+batched evaluator against the oracle's own implementations of the same
+algorithms."""
 import numpy as np
 import pytest
 
@@ -34,3 +35,22 @@ def test_pcg_relaxation_matches_oracle():
         assert np.abs(X[i] - Xo).max() < 1e-4
         assert np.abs(F[i] - Fo).max() < 1e-4
         assert Eo[-1] < Eo[0]
+
+
+def test_cls_relaxation_matches_oracle():
+    import paper_1603_02732_amd as sgo
+    from oracle.cls import relax_cls
+    pop = _pop()
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP64)
+    for s in pop:
+        B.add_system(s)
+    E, F, X, prm, st = B.relax_cls(2, **KW)
+    assert np.all(st == 0)
+    for i, s in enumerate(pop):
+        Eo, Xo, Fo = relax_cls(s, 2)
+        nat = len(s["symbols"])
+        say("  cand %d CLS energies gpu %s oracle %s fit %s" % (i, np.round(E[i], 7), np.round(Eo, 7),
+                                                             np.round(prm[i], 5)))
+        assert np.abs(E[i] - Eo).max() / nat < 1e-6
+        assert np.abs(X[i] - Xo).max() < 1e-4
+        assert np.abs(F[i] - Fo).max() < 1e-4

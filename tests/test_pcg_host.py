@@ -63,3 +63,15 @@ def test_preconditioner_parity():
         P = sgo.ff_preconditioner(H)
         Po = pcg.preconditioner(H)
         assert np.abs(P - Po).max() < 1e-9 * np.abs(Po).max()
+
+
+def test_guided_curve_parity():
+    from oracle import cls
+    for lat, pos in _configs():
+        for prm in ((0.21, 1.25, 2.7), (0.05, 0.8, 3.3)):
+            g = sgo.ff_guided_curve(lat, pos, prm)
+            o = cls.guided_curve(lat, prm, pos)
+            # same node count; rounding differences of the force sums grow
+            # along a 200-step descent (an iterated map), to ~1e-8 bohr here
+            assert g.shape == o.shape
+            assert np.abs(g - o).max() < 1e-6
