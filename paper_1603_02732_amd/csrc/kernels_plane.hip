@@ -210,22 +210,23 @@ __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __rest
 // part[chunk][z][y][x] = sum_pairs f_a Re(u)^2 + f_b Im(u)^2 (u = psi_a + i psi_b,
 // unnormalised), accumulated in FP64 in LDS (row stride N1 | 1).
 template <int N1>
-__device__ __forceinline__ void row_pass_density(const PlaneLds& p, int y, double* acc, double fa,
+__device__ __forceinline__ void row_pass_density(const PlaneLds& p, int y, float* acc, double fa,
                                                  double fb) {
   cplx<float> v[N1], w[N1];
   load_row<N1>(p, y, v);
   freg::fft<float, +1, N1>(v, w);
-  // this pair's contribution, then the FP64 accumulation in groups of 8 (a
-  // scheduling fence per group keeps the accumulator loads from all being
-  // hoisted at once)
+  // this pair's contribution, accumulated in FP32 over the chunk's band
+  // pairs (a few per chunk; the chunks are summed in FP64 afterwards) in
+  // groups of 8 (a scheduling fence per group keeps the accumulator loads
+  // from all being hoisted at once)
   const float fa32 = (float)fa, fb32 = (float)fb;
-  double* a = acc + y * (N1 | 1);
+  float* a = acc + y * (N1 | 1);
   freg::static_for<0, (N1 + 7) / 8>([&](auto q) {
     constexpr int K0 = 8 * decltype(q)::value;
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = K0; k < (K0 + 8 < N1 ? K0 + 8 : N1); ++k)
-      a[k] += (double)(fa32 * w[k].x * w[k].x + fb32 * w[k].y * w[k].y);
+      a[k] += fa32 * w[k].x * w[k].x + fb32 * w[k].y * w[k].y;
   });
 }
 
@@ -236,10 +237,10 @@ __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __r
   if (z >= cd.N3 || chunk >= cd.ndens_chunk) return;
   extern __shared__ __align__(16) char smem[];
   const PlaneLds p_outer = plane_of(cd, (cplx<float>*)smem);
-  double* acc = (double*)(smem + (size_t)cd.N2 * p_outer.sx * sizeof(cplx<float>));
+  float* acc = (float*)(smem + (size_t)cd.N2 * p_outer.sx * sizeof(cplx<float>));
   const int lane = threadIdx.x;
   const int N1 = cd.N1, N2 = cd.N2, ar = N1 | 1;
-  for (int e = lane; e < N2 * ar; e += 64) acc[e] = 0.0;
+  for (int e = lane; e < N2 * ar; e += 64) acc[e] = 0.f;
   const int per = (cd.npair + cd.ndens_chunk - 1) / cd.ndens_chunk;
   const int p0 = chunk * per, p1 = min(cd.npair, p0 + per);
   for (int pair = p0; pair < p1; ++pair) {
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __r
   }
   __syncthreads();
   double* out = cd.dens_part + (size_t)chunk * cd.ntot + (size_t)z * N1 * N2;
-  for (int e = lane; e < N1 * N2; e += 64) out[e] = acc[(e / N1) * ar + e % N1];
+  for (int e = lane; e < N1 * N2; e += 64) out[e] = (double)acc[(e / N1) * ar + e % N1];
 }
 
 // ------------------------------------------------------------ z transforms
@@ -466,7 +467,7 @@ void launch_z_forward_reg(const LaunchCtx& L, int src, int dst) {
 
 size_t plane_reg_lds(const BatchGeom& g, bool density) {
   size_t b = (size_t)g.N2max * g.pl_sx_max * sizeof(cplx<float>);
-  if (density) b += (size_t)g.N2max * (g.N1max | 1) * sizeof(double);
+  if (density) b += (size_t)g.N2max * (g.N1max | 1) * sizeof(float);
   return b;
 }
 
