@@ -281,7 +281,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __r
 // reads of the half sphere, each lane transforms one stick along z in
 // registers, and the sticks buffer [pair][z][stick] is written (or read) one
 // 64-stick row per z.
-constexpr int kZPairs = 32;
+constexpr int kZPairs = 16;
 __device__ __forceinline__ int mirror_stick_r(int s) { return s == 0 ? 0 : ((s & 1) ? s + 1 : s - 1); }
 
 template <int N3>
