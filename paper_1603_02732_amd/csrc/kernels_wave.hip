@@ -589,6 +589,9 @@ __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ c
 // B operand for the four column tiles, and each result row leaves as one
 // float4 per lane.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+// TT: 16-row output tiles per pass (2 when every output has at most 32 rows:
+// half the accumulator registers, more resident waves).
+template <int TT>
 __global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cds, int y0, int y1,
                                                  int y2, int a0, int a1, int a2, int mat, float alpha,
                                                  float beta, int use_h) {
@@ -627,10 +630,10 @@ __global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cd
     }
   }
   __syncthreads();
-  for (int i0 = 0; i0 < nout; i0 += 64) {
-    floatx4 acc[4][4];
+  for (int i0 = 0; i0 < nout; i0 += 16 * TT) {
+    floatx4 acc[TT][4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < TT; ++t)
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
     for (int j0 = 0; j0 < nin; j0 += 4) {
@@ -638,7 +641,7 @@ __global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cd
       const float4 b = j < nin ? As[j * 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
       const double hj = (use_h && j < nin) ? cd.hproj[j] : 1.0;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TT; ++t) {
         if (i0 + 16 * t >= nout) break;
         const int i = i0 + 16 * t + n;
         const float a = (j < nin && i < nout) ? (float)(hj * M[(size_t)j * nout + i]) : 0.f;
@@ -650,7 +653,7 @@ __global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cd
     }
     if (!kin) continue;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TT; ++t) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + 16 * t + 4 * g + r;
@@ -1250,9 +1253,14 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
   const size_t lds32 = (size_t)nin_max * 64 * sizeof(float);
   if (std::is_same<T, float>::value && lds32 <= 65536 && g.gemm_f32) {
     prof_before("k_gemm_acc", L.stream);
-    hipLaunchKernelGGL(k_gemm_f32, dim3((g.K_max + 63) / 64, narr, g.ncand), dim3(64), lds32,
-                       L.stream, L.desc, y[0], y1, y2, a[0], a1, a2, mat, (float)alpha,
-                       (float)beta, use_h);
+    if (g.nb_max <= 32)
+      hipLaunchKernelGGL(k_gemm_f32<2>, dim3((g.K_max + 63) / 64, narr, g.ncand), dim3(64), lds32,
+                         L.stream, L.desc, y[0], y1, y2, a[0], a1, a2, mat, (float)alpha,
+                         (float)beta, use_h);
+    else
+      hipLaunchKernelGGL(k_gemm_f32<4>, dim3((g.K_max + 63) / 64, narr, g.ncand), dim3(64), lds32,
+                         L.stream, L.desc, y[0], y1, y2, a[0], a1, a2, mat, (float)alpha,
+                         (float)beta, use_h);
     check_launch("k_gemm_acc");
     prof_after("k_gemm_acc", L.stream, rows_moved);
     return;
@@ -1390,7 +1398,8 @@ static void configure_t() {
   allow_lds((const void*)k_gemm_acc<T, 5>);
 }
 void configure_wave() {
-  allow_lds((const void*)k_gemm_f32);
+  allow_lds((const void*)k_gemm_f32<2>);
+  allow_lds((const void*)k_gemm_f32<4>);
   configure_t<float>();
   configure_t<double>();
 }
