@@ -220,6 +220,11 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
   const int cur = sl.cur, nvalid = sl.nvalid, iter = sl.it;
   const int H = cd.hist_len;
   double* sc = cd.scal;
+  // the Pulay system lives in LDS (dynamically indexed: in registers it would
+  // go to scratch memory); only lane 0 touches it
+  __shared__ double A[kMaxHist + 1][kMaxHist + 2];
+  __shared__ double x[kMaxHist + 1];
+  double ekin_w = 0.0;
   {
     // block partials of k_density_finalize and k_gspace_residual, summed in
     // a fixed order (one wavefront: lane-strided, then the cross-lane tree)
@@ -235,6 +240,10 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
     }
 #pragma unroll
     for (int k = 0; k < 13; ++k) v[k] = wave_sum(v[k]);
+    // band kinetic energy (lane-strided, then the cross-lane tree)
+    double ek = 0.0;
+    for (int i = threadIdx.x; i < cd.nb; i += 64) ek += cd.occ[i] * cd.bandw[i];
+    ekin_w = wave_sum(ek);
     if (threadIdx.x != 0) return;
     const double w = cd.omega / cd.ntot;
     sc[S_DRHO] = w * v[0] / fmax(cd.nelec, 1e-30);
@@ -250,7 +259,6 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
   }
   // Pulay: minimise |sum c_l R_l| with sum c_l = 1
   const int n = nvalid;
-  double A[kMaxHist + 1][kMaxHist + 2];
   double scale = 0.0;
   for (int l = 0; l < n; ++l) {
     const int sl = (cur - l + H) % H;
@@ -287,7 +295,6 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
       for (int c = k; c <= N; ++c) A[r][c] -= f * A[k][c];
     }
   }
-  double x[kMaxHist + 1];
   for (int k = N - 1; k >= 0; --k) {
     double s = A[k][N];
     for (int c = k + 1; c < N; ++c) s -= A[k][c] * x[c];
@@ -297,8 +304,7 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
   for (int l = 0; l < n; ++l) ok = ok && isfinite(x[l]);
   for (int l = 0; l < n; ++l) cd.coef[(cur - l + H) % H] = ok ? x[l] : (l == 0 ? 1.0 : 0.0);
   // energies
-  double ekin = 0.0;
-  for (int i = 0; i < cd.nb; ++i) ekin += cd.occ[i] * cd.bandw[i];
+  const double ekin = ekin_w;
   const double ekn = sc[S_EBAND] - sc[S_VRHO];
   const double ent = -cd.sigma * sc[S_ENTROPY];
   const double etot = ekn + sc[S_ELOC] + sc[S_EH] + sc[S_EXC] + sc[S_EEW] + ent;
