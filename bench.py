@@ -301,14 +301,24 @@ def main():
     # apply): the library counts them per launch
     bound, amount, unit = kernel_amount(dominant, geoms[0], prof)
     avg_active = prof["cand_launches"] / max(prof["launches"], 1)
+    hbm_bytes = amount if bound == "hbm" else None
+    nxa = active_x_columns(sgo, pop[0])
+    if dominant in ("k_plane_hpsi", "k_plane_density"):
+        # the plane passes are bound by FP32 arithmetic (FFT butterflies in
+        # registers, LDS transposes), not by HBM: roofline against the ALU
+        bound, unit = "alu", "TFLOP/s"
+        amount = plane_alu_flops(dominant, geoms[0], nxa) * avg_active
     avg_s = prof["ms"] * 1e-3 / max(prof["launches"], 1)
     if bound == "hbm":
         ach = amount / avg_s / 1e9
         peak = HBM_PEAK_GBS
+    elif dominant in ("k_plane_hpsi", "k_plane_density"):
+        ach = amount / avg_s / 1e12
+        peak = FP32_ALU_PEAK_TFLOPS
     else:
         ach = amount / avg_s / 1e12
         peak = FP64_PEAK_TFLOPS
-    traffic = counters_traffic(dominant) if bound == "hbm" else None
+    traffic = counters_traffic(dominant)
     roof = {"bound": bound, "kernel": dominant, "achieved": ach, "peak": peak, "unit": unit,
             "frac": ach / peak, "traffic": traffic, "avg_launch_us": avg_s * 1e6,
             "launches_per_step": prof["launches"] / a.steps,
@@ -316,10 +326,11 @@ def main():
             "rows_per_candidate_launch": (prof["cand_rows"] / max(prof["cand_launches"], 1)
                                           if dominant in ("k_gemm_acc", "k_gram") else None),
             ("bytes_per_launch" if bound == "hbm" else "flop_per_launch"): amount,
+            "algorithmic_hbm_bytes_per_launch": (hbm_bytes if hbm_bytes is not None else
+                                                 kernel_amount(dominant, geoms[0], prof)[1]),
             "share_of_step": {k: round(v, 4) for k, v in shares.items()}}
 
     # every candidate kernel against its bound, from its own profiled step
-    nxa = active_x_columns(sgo, pop[0])
     table = {}
     for k in CANDIDATE_KERNELS:
         p = kprof[k]
