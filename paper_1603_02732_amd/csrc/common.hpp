@@ -93,13 +93,14 @@ struct CandDesc {
   cplx<double>* vloc_G; // [ntot] on D, zero elsewhere
   cplx<double>* rho0_G; // [ntot]
   cplx<double>* rho_out_G;  // [ntot]
-  cplx<double>* hist_in;    // [kMaxHist][ntot]
-  cplx<double>* hist_res;   // [kMaxHist][ntot]
+  void* hist_in;            // [kMaxHist][ntot] complex, FP64 or FP32 (hist_f32)
+  void* hist_res;           // [kMaxHist][ntot]
   double* pulay;        // [kMaxHist*kMaxHist] residual dot products
   double* coef;         // [kMaxHist]
   double* dens_part;    // [nchunk][ntot]
   int ndens_chunk;
   int hist_len;         // history capacity in use
+  int hist_f32;         // Pulay history stored as complex FP32 (FP32 bulk forms)
   // atoms (FP64)
   const double* pos;    // [nat*3]
   const int* spec;      // [nat]

@@ -488,6 +488,9 @@ class Engine {
   }
 
   size_t tsize() const { return prec_ == SGO_FP64 ? sizeof(double) : sizeof(float); }
+  // Pulay history element: complex FP64, or complex FP32 in the FP32 bulk
+  // forms (sums and coefficients stay FP64)
+  size_t hist_bytes() const { return prec_ == SGO_FP64 ? 16 : 8; }
 
   // One device allocation per candidate, carved into 256-byte-aligned arrays.
   void alloc_cand(HostCand& c, const BatchGeom& g) {
@@ -520,8 +523,8 @@ class Engine {
         {(void**)&d.gam, nb * 8}, {(void**)&d.bandw, nb * 8},
         {(void**)&d.rho_in_r, nt * 8}, {(void**)&d.rho_out_r, nt * 8}, {(void**)&d.veff_r, nt * 8},
         {(void**)&d.zgrid, nt * 16}, {(void**)&d.vloc_G, nt * 16}, {(void**)&d.rho0_G, nt * 16},
-        {(void**)&d.rho_out_G, nt * 16}, {(void**)&d.hist_in, kMaxHist * nt * 16},
-        {(void**)&d.hist_res, kMaxHist * nt * 16}, {(void**)&d.pulay, kMaxHist * kMaxHist * 8},
+        {(void**)&d.rho_out_G, nt * 16}, {(void**)&d.hist_in, kMaxHist * nt * hist_bytes()},
+        {(void**)&d.hist_res, kMaxHist * nt * hist_bytes()}, {(void**)&d.pulay, kMaxHist * kMaxHist * 8},
         {(void**)&d.coef, kMaxHist * 8}, {(void**)&d.dens_part, (size_t)c.dens_chunks * nt * 8},
         {(void**)&d.pos, (size_t)3 * c.nat * 8}, {(void**)&d.spec, (size_t)c.nat * sizeof(int)},
         {(void**)&d.force, (size_t)3 * c.nat * 8}, {(void**)&d.force_ew, (size_t)3 * c.nat * 8},
@@ -582,6 +585,7 @@ class Engine {
     for (int k = 0; k < 3; ++k) d.plan[k] = c.plan[k];
     d.ndens_chunk = c.dens_chunks;
     d.hist_len = c.hist_len;
+    d.hist_f32 = prec_ == SGO_FP64 ? 0 : 1;
     d.ew_eta = c.ew_eta;
     d.ew_rcut = c.ew_rcut;
     d.ew_gcut = c.ew_gcut;

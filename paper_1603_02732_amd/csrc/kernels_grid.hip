@@ -169,6 +169,22 @@ __global__ void __launch_bounds__(kNT) k_density_finalize(const CandDesc* __rest
     for (int k = 0; k < 3; ++k) cd.red_part[kPartDens + 3 * blockIdx.x + k] = v[k];
 }
 
+// Pulay history element access (complex FP64, or complex FP32 when
+// hist_f32; arithmetic in FP64 either way)
+__device__ __forceinline__ cplx<double> hist_ld(const CandDesc& cd, const void* h, size_t i) {
+  if (cd.hist_f32) {
+    const float2 v = ((const float2*)h)[i];
+    return {(double)v.x, (double)v.y};
+  }
+  return ((const cplx<double>*)h)[i];
+}
+__device__ __forceinline__ void hist_st(const CandDesc& cd, void* h, size_t i, cplx<double> v) {
+  if (cd.hist_f32)
+    ((float2*)h)[i] = make_float2((float)v.x, (float)v.y);
+  else
+    ((cplx<double>*)h)[i] = v;
+}
+
 // After the forward FFT of rho_out: rho_out(G), density residual into the
 // history, Hartree and local energies, and the residual dot products of the
 // Pulay matrix row of this iteration.
@@ -188,9 +204,9 @@ __global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restr
     const cplx<double> z = cd.zgrid[e];
     const cplx<double> rg = {z.x * inv_n, z.y * inv_n};
     cd.rho_out_G[e] = rg;
-    const cplx<double> rin = cd.hist_in[(size_t)cur * cd.ntot + e];
+    const cplx<double> rin = hist_ld(cd, cd.hist_in, (size_t)cur * cd.ntot + e);
     const cplx<double> R = {rg.x - rin.x, rg.y - rin.y};
-    cd.hist_res[(size_t)cur * cd.ntot + e] = R;
+    hist_st(cd, cd.hist_res, (size_t)cur * cd.ntot + e, R);
     const GPoint p = gpoint(cd, e);
     if (p.inD) {
       if (p.g2 > 0.0) v[0] += 4.0 * kPi * (rg.x * rg.x + rg.y * rg.y) / p.g2;
@@ -201,7 +217,7 @@ __global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restr
     for (int l = 0; l < kMaxHist; ++l) {
       if (l < nvalid) {
         const int slot = (cur - l + H) % H;
-        const cplx<double> Rl = cd.hist_res[(size_t)slot * cd.ntot + e];
+        const cplx<double> Rl = hist_ld(cd, cd.hist_res, (size_t)slot * cd.ntot + e);
         v[2 + l] += Rl.x * R.x + Rl.y * R.y;
       }
     }
@@ -342,13 +358,13 @@ __global__ void __launch_bounds__(kNT) k_mix(const CandDesc* __restrict__ cds, i
       for (int l = 0; l < nvalid; ++l) {
         const int sl = (cur - l + H) % H;
         const double c = cd.coef[sl];
-        const cplx<double> ri = cd.hist_in[(size_t)sl * cd.ntot + e];
-        const cplx<double> rr = cd.hist_res[(size_t)sl * cd.ntot + e];
+        const cplx<double> ri = hist_ld(cd, cd.hist_in, (size_t)sl * cd.ntot + e);
+        const cplx<double> rr = hist_ld(cd, cd.hist_res, (size_t)sl * cd.ntot + e);
         rho.x += c * (ri.x + alpha * kk * rr.x);
         rho.y += c * (ri.y + alpha * kk * rr.y);
       }
     }
-    cd.hist_in[(size_t)next * cd.ntot + e] = rho;
+    hist_st(cd, cd.hist_in, (size_t)next * cd.ntot + e, rho);
     cplx<double> V = {0.0, 0.0};
     if (p.inD) {
       V = cd.vloc_G[e];
