@@ -461,7 +461,8 @@ int sgo_de_select(int n, const double* e_parent, const double* e_child, const in
 
 /* One generation on a population batch: for each target i, mutant from the
  * donors of its first acceptable draw, crossover with the target (P1 = the
- * mutant, P2 = the target), child rejected when closer than dmin or, with
+ * mutant, P2 = the target), child rejected when two atoms are closer than
+ * max(dmin, 1e-3 bohr) (the evaluator refuses coincident atoms) or, with
  * sim_tol > 0, less than sim_tol from any parent; then relax_steps batched CG
  * steps (sgo_batch_relax_cg) of every child and greedy selection.  A target
  * whose draws are all rejected relaxes its own structure instead. */

@@ -29,7 +29,8 @@ Readings where the text leaves the operator open:
   * child atoms fill P1's species slots in order: for each slot of species s,
     first P1's atoms of s (in P1 order), then P2's (in P2 order);
   * minimum distances and distance fingerprints use the minimum-image
-    convention over the 27 neighbouring cells;
+    convention over the 27 neighbouring cells; a child is rejected below
+    max(d_min, 1e-3 bohr) (the evaluator refuses coincident atoms);
   * similarity of two structures = mean absolute difference of their sorted
     pair-distance lists;
   * selection keeps the child when its energy is strictly lower and its
@@ -273,7 +274,7 @@ def make_trials(parents, e_parent, species, lattice, draws, mutation="triangle",
             else:
                 child, _ = cross_sphere(v, parents[i], species, draws["offset"][i][a],
                                         draws["radius"][i][a])
-            if min_distance(lattice, child) < dmin:
+            if min_distance(lattice, child) < max(dmin, 1e-3):
                 continue
             if sim_tol > 0 and any(similarity(lattice, child, parents[j]) < sim_tol for j in range(n)):
                 continue

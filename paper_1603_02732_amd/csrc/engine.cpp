@@ -1037,7 +1037,7 @@ class Engine {
       }
     };
     auto build_curves = [&]() {
-      const int nt = std::max(1, std::min(n, (int)std::thread::hardware_concurrency()));
+      const int nt = std::max(1, std::min({n, (int)std::thread::hardware_concurrency(), 16}));
       std::vector<std::thread> pool;
       std::vector<std::exception_ptr> err(nt);
       for (int t = 0; t < nt; ++t)
@@ -1138,7 +1138,7 @@ class Engine {
     };
     // the fits of different candidates are independent: spread them over host threads
     auto build_all = [&](const std::vector<std::vector<double>>& xs) {
-      const int nt = std::max(1, std::min(n, (int)std::thread::hardware_concurrency()));
+      const int nt = std::max(1, std::min({n, (int)std::thread::hardware_concurrency(), 16}));
       std::vector<std::thread> pool;
       std::vector<std::exception_ptr> err(nt);
       for (int t = 0; t < nt; ++t)
@@ -2210,7 +2210,8 @@ int sgo_batch_de_generation(sgo_batch* b, const sgo_de_opts* de, const sgo_scf_o
                                                    d.radius, child.data(), nullptr);
         if (rc == SGO_EINVAL) throw Error(SGO_EINVAL, "invalid crossover draw");
         if (rc != SGO_OK) continue;
-        if (sgo::de::min_distance(c0.A, nat, child.data()) < de->dmin) continue;
+        // below dmin (and never closer than the evaluator accepts) the child is rejected
+        if (sgo::de::min_distance(c0.A, nat, child.data()) < std::max(de->dmin, 1e-3)) continue;
         bool alike = false;
         for (int j = 0; j < n && de->sim_tol > 0 && !alike; ++j)
           alike = sgo::de::similarity(c0.A, nat, child.data(), P(j)) < de->sim_tol;
