@@ -112,3 +112,40 @@ def test_autotuner_times_and_caches(tmp_path, monkeypatch):
         for k in ("SGO_PLANE_KERNEL", "SGO_GEMM_KERNEL", "SGO_GRAM_KC", "SGO_SUB_THREADS",
                   "SGO_SP_CHUNK", "SGO_DENS_CHUNKS"):
             sgo.set_tuning(k, 0)
+
+
+def test_invalid_inputs_are_rejected_and_the_handle_stays_usable():
+    """Degenerate and out-of-range inputs fail with SGO_EINVAL (checked on
+    the host before any launch), and the same handle then solves a valid
+    structure to the energy a fresh handle gives."""
+    sgo = _sgo()
+    s = workloads.tiny_system("c", ecut=4.0, grid=(15, 15, 15), seed=21)
+    ref = sgo.context_from_system(s, sgo.SGO_FP64)
+    ref.scf(sgo.default_opts(tol_e=1e-10, tol_rho=1e-8, max_iter=200))
+    e_ref, _ = ref.energy()
+    ref.close()
+
+    ctx = sgo.context_from_system(s, sgo.SGO_FP64)
+    pos = np.asarray(s["positions"], dtype=float)
+    spec = ctx.atom_species
+    cases = {
+        "coincident atoms": lambda: ctx.set_atoms(spec, np.vstack([pos[:-1], pos[:1]])),
+        "no atoms": lambda: ctx.set_atoms(np.zeros(0, dtype=np.int32), np.zeros((0, 3))),
+        "flat cell": lambda: ctx.set_cell(np.diag([10.0, 10.0, 0.0])),
+        "grid below the sphere": lambda: ctx.set_cutoff(4.0, (6, 6, 6), 10, sgo.SGO_OCC_FERMI, 0.01),
+        "grid with a factor 7": lambda: ctx.set_cutoff(4.0, (14, 14, 14), 10, sgo.SGO_OCC_FERMI, 0.01),
+        "too few bands": lambda: ctx.set_cutoff(4.0, (15, 15, 15), 3, sgo.SGO_OCC_FIXED, 0.0),
+        "zero cutoff": lambda: ctx.set_cutoff(0.0, (15, 15, 15), 10, sgo.SGO_OCC_FERMI, 0.01),
+        "non-positive smearing": lambda: ctx.set_cutoff(4.0, (15, 15, 15), 10, sgo.SGO_OCC_FERMI, 0.0),
+    }
+    for name, call in cases.items():
+        with pytest.raises(sgo.SgoError) as err:
+            call()
+        say("  %s -> %s" % (name, err.value))
+        assert err.value.code == sgo.SGO_EINVAL
+    # restore the valid structure on the same handle and solve
+    ctx.load_system(s)
+    ctx.scf(sgo.default_opts(tol_e=1e-10, tol_rho=1e-8, max_iter=200))
+    e, _ = ctx.energy()
+    ctx.close()
+    assert abs(e - e_ref) < 1e-8

@@ -93,3 +93,28 @@ def test_de_generation_rejects_invalid_draws():
     draws["r"][2, 0] = [2, 0, 1]  # the target among its own donors
     with pytest.raises(sgo.SgoError):
         B.de_generation(parents, [0.0] * 4, draws, de=sgo.de_opts(attempts=1), **KW)
+
+
+def test_de_generation_needs_four_candidates_and_valid_options():
+    import paper_1603_02732_amd as sgo
+    pop = _population(3)
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP64)
+    for s in pop:
+        B.add_system(s)
+    parents = [np.asarray(s["positions"], dtype=float) for s in pop]
+    draws = {"r": np.zeros((3, 1, 3), dtype=np.int32), "normal": np.ones((3, 1, 3)),
+             "axis": np.ones((3, 1, 3)), "offset": np.zeros((3, 1, 3)), "radius": np.ones((3, 1))}
+    with pytest.raises(sgo.SgoError) as err:
+        B.de_generation(parents, [0.0] * 3, draws, de=sgo.de_opts(attempts=1), **KW)
+    assert err.value.code == sgo.SGO_EINVAL
+    pop4 = _population(4)
+    B4 = sgo.Batch(4, precision=sgo.SGO_FP64)
+    for s in pop4:
+        B4.add_system(s)
+    parents4 = [np.asarray(s["positions"], dtype=float) for s in pop4]
+    d4 = de_draws(4, 1, seed=3)
+    for bad in (sgo.de_opts(attempts=0), sgo.de_opts(relax_steps=-1), sgo.de_opts(dmin=-1.0),
+                sgo.de_opts(mutation=7), sgo.de_opts(crossover=5)):
+        with pytest.raises(sgo.SgoError) as err:
+            B4.de_generation(parents4, [0.0] * 4, d4, de=bad, **KW)
+        assert err.value.code == sgo.SGO_EINVAL
