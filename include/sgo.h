@@ -305,6 +305,17 @@ int sgo_batch_set_atoms(sgo_batch* b, int i, const double* pos);
  * three may be NULL.  Returns the worst status. */
 int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, double* forces,
                   int* status);
+/* Solve n batches at once, each from its own host thread on its own stream
+ * (sgo_batch_set_stream; the batches must not share a stream or a handle).
+ * A population split into a few batches keeps the GPU busy while each
+ * batch waits in its latency-bound phases (the FP64 subspace solves, the SCF
+ * control, the status read-back).  energies, forces and status are laid out
+ * as for sgo_batch_scf, concatenated in batch order (each nullable); each
+ * batch's own error text stays with its handle.  Returns the worst status.
+ * The measurement hooks (sgo_profile_begin/end) count the launches of every
+ * batch. */
+int sgo_batches_scf(sgo_batch* const* batches, int n, const sgo_scf_opts* opts,
+                    double* energies, double* forces, int* status);
 int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info);
 /* Conventional CG relaxation of every candidate, nsteps steps (Section 2.3
  * names CG among the relaxation options): Polak-Ribiere directions built

@@ -168,6 +168,7 @@ def load_library(path=None):
         "sgo_batch_set_atoms": (I, [P, I, dp]),
         "sgo_batch_scf": (I, [P, ctypes.POINTER(sgo_scf_opts), dp, dp, ip]),
         "sgo_batch_info": (I, [P, I, ctypes.POINTER(sgo_scf_info)]),
+        "sgo_batches_scf": (I, [ctypes.POINTER(P), I, ctypes.POINTER(sgo_scf_opts), dp, dp, ip]),
         "sgo_batch_size": (I, [P, ip]),
         "sgo_set_allocator": (I, [P, ALLOC_FN, FREE_FN, P]),
         "sgo_batch_set_allocator": (I, [P, ALLOC_FN, FREE_FN, P]),
@@ -620,6 +621,29 @@ def ff_guided_curve(lattice, pos, params):
     if rc != SGO_OK:
         raise SgoError(rc, "ff_guided_curve")
     return nodes[:k.value].copy()
+
+
+def batches_scf(batches, opts=None, **kw):
+    """Solve several Batch objects at once, each from its own host thread on
+    its own stream (set_stream each to a distinct stream first).  Returns
+    energies, forces (list of (natoms, 3)) and status concatenated in batch
+    order."""
+    o = opts if opts is not None else default_opts(**kw)
+    lib = load_library()
+    hs = (ctypes.c_void_p * len(batches))(*[b._h.value for b in batches])
+    n = sum(len(b.natoms) for b in batches)
+    nat = [na for b in batches for na in b.natoms]
+    e = np.zeros(n)
+    f = np.zeros(3 * sum(nat))
+    st = np.zeros(n, dtype=np.int32)
+    rc = lib.sgo_batches_scf(hs, len(batches), ctypes.byref(o), _dptr(e), _dptr(f), _iptr(st))
+    if rc not in (SGO_OK, SGO_ENOTCONV, SGO_ENUMERIC):
+        raise SgoError(rc, "; ".join((lib.sgo_batch_last_error(b._h) or b"").decode() for b in batches))
+    forces, off = [], 0
+    for na in nat:
+        forces.append(f[off:off + 3 * na].reshape(na, 3))
+        off += 3 * na
+    return e, forces, st
 
 
 def de_opts(mutation=SGO_DE_TRIANGLE, crossover=SGO_DE_PLANE, F=0.5, fitness_shift=1,

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <exception>
 #include <map>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -61,32 +62,50 @@ void allow_lds(const void* kernel) {
 struct ProfState {
   bool on = false;
   std::string name;
-  int active = 0;          // candidates active in the launches being issued
-  long long cand_launches = 0;  // sum over profiled launches of `active`
-  long long cand_rows = 0;      // sum over profiled launches of `active` x row passes
-  std::vector<hipEvent_t> ev;  // start/stop pairs
+  long long cand_launches = 0;  // sum over profiled launches of the active candidates
+  long long cand_rows = 0;      // sum over profiled launches of active x row passes
+  std::vector<hipEvent_t> ev;   // start/stop pairs
   size_t used = 0;
 };
+// Process-wide measurement hooks.  Batches may be solved from several host
+// threads at once (sgo_batches_scf): the shared state is guarded, and what
+// belongs to one thread's launch sequence (candidates active in its current
+// launches, the event pair it has open, whether it is capturing a graph) is
+// thread-local.
 static ProfState g_prof;
-static bool g_capturing = false;  // no event records inside a captured graph
+static std::mutex g_prof_mu;
+static thread_local bool g_capturing = false;  // no event records inside a captured graph
+static thread_local int t_active = 0;
+static thread_local size_t t_pending = 0;
 
 void prof_before(const char* name, hipStream_t s) {
   if (!g_prof.on || g_capturing || g_prof.name != name) return;
-  if (g_prof.used + 2 > g_prof.ev.size()) {
-    for (int k = 0; k < 2; ++k) {
-      hipEvent_t e;
-      HIPCHK(hipEventCreate(&e));
-      g_prof.ev.push_back(e);
+  hipEvent_t e;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    if (g_prof.used + 2 > g_prof.ev.size()) {
+      for (int k = 0; k < 2; ++k) {
+        hipEvent_t x;
+        HIPCHK(hipEventCreate(&x));
+        g_prof.ev.push_back(x);
+      }
     }
+    t_pending = g_prof.used;
+    g_prof.used += 2;
+    e = g_prof.ev[t_pending];
   }
-  HIPCHK(hipEventRecord(g_prof.ev[g_prof.used], s));
+  HIPCHK(hipEventRecord(e, s));
 }
 void prof_after(const char* name, hipStream_t s, long long rows) {
   if (!g_prof.on || g_capturing || g_prof.name != name) return;
-  HIPCHK(hipEventRecord(g_prof.ev[g_prof.used + 1], s));
-  g_prof.used += 2;
-  g_prof.cand_launches += g_prof.active;
-  g_prof.cand_rows += (long long)g_prof.active * rows;
+  hipEvent_t e;
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    e = g_prof.ev[t_pending + 1];
+    g_prof.cand_launches += t_active;
+    g_prof.cand_rows += (long long)t_active * rows;
+  }
+  HIPCHK(hipEventRecord(e, s));
 }
 
 void throw_unsupported(const char* what) { throw Error(SGO_EINVAL, what); }
@@ -699,7 +718,7 @@ class Engine {
       h[i].ncand_index = (int)i;
       nact += h[i].active ? 1 : 0;
     }
-    g_prof.active = nact;
+    t_active = nact;
     if (!d_desc_ || desc_cap_ < cands_.size()) {
       if (d_desc_) (void)hipFree(d_desc_);
       HIPCHK(hipMalloc(&d_desc_, sizeof(CandDesc) * cands_.size()));
@@ -1787,6 +1806,7 @@ const char* sgo_last_error(const sgo_ctx* c) { return c ? c->err.c_str() : g_err
 
 int sgo_profile_begin(const char* kernel) {
   if (!kernel) return SGO_EINVAL;
+  std::lock_guard<std::mutex> lk(sgo::g_prof_mu);
   sgo::g_prof.on = true;
   sgo::g_prof.name = kernel;
   sgo::g_prof.used = 0;
@@ -1798,6 +1818,7 @@ int sgo_profile_begin(const char* kernel) {
 int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches,
                     long long* cand_rows) {
   return guard(nullptr, [&] {
+    std::lock_guard<std::mutex> lk(sgo::g_prof_mu);
     auto& P = sgo::g_prof;
     double ms = 0.0;
     for (size_t k = 0; k + 1 < P.used; k += 2) {
@@ -2013,6 +2034,36 @@ int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, doub
     }
     return rc;
   });
+}
+
+int sgo_batches_scf(sgo_batch* const* batches, int n, const sgo_scf_opts* opts,
+                    double* energies, double* forces, int* status) {
+  if (!batches || n < 1) return SGO_EINVAL;
+  for (int k = 0; k < n; ++k) {
+    if (!batches[k]) return SGO_EINVAL;
+    for (int j = 0; j < k; ++j)
+      if (batches[j] == batches[k]) return SGO_EINVAL;
+  }
+  // output offsets in batch order
+  std::vector<size_t> eoff(n + 1, 0), foff(n + 1, 0);
+  for (int k = 0; k < n; ++k) {
+    const int m = batches[k]->eng->size();
+    size_t f = 0;
+    for (int i = 0; i < m; ++i) f += 3 * (size_t)batches[k]->eng->cand(i).nat;
+    eoff[k + 1] = eoff[k] + m;
+    foff[k + 1] = foff[k] + f;
+  }
+  std::vector<int> rc(n, SGO_OK);
+  std::vector<std::thread> pool;
+  for (int k = 0; k < n; ++k)
+    pool.emplace_back([&, k] {
+      rc[k] = sgo_batch_scf(batches[k], opts, energies ? energies + eoff[k] : nullptr,
+                            forces ? forces + foff[k] : nullptr, status ? status + eoff[k] : nullptr);
+    });
+  for (auto& t : pool) t.join();
+  int worst = SGO_OK;
+  for (int k = 0; k < n; ++k) worst = std::min(worst, rc[k]);
+  return worst;
 }
 
 int sgo_batch_info(sgo_batch* b, int i, sgo_scf_info* info) {

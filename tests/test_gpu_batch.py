@@ -127,3 +127,40 @@ def test_cg_relaxation_matches_oracle():
         assert Eo[-1] < Eo[0]  # the relaxation lowers the energy overall
         assert np.abs(X[i] - Xo).max() < 1e-4
         assert np.abs(F[i] - Fo).max() < 1e-4
+
+
+def test_concurrent_batches_match_one_batch():
+    """A population solved as two batches on two streams from two host
+    threads gives each candidate the state one batch gives it (converged
+    tightly: the random starting bands differ with the candidate's index)."""
+    import torch
+    import paper_1603_02732_amd as sgo
+    pop = _population()
+    opts = sgo.default_opts(tol_e=1e-10, tol_rho=1e-8, max_iter=200)
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP64)
+    for s in pop:
+        B.add_system(s)
+    E, F, st = B.scf(opts)
+    assert np.all(st == 0)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    halves = [pop[:2], pop[2:]]
+    Bs = []
+    for half, stream in zip(halves, streams):
+        b = sgo.Batch(len(half), precision=sgo.SGO_FP64)
+        b.set_stream(stream.cuda_stream)
+        for s in half:
+            b.add_system(s)
+        Bs.append(b)
+    sgo.profile_begin("k_gram")
+    E2, F2, st2 = sgo.batches_scf(Bs, opts)
+    torch.cuda.synchronize()
+    prof = sgo.profile_end()
+    assert np.all(st2 == 0)
+    nat = [len(s["symbols"]) for s in pop]
+    dE = max(abs(a - b) / n for a, b, n in zip(E, E2, nat))
+    dF = max(float(np.abs(a - b).max()) for a, b in zip(F, F2))
+    say("  two streams vs one batch: dE %.2e dF %.2e, profiled k_gram launches %d" % (dE, dF, prof["launches"]))
+    assert dE < 1e-8 and dF < 1e-5
+    assert prof["launches"] > 0 and prof["ms"] > 0
+    with pytest.raises(sgo.SgoError):
+        sgo.batches_scf([Bs[0], Bs[0]], opts)  # one handle twice
