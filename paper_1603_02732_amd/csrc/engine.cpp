@@ -108,6 +108,12 @@ void prof_after(const char* name, hipStream_t s, long long rows) {
   HIPCHK(hipEventRecord(e, s));
 }
 
+bool host_sync_allowed() { return !g_capturing; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw Error(SGO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
 void throw_unsupported(const char* what) { throw Error(SGO_EINVAL, what); }
 
 void check_launch(const char* name) {
@@ -225,6 +231,8 @@ class Engine {
     if (d_iter_) (void)hipFree(d_iter_);
     if (d_scal_all_) (void)hipFree(d_scal_all_);
     if (h_scal_all_) (void)hipHostFree(h_scal_all_);
+    if (d_jac_done_) (void)hipFree(d_jac_done_);
+    if (h_jac_done_) (void)hipHostFree(h_jac_done_);
     if (own_stream_) (void)hipStreamDestroy(own_stream_);
   }
 
@@ -729,12 +737,18 @@ class Engine {
     HIPCHK(hipStreamSynchronize(stream_));
   }
 
-  LaunchCtx ctx(const BatchGeom& g) const {
+  LaunchCtx ctx(const BatchGeom& g) {
     LaunchCtx L;
     L.stream = stream_;
     L.desc = d_desc_;
     L.species = d_species_;
     L.g = g;
+    if (!d_jac_done_) {
+      HIPCHK(hipMalloc(&d_jac_done_, sizeof(int) * capacity_));
+      HIPCHK(hipHostMalloc((void**)&h_jac_done_, sizeof(int) * capacity_, hipHostMallocDefault));
+    }
+    L.jac_done = d_jac_done_;
+    L.jac_done_host = h_jac_done_;
     return L;
   }
 
@@ -1418,7 +1432,9 @@ class Engine {
   CandDesc* d_desc_ = nullptr;
   size_t desc_cap_ = 0;
   int* d_iter_ = nullptr;             // SCF iteration counter (device)
-  double* d_scal_all_ = nullptr;      // [ncand][S_COUNT] gathered status scalars (device)
+  double* d_scal_all_ = nullptr;
+  int* d_jac_done_ = nullptr;  // Jacobi convergence flags [capacity]
+  int* h_jac_done_ = nullptr;      // [ncand][S_COUNT] gathered status scalars (device)
   void* (*alloc_fn_)(size_t, void*) = nullptr;  // caller's device allocator (arenas)
   void (*free_fn_)(void*, void*) = nullptr;
   void* alloc_user_ = nullptr;
@@ -1866,6 +1882,11 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
     HIPCHK(hipMalloc(&deps, n * 8));
     HIPCHK(hipMalloc(&dscal, sgo::S_COUNT * 8));
     HIPCHK(hipMalloc(&dclk, 8 * sizeof(long long)));
+    double* dred;
+    int *djac, *hjac;
+    HIPCHK(hipMalloc(&dred, 2048 * 8));
+    HIPCHK(hipMalloc(&djac, sizeof(int)));
+    HIPCHK(hipHostMalloc((void**)&hjac, sizeof(int), hipHostMallocDefault));
     HIPCHK(hipMemset(dscal, 0, sgo::S_COUNT * 8));
     HIPCHK(hipMemcpy(dSsave, S, nn * 8, hipMemcpyHostToDevice));
     if (H) HIPCHK(hipMemcpy(dHsave, H, nn * 8, hipMemcpyHostToDevice));
@@ -1879,6 +1900,7 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
     d.M = dM;
     d.eps = deps;
     d.scal = dscal;
+    d.red_part = dred;
     d.dbg_clk = clocks ? dclk : nullptr;
     sgo::CandDesc* dd;
     HIPCHK(hipMalloc(&dd, sizeof(d)));
@@ -1888,6 +1910,8 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
     L.desc = dd;
     L.g.ncand = 1;
     L.g.nb_max = n;
+    L.jac_done = djac;
+    L.jac_done_host = hjac;
     const char* env = std::getenv("SGO_SUB_THREADS");
     L.g.sub_threads = env ? std::max(64, std::min(512, std::atoi(env) / 64 * 64)) : 512;
     hipEvent_t e0, e1;
@@ -1914,8 +1938,10 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     for (void* p : {(void*)dS, (void*)dH, (void*)dC, (void*)dM, (void*)deps, (void*)dscal,
-                    (void*)dSsave, (void*)dHsave, (void*)dclk, (void*)dd})
+                    (void*)dSsave, (void*)dHsave, (void*)dclk, (void*)dd, (void*)dred,
+                    (void*)djac})
       (void)hipFree(p);
+    (void)hipHostFree(hjac);
     if (flag != 0.0) throw Error(SGO_ENUMERIC, "overlap matrix is not positive definite");
     return SGO_OK;
   });

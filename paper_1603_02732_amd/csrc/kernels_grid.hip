@@ -910,8 +910,12 @@ __device__ __forceinline__ void jacobi_rot(const double* A, int n, int p, int q,
   *s = t * cc;
 }
 
+// phase 0: the whole solve; 1: up to H' and V = I (the Jacobi rounds are
+// then run by k_jac_* over the whole GPU); 2: from the converged H' and V on
+// (eigenvalue order, M = W^T V).  Phases 1 and 2 keep the matrices in global
+// memory (use_lds = 0).
 __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict__ cds, int mode,
-                                                     int use_lds, int max_sweeps) {
+                                                     int use_lds, int max_sweeps, int phase) {
   const CandDesc& cd = cds[blockIdx.x];
   if (!cd.active) return;
   const int n = cd.nb;
@@ -938,165 +942,172 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   __shared__ int rank[640];
   __shared__ double rc[320], rs[320];
   __shared__ int rp[320], rq[320];
-  if (tid == 0) fail = 0;
   long long* clk = cd.dbg_clk;
-  if (clk && tid == 0) clk[0] = clock64();
-  __syncthreads();
-  // Cholesky S = L L^T (lower, in place, right-looking; two barriers per
-  // column).  The pivots are kept aside in P3 and written to the diagonal at
-  // the end, so no thread overwrites a pivot another thread still reads.
-  for (int k = 0; k < n; ++k) {
-    __syncthreads();  // trailing update of the previous column is complete
-    const double d = P0[k * n + k];
-    if (!(d > 0.0)) {
-      if (tid == 0) fail = 1;
-      break;
-    }
-    const double piv = sqrt(d);
-    const double inv = 1.0 / piv;
-    if (tid == 0) P3[k] = piv;
-    for (int i = k + 1 + tid; i < n; i += nthr) P0[i * n + k] *= inv;
+  if (phase == 2 && clk && tid == 0) {
+    clk[3] = clock64();
+    clk[5] = max_sweeps;  // the sweeps the grid rounds took
+  }
+  if (phase != 2) {
+    if (tid == 0) fail = 0;
+    if (clk && tid == 0) clk[0] = clock64();
     __syncthreads();
-    const int m = n - k - 1;
-    for (int t = tid; t < m * m; t += nthr) {
-      const int i = k + 1 + t / m, j = k + 1 + t % m;
-      if (j <= i) P0[i * n + j] -= P0[i * n + k] * P0[j * n + k];
-    }
-  }
-  __syncthreads();
-  if (!fail)
-    for (int k = tid; k < n; k += nthr) P0[k * n + k] = P3[k];
-  __syncthreads();
-  if (fail) {
-    if (tid == 0) cd.scal[S_ERR] = 2.0;
-    for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
-    return;
-  }
-  // W = L^-1 by elimination on [L | I]: at step j, rows i > j subtract
-  // L[i][j] * row j (final since step j-1); row j+1 is complete after this
-  // step and is divided by its pivot.  One barrier per step.
-  for (int e = tid; e < n * n; e += nthr) {
-    const int i = e / n, j = e % n;
-    P2[e] = i == j ? (i == 0 ? 1.0 / P0[0] : 1.0) : 0.0;
-  }
-  __syncthreads();
-  for (int j = 0; j + 1 < n; ++j) {
-    const int rows = n - 1 - j, cols = j + 1;
-    for (int t = tid; t < rows * cols + 1; t += nthr) {
-      if (t == rows * cols) {
-        P2[(j + 1) * n + j + 1] = 1.0 / P0[(j + 1) * n + j + 1];
-        continue;
+    // Cholesky S = L L^T (lower, in place, right-looking; two barriers per
+    // column).  The pivots are kept aside in P3 and written to the diagonal at
+    // the end, so no thread overwrites a pivot another thread still reads.
+    for (int k = 0; k < n; ++k) {
+      __syncthreads();  // trailing update of the previous column is complete
+      const double d = P0[k * n + k];
+      if (!(d > 0.0)) {
+        if (tid == 0) fail = 1;
+        break;
       }
-      const int i = j + 1 + t / cols, c = t % cols;
-      double w = P2[i * n + c] - P0[i * n + j] * P2[j * n + c];
-      if (i == j + 1) w /= P0[i * n + i];
-      P2[i * n + c] = w;
+      const double piv = sqrt(d);
+      const double inv = 1.0 / piv;
+      if (tid == 0) P3[k] = piv;
+      for (int i = k + 1 + tid; i < n; i += nthr) P0[i * n + k] *= inv;
+      __syncthreads();
+      const int m = n - k - 1;
+      for (int t = tid; t < m * m; t += nthr) {
+        const int i = k + 1 + t / m, j = k + 1 + t % m;
+        if (j <= i) P0[i * n + j] -= P0[i * n + k] * P0[j * n + k];
+      }
     }
     __syncthreads();
-  }
-  if (clk && tid == 0) clk[1] = clock64();
-  if (mode == 1) {
-    for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * n + e / n];
-    return;
-  }
-  // H' = W H W^T (symmetrised)
-  for (int e = tid; e < n * n; e += nthr) {
-    const int i = e / n, j = e % n;
-    double s = 0.0;
-    for (int k = 0; k <= i; ++k) s = fma(P2[i * n + k], P1[k * n + j], s);
-    P3[e] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += nthr) {
-    const int i = e / n, j = e % n;
-    double s = 0.0;
-    for (int k = 0; k <= j; ++k) s = fma(P3[i * n + k], P2[j * n + k], s);
-    P1[e] = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < n * n; e += nthr) {
-    const int i = e / n, j = e % n;
-    if (i < j) {
-      const double a = 0.5 * (P1[i * n + j] + P1[j * n + i]);
-      P1[i * n + j] = a;
-      P1[j * n + i] = a;
+    if (!fail)
+      for (int k = tid; k < n; k += nthr) P0[k * n + k] = P3[k];
+    __syncthreads();
+    if (fail) {
+      if (tid == 0) cd.scal[S_ERR] = 2.0;
+      for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
+      return;
     }
-    P3[e] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  // Cyclic Jacobi with the round-robin ordering of disjoint index pairs.
-  // Phase A computes the rotations of a round; in phase B the threads take
-  // the (row pair, column pair) 2x2 blocks, rotating them in place, then
-  // V's columns.
-  // Blocks whose two rotations are both the identity are skipped.  Stop when
-  // the off-diagonal norm is below 1e-13 of the diagonal norm.
-  const int n2 = n + (n & 1);
-  const int npair = n2 / 2;
-  if (clk && tid == 0) clk[2] = clock64();
-  int nsweep = 0;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    double v[2] = {0.0, 0.0};
+    // W = L^-1 by elimination on [L | I]: at step j, rows i > j subtract
+    // L[i][j] * row j (final since step j-1); row j+1 is complete after this
+    // step and is divided by its pivot.  One barrier per step.
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
-      const double a = P1[e];
-      if (i == j) v[1] += a * a;
-      else v[0] += a * a;
+      P2[e] = i == j ? (i == 0 ? 1.0 / P0[0] : 1.0) : 0.0;
     }
-    block_sum<2>(v, sh);
-    if (!(v[0] > 1e-26 * v[1] + 1e-300)) break;
-    ++nsweep;
-    for (int r = 0; r < n2 - 1; ++r) {
-      for (int k = tid; k < npair; k += nthr) {
-        int p, q;
-        jacobi_pair(r, k, n2, &p, &q);
-        double c, sn;
-        jacobi_rot(P1, n, p, q, &c, &sn);
-        rp[k] = p;
-        rq[k] = q;
-        rc[k] = c;
-        rs[k] = sn;
-      }
-      __syncthreads();
-      // every (row pair P, column pair Q) block of the round over all
-      // threads (consecutive threads take consecutive Q of one P)
-      for (int t = tid; t < npair * npair; t += nthr) {
-        const int P = t / npair, Q = t - P * npair;
-        const double sP = rs[P], sQ = rs[Q];
-        if (sP == 0.0 && sQ == 0.0) continue;
-        const double cP = rc[P], cQ = rc[Q];
-        const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
-        const bool p2v = p2 < n, q2v = q2 < n;
-        const double a11 = P1[p1 * n + q1];
-        const double a12 = q2v ? P1[p1 * n + q2] : 0.0;
-        const double a21 = p2v ? P1[p2 * n + q1] : 0.0;
-        const double a22 = (p2v && q2v) ? P1[p2 * n + q2] : 0.0;
-        // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
-        const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
-        const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
-        // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
-        P1[p1 * n + q1] = cQ * b11 - sQ * b12;
-        if (q2v) P1[p1 * n + q2] = sQ * b11 + cQ * b12;
-        if (p2v) P1[p2 * n + q1] = cQ * b21 - sQ * b22;
-        if (p2v && q2v) P1[p2 * n + q2] = sQ * b21 + cQ * b22;
-      }
-      // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
-      // pair P updates rows p1, p2 of P3 (consecutive threads, consecutive i)
-      for (int t = tid; t < npair * n; t += nthr) {
-        const int P = t / n, i = t - P * n;
-        const double sP = rs[P];
-        const int p1 = rp[P], p2 = rq[P];
-        if (sP == 0.0 || p2 >= n) continue;
-        const double cP = rc[P];
-        const double vp = P3[p1 * n + i], vq = P3[p2 * n + i];
-        P3[p1 * n + i] = cP * vp - sP * vq;
-        P3[p2 * n + i] = sP * vp + cP * vq;
+    __syncthreads();
+    for (int j = 0; j + 1 < n; ++j) {
+      const int rows = n - 1 - j, cols = j + 1;
+      for (int t = tid; t < rows * cols + 1; t += nthr) {
+        if (t == rows * cols) {
+          P2[(j + 1) * n + j + 1] = 1.0 / P0[(j + 1) * n + j + 1];
+          continue;
+        }
+        const int i = j + 1 + t / cols, c = t % cols;
+        double w = P2[i * n + c] - P0[i * n + j] * P2[j * n + c];
+        if (i == j + 1) w /= P0[i * n + i];
+        P2[i * n + c] = w;
       }
       __syncthreads();
     }
-  }
-  if (clk && tid == 0) {
-    clk[3] = clock64();
-    clk[5] = nsweep;
+    if (clk && tid == 0) clk[1] = clock64();
+    if (mode == 1) {
+      for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * n + e / n];
+      return;
+    }
+    // H' = W H W^T (symmetrised)
+    for (int e = tid; e < n * n; e += nthr) {
+      const int i = e / n, j = e % n;
+      double s = 0.0;
+      for (int k = 0; k <= i; ++k) s = fma(P2[i * n + k], P1[k * n + j], s);
+      P3[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nthr) {
+      const int i = e / n, j = e % n;
+      double s = 0.0;
+      for (int k = 0; k <= j; ++k) s = fma(P3[i * n + k], P2[j * n + k], s);
+      P1[e] = s;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nthr) {
+      const int i = e / n, j = e % n;
+      if (i < j) {
+        const double a = 0.5 * (P1[i * n + j] + P1[j * n + i]);
+        P1[i * n + j] = a;
+        P1[j * n + i] = a;
+      }
+      P3[e] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (phase == 1) return;
+    // Cyclic Jacobi with the round-robin ordering of disjoint index pairs.
+    // Phase A computes the rotations of a round; in phase B the threads take
+    // the (row pair, column pair) 2x2 blocks, rotating them in place, then
+    // V's columns.
+    // Blocks whose two rotations are both the identity are skipped.  Stop when
+    // the off-diagonal norm is below 1e-13 of the diagonal norm.
+    const int n2 = n + (n & 1);
+    const int npair = n2 / 2;
+    if (clk && tid == 0) clk[2] = clock64();
+    int nsweep = 0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      double v[2] = {0.0, 0.0};
+      for (int e = tid; e < n * n; e += nthr) {
+        const int i = e / n, j = e % n;
+        const double a = P1[e];
+        if (i == j) v[1] += a * a;
+        else v[0] += a * a;
+      }
+      block_sum<2>(v, sh);
+      if (!(v[0] > 1e-26 * v[1] + 1e-300)) break;
+      ++nsweep;
+      for (int r = 0; r < n2 - 1; ++r) {
+        for (int k = tid; k < npair; k += nthr) {
+          int p, q;
+          jacobi_pair(r, k, n2, &p, &q);
+          double c, sn;
+          jacobi_rot(P1, n, p, q, &c, &sn);
+          rp[k] = p;
+          rq[k] = q;
+          rc[k] = c;
+          rs[k] = sn;
+        }
+        __syncthreads();
+        // every (row pair P, column pair Q) block of the round over all
+        // threads (consecutive threads take consecutive Q of one P)
+        for (int t = tid; t < npair * npair; t += nthr) {
+          const int P = t / npair, Q = t - P * npair;
+          const double sP = rs[P], sQ = rs[Q];
+          if (sP == 0.0 && sQ == 0.0) continue;
+          const double cP = rc[P], cQ = rc[Q];
+          const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
+          const bool p2v = p2 < n, q2v = q2 < n;
+          const double a11 = P1[p1 * n + q1];
+          const double a12 = q2v ? P1[p1 * n + q2] : 0.0;
+          const double a21 = p2v ? P1[p2 * n + q1] : 0.0;
+          const double a22 = (p2v && q2v) ? P1[p2 * n + q2] : 0.0;
+          // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
+          const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
+          const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
+          // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
+          P1[p1 * n + q1] = cQ * b11 - sQ * b12;
+          if (q2v) P1[p1 * n + q2] = sQ * b11 + cQ * b12;
+          if (p2v) P1[p2 * n + q1] = cQ * b21 - sQ * b22;
+          if (p2v && q2v) P1[p2 * n + q2] = sQ * b21 + cQ * b22;
+        }
+        // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
+        // pair P updates rows p1, p2 of P3 (consecutive threads, consecutive i)
+        for (int t = tid; t < npair * n; t += nthr) {
+          const int P = t / n, i = t - P * n;
+          const double sP = rs[P];
+          const int p1 = rp[P], p2 = rq[P];
+          if (sP == 0.0 || p2 >= n) continue;
+          const double cP = rc[P];
+          const double vp = P3[p1 * n + i], vq = P3[p2 * n + i];
+          P3[p1 * n + i] = cP * vp - sP * vq;
+          P3[p2 * n + i] = sP * vp + cP * vq;
+        }
+        __syncthreads();
+      }
+    }
+    if (clk && tid == 0) {
+      clk[3] = clock64();
+      clk[5] = nsweep;
+    }
   }
   // ranks of the eigenvalues (ascending, ties by index)
   for (int i = tid; i < n; i += nthr) {
@@ -1122,6 +1133,97 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   }
   for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = P1[i * n + i];
   if (clk && tid == 0) clk[4] = clock64();
+}
+
+// ------------------------------------------- Jacobi rounds over the GPU
+// For large band counts a round of the cyclic Jacobi iteration (the same
+// round-robin pairs, rotations and 2x2 block updates as in k_subspace) is two
+// launches over all candidates: the rotations of the round's pairs, then
+// every (row pair, column pair) block of H' and every column pair of V.  The
+// rotations and the per-candidate convergence flag live at the start of the
+// reduction scratch (free while the subspace problem is solved).
+constexpr int kJacDone = 0;  // 1.0 once the candidate's H' is diagonal
+constexpr int kJacRot = 8;   // [npair][4]: p, q, c, s
+
+// Off-diagonal vs diagonal norm of H' (one block per candidate): sets the
+// candidate's flag and done_all[c] (1 for inactive candidates).
+__global__ void __launch_bounds__(kNT) k_jac_offnorm(const CandDesc* __restrict__ cds,
+                                                     int* done_all) {
+  const CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active) {
+    if (threadIdx.x == 0) done_all[blockIdx.x] = 1;
+    return;
+  }
+  __shared__ double sh[16 * 2];
+  const int n = cd.nb;
+  double v[2] = {0.0, 0.0};
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const double a = cd.Hs[e];
+    if (e / n == e % n) v[1] += a * a;
+    else v[0] += a * a;
+  }
+  block_sum<2>(v, sh);
+  if (threadIdx.x == 0) {
+    const int done = v[0] > 1e-26 * v[1] + 1e-300 ? 0 : 1;
+    cd.red_part[kJacDone] = done;
+    done_all[blockIdx.x] = done;
+  }
+}
+
+__global__ void __launch_bounds__(kNT) k_jac_params(const CandDesc* __restrict__ cds, int r) {
+  const CandDesc& cd = cds[blockIdx.y];
+  if (!cd.active || cd.red_part[kJacDone] != 0.0) return;
+  const int n = cd.nb, n2 = n + (n & 1), npair = n2 / 2;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npair) return;
+  int p, q;
+  jacobi_pair(r, k, n2, &p, &q);
+  double c, sn;
+  jacobi_rot(cd.Hs, n, p, q, &c, &sn);
+  double* rot = cd.red_part + kJacRot + 4 * k;
+  rot[0] = p;
+  rot[1] = q;
+  rot[2] = c;
+  rot[3] = sn;
+}
+
+__global__ void __launch_bounds__(kNT) k_jac_apply(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.y];
+  if (!cd.active || cd.red_part[kJacDone] != 0.0) return;
+  const int n = cd.nb, n2 = n + (n & 1), npair = n2 / 2;
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const double* rot = cd.red_part + kJacRot;
+  double* A = cd.Hs;
+  double* Vt = cd.M;  // V stored transposed: Vt[q][i] = V[i][q]
+  if (t < npair * npair) {
+    const int P = t / npair, Q = t - P * npair;
+    const double sP = rot[4 * P + 3], sQ = rot[4 * Q + 3];
+    if (sP == 0.0 && sQ == 0.0) return;
+    const double cP = rot[4 * P + 2], cQ = rot[4 * Q + 2];
+    const int p1 = (int)rot[4 * P], p2 = (int)rot[4 * P + 1];
+    const int q1 = (int)rot[4 * Q], q2 = (int)rot[4 * Q + 1];
+    const bool p2v = p2 < n, q2v = q2 < n;
+    const double a11 = A[p1 * n + q1];
+    const double a12 = q2v ? A[p1 * n + q2] : 0.0;
+    const double a21 = p2v ? A[p2 * n + q1] : 0.0;
+    const double a22 = (p2v && q2v) ? A[p2 * n + q2] : 0.0;
+    const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
+    const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
+    A[p1 * n + q1] = cQ * b11 - sQ * b12;
+    if (q2v) A[p1 * n + q2] = sQ * b11 + cQ * b12;
+    if (p2v) A[p2 * n + q1] = cQ * b21 - sQ * b22;
+    if (p2v && q2v) A[p2 * n + q2] = sQ * b21 + cQ * b22;
+  } else if (t < npair * npair + npair * n) {
+    const int u = t - npair * npair;
+    const int P = u / n, i = u - P * n;
+    const double sP = rot[4 * P + 3];
+    const int p1 = (int)rot[4 * P], p2 = (int)rot[4 * P + 1];
+    if (sP == 0.0 || p2 >= n) return;
+    const double cP = rot[4 * P + 2];
+    const double vp = Vt[p1 * n + i], vq = Vt[p2 * n + i];
+    Vt[p1 * n + i] = cP * vp - sP * vq;
+    Vt[p2 * n + i] = sP * vp + cP * vq;
+  }
 }
 
 // Set or advance the batch's SCF iteration counter (one thread).
@@ -1256,15 +1358,51 @@ void launch_occupations(const LaunchCtx& L) {
 }
 void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   // up to 64 bands the matrices live in LDS; the thread count is a tuning
-  // parameter (a single wavefront makes barriers almost free).
+  // parameter (a single wavefront makes barriers almost free).  From
+  // kJacGridBands bands on, the Jacobi rounds run over the whole GPU (one
+  // workgroup would take tens of microseconds per round in global memory);
+  // that needs a host read of the convergence flags per sweep, so it is not
+  // used while a graph is being captured.
   const int n = L.g.nb_max;
   const int use_lds = n <= 64 ? 1 : 0;
   size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * n : 0;
   const int nthr = L.g.sub_threads;
   prof_before("k_subspace", L.stream);
-  hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode,
-                     use_lds, max_sweeps);
-  check_launch("k_subspace");
+  if (mode == 3 && n >= kJacGridBands && L.jac_done && host_sync_allowed()) {
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
+                       max_sweeps, 1);
+    check_launch("k_subspace");
+    const int n2 = n + (n & 1), npair = n2 / 2;
+    const dim3 gp((npair + kNT - 1) / kNT, L.g.ncand);
+    const dim3 ga((npair * npair + npair * n + kNT - 1) / kNT, L.g.ncand);
+    int done_sweeps = 0;
+    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+      hipLaunchKernelGGL(k_jac_offnorm, dim3(L.g.ncand), dim3(kNT), 0, L.stream, L.desc,
+                         L.jac_done);
+      check_launch("k_jac_offnorm");
+      hip_check(hipMemcpyAsync(L.jac_done_host, L.jac_done, sizeof(int) * L.g.ncand,
+                               hipMemcpyDeviceToHost, L.stream),
+                "Jacobi flags");
+      hip_check(hipStreamSynchronize(L.stream), "Jacobi flags");
+      bool all = true;
+      for (int c = 0; c < L.g.ncand; ++c) all = all && L.jac_done_host[c] != 0;
+      if (all) break;
+      for (int r = 0; r < n2 - 1; ++r) {
+        hipLaunchKernelGGL(k_jac_params, gp, dim3(kNT), 0, L.stream, L.desc, r);
+        hipLaunchKernelGGL(k_jac_apply, ga, dim3(kNT), 0, L.stream, L.desc);
+      }
+      check_launch("k_jac_apply");
+      ++done_sweeps;
+    }
+    // phase 2 takes the sweep count in place of the sweep limit (debug clocks)
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
+                       done_sweeps, 2);
+    check_launch("k_subspace");
+  } else {
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode,
+                       use_lds, max_sweeps, 0);
+    check_launch("k_subspace");
+  }
   prof_after("k_subspace", L.stream);
 }
 

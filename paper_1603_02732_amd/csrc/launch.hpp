@@ -36,7 +36,14 @@ struct LaunchCtx {
   const CandDesc* desc;      // device array [ncand]
   const SpeciesDev* species; // device array [kMaxSpecies]
   BatchGeom g;
+  int* jac_done = nullptr;       // device [ncand]: per-candidate Jacobi convergence flags
+  int* jac_done_host = nullptr;  // pinned host copy of them
 };
+// Band count from which the Jacobi rounds of the subspace solve run over the
+// whole GPU instead of one workgroup per candidate.
+constexpr int kJacGridBands = 160;
+// False while the calling thread captures a graph (no host synchronisation).
+bool host_sync_allowed();
 
 template <typename T> void launch_hpsi(const LaunchCtx& L, int src /*W_X or W_D*/);
 template <typename T> void launch_density(const LaunchCtx& L);
@@ -84,6 +91,8 @@ void launch_proj_bf16(const LaunchCtx& L, int src, int dst);
 void allow_lds(const void* kernel);
 // Report a failed launch by kernel name (throws on the host side).
 void check_launch(const char* name);
+// Throws the library error for a failed HIP runtime call.
+void hip_check(hipError_t e, const char* what);
 // Reject a launch shape the kernels do not support (throws on the host side).
 void throw_unsupported(const char* what);
 // Optional event timing of every launch of one named kernel.
