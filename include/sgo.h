@@ -260,7 +260,10 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
  * K share (at most SGO_GRAM_KC/4 terms) and FP64 sums of those),
  * "SGO_PCG_TRIAL" (cap of the PCG trial step on the largest atom
  * displacement, milli-bohr, default 100), "SGO_PCG_FLOOR" (eigenvalue floor
- * of the PCG preconditioner, thousandths of max|tau|, default 100).
+ * of the PCG preconditioner, thousandths of max|tau|, default 100),
+ * "SGO_JAC_GRID" (band count from which the subspace products and Jacobi
+ * rounds run over the whole GPU instead of one workgroup per candidate,
+ * default 160).
  * value <= 0 restores the default (or the environment variable of the same
  * name).  SGO_EINVAL for an unknown key.  sgo_get_tuning returns the value
  * set (0 if none). */

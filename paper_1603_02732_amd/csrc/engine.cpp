@@ -679,6 +679,7 @@ class Engine {
     g.kc_len = std::max(tune("SGO_GRAM_KC", 256), ((g.K_max + 31) / 32 + 31) / 32 * 32);
     g.kc_len = (g.kc_len + 31) / 32 * 32;
     g.sub_threads = std::max(64, std::min(512, tune("SGO_SUB_THREADS", 512) / 64 * 64));
+    g.jac_grid = tune("SGO_JAC_GRID", kJacGridBandsDefault);
     g.nkc_max = (g.K_max + g.kc_len - 1) / g.kc_len;
     // FP32 register-FFT plane kernels when every line length is supported
     // and the compact plane (plus the density accumulator) fits the LDS
@@ -1952,7 +1953,7 @@ int sgo_set_tuning(const char* key, int value) {
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
                                 "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
                                 "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL", "SGO_PCG_TRIAL",
-                                "SGO_PCG_FLOOR"};
+                                "SGO_PCG_FLOOR", "SGO_JAC_GRID"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;

@@ -910,10 +910,11 @@ __device__ __forceinline__ void jacobi_rot(const double* A, int n, int p, int q,
   *s = t * cc;
 }
 
-// phase 0: the whole solve; 1: up to H' and V = I (the Jacobi rounds are
-// then run by k_jac_* over the whole GPU); 2: from the converged H' and V on
-// (eigenvalue order, M = W^T V).  Phases 1 and 2 keep the matrices in global
-// memory (use_lds = 0).
+// phase 0: the whole solve; 1: Cholesky and W = L^-1 only (the congruence,
+// the Jacobi rounds and M = W^T V then run over the whole GPU: k_sub_*,
+// k_jac_*); 2: eigenvalue order and the sorted M, eps from the converged H'
+// and the product W^T V already in S.  Phases 1 and 2 keep the matrices in
+// global memory (use_lds = 0).
 __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict__ cds, int mode,
                                                      int use_lds, int max_sweeps, int phase) {
   const CandDesc& cd = cds[blockIdx.x];
@@ -1008,6 +1009,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * n + e / n];
       return;
     }
+    if (phase == 1) return;  // W is ready; the products run over the GPU
     // H' = W H W^T (symmetrised)
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
@@ -1033,7 +1035,6 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       P3[e] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    if (phase == 1) return;
     // Cyclic Jacobi with the round-robin ordering of disjoint index pairs.
     // Phase A computes the rotations of a round; in phase B the threads take
     // the (row pair, column pair) 2x2 blocks, rotating them in place, then
@@ -1119,12 +1120,15 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     }
     rank[i] = rnk;
   }
-  // M = W^T V into P0 (L is no longer needed); P3 holds V^T
-  for (int e = tid; e < n * n; e += nthr) {
-    const int j = e / n, i = e % n;
-    double s = 0.0;
-    for (int k = j; k < n; ++k) s = fma(P2[k * n + j], P3[i * n + k], s);
-    P0[e] = s;
+  // M = W^T V into P0 (L is no longer needed); P3 holds V^T.  In phase 2
+  // the product has already been formed over the GPU (k_sub_compose).
+  if (phase != 2) {
+    for (int e = tid; e < n * n; e += nthr) {
+      const int j = e / n, i = e % n;
+      double s = 0.0;
+      for (int k = j; k < n; ++k) s = fma(P2[k * n + j], P3[i * n + k], s);
+      P0[e] = s;
+    }
   }
   __syncthreads();
   for (int e = tid; e < n * n; e += nthr) {
@@ -1133,6 +1137,55 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   }
   for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = P1[i * n + i];
   if (clk && tid == 0) clk[4] = clock64();
+}
+
+// ------------------------------------- subspace products over the GPU
+// Large subspace problems: T = W H (W = L^-1 lower triangular, in C), then
+// H' = T W^T symmetrised (both halves from one thread) and V = I, then after
+// the Jacobi rounds M0 = W^T V (V stored transposed in M) into S.  One thread
+// per output element, all candidates in one launch.
+__global__ void __launch_bounds__(kNT) k_sub_wh(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.y];
+  if (!cd.active) return;
+  const int n = cd.nb;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e / n, j = e - i * n;
+  const double* W = cd.C;
+  double s = 0.0;
+  for (int k = 0; k <= i; ++k) s = fma(W[i * n + k], cd.Hs[k * n + j], s);
+  cd.S[e] = s;  // T
+}
+__global__ void __launch_bounds__(kNT) k_sub_twt(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.y];
+  if (!cd.active) return;
+  const int n = cd.nb;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int i = e / n, j = e - i * n;
+  cd.M[e] = i == j ? 1.0 : 0.0;  // V^T = I
+  if (i > j) return;
+  const double* W = cd.C;
+  const double* T = cd.S;
+  double a = 0.0, b = 0.0;  // H'[i][j] and H'[j][i]
+  for (int k = 0; k <= j; ++k) a = fma(T[i * n + k], W[j * n + k], a);
+  for (int k = 0; k <= i; ++k) b = fma(T[j * n + k], W[i * n + k], b);
+  const double h = i == j ? a : 0.5 * (a + b);
+  cd.Hs[i * n + j] = h;
+  cd.Hs[j * n + i] = h;
+}
+__global__ void __launch_bounds__(kNT) k_sub_compose(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.y];
+  if (!cd.active) return;
+  const int n = cd.nb;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * n) return;
+  const int j = e / n, i = e - j * n;
+  const double* W = cd.C;
+  const double* Vt = cd.M;
+  double s = 0.0;
+  for (int k = j; k < n; ++k) s = fma(W[k * n + j], Vt[i * n + k], s);
+  cd.S[e] = s;
 }
 
 // ------------------------------------------- Jacobi rounds over the GPU
@@ -1359,7 +1412,7 @@ void launch_occupations(const LaunchCtx& L) {
 void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   // up to 64 bands the matrices live in LDS; the thread count is a tuning
   // parameter (a single wavefront makes barriers almost free).  From
-  // kJacGridBands bands on, the Jacobi rounds run over the whole GPU (one
+  // g.jac_grid bands on, the Jacobi rounds run over the whole GPU (one
   // workgroup would take tens of microseconds per round in global memory);
   // that needs a host read of the convergence flags per sweep, so it is not
   // used while a graph is being captured.
@@ -1368,10 +1421,14 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * n : 0;
   const int nthr = L.g.sub_threads;
   prof_before("k_subspace", L.stream);
-  if (mode == 3 && n >= kJacGridBands && L.jac_done && host_sync_allowed()) {
+  if (mode == 3 && n >= L.g.jac_grid && L.jac_done && host_sync_allowed()) {
     hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
                        max_sweeps, 1);
     check_launch("k_subspace");
+    const dim3 ge((n * n + kNT - 1) / kNT, L.g.ncand);
+    hipLaunchKernelGGL(k_sub_wh, ge, dim3(kNT), 0, L.stream, L.desc);
+    hipLaunchKernelGGL(k_sub_twt, ge, dim3(kNT), 0, L.stream, L.desc);
+    check_launch("k_sub_twt");
     const int n2 = n + (n & 1), npair = n2 / 2;
     const dim3 gp((npair + kNT - 1) / kNT, L.g.ncand);
     const dim3 ga((npair * npair + npair * n + kNT - 1) / kNT, L.g.ncand);
@@ -1394,6 +1451,8 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
       check_launch("k_jac_apply");
       ++done_sweeps;
     }
+    hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
+    check_launch("k_sub_compose");
     // phase 2 takes the sweep count in place of the sweep limit (debug clocks)
     hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
                        done_sweeps, 2);

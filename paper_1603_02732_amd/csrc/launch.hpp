@@ -10,6 +10,11 @@ enum WArr { W_X = 0, W_HX = 1, W_D = 2, W_HD = 3, W_BETA = 4 };
 enum MArr { M_S = 0, M_H = 1, M_M = 2, M_C = 3 };
 
 // Launch geometry shared by all candidates of a batch (maxima over them).
+// Default band count from which the subspace products and Jacobi rounds run
+// over the whole GPU instead of one workgroup per candidate (BatchGeom
+// jac_grid, tuning key SGO_JAC_GRID).
+constexpr int kJacGridBandsDefault = 160;
+
 struct BatchGeom {
   int ncand;
   int npair_max, nsp_max, nb_max, nproj_max, nat_max;
@@ -29,6 +34,7 @@ struct BatchGeom {
   int ew_ng_max;     // reciprocal Ewald vectors enumerated (box size)
   int ew_nimg_max;
   int sub_threads;   // threads of the LDS-resident subspace solver
+  int jac_grid = kJacGridBandsDefault;  // band count from which the subspace solve runs over the GPU
 };
 
 struct LaunchCtx {
@@ -39,9 +45,7 @@ struct LaunchCtx {
   int* jac_done = nullptr;       // device [ncand]: per-candidate Jacobi convergence flags
   int* jac_done_host = nullptr;  // pinned host copy of them
 };
-// Band count from which the Jacobi rounds of the subspace solve run over the
-// whole GPU instead of one workgroup per candidate.
-constexpr int kJacGridBands = 160;
+
 // False while the calling thread captures a graph (no host synchronisation).
 bool host_sync_allowed();
 
