@@ -110,6 +110,19 @@ void prof_after(const char* name, hipStream_t s, long long rows) {
 
 bool host_sync_allowed() { return !g_capturing; }
 
+// Device LDS limit and the kernels' dynamic-LDS attributes, once per
+// process (handles may be created from several threads).
+static std::once_flag g_config_once;
+void configure_once(int device) {
+  std::call_once(g_config_once, [device] {
+    int lim = 0;
+    HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    g_lds_limit = lim;
+    (void)hipGetLastError();
+    configure_kernels();
+  });
+}
+
 void hip_check(hipError_t e, const char* what) {
   if (e != hipSuccess) throw Error(SGO_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
@@ -208,15 +221,7 @@ class Engine {
     HIPCHK(hipGetDeviceCount(&ndev));
     if (device < 0 || device >= ndev) throw Error(SGO_EINVAL, "no such HIP device");
     HIPCHK(hipSetDevice(device));
-    static bool configured = false;
-    if (!configured) {
-      int lim = 0;
-      HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
-      g_lds_limit = lim;
-      (void)hipGetLastError();
-      configure_kernels();
-      configured = true;
-    }
+    configure_once(device);
     HIPCHK(hipMalloc(&d_species_, sizeof(SpeciesDev) * kMaxSpecies));
     HIPCHK(hipMemset(d_species_, 0, sizeof(SpeciesDev) * kMaxSpecies));
     HIPCHK(hipMalloc(&d_iter_, 64));
@@ -1863,14 +1868,7 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
       throw Error(SGO_EINVAL, "bad subspace_solve arguments");
     if (reps < 1) reps = 1;
     HIPCHK(hipSetDevice(device));
-    static bool configured = false;
-    if (!configured) {
-      int lim = 0;
-      HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
-      sgo::g_lds_limit = lim;
-      sgo::configure_kernels();
-      configured = true;
-    }
+    sgo::configure_once(device);
     const size_t nn = (size_t)n * n;
     double *dS, *dH, *dC, *dM, *deps, *dscal, *dSsave, *dHsave;
     long long* dclk;
