@@ -212,7 +212,7 @@ def main():
         summarize_counters(*a.summarize_counters)
         return
     if a.gpus != 1:
-        print("bench.py measures one GPU only; --gpus %d is not supported by this build "
+        print("bench.py measures one GPU only; --gpus %d is not supported "
               "(candidates are independent and would shard one population slice per GPU)"
               % a.gpus, file=sys.stderr)
         sys.exit(2)
