@@ -232,7 +232,7 @@ const char* sgo_last_error(const sgo_ctx* ctx);
 int sgo_grid_info(sgo_ctx* ctx, int info[10]);
 
 /* The FP64 subspace step on host matrices (n <= 640): Cholesky S = L L^T
- * (Gram-Schmidt in band order, Algorithm 1 "Orthogonalization") and, for
+ * (Gram-Schmidt in band order: the orthogonalisation step of Algorithm 1) and, for
  * mode 3, diagonalisation of H' = L^-1 H L^-T (subspace diagonalisation).
  * Writes M [n*n] (row-major; new band i = sum_j old band j * M[j*n+i]):
  * mode 1: M = L^-T; mode 3: M = L^-T V with eigenvalues eps [n] ascending.

@@ -1,10 +1,11 @@
 // FP64 grid-side kernels: full-grid FFT passes, output density and energy
-// sums, density residual and Pulay/Kerker mixing (the "rho_out is mixed with
-// rho_in" step of the SCF loop, Section 2.4), potentials, per-geometry setup
-// (local potential and starting density from structure factors, Ewald sum),
-// Hellmann-Feynman force sums, occupations, and the FP64 subspace solver
-// (Cholesky orthonormalisation + Jacobi diagonalisation, Algorithm 1 lines
-// "Orthogonalization" and "subspace diagonalization").
+// sums, density residual and Pulay/Kerker mixing (the step of the SCF loop of
+// Section 2.4 that combines the output density with the input one),
+// potentials, per-geometry setup (local potential and starting density from
+// structure factors, Ewald sum), Hellmann-Feynman force sums, occupations,
+// and the FP64 subspace solver (Cholesky orthonormalisation + Jacobi
+// diagonalisation: the orthogonalisation and subspace-diagonalisation steps
+// of Algorithm 1).
 #include "device.hpp"
 #include "launch.hpp"
 

@@ -1,5 +1,5 @@
 // FP32 plane kernels of the band FFTs with register-resident line transforms
-// (Algorithm 1 "Calculate H|psi>": the local-potential product in real
+// (the H psi step of Algorithm 1: the local-potential product in real
 // space; Section 2.4: the output density).  One wavefront takes one z-plane
 // of one band pair.  The plane lives in LDS only over its active x columns
 // (the projection of the wavefunction sphere, |m1| <= m1max, stored

@@ -1,6 +1,6 @@
 // Kleinman-Bylander projector products with BF16 inputs and FP32
-// accumulation on MFMA (the FP32_BF16PROJ precision form; Algorithm 1
-// "Calculate H|psi>", nonlocal part):
+// accumulation on MFMA (the FP32_BF16PROJ precision form; the nonlocal part
+// of the H psi step of Algorithm 1):
 //   P = beta^T Psi          split-K partials in FP32, summed over the K
 //                           chunks in FP64 in a fixed order;
 //   H Psi += beta (h P)     FP32 accumulation.

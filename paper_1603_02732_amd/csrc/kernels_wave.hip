@@ -1,6 +1,6 @@
 // Wavefunction-side kernels, templated on the bulk precision T.
 //
-//  * H|psi> (Algorithm 1, the bold "Calculate H|Psi>" steps): Gamma-point
+//  * H|psi> (the H psi steps of Algorithm 1): Gamma-point
 //    two-bands-per-FFT packing, sphere-pruned z transforms on the occupied
 //    stick pairs, a fused per-plane kernel (inverse 2-D FFT, multiply by
 //    V_eff(r), forward 2-D FFT) and a gather that unpacks the two bands and

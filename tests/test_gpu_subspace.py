@@ -1,5 +1,6 @@
 """The FP64 subspace step against plain linear algebra: Cholesky-QR equals
-classical Gram-Schmidt in band order (Algorithm 1 "Orthogonalization"), and
+classical Gram-Schmidt in band order (the orthogonalisation step of
+Algorithm 1), and
 the Rayleigh-Ritz rotation solves the generalised eigenproblem H c = e S c."""
 import numpy as np
 import pytest
