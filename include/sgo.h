@@ -314,8 +314,9 @@ int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, doub
  * batch waits in its latency-bound phases (the FP64 subspace solves, the SCF
  * control, the status read-back).  energies, forces and status are laid out
  * as for sgo_batch_scf, concatenated in batch order (each nullable); each
- * batch's own error text stays with its handle.  Returns the worst status.
- * The measurement hooks (sgo_profile_begin/end) count the launches of every
+ * batch's own error text stays with its handle.  Returns the first error
+ * other than SGO_ENOTCONV/SGO_ENUMERIC that a batch returned (batch order),
+ * else the worst status as for sgo_batch_scf.  The measurement hooks (sgo_profile_begin/end) count the launches of every
  * batch. */
 int sgo_batches_scf(sgo_batch* const* batches, int n, const sgo_scf_opts* opts,
                     double* energies, double* forces, int* status);

@@ -13,6 +13,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -2079,13 +2080,27 @@ int sgo_batches_scf(sgo_batch* const* batches, int n, const sgo_scf_opts* opts,
     foff[k + 1] = foff[k] + f;
   }
   std::vector<int> rc(n, SGO_OK);
+  auto run = [&](int k) {
+    rc[k] = sgo_batch_scf(batches[k], opts, energies ? energies + eoff[k] : nullptr,
+                          forces ? forces + foff[k] : nullptr, status ? status + eoff[k] : nullptr);
+  };
   std::vector<std::thread> pool;
-  for (int k = 0; k < n; ++k)
-    pool.emplace_back([&, k] {
-      rc[k] = sgo_batch_scf(batches[k], opts, energies ? energies + eoff[k] : nullptr,
-                            forces ? forces + foff[k] : nullptr, status ? status + eoff[k] : nullptr);
-    });
+  int inline_from = n;  // batches from here on run on the calling thread
+  for (int k = 0; k < n; ++k) {
+    try {
+      pool.emplace_back(run, k);
+    } catch (const std::system_error&) {
+      inline_from = k;  // no thread could be started: solve the rest here
+      break;
+    }
+  }
+  for (int k = inline_from; k < n; ++k) run(k);
   for (auto& t : pool) t.join();
+  // a hard error of any batch (invalid input, allocation, device or state)
+  // comes first, in batch order; otherwise the per-candidate outcomes
+  // combine as in sgo_batch_scf (SGO_ENUMERIC over SGO_ENOTCONV over SGO_OK)
+  for (int k = 0; k < n; ++k)
+    if (rc[k] != SGO_OK && rc[k] != SGO_ENOTCONV && rc[k] != SGO_ENUMERIC) return rc[k];
   int worst = SGO_OK;
   for (int k = 0; k < n; ++k) worst = std::min(worst, rc[k]);
   return worst;

@@ -129,6 +129,40 @@ def test_cg_relaxation_matches_oracle():
         assert np.abs(F[i] - Fo).max() < 1e-4
 
 
+class _NoMemory:
+    """Caller allocator with nothing to give: every request returns NULL."""
+
+    def __init__(self, sgo):
+        self.alloc = sgo.ALLOC_FN(lambda nbytes, user: None)
+        self.free = sgo.FREE_FN(lambda ptr, user: None)
+
+
+def test_concurrent_batches_report_a_hard_error_first():
+    """Two batches at once, one stopping unconverged (SGO_ENOTCONV) and one
+    whose arena allocation fails (SGO_ENOMEM): the call returns the
+    allocation error, which no candidate status can stand in for."""
+    import torch
+    import paper_1603_02732_amd as sgo
+    pop = _population()
+    opts = sgo.default_opts(max_iter=2)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    Bs = []
+    for half, stream in zip((pop[:2], pop[2:]), streams):
+        b = sgo.Batch(len(half), precision=sgo.SGO_FP64)
+        b.set_stream(stream.cuda_stream)
+        for s in half:
+            b.add_system(s)
+        Bs.append(b)
+    Bs[1].set_allocator(_NoMemory(sgo))
+    with pytest.raises(sgo.SgoError) as err:
+        sgo.batches_scf(Bs, opts)
+    torch.cuda.synchronize()
+    say("  unconverged batch beside a failed allocation: code %d" % err.value.code)
+    assert err.value.code == sgo.SGO_ENOMEM
+    _, _, st = Bs[0].scf(opts)  # alone, the first batch only stops unconverged
+    assert np.all(st == sgo.SGO_ENOTCONV)
+
+
 def test_concurrent_batches_match_one_batch():
     """A population solved as two batches on two streams from two host
     threads gives each candidate the state one batch gives it (converged
