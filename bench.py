@@ -38,6 +38,7 @@ FP32_ALU_PEAK_TFLOPS = 78.6
 COUNTERS = os.path.join(ROOT, "profiles", "c3_population_hbm_counters.txt")
 # profiling-hook names of the kernels as rocprofv3 reports them
 HOOK_OF = {"k_gemm_f32": "k_gemm_acc", "k_plane_hpsi_reg": "k_plane_hpsi",
+           "k_plane_hpsi_group": "k_plane_hpsi",
            "k_plane_density_reg": "k_plane_density", "k_z_inverse_reg": "k_z_inverse",
            "k_z_forward_reg": "k_z_forward", "k_linemin_r": "k_linemin",
            "k_cg_direction_r": "k_cg_direction"}

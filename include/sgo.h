@@ -263,7 +263,10 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
  * of the PCG preconditioner, thousandths of max|tau|, default 100),
  * "SGO_JAC_GRID" (band count from which the subspace products and Jacobi
  * rounds run over the whole GPU instead of one workgroup per candidate,
- * default 160).
+ * default 160), "SGO_PLANE_GROUP" (consecutive z-planes per four-wavefront
+ * workgroup of the FP32 register H psi plane kernel, 2..8; 1 = one plane per
+ * wavefront; by default the size that keeps the most lanes busy while two
+ * groups still share a compute unit's LDS, or 1 where no group saves 10%).
  * value <= 0 restores the default (or the environment variable of the same
  * name).  SGO_EINVAL for an unknown key.  sgo_get_tuning returns the value
  * set (0 if none). */

@@ -695,6 +695,9 @@ class Engine {
           !plane_reg_length_ok(c.N[2]))
         g.plane_reg = 0;
     if (plane_reg_lds(g, true) > (size_t)g_lds_limit) g.plane_reg = 0;
+    // consecutive z-planes per workgroup of the H psi plane kernel where
+    // that fills the lanes better (tuning key SGO_PLANE_GROUP, 1 = off)
+    g.plane_group = g.plane_reg ? plane_group_size(g, (size_t)g_lds_limit, tune("SGO_PLANE_GROUP", 0)) : 1;
     g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
     g.gram_f32 = tsize() == 4 && tune("SGO_GRAM_KERNEL", 1) == 2 ? 1 : 0;
     g.bf16proj = prec_ == SGO_FP32_BF16PROJ ? 1 : 0;
@@ -1952,7 +1955,7 @@ int sgo_set_tuning(const char* key, int value) {
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
                                 "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
                                 "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL", "SGO_PCG_TRIAL",
-                                "SGO_PCG_FLOOR", "SGO_JAC_GRID"};
+                                "SGO_PCG_FLOOR", "SGO_JAC_GRID", "SGO_PLANE_GROUP"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;

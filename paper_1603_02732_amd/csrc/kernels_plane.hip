@@ -206,6 +206,138 @@ __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __rest
   }
 }
 
+// H psi, local part, of a group of consecutive z-planes of one band pair
+// per workgroup of four wavefronts.  The line transforms of all the planes
+// of the group are spread over the 256 lanes, so that planes whose line
+// counts leave part of a wavefront idle (say 35 active columns and 48 rows
+// on 64 lanes) share the lanes.  Each line is transformed exactly as in
+// k_plane_hpsi_reg; the planes lie one after another in LDS, each compact
+// (N2 rows of stride sx).
+constexpr int kPlaneGroupThreads = 256;
+
+template <int N2, int S>
+__device__ __forceinline__ void column_lines(cplx<float>* Q0, int pstride, int sx, int nx, int nlines,
+                                             int tid) {
+  for (int l = tid; l < nlines; l += kPlaneGroupThreads) {
+    // strides re-declared opaque per line: the per-element offsets are
+    // recomputed in each pass of the loop instead of all being hoisted
+    int sxl = sx, psl = pstride;
+    asm volatile("" : "+s"(sxl), "+s"(psl));
+    const int j = l / nx, c = l - j * nx;
+    cplx<float>* q = Q0 + j * psl + c;
+    cplx<float> v[N2], w[N2];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) v[k] = q[k * sxl];
+    freg::fft<float, S, N2>(v, w);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) q[k * sxl] = w[k];
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void column_lines_rt(cplx<float>* Q0, int pstride, int sx, int nx, int N2,
+                                                int nlines, int tid) {
+  switch (N2) {
+#define SGO_CASE(N)                                                 \
+  case N:                                                           \
+    column_lines<N, S>(Q0, pstride, sx, nx, nlines, tid);           \
+    break;
+    SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+    default:
+      break;
+  }
+}
+
+template <int N1>
+__device__ __forceinline__ void row_lines_hpsi(const PlaneLds& p0, int pstride, int N2, int nlines,
+                                               const float* __restrict__ V0, int tid) {
+  for (int l = tid; l < nlines; l += kPlaneGroupThreads) {
+    const int j = l / N2, y = l - j * N2;
+    PlaneLds p = p0;
+    int psl = pstride;
+    asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl), "+s"(psl));
+    p.Q = p0.Q + j * psl;
+    row_pass_hpsi<N1>(p, y, V0 + ((size_t)j * N2 + y) * N1);
+  }
+}
+
+__global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
+    const CandDesc* __restrict__ cds, int group) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int z0 = blockIdx.x * group, pair = blockIdx.y;
+  if (z0 >= cd.N3 || pair >= cd.npair) return;
+  const int np = min(group, cd.N3 - z0);
+  extern __shared__ __align__(16) char smem[];
+  PlaneLds p = plane_of(cd, (cplx<float>*)smem);
+  const int tid = threadIdx.x;
+  const int N1 = cd.N1, N2 = cd.N2, nst = cd.nst;
+  const int pstride = N2 * p.sx;
+  cplx<float>* st = (cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z0) * nst;
+  // sticks of the np planes into the compact planes (zeros elsewhere); the
+  // stick positions are read once per batch and serve every plane
+  for (int e = tid; e < np * pstride; e += kPlaneGroupThreads) p.Q[e] = {0.f, 0.f};
+  __syncthreads();
+  for (int s0 = tid; s0 < nst; s0 += 4 * kPlaneGroupThreads) {
+    int off[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + kPlaneGroupThreads * u;
+      const int xy = s < nst ? cd.stick_xy[s] : 0;
+      off[u] = (xy >> 16) * p.sx + col_of_x(p, N1, xy & 0xFFFF);
+    }
+    for (int j = 0; j < np; ++j) {
+      cplx<float> v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = s0 + kPlaneGroupThreads * u;
+        v[u] = s < nst ? st[(size_t)j * nst + s] : cplx<float>{0.f, 0.f};
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (s0 + kPlaneGroupThreads * u < nst) p.Q[j * pstride + off[u]] = v[u];
+    }
+  }
+  __syncthreads();
+  column_lines_rt<+1>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
+  __syncthreads();
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  {
+    const float* V0 = (const float*)cd.veff_t + (size_t)z0 * N2 * N1;
+    switch (N1) {
+#define SGO_CASE(N)                                              \
+  case N:                                                        \
+    row_lines_hpsi<N>(p, pstride, N2, np * N2, V0, tid);         \
+    break;
+      SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+      default:
+        break;
+    }
+  }
+  __syncthreads();
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  column_lines_rt<-1>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
+  __syncthreads();
+  for (int s0 = tid; s0 < nst; s0 += 4 * kPlaneGroupThreads) {
+    int off[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + kPlaneGroupThreads * u;
+      const int xy = s < nst ? cd.stick_xy[s] : 0;
+      off[u] = (xy >> 16) * p.sx + col_of_x(p, N1, xy & 0xFFFF);
+    }
+    for (int j = 0; j < np; ++j) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = s0 + kPlaneGroupThreads * u;
+        if (s < nst) st[(size_t)j * nst + s] = p.Q[j * pstride + off[u]];
+      }
+    }
+  }
+}
+
 // Density of one plane summed over a chunk of band pairs,
 // part[chunk][z][y][x] = sum_pairs f_a Re(u)^2 + f_b Im(u)^2 (u = psi_a + i psi_b,
 // unnormalised), accumulated in FP64 in LDS (row stride N1 | 1).
@@ -471,11 +603,45 @@ size_t plane_reg_lds(const BatchGeom& g, bool density) {
   return b;
 }
 
+size_t plane_group_lds(const BatchGeom& g, int group) {
+  return (size_t)group * g.N2max * g.pl_sx_max * sizeof(cplx<float>);
+}
+
+int plane_group_size(const BatchGeom& g, size_t lds_per_cu, int forced) {
+  // wavefront time per plane, in line-transform rounds of one wavefront:
+  // one plane per wavefront takes 2 column rounds and 2 row rounds
+  // (ceil(lines / 64) each); a group of P planes on four wavefronts takes
+  // 4 x the rounds over 256 lanes, shared by P planes.  Two groups must fit
+  // one compute unit's LDS, as two one-plane wavefronts per SIMD do.
+  auto rounds = [](int lines, int lanes) { return (lines + lanes - 1) / lanes; };
+  const int nx = std::max(1, g.pl_sx_max), N2 = std::max(1, g.N2max);
+  const double single = 2.0 * rounds(nx, 64) + 2.0 * rounds(N2, 64);
+  int best = 1;
+  double best_t = single;
+  for (int P = 2; P <= 8; ++P) {
+    if (2 * plane_group_lds(g, P) > lds_per_cu) break;
+    const double t = 4.0 * (2 * rounds(P * nx, kPlaneGroupThreads) +
+                            2 * rounds(P * N2, kPlaneGroupThreads)) / P;
+    if (forced == P) return P;
+    if (t < 0.9 * best_t) {
+      best = P;
+      best_t = t;
+    }
+  }
+  return forced == 1 ? 1 : best;
+}
+
 void launch_plane_hpsi_reg(const LaunchCtx& L) {
   const BatchGeom& g = L.g;
-  dim3 gp(g.N3max, g.npair_max, g.ncand);
   prof_before("k_plane_hpsi", L.stream);
-  hipLaunchKernelGGL(k_plane_hpsi_reg, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
+  if (g.plane_group > 1) {
+    dim3 gp((g.N3max + g.plane_group - 1) / g.plane_group, g.npair_max, g.ncand);
+    hipLaunchKernelGGL(k_plane_hpsi_group, gp, dim3(kPlaneGroupThreads),
+                       plane_group_lds(g, g.plane_group), L.stream, L.desc, g.plane_group);
+  } else {
+    dim3 gp(g.N3max, g.npair_max, g.ncand);
+    hipLaunchKernelGGL(k_plane_hpsi_reg, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
+  }
   check_launch("k_plane_hpsi");
   prof_after("k_plane_hpsi", L.stream);
 }
@@ -491,6 +657,7 @@ void launch_plane_density_reg(const LaunchCtx& L) {
 
 void configure_plane_kernels() {
   allow_lds((const void*)k_plane_hpsi_reg);
+  allow_lds((const void*)k_plane_hpsi_group);
   allow_lds((const void*)k_plane_density_reg);
   allow_lds((const void*)k_z_inverse_reg);
   allow_lds((const void*)k_z_forward_reg);

@@ -35,6 +35,7 @@ struct BatchGeom {
   int ew_nimg_max;
   int sub_threads;   // threads of the LDS-resident subspace solver
   int jac_grid = kJacGridBandsDefault;  // band count from which the subspace solve runs over the GPU
+  int plane_group = 1;  // z-planes per workgroup of the H psi plane kernel (1: one per wavefront)
 };
 
 struct LaunchCtx {
@@ -84,6 +85,10 @@ void configure_kernels();
 bool plane_reg_length_ok(int n);
 size_t plane_reg_lds(const BatchGeom& g, bool density);
 void launch_plane_hpsi_reg(const LaunchCtx& L);
+// Planes per workgroup of the grouped H psi plane kernel for this geometry
+// (1: the one-plane kernel; `forced` > 0 asks for that size where it fits).
+int plane_group_size(const BatchGeom& g, size_t lds_per_cu, int forced);
+size_t plane_group_lds(const BatchGeom& g, int group);
 void launch_plane_density_reg(const LaunchCtx& L);
 void launch_z_inverse_reg(const LaunchCtx& L, int src);
 void launch_z_forward_reg(const LaunchCtx& L, int src, int dst);

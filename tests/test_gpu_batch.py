@@ -129,6 +129,39 @@ def test_cg_relaxation_matches_oracle():
         assert np.abs(F[i] - Fo).max() < 1e-4
 
 
+def test_plane_groups_agree_with_one_plane_per_wavefront():
+    """The H psi plane kernel with several z-planes per workgroup (the
+    default where it fills the lanes better; forced sizes 2, 3 and 8, so that
+    the last group of a candidate is partial) against one plane per
+    wavefront, on an uneven FP32 batch: each line goes through the same
+    transform either way, so the solves agree to FP32 rounding."""
+    import paper_1603_02732_amd as sgo
+    pop = _population()
+    nat = [len(s["symbols"]) for s in pop]
+    opts = sgo.default_opts(tol_e=1e-8, tol_rho=1e-6, max_iter=200)
+    out = {}
+    try:
+        for grp in (1, 0, 2, 3, 8):
+            sgo.set_tuning("SGO_PLANE_GROUP", grp)
+            B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+            for s in pop:
+                B.add_system(s)
+            E, F, st = B.scf(opts)
+            B.close()
+            assert np.all(st == 0)
+            out[grp] = (E, F)
+    finally:
+        sgo.set_tuning("SGO_PLANE_GROUP", 0)
+    E1, F1 = out[1]
+    for grp in (0, 2, 3, 8):
+        E, F = out[grp]
+        dE = max(abs(a - b) / n for a, b, n in zip(E, E1, nat))
+        dF = max(float(np.abs(a - b).max()) for a, b in zip(F, F1))
+        say("  plane group %d vs 1: dE/atom %.2e dF %.2e%s" % (grp, dE, dF,
+            " (bit for bit)" if dE == 0 and dF == 0 else ""))
+        assert dE < 1e-6 and dF < 1e-4
+
+
 class _NoMemory:
     """Caller allocator with nothing to give: every request returns NULL."""
 
