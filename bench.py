@@ -121,6 +121,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--leg", choices=sorted(LEGS),
+                    help="run only this workload leg and print its result (profiling aid; "
+                         "not the bench line)")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the HBM counter summary of two rocprofv3 --pmc runs and exit")
     return ap.parse_args()
@@ -207,6 +210,13 @@ def kernel_amount(name, g, prof, tsize=4):
     return bound, per * prof["cand_launches"] / n, unit
 
 
+# workload legs that run on their own (bench.py --leg NAME)
+LEGS = {
+    "C4_uneven_population_batched": lambda sgo, wl, sync: c4_run(sgo, wl, sync),
+    "C5_large_cell": lambda sgo, wl, sync: c5_run(sgo, wl, sync),
+}
+
+
 def main():
     a = parse()
     if a.summarize_counters:
@@ -229,6 +239,11 @@ def main():
     def sync():
         if have_torch:
             torch.cuda.synchronize()
+
+    if a.leg:
+        # one leg on its own, e.g. under rocprofv3 --kernel-trace
+        print(json.dumps({"leg": a.leg, **LEGS[a.leg](sgo, workloads, sync)}), flush=True)
+        return
 
     pop = workloads.config_c3()
     from paper_1603_02732_amd import autotune
