@@ -888,13 +888,13 @@ __device__ __forceinline__ double rsq_nr(double x) {
   const double r = __builtin_amdgcn_rsq(x);
   return r * fma(-0.5 * x * r, r, 1.5);
 }
-__device__ __forceinline__ void jacobi_rot(const double* A, int n, int p, int q, double* c,
+__device__ __forceinline__ void jacobi_rot(const double* A, int n, int ld, int p, int q, double* c,
                                            double* s) {
   *c = 1.0;
   *s = 0.0;
   if (q >= n) return;
-  const double apq = A[p * n + q];
-  const double app = A[p * n + p], aqq = A[q * n + q];
+  const double apq = A[p * ld + q];
+  const double app = A[p * ld + p], aqq = A[q * ld + q];
   // skip entries at rounding level: |a_pq|^2 <= 1e-34 |a_pp a_qq|
   if (!(apq * apq > 1e-34 * fabs(app * aqq) + 1e-300)) return;
   const double th = 0.5 * (aqq - app) * rcp_nr(apq);
@@ -922,16 +922,20 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   if (!cd.active) return;
   const int n = cd.nb;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  // row stride of the four matrices: n + 1 in LDS (rows and columns of
+  // FP64 entries then fall in different banks), n in global memory
+  const int ld = use_lds ? n + 1 : n;
   extern __shared__ __align__(16) char smem[];
   double *P0, *P1, *P2, *P3;  // L, H / H', W = L^-1, scratch / V
   if (use_lds) {
     P0 = (double*)smem;
-    P1 = P0 + n * n;
-    P2 = P1 + n * n;
-    P3 = P2 + n * n;
+    P1 = P0 + n * ld;
+    P2 = P1 + n * ld;
+    P3 = P2 + n * ld;
     for (int e = tid; e < n * n; e += nthr) {
-      P0[e] = cd.S[e];
-      P1[e] = cd.Hs[e];
+      const int i = e / n, j = e - i * n;
+      P0[i * ld + j] = cd.S[e];
+      P1[i * ld + j] = cd.Hs[e];
     }
   } else {
     P0 = cd.S;
@@ -958,7 +962,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     // the end, so no thread overwrites a pivot another thread still reads.
     for (int k = 0; k < n; ++k) {
       __syncthreads();  // trailing update of the previous column is complete
-      const double d = P0[k * n + k];
+      const double d = P0[k * ld + k];
       if (!(d > 0.0)) {
         if (tid == 0) fail = 1;
         break;
@@ -966,17 +970,17 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       const double piv = sqrt(d);
       const double inv = 1.0 / piv;
       if (tid == 0) P3[k] = piv;
-      for (int i = k + 1 + tid; i < n; i += nthr) P0[i * n + k] *= inv;
+      for (int i = k + 1 + tid; i < n; i += nthr) P0[i * ld + k] *= inv;
       __syncthreads();
       const int m = n - k - 1;
       for (int t = tid; t < m * m; t += nthr) {
         const int i = k + 1 + t / m, j = k + 1 + t % m;
-        if (j <= i) P0[i * n + j] -= P0[i * n + k] * P0[j * n + k];
+        if (j <= i) P0[i * ld + j] -= P0[i * ld + k] * P0[j * ld + k];
       }
     }
     __syncthreads();
     if (!fail)
-      for (int k = tid; k < n; k += nthr) P0[k * n + k] = P3[k];
+      for (int k = tid; k < n; k += nthr) P0[k * ld + k] = P3[k];
     __syncthreads();
     if (fail) {
       if (tid == 0) cd.scal[S_ERR] = 2.0;
@@ -988,26 +992,26 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     // step and is divided by its pivot.  One barrier per step.
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
-      P2[e] = i == j ? (i == 0 ? 1.0 / P0[0] : 1.0) : 0.0;
+      P2[i * ld + j] = i == j ? (i == 0 ? 1.0 / P0[0] : 1.0) : 0.0;
     }
     __syncthreads();
     for (int j = 0; j + 1 < n; ++j) {
       const int rows = n - 1 - j, cols = j + 1;
       for (int t = tid; t < rows * cols + 1; t += nthr) {
         if (t == rows * cols) {
-          P2[(j + 1) * n + j + 1] = 1.0 / P0[(j + 1) * n + j + 1];
+          P2[(j + 1) * ld + j + 1] = 1.0 / P0[(j + 1) * ld + j + 1];
           continue;
         }
         const int i = j + 1 + t / cols, c = t % cols;
-        double w = P2[i * n + c] - P0[i * n + j] * P2[j * n + c];
-        if (i == j + 1) w /= P0[i * n + i];
-        P2[i * n + c] = w;
+        double w = P2[i * ld + c] - P0[i * ld + j] * P2[j * ld + c];
+        if (i == j + 1) w /= P0[i * ld + i];
+        P2[i * ld + c] = w;
       }
       __syncthreads();
     }
     if (clk && tid == 0) clk[1] = clock64();
     if (mode == 1) {
-      for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * n + e / n];
+      for (int e = tid; e < n * n; e += nthr) cd.M[e] = P2[(e % n) * ld + e / n];
       return;
     }
     if (phase == 1) return;  // W is ready; the products run over the GPU
@@ -1015,25 +1019,25 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
       double s = 0.0;
-      for (int k = 0; k <= i; ++k) s = fma(P2[i * n + k], P1[k * n + j], s);
-      P3[e] = s;
+      for (int k = 0; k <= i; ++k) s = fma(P2[i * ld + k], P1[k * ld + j], s);
+      P3[i * ld + j] = s;
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
       double s = 0.0;
-      for (int k = 0; k <= j; ++k) s = fma(P3[i * n + k], P2[j * n + k], s);
-      P1[e] = s;
+      for (int k = 0; k <= j; ++k) s = fma(P3[i * ld + k], P2[j * ld + k], s);
+      P1[i * ld + j] = s;
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
       if (i < j) {
-        const double a = 0.5 * (P1[i * n + j] + P1[j * n + i]);
-        P1[i * n + j] = a;
-        P1[j * n + i] = a;
+        const double a = 0.5 * (P1[i * ld + j] + P1[j * ld + i]);
+        P1[i * ld + j] = a;
+        P1[j * ld + i] = a;
       }
-      P3[e] = (i == j) ? 1.0 : 0.0;
+      P3[i * ld + j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
     // Cyclic Jacobi with the round-robin ordering of disjoint index pairs.
@@ -1050,7 +1054,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       double v[2] = {0.0, 0.0};
       for (int e = tid; e < n * n; e += nthr) {
         const int i = e / n, j = e % n;
-        const double a = P1[e];
+        const double a = P1[i * ld + j];
         if (i == j) v[1] += a * a;
         else v[0] += a * a;
       }
@@ -1062,7 +1066,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
           int p, q;
           jacobi_pair(r, k, n2, &p, &q);
           double c, sn;
-          jacobi_rot(P1, n, p, q, &c, &sn);
+          jacobi_rot(P1, n, ld, p, q, &c, &sn);
           rp[k] = p;
           rq[k] = q;
           rc[k] = c;
@@ -1078,18 +1082,18 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
           const double cP = rc[P], cQ = rc[Q];
           const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
           const bool p2v = p2 < n, q2v = q2 < n;
-          const double a11 = P1[p1 * n + q1];
-          const double a12 = q2v ? P1[p1 * n + q2] : 0.0;
-          const double a21 = p2v ? P1[p2 * n + q1] : 0.0;
-          const double a22 = (p2v && q2v) ? P1[p2 * n + q2] : 0.0;
+          const double a11 = P1[p1 * ld + q1];
+          const double a12 = q2v ? P1[p1 * ld + q2] : 0.0;
+          const double a21 = p2v ? P1[p2 * ld + q1] : 0.0;
+          const double a22 = (p2v && q2v) ? P1[p2 * ld + q2] : 0.0;
           // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
           const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
           const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
           // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
-          P1[p1 * n + q1] = cQ * b11 - sQ * b12;
-          if (q2v) P1[p1 * n + q2] = sQ * b11 + cQ * b12;
-          if (p2v) P1[p2 * n + q1] = cQ * b21 - sQ * b22;
-          if (p2v && q2v) P1[p2 * n + q2] = sQ * b21 + cQ * b22;
+          P1[p1 * ld + q1] = cQ * b11 - sQ * b12;
+          if (q2v) P1[p1 * ld + q2] = sQ * b11 + cQ * b12;
+          if (p2v) P1[p2 * ld + q1] = cQ * b21 - sQ * b22;
+          if (p2v && q2v) P1[p2 * ld + q2] = sQ * b21 + cQ * b22;
         }
         // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
         // pair P updates rows p1, p2 of P3 (consecutive threads, consecutive i)
@@ -1099,9 +1103,9 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
           const int p1 = rp[P], p2 = rq[P];
           if (sP == 0.0 || p2 >= n) continue;
           const double cP = rc[P];
-          const double vp = P3[p1 * n + i], vq = P3[p2 * n + i];
-          P3[p1 * n + i] = cP * vp - sP * vq;
-          P3[p2 * n + i] = sP * vp + cP * vq;
+          const double vp = P3[p1 * ld + i], vq = P3[p2 * ld + i];
+          P3[p1 * ld + i] = cP * vp - sP * vq;
+          P3[p2 * ld + i] = sP * vp + cP * vq;
         }
         __syncthreads();
       }
@@ -1113,10 +1117,10 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   }
   // ranks of the eigenvalues (ascending, ties by index)
   for (int i = tid; i < n; i += nthr) {
-    const double li = P1[i * n + i];
+    const double li = P1[i * ld + i];
     int rnk = 0;
     for (int j = 0; j < n; ++j) {
-      const double lj = P1[j * n + j];
+      const double lj = P1[j * ld + j];
       if (lj < li || (lj == li && j < i)) ++rnk;
     }
     rank[i] = rnk;
@@ -1127,16 +1131,16 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     for (int e = tid; e < n * n; e += nthr) {
       const int j = e / n, i = e % n;
       double s = 0.0;
-      for (int k = j; k < n; ++k) s = fma(P2[k * n + j], P3[i * n + k], s);
-      P0[e] = s;
+      for (int k = j; k < n; ++k) s = fma(P2[k * ld + j], P3[i * ld + k], s);
+      P0[j * ld + i] = s;
     }
   }
   __syncthreads();
   for (int e = tid; e < n * n; e += nthr) {
     const int j = e / n, i = e % n;
-    cd.M[j * n + rank[i]] = P0[e];
+    cd.M[j * n + rank[i]] = P0[j * ld + i];
   }
-  for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = P1[i * n + i];
+  for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = P1[i * ld + i];
   if (clk && tid == 0) clk[4] = clock64();
 }
 
@@ -1233,7 +1237,7 @@ __global__ void __launch_bounds__(kNT) k_jac_params(const CandDesc* __restrict__
   int p, q;
   jacobi_pair(r, k, n2, &p, &q);
   double c, sn;
-  jacobi_rot(cd.Hs, n, p, q, &c, &sn);
+  jacobi_rot(cd.Hs, n, n, p, q, &c, &sn);
   double* rot = cd.red_part + kJacRot + 4 * k;
   rot[0] = p;
   rot[1] = q;
@@ -1419,7 +1423,7 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   // used while a graph is being captured.
   const int n = L.g.nb_max;
   const int use_lds = n <= 64 ? 1 : 0;
-  size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * n : 0;
+  size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1) : 0;  // rows padded to n + 1
   const int nthr = L.g.sub_threads;
   prof_before("k_subspace", L.stream);
   if (mode == 3 && n >= L.g.jac_grid && L.jac_done && host_sync_allowed()) {
