@@ -1073,39 +1073,45 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
           rs[k] = sn;
         }
         __syncthreads();
-        // every (row pair P, column pair Q) block of the round over all
-        // threads (consecutive threads take consecutive Q of one P)
-        for (int t = tid; t < npair * npair; t += nthr) {
-          const int P = t / npair, Q = t - P * npair;
-          const double sP = rs[P], sQ = rs[Q];
-          if (sP == 0.0 && sQ == 0.0) continue;
-          const double cP = rc[P], cQ = rc[Q];
-          const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
-          const bool p2v = p2 < n, q2v = q2 < n;
-          const double a11 = P1[p1 * ld + q1];
-          const double a12 = q2v ? P1[p1 * ld + q2] : 0.0;
-          const double a21 = p2v ? P1[p2 * ld + q1] : 0.0;
-          const double a22 = (p2v && q2v) ? P1[p2 * ld + q2] : 0.0;
-          // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
-          const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
-          const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
-          // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
-          P1[p1 * ld + q1] = cQ * b11 - sQ * b12;
-          if (q2v) P1[p1 * ld + q2] = sQ * b11 + cQ * b12;
-          if (p2v) P1[p2 * ld + q1] = cQ * b21 - sQ * b22;
-          if (p2v && q2v) P1[p2 * ld + q2] = sQ * b21 + cQ * b22;
-        }
-        // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
-        // pair P updates rows p1, p2 of P3 (consecutive threads, consecutive i)
-        for (int t = tid; t < npair * n; t += nthr) {
-          const int P = t / n, i = t - P * n;
-          const double sP = rs[P];
-          const int p1 = rp[P], p2 = rq[P];
-          if (sP == 0.0 || p2 >= n) continue;
-          const double cP = rc[P];
-          const double vp = P3[p1 * ld + i], vq = P3[p2 * ld + i];
-          P3[p1 * ld + i] = cP * vp - sP * vq;
-          P3[p2 * ld + i] = sP * vp + cP * vq;
+        // the (row pair P, column pair Q) blocks (two rotations each) on the
+        // first half of the threads, consecutive threads taking consecutive
+        // Q of one P; the column pairs of V (one rotation each, twice as
+        // many) on the second half: both halves carry about the same work
+        const int half = nthr / 2;
+        if (tid < half) {
+          for (int t = tid; t < npair * npair; t += half) {
+            const int P = t / npair, Q = t - P * npair;
+            const double sP = rs[P], sQ = rs[Q];
+            if (sP == 0.0 && sQ == 0.0) continue;
+            const double cP = rc[P], cQ = rc[Q];
+            const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
+            const bool p2v = p2 < n, q2v = q2 < n;
+            const double a11 = P1[p1 * ld + q1];
+            const double a12 = q2v ? P1[p1 * ld + q2] : 0.0;
+            const double a21 = p2v ? P1[p2 * ld + q1] : 0.0;
+            const double a22 = (p2v && q2v) ? P1[p2 * ld + q2] : 0.0;
+            // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
+            const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
+            const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
+            // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
+            P1[p1 * ld + q1] = cQ * b11 - sQ * b12;
+            if (q2v) P1[p1 * ld + q2] = sQ * b11 + cQ * b12;
+            if (p2v) P1[p2 * ld + q1] = cQ * b21 - sQ * b22;
+            if (p2v && q2v) P1[p2 * ld + q2] = sQ * b21 + cQ * b22;
+          }
+        } else {
+          // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
+          // pair P updates rows p1, p2 of P3 (consecutive threads, consecutive i)
+          for (int t = tid - half; t < npair * n; t += half) {
+            const int P = t / n, i = t - P * n;
+            const double sP = rs[P];
+            const int p1 = rp[P], p2 = rq[P];
+            if (sP == 0.0 || p2 >= n) continue;
+            const double cP = rc[P];
+            const double vp = P3[p1 * ld + i], vq = P3[p2 * ld + i];
+            P3[p1 * ld + i] = cP * vp - sP * vq;
+            P3[p2 * ld + i] = sP * vp + cP * vq;
+          }
         }
         __syncthreads();
       }
