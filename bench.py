@@ -29,10 +29,15 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
-# FP32 vector arithmetic without packed FP32 instructions (the build turns
-# them off): 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz; the published
-# 157.3 TFLOP/s counts the packed form
+# FP32 vector arithmetic: the published 157.3 TFLOP/s counts packed FP32
+# instructions; without them (the build turns them off) the chip issues
+# 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s
+FP32_PUBLISHED_PEAK_TFLOPS = 157.3
 FP32_ALU_PEAK_TFLOPS = 78.6
+# tolerances of the FP32 bulk form against the FP64 oracle (energy per atom:
+# the metric's gate; forces: the stated FP32 force tolerance)
+E_GATE = 1e-5
+F_GATE = 5e-4
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "c3_population_hbm_counters.txt")
@@ -315,22 +320,17 @@ def main():
     # number of rows (2 per band for the in-place rotation of X, HX and D, 3
     # for the accumulation D -= X C, band + projector rows for the nonlocal
     # apply): the library counts them per launch
+    # the FFT and H psi kernels are rated against HBM with their algorithmic
+    # bytes (sticks and bands read and written once, V_eff once); the plane
+    # passes' FP32 arithmetic is reported beside it against the published
+    # FP32 peak and the non-packed rate the build can issue
     bound, amount, unit = kernel_amount(dominant, geoms[0], prof)
     avg_active = prof["cand_launches"] / max(prof["launches"], 1)
-    hbm_bytes = amount if bound == "hbm" else None
     nxa = active_x_columns(sgo, pop[0])
-    if dominant in ("k_plane_hpsi", "k_plane_density"):
-        # the plane passes are bound by FP32 arithmetic (FFT butterflies in
-        # registers, LDS transposes), not by HBM: roofline against the ALU
-        bound, unit = "alu", "TFLOP/s"
-        amount = plane_alu_flops(dominant, geoms[0], nxa) * avg_active
     avg_s = prof["ms"] * 1e-3 / max(prof["launches"], 1)
     if bound == "hbm":
         ach = amount / avg_s / 1e9
         peak = HBM_PEAK_GBS
-    elif dominant in ("k_plane_hpsi", "k_plane_density"):
-        ach = amount / avg_s / 1e12
-        peak = FP32_ALU_PEAK_TFLOPS
     else:
         ach = amount / avg_s / 1e12
         peak = FP64_PEAK_TFLOPS
@@ -342,9 +342,12 @@ def main():
             "rows_per_candidate_launch": (prof["cand_rows"] / max(prof["cand_launches"], 1)
                                           if dominant in ("k_gemm_acc", "k_gram") else None),
             ("bytes_per_launch" if bound == "hbm" else "flop_per_launch"): amount,
-            "algorithmic_hbm_bytes_per_launch": (hbm_bytes if hbm_bytes is not None else
-                                                 kernel_amount(dominant, geoms[0], prof)[1]),
             "share_of_step": {k: round(v, 4) for k, v in shares.items()}}
+    if dominant in ("k_plane_hpsi", "k_plane_density"):
+        fl = plane_alu_flops(dominant, geoms[0], nxa) * avg_active
+        roof["fp32_alu"] = {"flop_per_launch": fl, "achieved_TFLOPs": fl / avg_s / 1e12,
+                            "frac_of_published_157_3": fl / avg_s / 1e12 / FP32_PUBLISHED_PEAK_TFLOPS,
+                            "frac_of_non_packed_78_6": fl / avg_s / 1e12 / FP32_ALU_PEAK_TFLOPS}
 
     # every candidate kernel against its bound, from its own profiled step
     table = {}
@@ -363,8 +366,9 @@ def main():
             row.update({"bound": "latency (FP64 flops)", "achieved_TFLOPs": round(amt / avg / 1e12, 4)})
         if k in ("k_plane_hpsi", "k_plane_density"):
             fl = plane_alu_flops(k, geoms[0], nxa) * p["cand_launches"] / p["launches"]
-            row.update({"bound": "alu", "alu_TFLOPs": round(fl / avg / 1e12, 2),
-                        "frac_of_fp32_alu_peak": round(fl / avg / 1e12 / FP32_ALU_PEAK_TFLOPS, 3)})
+            row.update({"alu_TFLOPs": round(fl / avg / 1e12, 2),
+                        "frac_of_fp32_published_peak": round(fl / avg / 1e12 / FP32_PUBLISHED_PEAK_TFLOPS, 3),
+                        "frac_of_fp32_non_packed_peak": round(fl / avg / 1e12 / FP32_ALU_PEAK_TFLOPS, 3)})
         table[k] = row
     roof["kernels"] = table
 
@@ -376,6 +380,9 @@ def main():
             ref = json.load(open(p))
             gates.append(abs(E[k] - ref["energy"]) / 13)
             fgates.append(float(np.abs(np.asarray(F[k]) - np.asarray(ref["forces"])).max()))
+    # an evaluation counts only if it converged and, where the oracle's
+    # result is stored, lies within the gates: otherwise no value is reported
+    gate_ok = bool(status_ok and gates and max(gates) <= E_GATE and max(fgates) <= F_GATE)
 
     plain = None
     if not a.no_plain:
@@ -393,7 +400,7 @@ def main():
         cpu = cpu_baseline(pop[0])
 
     out = {"metric": "SCF energy+force evals/sec at |dE|<=1e-5 Ha/atom; batched vs plain, one GPU",
-           "value": value, "unit": "evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+           "value": value if gate_ok else None, "unit": "evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "C3 population, one batched solve per step: 32 x 13-atom "
@@ -404,6 +411,9 @@ def main():
                       "scf_gate": {"dE_per_atom": 1e-5, "density_residual": RHO_GATE},
                       "solver": dict(CLUSTER_MIXING, history=8, mixing="Pulay+Kerker", ncg=3),
                       "launch_schedule": schedule or "library defaults",
+                      "gate": {"passed": gate_ok, "dE_per_atom": E_GATE, "max_dF": F_GATE,
+                               "candidates_with_oracle_result": len(gates),
+                               "measured_if_failed": None if gate_ok else value},
                       "dE_per_atom_vs_oracle": gates, "max_dF_vs_oracle": fgates},
            "plain": plain, "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)

@@ -174,15 +174,24 @@ int sgo_set_cutoff(sgo_ctx* ctx, double ecut, const int fft[3], int nbands,
  * (results still readable). */
 int sgo_scf(sgo_ctx* ctx, const sgo_scf_opts* opts, sgo_scf_info* info);
 
-/* Total free energy and (nullable) its parts after sgo_scf. */
+/* Total free energy and (nullable) its parts after sgo_scf: the energy of
+ * the structure that the evaluation level returns to the relaxation and
+ * search levels (Section 2.1, Fig. 1), at the self-consistent density of
+ * Section 2.4. */
 int sgo_energy(sgo_ctx* ctx, double* etot, sgo_energy_terms* terms);
 
 /* Hellmann-Feynman forces [natoms*3] after sgo_scf (local, nonlocal and
- * Ewald parts; -dF/dR of the free energy at self-consistency). */
+ * Ewald parts; -dF/dR of the free energy at self-consistency): the atomic
+ * forces of the structure that the local relaxations consume (Section 2.1,
+ * Fig. 1; Section 2.3). */
 int sgo_forces(sgo_ctx* ctx, double* forces);
 
-/* Fixed-basis stress after sgo_scf (Appendix A, stress of the plane-wave
- * functional): sigma_ab = (1/Omega) dF/d eps_ab for the homogeneous strain
+/* Fixed-basis stress after sgo_scf.  The paper evaluates energies and
+ * forces only; the stress is this library's addition, the strain derivative
+ * of the same discrete functional, so that the energy of a cell can be
+ * differentiated in its lattice vectors (the 128-atom silicon supercell is
+ * measured with energy, forces and stress).
+ * sigma_ab = (1/Omega) dF/d eps_ab for the homogeneous strain
  * r -> (1 + eps) r of cell and atoms together, at the current Miller set and
  * fixed coefficients and occupations (the Mermin free energy is stationary
  * in both at self-consistency).  Ha/bohr^3, row-major symmetric [3][3]; a
@@ -193,10 +202,14 @@ int sgo_forces(sgo_ctx* ctx, double* forces);
  * structure must have been solved (SGO_ESTATE otherwise). */
 int sgo_stress(sgo_ctx* ctx, double stress[9], double* parts);
 
-/* Eigenvalues [nbands] (ascending) and, if occ != NULL, occupations. */
+/* Eigenvalues [nbands] (ascending) and, if occ != NULL, occupations: the
+ * eps_i of the last subspace diagonalisation of Algorithm 1 at
+ * self-consistency, and the occupations of Section 2.4's output density. */
 int sgo_eigenvalues(sgo_ctx* ctx, double* eig, double* occ);
 
-/* Adjoint of the energy: grad_pos = gE * dE/dR = -gE * F  [natoms*3] and,
+/* Adjoint of the energy (the gradient the relaxations of Section 2.3 follow,
+ * for a caller that differentiates a function of the energy):
+ * grad_pos = gE * dE/dR = -gE * F  [natoms*3] and,
  * if grad_lattice != NULL, gE * dE/dA [3][3] (A rows = lattice vectors) with
  * the Cartesian positions as given held fixed and the Miller set of the
  * current basis held fixed: dE/dA = A^-T (Omega sigma + sum_I R_I F_I^T),
@@ -300,13 +313,20 @@ int sgo_batch_set_stream(sgo_batch* b, void* hip_stream);
 int sgo_batch_set_allocator(sgo_batch* b, void* (*alloc)(size_t bytes, void* user),
                             void (*dealloc)(void* ptr, void* user), void* user);
 int sgo_batch_set_species(sgo_batch* b, int id, const sgo_species* sp);
-/* Append a candidate; *index_out receives its index (add order). */
+/* Append a candidate of the generation's population (Section 2.4, last
+ * paragraph; Section 2.2: the individuals of one DE generation are relaxed
+ * independently); *index_out receives its index (add order).  Arguments as
+ * for sgo_set_cell, sgo_set_atoms and sgo_set_cutoff; SGO_EINVAL on the same
+ * conditions, or when the batch is full. */
 int sgo_batch_add(sgo_batch* b, const double lattice[9], int natoms, const int* species,
                   const double* pos, double ecut, const int fft[3], int nbands,
                   int occ_kind, double sigma, int* index_out);
 /* Move the atoms of candidate i (warm start kept). */
 int sgo_batch_set_atoms(sgo_batch* b, int i, const double* pos);
-/* Solve every candidate.  energies [n], forces [sum natoms*3] in add order,
+/* Solve every candidate: the self-consistent loop of Section 2.4 with the
+ * all-band CG of Algorithm 1, for all candidates of the population at once
+ * (Section 2.4, last paragraph: the relaxations of a generation run side by
+ * side).  energies [n], forces [sum natoms*3] in add order,
  * status [n] per candidate (SGO_OK, SGO_ENOTCONV or SGO_ENUMERIC); any of the
  * three may be NULL.  Returns the worst status. */
 int sgo_batch_scf(sgo_batch* b, const sgo_scf_opts* opts, double* energies, double* forces,

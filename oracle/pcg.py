@@ -177,6 +177,16 @@ def build_preconditioner(lattice, samples, pos):
 
 
 # ------------------------------------------------------------- relaxation
+def pcg_beta(F_new, g_new, F_old, g_old):
+    """Preconditioned Polak-Ribiere coefficient, g = P F:
+    max(0, F_new.(g_new - g_old) / F_old.g_old) (0 when the denominator is
+    not positive)."""
+    den = float(np.sum(F_old * g_old))
+    if den <= 0:
+        return 0.0
+    return max(0.0, float(np.sum(F_new * (g_new - g_old))) / den)
+
+
 def pcg_core(evaluate_fn, x0, make_P, nsteps, refit=1):
     """PCG with the secant line search.  evaluate_fn(x) -> (E, F);
     make_P(samples, x) -> P [3n, 3n].  Returns (energies, x, F)."""
@@ -205,9 +215,7 @@ def pcg_core(evaluate_fn, x0, make_P, nsteps, refit=1):
         if refit > 0 and (step + 1) % refit == 0:
             P = make_P(samples, x)
         g2 = (P @ F2.reshape(-1)).reshape(F2.shape)
-        den = float(np.sum(F * (P @ F.reshape(-1)).reshape(F.shape)))
-        beta = max(0.0, float(np.sum(F2 * (g2 - (P @ F.reshape(-1)).reshape(F.shape)))) / den) \
-            if den > 0 else 0.0
+        beta = pcg_beta(F2, g2, F, (P @ F.reshape(-1)).reshape(F.shape))
         d = g2 + beta * d
         F = F2
         energies.append(E)

@@ -26,6 +26,11 @@ def evaluate(system, positions, **kw):
     return r["energy"], F
 
 
+def pr_beta(F_new, F_old):
+    """Polak-Ribiere coefficient of the next direction, clipped at zero."""
+    return max(0.0, np.sum(F_new * (F_new - F_old)) / np.sum(F_old * F_old))
+
+
 def relax_cg(system, nsteps, **kw):
     x = np.array(system["positions"], dtype=float)
     E, F = evaluate(system, x, **kw)
@@ -45,7 +50,7 @@ def relax_cg(system, nsteps, **kw):
         alpha_prev = a2
         x = x + a2 * d
         E, F2 = evaluate(system, x, **kw)
-        beta = max(0.0, np.sum(F2 * (F2 - F)) / np.sum(F * F))
+        beta = pr_beta(F2, F)
         d = F2 + beta * d
         F = F2
         energies.append(E)

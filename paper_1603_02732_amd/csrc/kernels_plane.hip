@@ -340,7 +340,8 @@ __global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
 
 // Density of one plane summed over a chunk of band pairs,
 // part[chunk][z][y][x] = sum_pairs f_a Re(u)^2 + f_b Im(u)^2 (u = psi_a + i psi_b,
-// unnormalised), accumulated in FP64 in LDS (row stride N1 | 1).
+// unnormalised), accumulated in FP32 in LDS over the chunk's band pairs (row
+// stride N1 | 1); the chunks are summed in FP64 by k_density_finalize.
 template <int N1>
 __device__ __forceinline__ void row_pass_density(const PlaneLds& p, int y, float* acc, double fa,
                                                  double fb) {
