@@ -257,6 +257,25 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
                        double* M, double* eps, int reps, double* ms_per_call,
                        long long* clocks);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): the subspace step of
+ * sgo_subspace_solve on device arrays, with its workspace (descriptor,
+ * status block, working copies of S and H and one more n x n matrix) in a
+ * fixed array of the library on each GPU (about 1.5 MiB, held until the
+ * process ends).  S, H [n*n] (H ignored for mode 1) are device inputs, left
+ * unchanged; M [n*n] and eps [n] (mode 3) are device outputs in the layout
+ * of sgo_subspace_solve; all are owned by the caller.  Work is enqueued on
+ * hip_stream (NULL: the null stream) of `device`.  status (device int,
+ * nullable): when given, the call only enqueues, and *status receives 0 or
+ * SGO_ENUMERIC (S not positive definite) in stream order; when NULL, the
+ * call waits for the stream and returns SGO_ENUMERIC itself.  n must be
+ * 1..256 (SGO_EINVAL otherwise: the workspace holds no more); the solve runs
+ * in one workgroup at every size.  Calls no allocator.  All calls on one GPU
+ * share its workspace, which keeps the last call's contents: calls that
+ * overlap on one GPU (other streams, other host threads) race. */
+int sgo_subspace_solve_noalloc(int device, int n, int mode, const double* S, const double* H,
+                               double* M, double* eps, int* status, void* hip_stream);
+
 /* Launch-schedule tuning (process-wide; read when a solve starts).  Keys:
  * "SGO_GRAM_KC" (K range of one split-K Gram block, multiple of 32),
  * "SGO_SUB_THREADS" (threads of the subspace solver, 64..512),

@@ -157,6 +157,7 @@ def load_library(path=None):
         "sgo_get_tuning": (I, [ctypes.c_char_p]),
         "sgo_subspace_solve": (I, [I, I, I, dp, dp, dp, dp, I, dp,
                                    ctypes.POINTER(ctypes.c_longlong)]),
+        "sgo_subspace_solve_noalloc": (I, [I, I, I, P, P, P, P, P, P]),
         "sgo_profile_begin": (I, [ctypes.c_char_p]),
         "sgo_profile_end": (I, [ip, dp, ctypes.POINTER(ctypes.c_longlong),
                              ctypes.POINTER(ctypes.c_longlong)]),
@@ -426,6 +427,17 @@ def subspace_solve(S, H=None, mode=3, reps=1, device=0, clocks=False):
     if rc != SGO_OK:
         raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
     return M, eps, ms.value, list(clk) if clocks else None
+
+
+def subspace_solve_noalloc(S, H, M, eps, n, mode=3, status=None, stream=None, device=0):
+    """The subspace step on device arrays with the library's fixed workspace
+    (no allocation).  S, H, M, eps, status are device addresses (ints, e.g.
+    tensor.data_ptr()); H may be None for mode 1, status None to wait and
+    raise on failure.  stream: a hipStream_t address or None."""
+    lib = load_library()
+    rc = lib.sgo_subspace_solve_noalloc(device, n, mode, S, H, M, eps, status, stream)
+    if rc != SGO_OK:
+        raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
 
 
 def set_tuning(key, value):

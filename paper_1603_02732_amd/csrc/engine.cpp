@@ -1950,6 +1950,26 @@ int sgo_subspace_solve(int device, int n, int mode, const double* S, const doubl
   });
 }
 
+int sgo_subspace_solve_noalloc(int device, int n, int mode, const double* S, const double* H,
+                               double* M, double* eps, int* status, void* hip_stream) {
+  return guard(nullptr, [&] {
+    if (!S || !M || (mode != 1 && mode != 3) || (mode == 3 && (!H || !eps)))
+      throw Error(SGO_EINVAL, "bad subspace_solve_noalloc arguments");
+    if (n < 1 || n > sgo::kNoAllocMaxN)
+      throw Error(SGO_EINVAL, "subspace_solve_noalloc: n = " + std::to_string(n) +
+                                  " is outside 1.." + std::to_string(sgo::kNoAllocMaxN) +
+                                  " (the size of its fixed workspace)");
+    HIPCHK(hipSetDevice(device));
+    sgo::configure_once(device);
+    const char* env = std::getenv("SGO_SUB_THREADS");
+    const int nthr = env ? std::max(64, std::min(512, std::atoi(env) / 64 * 64)) : 512;
+    const int rc = sgo::subspace_noalloc(device, n, mode, S, H, M, eps, status, SGO_ENUMERIC,
+                                         (hipStream_t)hip_stream, nthr);
+    if (rc != 0) throw Error(SGO_ENUMERIC, "overlap matrix is not positive definite");
+    return SGO_OK;
+  });
+}
+
 int sgo_set_tuning(const char* key, int value) {
   if (!key) return SGO_EINVAL;
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",

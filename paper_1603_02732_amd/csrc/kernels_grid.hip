@@ -10,6 +10,8 @@
 #include "launch.hpp"
 
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 
 namespace sgo {
 
@@ -1474,6 +1476,96 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
     check_launch("k_subspace");
   }
   prof_after("k_subspace", L.stream);
+}
+
+// ------------------------------------------------ allocation-free subspace
+// Workspace of the allocation-free form of the subspace step (for callers
+// that cannot allocate device memory: code under HIP graph capture, serving
+// loops): one fixed device array per GPU holding the solver's descriptor,
+// its status block and working copies of S and H plus the third matrix of
+// the global-memory solver, for up to kNoAllocMaxN bands.  The array lives
+// until the process ends; host code reaches it only through the address that
+// hipGetSymbolAddress returns on each device (the array's name is a
+// host-side stand-in, not a device address).  Every call on a GPU shares
+// that GPU's array: calls that overlap on one GPU race.
+constexpr size_t kNoAllocDescBytes = 1024;
+constexpr size_t kNoAllocScalBytes = 256;
+constexpr size_t kNoAllocMatBytes = (size_t)8 * kNoAllocMaxN * kNoAllocMaxN;
+constexpr size_t kNoAllocBytes = kNoAllocDescBytes + kNoAllocScalBytes + 3 * kNoAllocMatBytes;
+static_assert(sizeof(CandDesc) <= kNoAllocDescBytes, "descriptor slot too small");
+static_assert(S_COUNT * 8 <= kNoAllocScalBytes, "status slot too small");
+static __device__ __align__(256) char scratch[kNoAllocBytes];
+
+namespace {
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[kNoAllocDevices] = {};
+}  // namespace
+
+// Device address of this GPU's workspace array (the device must be current);
+// taken once per device.
+static char* noalloc_workspace(int device) {
+  if (device < 0 || device >= kNoAllocDevices) throw_unsupported("device index out of range");
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[device]) {
+    void* p = nullptr;
+    hip_check(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the subspace workspace");
+    g_noalloc_ptr[device] = (char*)p;
+  }
+  return g_noalloc_ptr[device];
+}
+
+// Descriptor into the workspace, status block cleared, S and H copied into
+// the working matrices (the solver overwrites its inputs).
+__global__ void k_noalloc_stage(CandDesc d, CandDesc* __restrict__ dst, const double* __restrict__ S,
+                                const double* __restrict__ H, int nn) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) *dst = d;
+  if (e < S_COUNT) d.scal[e] = 0.0;
+  if (e < nn) {
+    d.S[e] = S[e];
+    if (H) d.Hs[e] = H[e];
+  }
+}
+
+__global__ void k_noalloc_status(const double* __restrict__ scal, int* __restrict__ status,
+                                 int fail_code) {
+  if (threadIdx.x == 0) *status = scal[S_ERR] != 0.0 ? fail_code : 0;
+}
+
+int subspace_noalloc(int device, int n, int mode, const double* S, const double* H, double* M,
+                     double* eps, int* status, int fail_code, hipStream_t stream, int nthreads) {
+  if (n < 1 || n > kNoAllocMaxN) throw_unsupported("band count outside 1..256 for the allocation-free subspace step");
+  char* ws = noalloc_workspace(device);
+  CandDesc d;
+  memset(&d, 0, sizeof(d));
+  d.nb = n;
+  d.active = 1;
+  d.scal = (double*)(ws + kNoAllocDescBytes);
+  d.S = (double*)(ws + kNoAllocDescBytes + kNoAllocScalBytes);
+  d.Hs = (double*)((char*)d.S + kNoAllocMatBytes);
+  d.C = (double*)((char*)d.Hs + kNoAllocMatBytes);
+  d.M = M;
+  d.eps = eps;
+  CandDesc* dd = (CandDesc*)ws;
+  const int nn = n * n;
+  const int nel = std::max(nn, (int)S_COUNT);
+  hipLaunchKernelGGL(k_noalloc_stage, dim3((nel + kNT - 1) / kNT), dim3(kNT), 0, stream, d, dd, S,
+                     mode == 3 ? H : nullptr, nn);
+  check_launch("k_noalloc_stage");
+  const int use_lds = n <= 64 ? 1 : 0;
+  const size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1) : 0;
+  hipLaunchKernelGGL(k_subspace, dim3(1), dim3(nthreads), lds, stream, dd, mode, use_lds, 40, 0);
+  check_launch("k_subspace");
+  if (status) {
+    hipLaunchKernelGGL(k_noalloc_status, dim3(1), dim3(64), 0, stream, d.scal, status, fail_code);
+    check_launch("k_noalloc_status");
+    return 0;
+  }
+  hip_check(hipStreamSynchronize(stream), "subspace step");
+  double flag = 0.0;
+  hip_check(hipMemcpy(&flag, d.scal + S_ERR, sizeof(double), hipMemcpyDeviceToHost), "status");
+  return flag != 0.0 ? fail_code : 0;
 }
 
 void configure_wave();

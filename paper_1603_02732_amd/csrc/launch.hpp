@@ -65,6 +65,14 @@ template <typename T> void launch_force_nonlocal(const LaunchCtx& L);
 template <typename T> void launch_stress_waves(const LaunchCtx& L);
 template <typename T> void launch_potential_finalize(const LaunchCtx& L);
 void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps = 40);
+// The subspace step with its workspace in a fixed per-device array (no
+// allocation): S, H (mode 3) device inputs [n*n], M [n*n] and eps [n] device
+// outputs; n <= kNoAllocMaxN.  With status != NULL it only enqueues on
+// `stream` and a kernel writes 0 or fail_code to *status; otherwise it waits
+// for the stream and returns 0 or fail_code.
+constexpr int kNoAllocMaxN = 256;
+int subspace_noalloc(int device, int n, int mode, const double* S, const double* H, double* M,
+                     double* eps, int* status, int fail_code, hipStream_t stream, int nthreads);
 void launch_occupations(const LaunchCtx& L);
 void launch_grid_fft(const LaunchCtx& L, int sign);
 void launch_density_finalize(const LaunchCtx& L);
