@@ -143,6 +143,11 @@ CLUSTER_MIXING = {"mix_alpha": 0.3, "kerker_q0": 0.3, "ncg_first": 6}
 # density residual below RHO_GATE (the residual bounds the force error at
 # termination: 3e-4 keeps it well inside the FP32 force tolerance)
 RHO_GATE = 3e-4
+# solver settings of the uneven population: mixing weight 0.3 (the dilute
+# metallic candidates oscillate at the dense-cell default 0.5) and the
+# residual gate on the CG steps (a candidate is converged only when its
+# charged bands are)
+C4_OPTS = dict(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=300, mix_alpha=0.3, cg_tol=1e-4)
 
 CANDIDATE_KERNELS = ("k_plane_hpsi", "k_subspace", "k_gram", "k_gram_reduce", "k_gemm_acc", "k_z_inverse",
                      "k_z_forward", "k_cg_direction", "k_linemin", "k_plane_density")
@@ -219,7 +224,67 @@ def kernel_amount(name, g, prof, tsize=4):
 LEGS = {
     "C4_uneven_population_batched": lambda sgo, wl, sync: c4_run(sgo, wl, sync),
     "C5_large_cell": lambda sgo, wl, sync: c5_run(sgo, wl, sync),
+    "cpu_oracle": lambda sgo, wl, sync: cpu_oracle_run(wl),
 }
+CPU_PROFILE = os.path.join(ROOT, "profiles", "cpu_oracle_baseline.txt")
+
+
+def host_info():
+    """Host cores, CPU model and the numerical libraries the oracle runs on."""
+    import numpy
+    import scipy
+    model = None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    blas = []
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{"api": i.get("internal_api"), "version": i.get("version"),
+                 "threads": i.get("num_threads")} for i in threadpool_info()
+                if i.get("user_api") == "blas"]
+    except Exception:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "cpu_model": model, "numpy": numpy.__version__,
+            "scipy": scipy.__version__, "blas": blas}
+
+
+def _oracle_eval(system, mixing):
+    """One oracle evaluation to the bench's gate (|dE| <= 1e-5 Ha/atom between
+    iterations, density residual below RHO_GATE) plus its forces: seconds,
+    first-iteration seconds, iterations."""
+    from oracle.scf import run_scf
+    from oracle.forces import hf_forces
+    import contextlib
+    nat = len(system["symbols"])
+    t0 = time.perf_counter()
+    # one progress line per oracle iteration, on stderr
+    with contextlib.redirect_stdout(sys.stderr):
+        r = run_scf(system, tol_e=1e-5 * nat, tol_rho=RHO_GATE, verbose=True, **mixing)
+    sys.stderr.flush()
+    hf_forces(r)
+    t = time.perf_counter() - t0
+    tr = r["info"]["trace"]
+    return {"seconds": t, "first_iteration_seconds": tr[0][3], "iterations": r["info"]["iterations"],
+            "energy": r["energy"]}
+
+
+def cpu_oracle_run(wl):
+    """The oracle timed in full on this host: one evaluation of cluster
+    candidate 0 of the population (all cores) and of the Si8 cell (one
+    core), each to the bench's gate with forces."""
+    from threadpoolctl import threadpool_limits
+    mix = {k: CLUSTER_MIXING[k] for k in ("mix_alpha", "kerker_q0")}
+    out = {"host": host_info()}
+    out["C3_candidate0_all_cores"] = _oracle_eval(wl.config_c3(1)[0], mix)
+    with threadpool_limits(1):
+        out["C1_one_core"] = _oracle_eval(wl.config_c1(), {})
+        out["C1_one_core"]["threads"] = 1
+    return out
 
 
 def main():
@@ -253,11 +318,22 @@ def main():
     pop = workloads.config_c3()
     from paper_1603_02732_amd import autotune
     schedule = autotune.lookup(pop, sgo.SGO_FP32)  # tuned launch schedule, if one is stored
-    B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
-    if have_torch:
-        B.set_stream(torch.cuda.current_stream().cuda_stream)
-    for s in pop:
-        B.add_system(s)
+    # the tuner's batch schedule: the population as one batch, or split into
+    # k batches solved at once, each on its own stream from its own host thread
+    nsplit = int(schedule.get("batches", 1)) if schedule else 1
+    if not have_torch:
+        nsplit = 1
+    bounds = [len(pop) * j // nsplit for j in range(nsplit + 1)]
+    streams = [torch.cuda.Stream() for _ in range(nsplit)] if nsplit > 1 else []
+    Bs = []
+    for j in range(nsplit):
+        b = sgo.Batch(bounds[j + 1] - bounds[j], precision=sgo.SGO_FP32)
+        if have_torch:
+            b.set_stream(streams[j].cuda_stream if nsplit > 1
+                         else torch.cuda.current_stream().cuda_stream)
+        for s in pop[bounds[j]:bounds[j + 1]]:
+            b.add_system(s)
+        Bs.append(b)
     opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=150,
                             use_graph=int(schedule["use_graph"]) if schedule else 0,
                             **CLUSTER_MIXING)
@@ -269,8 +345,11 @@ def main():
     geoms = geoms * len(pop)
 
     def step():
-        B.reset()  # cold start: fresh wavefunctions and starting density
-        return B.scf(opts)
+        for b in Bs:
+            b.reset()  # cold start: fresh wavefunctions and starting density
+        if nsplit == 1:
+            return Bs[0].scf(opts)
+        return sgo.batches_scf(Bs, opts)
 
     # warm-up, and the per-kernel share of a step to find the dominant kernel
     for _ in range(a.warmup):
@@ -324,19 +403,24 @@ def main():
     # bytes (sticks and bands read and written once, V_eff once); the plane
     # passes' FP32 arithmetic is reported beside it against the published
     # FP32 peak and the non-packed rate the build can issue
+    # achieved rate: the algorithmic work of all launches over the time during
+    # which at least one of them ran (with concurrent batches, launches on the
+    # two streams overlap; on one stream this is the summed launch time)
     bound, amount, unit = kernel_amount(dominant, geoms[0], prof)
     avg_active = prof["cand_launches"] / max(prof["launches"], 1)
     nxa = active_x_columns(sgo, pop[0])
     avg_s = prof["ms"] * 1e-3 / max(prof["launches"], 1)
+    span_s = prof["union_ms"] * 1e-3 / max(prof["launches"], 1)  # per launch, overlap removed
     if bound == "hbm":
-        ach = amount / avg_s / 1e9
+        ach = amount / span_s / 1e9
         peak = HBM_PEAK_GBS
     else:
-        ach = amount / avg_s / 1e12
+        ach = amount / span_s / 1e12
         peak = FP64_PEAK_TFLOPS
     traffic = counters_traffic(dominant)
     roof = {"bound": bound, "kernel": dominant, "achieved": ach, "peak": peak, "unit": unit,
             "frac": ach / peak, "traffic": traffic, "avg_launch_us": avg_s * 1e6,
+            "union_us_per_launch": span_s * 1e6,
             "launches_per_step": prof["launches"] / a.steps,
             "active_candidates_per_launch": avg_active,
             "rows_per_candidate_launch": (prof["cand_rows"] / max(prof["cand_launches"], 1)
@@ -345,9 +429,9 @@ def main():
             "share_of_step": {k: round(v, 4) for k, v in shares.items()}}
     if dominant in ("k_plane_hpsi", "k_plane_density"):
         fl = plane_alu_flops(dominant, geoms[0], nxa) * avg_active
-        roof["fp32_alu"] = {"flop_per_launch": fl, "achieved_TFLOPs": fl / avg_s / 1e12,
-                            "frac_of_published_157_3": fl / avg_s / 1e12 / FP32_PUBLISHED_PEAK_TFLOPS,
-                            "frac_of_non_packed_78_6": fl / avg_s / 1e12 / FP32_ALU_PEAK_TFLOPS}
+        roof["fp32_alu"] = {"flop_per_launch": fl, "achieved_TFLOPs": fl / span_s / 1e12,
+                            "frac_of_published_157_3": fl / span_s / 1e12 / FP32_PUBLISHED_PEAK_TFLOPS,
+                            "frac_of_non_packed_78_6": fl / span_s / 1e12 / FP32_ALU_PEAK_TFLOPS}
 
     # every candidate kernel against its bound, from its own profiled step
     table = {}
@@ -356,9 +440,10 @@ def main():
         if p["launches"] == 0:
             continue
         kb, amt, ku = kernel_amount(k, geoms[0], p)
-        avg = p["ms"] * 1e-3 / p["launches"]
+        avg = p["union_ms"] * 1e-3 / p["launches"]
         row = {"share_of_step": round(shares[k], 4), "launches": p["launches"],
-               "avg_launch_us": round(avg * 1e6, 2)}
+               "avg_launch_us": round(p["ms"] * 1e3 / p["launches"], 2),
+               "union_us_per_launch": round(avg * 1e6, 2)}
         if kb == "hbm" and amt > 0:
             row.update({"bound": "hbm", "achieved_GBps": round(amt / avg / 1e9, 1),
                         "frac_of_hbm_peak": round(amt / avg / 1e9 / HBM_PEAK_GBS, 3)})
@@ -388,7 +473,7 @@ def main():
     if not a.no_plain:
         plain = plain_runs(sgo, workloads, sync)
         plain["C3_batched_fp32_bf16proj"] = bf16proj_run(sgo, pop, opts, sync)
-        plain["C3_two_batches_two_streams"] = two_stream_run(sgo, pop, opts, sync)
+        plain["C3_one_batch_one_stream"] = one_batch_run(sgo, pop, opts, sync)
         plain["C4_uneven_population_batched"] = c4_run(sgo, workloads, sync)
         plain["C4_relax_5_cg_steps"] = c4_relax_run(sgo, workloads, sync)
         plain["C5_large_cell"] = c5_run(sgo, workloads, sync)
@@ -403,10 +488,13 @@ def main():
            "value": value if gate_ok else None, "unit": "evals/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
            "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": "C3 population, one batched solve per step: 32 x 13-atom "
-                                  "clusters, 24 bohr box, Ecut 10 Ha, FFT 48^3, 32 bands, "
-                                  "s-channel KB, Fermi-Dirac 0.01 Ha, FP32 bulk + FP64 "
-                                  "Cholesky/Rayleigh-Ritz/energy sums",
+           "config": {"workload": "C3 population, one batched solve of all 32 candidates per "
+                                  "step: 32 x 13-atom clusters, 24 bohr box, Ecut 10 Ha, FFT "
+                                  "48^3, 32 bands, s-channel KB, Fermi-Dirac 0.01 Ha, FP32 bulk "
+                                  "+ FP64 Cholesky/Rayleigh-Ritz/energy sums",
+                      "batch_schedule": ("one batch" if nsplit == 1 else
+                                         "%d concurrent batches of %d on %d streams (autotuner's "
+                                         "pick)" % (nsplit, len(pop) // nsplit, nsplit)),
                       "candidates_per_step": len(pop), "all_converged": status_ok,
                       "scf_gate": {"dE_per_atom": 1e-5, "density_residual": RHO_GATE},
                       "solver": dict(CLUSTER_MIXING, history=8, mixing="Pulay+Kerker", ncg=3),
@@ -510,7 +598,7 @@ def c4_run(sgo, workloads, sync):
     B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
     for s in pop:
         B.add_system(s)
-    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=300)
+    opts = sgo.default_opts(**C4_OPTS)
     B.reset()
     B.scf(opts)
     sync()
@@ -521,31 +609,33 @@ def c4_run(sgo, workloads, sync):
     dt = time.perf_counter() - t0
     its = [B.info(i)["iterations"] for i in range(len(pop))]
     B.close()
-    return {"evals_per_s": len(pop) / dt, "ms_per_solve": dt * 1e3,
+    gates = {}
+    for k in range(len(pop)):
+        p = os.path.join(ROOT, "tests", "golden", "C4-%d.json" % k)
+        if os.path.exists(p):
+            ref = json.load(open(p))
+            gates[k] = {"dE_per_atom": abs(E[k] - ref["energy"]) / len(pop[k]["symbols"]),
+                        "max_dF": float(np.abs(np.asarray(F[k]) - np.asarray(ref["forces"])).max())}
+    ok = bool((st == 0).all()) and all(v["dE_per_atom"] <= E_GATE and v["max_dF"] <= F_GATE
+                                       for v in gates.values())
+    return {"evals_per_s": len(pop) / dt if ok else None, "measured_evals_per_s": len(pop) / dt,
+            "ms_per_solve": dt * 1e3, "gate_passed": ok, "oracle_gates": gates,
             "all_converged": bool((st == 0).all()), "scf_iterations_max": max(its),
-            "scf_iterations_mean": float(np.mean(its))}
+            "scf_iterations_mean": float(np.mean(its)), "scf_iterations": its,
+            "solver": C4_OPTS}
 
 
-def two_stream_run(sgo, pop, opts, sync, steps=3):
-    """The same population as two batches of 16 on two streams, solved
-    concurrently from two host threads (sgo_batches_scf): one batch's
-    latency-bound phases overlap the other's throughput kernels."""
+def one_batch_run(sgo, pop, opts, sync, steps=3):
+    """The same population as one batch on one stream (every launch covers
+    all 32 candidates), timed the same way, beside the tuned schedule."""
     import numpy as np
-    import torch
-    half = len(pop) // 2
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
-    Bs = []
-    for sub, stream in ((pop[:half], streams[0]), (pop[half:], streams[1])):
-        b = sgo.Batch(len(sub), precision=sgo.SGO_FP32)
-        b.set_stream(stream.cuda_stream)
-        for s in sub:
-            b.add_system(s)
-        Bs.append(b)
+    B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+    for s in pop:
+        B.add_system(s)
 
     def step():
-        for b in Bs:
-            b.reset()
-        return sgo.batches_scf(Bs, opts)
+        B.reset()
+        return B.scf(opts)
 
     step()
     sync()
@@ -554,15 +644,9 @@ def two_stream_run(sgo, pop, opts, sync, steps=3):
         E, F, st = step()
     sync()
     dt = (time.perf_counter() - t0) / steps
-    gates = []
-    for k in range(len(pop)):
-        p = os.path.join(ROOT, "tests", "golden", "C3-%d.json" % k)
-        if os.path.exists(p):
-            gates.append(abs(E[k] - json.load(open(p))["energy"]) / 13)
-    for b in Bs:
-        b.close()
+    B.close()
     return {"evals_per_s": len(pop) / dt, "ms_per_step": dt * 1e3,
-            "all_converged": bool((st == 0).all()), "dE_per_atom_vs_oracle": gates}
+            "all_converged": bool((st == 0).all())}
 
 
 def c4_relax_run(sgo, workloads, sync, steps=5):
@@ -574,7 +658,7 @@ def c4_relax_run(sgo, workloads, sync, steps=5):
     B = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
     for s in pop:
         B.add_system(s)
-    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=300)
+    opts = sgo.default_opts(**C4_OPTS)
     B.scf(opts)  # allocation
     B.reset()
     sync()
@@ -647,41 +731,39 @@ def plain_runs(sgo, workloads, sync):
 
 def cpu_baseline(system):
     """The FP64 oracle on the host cores, on a bounded sample: the first SCF
-    iteration of candidate 0 of the same population.  Scaled to one
-    evaluation with the oracle's own time profile from its stored converged
-    run of that candidate: (time to the 1e-5 Ha/atom gate) / (time of its
-    first iteration)."""
+    iteration of candidate 0 of the same population, scaled to one whole
+    evaluation (to the gate, with forces) by the ratio measured on the GPU
+    host in full (bench.py --leg cpu_oracle, summary in
+    profiles/cpu_oracle_baseline.txt).  The full measurement itself is
+    reported beside it."""
     from oracle.scf import run_scf
-    ratio, n_gate = None, None
-    p = os.path.join(ROOT, "tests", "golden", "C3-0.json")
-    if os.path.exists(p):
-        ref = json.load(open(p))
-        nat = len(system["symbols"])
-        tr = ref.get("trace", [])
-        if tr and len(tr[0]) > 3:
-            for k, row in enumerate(tr, 1):
-                if row[1] < 1e-5 * nat and row[2] < RHO_GATE:
-                    n_gate = k
-                    ratio = row[3] / tr[0][3]
-                    break
+    full = None
+    if os.path.exists(CPU_PROFILE):
+        for ln in open(CPU_PROFILE):
+            if ln.startswith("{"):
+                full = json.loads(ln)
+                break
     t0 = time.perf_counter()
-    run_scf(system, stop_after=1)
+    run_scf(system, stop_after=1, **{k: CLUSTER_MIXING[k] for k in ("mix_alpha", "kerker_q0")})
     t = time.perf_counter() - t0
-    if ratio is None:
-        ratio = 30.0
-    per_eval = t * ratio
-    threads = os.cpu_count()
-    try:
-        from threadpoolctl import threadpool_info
-        blas = [i["num_threads"] for i in threadpool_info() if i.get("user_api") == "blas"]
-        if blas:
-            threads = max(blas)
-    except Exception:
-        pass
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": threads, "kind": "oracle",
-            "sample": "first oracle SCF iteration of candidate 0 (%.1f s), scaled by %.2f = the "
-                      "oracle's time to the 1e-5 Ha/atom gate (%s iterations) over its first "
-                      "iteration" % (t, ratio, n_gate)}
+    info = host_info()
+    threads = max([b["threads"] for b in info["blas"] if b.get("threads")] or [os.cpu_count()])
+    out = {"unit": "evals/s", "cores": threads, "kind": "oracle", "host": info}
+    if full is not None:
+        c3 = full["C3_candidate0_all_cores"]
+        ratio = c3["seconds"] / c3["first_iteration_seconds"]
+        out["value"] = 1.0 / (t * ratio)
+        out["sample"] = ("first oracle SCF iteration of cluster candidate 0 (%.1f s here), scaled by "
+                         "%.2f = full evaluation / first iteration measured on the GPU host "
+                         "(%.1f s to the gate with forces, %d iterations, %s)"
+                         % (t, ratio, c3["seconds"], c3["iterations"], full["host"].get("cpu_model")))
+        out["measured_full_evaluation_s"] = c3["seconds"]
+        out["measured_value"] = 1.0 / c3["seconds"]
+        out["one_core_si8_evaluation_s"] = full["C1_one_core"]["seconds"]
+    else:
+        out["value"] = None
+        out["sample"] = "first oracle SCF iteration of cluster candidate 0 (%.1f s); no full measurement" % t
+    return out
 
 
 if __name__ == "__main__":

@@ -99,7 +99,22 @@ typedef struct {
                         mix_alpha 0.3) */
   int history;       /* Pulay history length, 2..8 (default 8) */
   unsigned seed;     /* seed of the starting wavefunctions (default 1) */
-  int use_graph;     /* capture one SCF iteration in a HIP graph (default 0) */
+  int use_graph;     /* K >= 1: capture K SCF iterations in one HIP graph and
+                        replay it, structures that converge inside it masking
+                        themselves on the device, the status read back once
+                        per K iterations; 0 (default): eager launches, the
+                        status read after every iteration */
+  double cg_tol;     /* residual gate of the CG steps (Algorithm 1 repeats them
+                        until the residuals meet the convergence condition):
+                        0 (default) runs ncg (ncg_first) steps every SCF
+                        iteration; > 0 lets a structure stop its steps in an
+                        iteration once every band holding charge has
+                        (f/2) |H psi - eps psi| <= max(cg_tol, 0.1 sqrt(|dE|
+                        per atom of the previous iteration)) (Ha; f in [0, 2]
+                        the band's occupation), ncg staying the limit; from
+                        the third iteration of a solve on.  With cg_tol > 0
+                        a structure also counts as converged only when those
+                        weighted residuals are <= max(cg_tol, 0.1 sqrt(tol_e)) */
 } sgo_scf_opts;
 
 typedef struct {
@@ -216,6 +231,26 @@ int sgo_eigenvalues(sgo_ctx* ctx, double* eig, double* occ);
  * from the stress sigma (sgo_stress) and forces. */
 int sgo_adjoint(sgo_ctx* ctx, double gE, double* grad_pos, double* grad_lattice);
 
+/* Brillouin-zone sampling with k-points (Section 2.3 allows "rough
+ * K-points" for the energy evaluations of a search); SGO_FP64 handles only.
+ * kfrac [nk][3]: k in units of the reciprocal lattice vectors
+ * (k = sum_i kfrac_i b_i, b = 2 pi A^-T); weights [nk], positive, normalised
+ * by the library.  Each k has its own shifted sphere |k+G|^2/2 <= Ecut of
+ * complex coefficients (one complex FFT per band, complex Hermitian
+ * subspace matrices); the density sums the k-points with their weights, and
+ * the occupations share one chemical potential (Fermi-Dirac) or fill the
+ * lowest N_el/2 states of every k (fixed).  nk = 0 returns to the
+ * Gamma-point path.  Call after sgo_set_cutoff; sgo_scf, sgo_energy and
+ * sgo_forces then use the k-points (sgo_stress, sgo_eigenvalues and the
+ * lattice gradient of sgo_adjoint return SGO_EINVAL).  SGO_EINVAL for a
+ * non-FP64 handle, non-positive weights or non-finite k; SGO_EINVAL at
+ * sgo_scf when the FFT grid does not hold a k-point's sphere. */
+int sgo_set_kpoints(sgo_ctx* ctx, int nk, const double* kfrac, const double* weights);
+/* Eigenvalues eig [nk][nbands] (ascending per k) and, if occ != NULL, the
+ * occupations of the last k-point solve (the eps_nk of the subspace
+ * diagonalisation of Algorithm 1 at each k); SGO_ESTATE before one. */
+int sgo_kpoint_eigenvalues(sgo_ctx* ctx, double* eig, double* occ);
+
 /* Drop the warm-start wavefunctions and density. */
 int sgo_reset(sgo_ctx* ctx);
 
@@ -298,7 +333,10 @@ int sgo_subspace_solve_noalloc(int device, int n, int mode, const double* S, con
  * default 160), "SGO_PLANE_GROUP" (consecutive z-planes per four-wavefront
  * workgroup of the FP32 register H psi plane kernel, 2..8; 1 = one plane per
  * wavefront; by default the size that keeps the most lanes busy while two
- * groups still share a compute unit's LDS, or 1 where no group saves 10%).
+ * groups still share a compute unit's LDS, or 1 where no group saves 10%),
+ * "SGO_COMPACT" (1, the default: once some candidates of a population have
+ * converged, the SCF iterations launch over the active ones only; 0: every
+ * launch spans the whole population, converged candidates returning at once).
  * value <= 0 restores the default (or the environment variable of the same
  * name).  SGO_EINVAL for an unknown key.  sgo_get_tuning returns the value
  * set (0 if none). */
@@ -318,7 +356,7 @@ int sgo_get_tuning(const char* key);
  * share reads or writes (0 for kernels that do not state it). */
 int sgo_profile_begin(const char* kernel);
 int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches,
-                    long long* cand_rows);
+                    long long* cand_rows, double* union_ms);
 
 /* ---- Population of candidates, solved together (Section 2.4 last
  * paragraph: the relaxations of one generation may run side by side).  The
@@ -440,6 +478,10 @@ int sgo_batch_reset(sgo_batch* b);
  * [N3][N2][N1]; energy terms. */
 int sgo_batch_get_state(sgo_batch* b, int i, int* info, int* millers, double* psi, double* eig,
                         double* occ, double* rho, double* veff, sgo_energy_terms* terms);
+/* Input density of candidate i's last SCF iteration, rho_in [N3][N2][N1]
+ * (the mixed density of Section 2.4 from which the V_eff of
+ * sgo_batch_get_state was built); SGO_ESTATE before a solve. */
+int sgo_batch_get_input_density(sgo_batch* b, int i, double* rho_in);
 /* Fixed-basis stress [n][3][3] of every solved candidate (conventions of
  * sgo_stress); candidates not yet solved get SGO_ESTATE. */
 int sgo_batch_stress(sgo_batch* b, double* stress);

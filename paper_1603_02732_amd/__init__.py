@@ -43,7 +43,8 @@ class sgo_scf_opts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int), ("ncg", ctypes.c_int), ("ncg_first", ctypes.c_int),
                 ("tol_e", ctypes.c_double), ("tol_rho", ctypes.c_double),
                 ("mix_alpha", ctypes.c_double), ("kerker_q0", ctypes.c_double),
-                ("history", ctypes.c_int), ("seed", ctypes.c_uint), ("use_graph", ctypes.c_int)]
+                ("history", ctypes.c_int), ("seed", ctypes.c_uint), ("use_graph", ctypes.c_int),
+                ("cg_tol", ctypes.c_double)]
 
 
 class sgo_scf_info(ctypes.Structure):
@@ -160,7 +161,7 @@ def load_library(path=None):
         "sgo_subspace_solve_noalloc": (I, [I, I, I, P, P, P, P, P, P]),
         "sgo_profile_begin": (I, [ctypes.c_char_p]),
         "sgo_profile_end": (I, [ip, dp, ctypes.POINTER(ctypes.c_longlong),
-                             ctypes.POINTER(ctypes.c_longlong)]),
+                                ctypes.POINTER(ctypes.c_longlong), dp]),
         "sgo_batch_create": (I, [ctypes.POINTER(P), I, I, I]),
         "sgo_batch_destroy": (I, [P]),
         "sgo_batch_set_stream": (I, [P, P]),
@@ -178,6 +179,9 @@ def load_library(path=None):
         "sgo_batch_relax_cg": (I, [P, I, ctypes.POINTER(sgo_scf_opts), dp, dp, dp, ip]),
         "sgo_batch_get_state": (I, [P, I, ip, ip, dp, dp, dp, dp, dp,
                                     ctypes.POINTER(sgo_energy_terms)]),
+        "sgo_set_kpoints": (I, [P, I, dp, dp]),
+        "sgo_kpoint_eigenvalues": (I, [P, dp, dp]),
+        "sgo_batch_get_input_density": (I, [P, I, dp]),
         "sgo_batch_last_error": (ctypes.c_char_p, [P]),
         "sgo_de_mutate": (I, [I, dp, dp, dp, D, D, D, I, D, dp]),
         "sgo_de_cross_plane": (I, [I, ip, dp, dp, dp, dp, dp, ip, dp]),
@@ -217,7 +221,10 @@ def _iptr(a):
 def default_opts(**kw):
     o = sgo_scf_opts()
     load_library().sgo_default_opts(ctypes.byref(o))
+    names = {n for n, _ in sgo_scf_opts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError("unknown SCF option %r" % k)
         setattr(o, k, v)
     return o
 
@@ -329,6 +336,26 @@ class Context:
                          allow=allow)
         return {"status": rc, "iterations": info.iterations, "converged": bool(info.converged),
                 "de": info.de, "drho": info.drho}
+
+    def set_kpoints(self, kfrac, weights):
+        """k-point sampling (FP64 handles): kfrac (nk, 3) in units of the
+        reciprocal lattice vectors, weights (nk,); an empty list returns to
+        the Gamma-point path."""
+        k = np.ascontiguousarray(np.asarray(kfrac, dtype=np.float64).reshape(-1, 3))
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
+        if len(k) != len(w):
+            raise ValueError("one weight per k-point")
+        self.nk = len(k)
+        self._check(self._lib.sgo_set_kpoints(self._h, len(k), _dptr(k) if len(k) else None,
+                                              _dptr(w) if len(w) else None))
+
+    def kpoint_eigenvalues(self):
+        """(eigenvalues, occupations), each (nk, nbands), of the last k-point solve."""
+        nb = self.geometry()["nbands"]
+        e = np.zeros((self.nk, nb))
+        o = np.zeros((self.nk, nb))
+        self._check(self._lib.sgo_kpoint_eigenvalues(self._h, _dptr(e), _dptr(o)))
+        return e, o
 
     def energy(self):
         e = ctypes.c_double()
@@ -463,11 +490,14 @@ def profile_end():
     ms = ctypes.c_double()
     cl = ctypes.c_longlong()
     cr = ctypes.c_longlong()
+    um = ctypes.c_double()
     lib = load_library()
-    rc = lib.sgo_profile_end(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(cl), ctypes.byref(cr))
+    rc = lib.sgo_profile_end(ctypes.byref(n), ctypes.byref(ms), ctypes.byref(cl), ctypes.byref(cr),
+                             ctypes.byref(um))
     if rc != SGO_OK:
         raise SgoError(rc, (lib.sgo_last_error(None) or b"").decode())
-    return {"launches": n.value, "ms": ms.value, "cand_launches": cl.value, "cand_rows": cr.value}
+    return {"launches": n.value, "ms": ms.value, "cand_launches": cl.value, "cand_rows": cr.value,
+            "union_ms": um.value}
 
 
 def _f64(a, shape=None):
@@ -784,8 +814,11 @@ class Batch:
         self._check(self._lib.sgo_batch_get_state(self._h, int(i), None, _iptr(m), _dptr(psi),
                                                   _dptr(eig), _dptr(occ), _dptr(rho),
                                                   _dptr(veff), ctypes.byref(t)))
+        rho_in = np.zeros(ntot)
+        self._check(self._lib.sgo_batch_get_input_density(self._h, int(i), _dptr(rho_in)))
         return {"grid": (N1, N2, N3), "millers": m, "psi": psi, "eig": eig, "occ": occ,
                 "rho": rho.reshape(N3, N2, N1), "veff": veff.reshape(N3, N2, N1),
+                "rho_in": rho_in.reshape(N3, N2, N1),
                 "terms": {n: getattr(t, n) for n, _ in sgo_energy_terms._fields_}}
 
     def relax_cg(self, nsteps, opts=None, **kw):

@@ -20,14 +20,23 @@ from . import set_tuning, default_opts, SGO_ENOTCONV
 
 SPACE = {
     "SGO_PLANE_KERNEL": [1, 2],
+    "SGO_PLANE_GROUP": [1, 2, 3, 4, 5, 6, 8],
     "SGO_GEMM_KERNEL": [1, 2],
     "SGO_GRAM_KERNEL": [1, 2],
     "SGO_GRAM_KC": [256, 512, 1024, 2048],
-    "SGO_SUB_THREADS": [128, 256, 512],
-    "SGO_SP_CHUNK": [4, 8, 13, 20, 32],
+    "SGO_SUB_THREADS": [64, 128, 256, 512],
     "SGO_DENS_CHUNKS": [1, 2, 4, 8],
-    "use_graph": [0, 1],
+    "SGO_RR_SWEEPS": [1, 2],
+    "SGO_JAC_GRID": [96, 160, 100000],
+    "use_graph": [0, 1, 2, 4],
 }
+# keys that only act from some band count on (largest band count of the
+# population must reach it, else the key is not timed)
+MIN_BANDS = {"SGO_JAC_GRID": 96}
+# batch schedule: the population split into this many batches, each on its
+# own stream from its own host thread (sgo_batches_scf), timed as whole
+# solves to the caller's gate
+BATCH_SPLITS = [1, 2, 4]
 # schedules tuned for the standard workloads, shipped with the package and
 # consulted when the user cache has no entry (python -m
 # paper_1603_02732_amd.autotune --write-table regenerates it on the device)
@@ -58,7 +67,7 @@ def _time(batch, opts, reps=2):
 
 def apply(schedule):
     for k, v in schedule.items():
-        if k != "use_graph":
+        if k.startswith("SGO_"):
             set_tuning(k, v)
 
 
@@ -92,19 +101,23 @@ def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False, 
     if use_cache and key in cache:
         apply(cache[key]["schedule"])
         return dict(cache[key]["schedule"], cached=True)
-    sched = {"SGO_PLANE_KERNEL": 0, "SGO_GEMM_KERNEL": 0, "SGO_GRAM_KERNEL": 0, "SGO_GRAM_KC": 0, "SGO_SUB_THREADS": 0,
-             "SGO_SP_CHUNK": 0, "SGO_DENS_CHUNKS": 0, "use_graph": 0}
+    sched = {k: 0 for k in SPACE}
     apply(sched)
 
     def opts():
         # a fixed number of iterations: the stop tests can never be met
-        return default_opts(tol_e=-1.0, tol_rho=-1.0, max_iter=iters,
+        # iters iterations after the first (a graph of K iterations needs
+        # K of them before max_iter)
+        return default_opts(tol_e=-1.0, tol_rho=-1.0, max_iter=iters + 1,
                             use_graph=sched["use_graph"])
 
     batch.scf(opts())  # warm-up (allocation, first-touch)
     base = _time(batch, opts())
     timings = {"default": base}
+    nb_max = max(int(x["nbands"]) for x in systems)
     for name, values in SPACE.items():
+        if nb_max < MIN_BANDS.get(name, 0):
+            continue
         best_v, best_t = sched[name], base
         for v in values:
             trial = dict(sched)
@@ -128,7 +141,53 @@ def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False, 
         cache[key] = out
         with open(path, "w") as f:
             json.dump(cache, f, indent=1)
-    return dict(sched, cached=False)
+    return dict(sched, cached=False, timings=timings, seconds_per_iterations=base)
+
+
+def tune_batch_split(systems, precision, gate_opts, splits=None, reps=2, verbose=False):
+    """Time whole cold solves of the population to the caller's gate, as one
+    batch and split into k batches solved at once on k streams (one host
+    thread each).  Returns (best k, {k: seconds})."""
+    import torch
+    from . import Batch, batches_scf
+    timings = {}
+    for k in splits or BATCH_SPLITS:
+        if k > len(systems):
+            continue
+        bounds = [len(systems) * j // k for j in range(k + 1)]
+        streams = [torch.cuda.Stream() for _ in range(k)]
+        bs = []
+        for j in range(k):
+            b = Batch(bounds[j + 1] - bounds[j], precision=precision)
+            b.set_stream(streams[j].cuda_stream)
+            for x in systems[bounds[j]:bounds[j + 1]]:
+                b.add_system(x)
+            bs.append(b)
+
+        def solve():
+            for b in bs:
+                b.reset()
+            if k == 1:
+                bs[0].scf(gate_opts)
+            else:
+                batches_scf(bs, gate_opts)
+            torch.cuda.synchronize()
+
+        solve()  # warm-up and allocation
+        best = float("inf")
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            solve()
+            best = min(best, time.perf_counter() - t0)
+        for b in bs:
+            b.close()
+        timings[k] = best
+        if verbose:
+            print("autotune batches=%d: %.2f ms" % (k, best * 1e3), flush=True)
+    best_k = min(timings, key=timings.get)
+    if timings[best_k] > 0.98 * timings.get(1, float("inf")):
+        best_k = 1
+    return best_k, timings
 
 
 def _main():
@@ -149,8 +208,23 @@ def _main():
         B = Batch(len(pop), precision=SGO_FP32)
         for s in pop:
             B.add_system(s)
-        res = autotune(B, pop, SGO_FP32, iters=a.iters, use_cache=True, verbose=True,
-                       path=a.table_path if a.write_table else None)
+        res = autotune(B, pop, SGO_FP32, iters=a.iters, use_cache=False, verbose=True)
+        B.close()
+        gate = default_opts(tol_e=1e-5, tol_rho=3e-4, max_iter=150, mix_alpha=0.3, kerker_q0=0.3,
+                            ncg_first=6, use_graph=res["use_graph"])
+        k, tk = tune_batch_split(pop, SGO_FP32, gate, verbose=True)
+        res["batches"] = k
+        path = a.table_path if a.write_table else cache_path()
+        table = _load(path)
+        entry = table.get(key_of(pop, SGO_FP32), {})
+        entry["timings"] = res.pop("timings")
+        entry["seconds_per_%d_iterations" % a.iters] = res.pop("seconds_per_iterations")
+        entry["schedule"] = {kk: v for kk, v in res.items() if kk != "cached"}
+        entry["batch_split_seconds"] = {str(kk): v for kk, v in tk.items()}
+        table[key_of(pop, SGO_FP32)] = entry
+        os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(table, f, indent=1)
         print(name, res, flush=True)
         out[name] = res
     return out

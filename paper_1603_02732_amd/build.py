@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsgo.so")
-SOURCES = ["kernels_wave.hip", "kernels_grid.hip", "kernels_plane.hip", "kernels_proj.hip", "engine.cpp",
+SOURCES = ["kernels_wave.hip", "kernels_grid.hip", "kernels_plane.hip", "kernels_proj.hip", "kernels_kpt.hip",
+           "engine.cpp",
            "de.cpp", "pcg.cpp"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

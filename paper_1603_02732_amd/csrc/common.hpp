@@ -33,6 +33,7 @@ enum Scal {
   S_ETOT = 0, S_EKIN, S_ENL, S_ELOC, S_EH, S_EXC, S_EEW, S_ENTROPY_TERM,
   S_EBAND, S_VRHO, S_DRHO, S_DE, S_EPREV, S_MU, S_ENTROPY, S_CONV,
   S_ERR, S_ITER, S_NHIST, S_NSCF, S_EHARRIS, S_EWRECIP,
+  S_CGSKIP, S_CGHOLD,  // residual gate of the CG steps (set and cleared within an iteration)
   S_COUNT = 32
 };
 
@@ -85,6 +86,7 @@ struct CandDesc {
   double* occ;     // [nb]
   double* gam;     // [nb]  gamma of the previous CG step
   double* bandw;   // [nb]  per-band scratch
+  double* resn;    // [nb]  |H psi - eps psi|^2 of each band at the last CG direction
   // grid side (FP64)
   double* rho_in_r;     // [ntot]
   double* rho_out_r;    // [ntot]

@@ -231,9 +231,11 @@ class Engine {
   }
   ~Engine() {
     (void)hipSetDevice(device_);
+    k_free();
     for (auto& c : cands_) free_cand(c);
     if (d_species_) (void)hipFree(d_species_);
     if (d_desc_) (void)hipFree(d_desc_);
+    if (d_desc_act_) (void)hipFree(d_desc_act_);
     if (d_iter_) (void)hipFree(d_iter_);
     if (d_scal_all_) (void)hipFree(d_scal_all_);
     if (h_scal_all_) (void)hipHostFree(h_scal_all_);
@@ -553,7 +555,7 @@ class Engine {
         {(void**)&d.proj_lm, c.nproj * sizeof(int) + 8}, {(void**)&d.proj_r, c.nproj * sizeof(double) + 8},
         {(void**)&d.S, nb * nb * 8}, {(void**)&d.Hs, nb * nb * 8}, {(void**)&d.M, nb * nb * 8},
         {(void**)&d.C, nbm * nb * 8}, {(void**)&d.eps, nb * 8}, {(void**)&d.occ, nb * 8},
-        {(void**)&d.gam, nb * 8}, {(void**)&d.bandw, nb * 8},
+        {(void**)&d.gam, nb * 8}, {(void**)&d.bandw, nb * 8}, {(void**)&d.resn, nb * 8},
         {(void**)&d.rho_in_r, nt * 8}, {(void**)&d.rho_out_r, nt * 8}, {(void**)&d.veff_r, nt * 8},
         {(void**)&d.zgrid, nt * 16}, {(void**)&d.vloc_G, nt * 16}, {(void**)&d.rho0_G, nt * 16},
         {(void**)&d.rho_out_G, nt * 16}, {(void**)&d.hist_in, kMaxHist * nt * hist_bytes()},
@@ -762,6 +764,55 @@ class Engine {
     return L;
   }
 
+  // Launch context over the active candidates only (the population's tail:
+  // converged candidates would otherwise still fill every launch grid).
+  // The descriptors of the active candidates are uploaded contiguously; the
+  // grid extents are the maxima over them, while every parameter that fixes
+  // a buffer layout (K ranges, density chunks, stick chunks, plane groups,
+  // thread counts) stays that of the whole batch.  act receives the indices.
+  LaunchCtx ctx_active(const BatchGeom& full, std::vector<int>& act) {
+    act.clear();
+    std::vector<CandDesc> h;
+    for (size_t i = 0; i < cands_.size(); ++i)
+      if (cands_[i].d.active) {
+        act.push_back((int)i);
+        h.push_back(cands_[i].d);
+        h.back().ncand_index = (int)i;
+      }
+    if (h.empty()) return ctx(full);
+    if (!d_desc_act_ || desc_act_cap_ < h.size()) {
+      if (d_desc_act_) (void)hipFree(d_desc_act_);
+      HIPCHK(hipMalloc(&d_desc_act_, sizeof(CandDesc) * cands_.size()));
+      desc_act_cap_ = cands_.size();
+    }
+    HIPCHK(hipMemcpyAsync(d_desc_act_, h.data(), sizeof(CandDesc) * h.size(), hipMemcpyHostToDevice,
+                          stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
+    BatchGeom g = full;
+    g.ncand = (int)h.size();
+    g.npair_max = g.nsp_max = g.nb_max = g.nproj_max = g.nat_max = 0;
+    g.N1max = g.N2max = g.N3max = g.ntot_max = g.plane_max = g.K_max = g.pl_sx_max = 0;
+    for (int i : act) {
+      const HostCand& c = cands_[i];
+      g.npair_max = std::max(g.npair_max, c.npair);
+      g.nsp_max = std::max(g.nsp_max, c.nsp);
+      g.nb_max = std::max(g.nb_max, c.nb);
+      g.nproj_max = std::max(g.nproj_max, c.nproj);
+      g.nat_max = std::max(g.nat_max, c.nat);
+      g.N1max = std::max(g.N1max, c.N[0]);
+      g.N2max = std::max(g.N2max, c.N[1]);
+      g.N3max = std::max(g.N3max, c.N[2]);
+      g.ntot_max = std::max(g.ntot_max, c.ntot);
+      g.plane_max = std::max(g.plane_max, c.N[0] * c.N[1]);
+      g.K_max = std::max(g.K_max, c.K);
+      g.pl_sx_max = std::max(g.pl_sx_max, c.pl_sx);
+    }
+    g.nkc_max = (g.K_max + g.kc_len - 1) / g.kc_len;
+    LaunchCtx L = ctx(g);
+    L.desc = d_desc_act_;
+    return L;
+  }
+
   // Build every candidate that needs it and run the per-geometry setup.
   BatchGeom prepare(unsigned seed, int hist) {
     if (cands_.empty()) throw Error(SGO_ESTATE, "no structure set");
@@ -808,13 +859,17 @@ class Engine {
     launch_gemm_acc<T>(L, with_d ? 3 : 2, y, y, M_M, 0.0, 1.0, 0);
   }
 
+  // All-band CG of Algorithm 1: at most ncg steps; with cg_tol > 0 a
+  // candidate stops once its residuals meet the gate (k_cg_gate) and then
+  // gets the full subspace diagonalisation the last step would have given.
   template <typename T>
-  void eigensolver(const LaunchCtx& L, int ncg) {
+  void eigensolver(const LaunchCtx& L, int ncg, double cg_tol) {
     const int inter = tune("SGO_RR_SWEEPS", 1);
     launch_hpsi<T>(L, W_X);
     subspace_rotate<T>(L, false, inter);
     for (int k = 0; k < ncg; ++k) {
       launch_cg_direction<T>(L, k == 0 ? 1 : 0);
+      if (cg_tol > 0.0) launch_cg_gate(L, cg_tol);
       int a[1] = {W_X}, b[1] = {W_D}, o[1] = {M_C};
       launch_gram<T>(L, 1, a, b, o);
       int y[1] = {W_D}, aa[1] = {W_X};
@@ -822,6 +877,11 @@ class Engine {
       launch_hpsi<T>(L, W_D);
       launch_linemin<T>(L);
       subspace_rotate<T>(L, true, k + 1 == ncg ? 40 : inter);
+    }
+    if (cg_tol > 0.0) {
+      launch_cg_release(L, 0);
+      subspace_rotate<T>(L, false, 40);
+      launch_cg_release(L, 1);
     }
   }
 
@@ -862,7 +922,7 @@ class Engine {
   // input potential, solve (Algorithm 1), occupations, output density,
   // residual and Pulay row, energies and convergence flags, advance the
   // device-side iteration counter.  Captured once into a HIP graph when
-  // opts.use_graph is set.
+  // opts.use_graph is set (K iterations per graph for use_graph = K).
   template <typename T>
   void iteration_body(const LaunchCtx& L, const sgo_scf_opts& o) {
     launch_mix(L, 0, o.mix_alpha, o.kerker_q0);
@@ -872,20 +932,22 @@ class Engine {
   }
   template <typename T>
   void iteration_solve(const LaunchCtx& L, const sgo_scf_opts& o, int ncg) {
-    eigensolver<T>(L, ncg);
+    eigensolver<T>(L, ncg, o.cg_tol);
     launch_occupations(L);
     launch_band_kinetic<T>(L);
     launch_density<T>(L);
     launch_density_finalize(L);
     launch_grid_fft(L, -1);
     launch_gspace_residual(L);
-    launch_scf_control(L, o.tol_e, o.tol_rho);
+    launch_scf_control(L, o.tol_e, o.tol_rho, o.cg_tol);
     launch_iter_set(L, d_iter_, 1, 1);
+    launch_mask_done(L);
   }
 
   // Read the status block of every active candidate; mask out the converged
   // and failed ones.  Returns the number still active.
   int update_active(int it) {
+    (void)it;  // per-candidate counts come from the device (S_ITER)
     std::vector<std::array<double, S_COUNT>> sc;
     read_scal(sc);
     bool changed = false;
@@ -893,7 +955,7 @@ class Engine {
     for (size_t i = 0; i < cands_.size(); ++i) {
       HostCand& c = cands_[i];
       if (!c.d.active) continue;
-      c.info.iterations = it + 1;
+      c.info.iterations = (int)sc[i][S_ITER];
       c.info.de = sc[i][S_DE];
       c.info.drho = sc[i][S_DRHO];
       if (sc[i][S_ERR] != 0.0) {
@@ -940,13 +1002,39 @@ class Engine {
     int nactive = update_active(it);
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
-    for (it = 1; it < o.max_iter && nactive > 0; ++it) {
-      if (o.use_graph) {
+    // the iterations launch over the active candidates only once some have
+    // converged (tuning key SGO_COMPACT, 0 = off)
+    const bool compact = tune("SGO_COMPACT", 1) != 0;
+    LaunchCtx Li = L;
+    std::vector<int> act_now, act_prev;
+    // use_graph = K >= 1: K iterations per captured graph (candidates that
+    // converge inside it mask themselves on the device, k_mask_done), the
+    // status read once per K; iterations left over before max_iter run eagerly
+    const int K = std::max(1, o.use_graph);
+    for (it = 1; it < o.max_iter && nactive > 0;) {
+      const int k = (o.use_graph && it + K <= o.max_iter) ? K : 1;
+      if (compact && nactive < (int)cands_.size()) {
+        act_now.clear();
+        for (size_t i = 0; i < cands_.size(); ++i)
+          if (cands_[i].d.active) act_now.push_back((int)i);
+        if (act_now != act_prev) {
+          Li = ctx_active(g, act_prev);
+          if (exec) {
+            (void)hipGraphExecDestroy(exec);
+            exec = nullptr;
+          }
+          if (graph) {
+            (void)hipGraphDestroy(graph);
+            graph = nullptr;
+          }
+        }
+      }
+      if (o.use_graph && k == K) {
         if (!exec) {
           g_capturing = true;
           HIPCHK(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal));
           try {
-            iteration_body<T>(L, o);
+            for (int r = 0; r < K; ++r) iteration_body<T>(Li, o);
           } catch (...) {
             hipGraph_t dummy;
             (void)hipStreamEndCapture(stream_, &dummy);
@@ -959,10 +1047,11 @@ class Engine {
         }
         HIPCHK(hipGraphLaunch(exec, stream_));
       } else {
-        iteration_body<T>(L, o);
+        iteration_body<T>(Li, o);
       }
       HIPCHK(hipGetLastError());
-      nactive = update_active(it);
+      it += k;
+      nactive = update_active(it - 1);
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1006,8 +1095,311 @@ class Engine {
     else stress_t<float>();
   }
 
+  // ---- k-point sampling of one structure (FP64): the "rough K-points"
+  // of Section 2.3.  Each k has its shifted sphere |k+G|^2/2 <= Ecut of
+  // complex coefficients; the grid side (density, potentials, mixing,
+  // energies, local and Ewald forces) is the structure's Gamma setup.
+  struct KPt {
+    double kf[3] = {0, 0, 0};
+    double w = 0;
+    int npw = 0;
+    char* mem = nullptr;
+    KptBands kb{};
+    cplx<double>*X = nullptr, *HX = nullptr, *D = nullptr, *HD = nullptr;
+  };
+  std::vector<KPt> kpts_;
+  char* kshared_ = nullptr;
+  cplx<double>*kz_ = nullptr, *kS_ = nullptr, *kH_ = nullptr, *kW_ = nullptr, *kV_ = nullptr,
+              *kM_ = nullptr, *kC_ = nullptr, *kP_ = nullptr, *kdP_ = nullptr, *ktmp_ = nullptr;
+  double *keps_ = nullptr, *kocc_ = nullptr, *kgam_ = nullptr, *kbandw_ = nullptr, *kw_ = nullptr,
+         *kfnl_ = nullptr;
+  int* kfail_ = nullptr;
+  int k_nb_ = 0;
+  bool k_solved_ = false;
+
+  bool kmode() const { return !kpts_.empty(); }
+  int nkpts() const { return (int)kpts_.size(); }
+
+  void k_free() {
+    for (auto& k : kpts_)
+      if (k.mem) {
+        (void)hipFree(k.mem);
+        k.mem = nullptr;
+      }
+    if (kshared_) (void)hipFree(kshared_);
+    kshared_ = nullptr;
+    k_nb_ = 0;
+  }
+
+  void set_kpoints(int nk, const double* kf, const double* w) {
+    if (nk < 0 || (nk > 0 && (!kf || !w))) throw Error(SGO_EINVAL, "bad k-point arguments");
+    if (nk > 0 && prec_ != SGO_FP64) throw Error(SGO_EINVAL, "k-point sampling needs an SGO_FP64 handle");
+    double tot = 0.0;
+    for (int i = 0; i < nk; ++i) {
+      if (!(w[i] > 0.0)) throw Error(SGO_EINVAL, "k-point weights must be positive");
+      for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(kf[3 * i + a])) throw Error(SGO_EINVAL, "k-point coordinates must be finite");
+      tot += w[i];
+    }
+    HIPCHK(hipSetDevice(device_));
+    HIPCHK(hipDeviceSynchronize());
+    k_free();
+    kpts_.clear();
+    k_solved_ = false;
+    for (int i = 0; i < nk; ++i) {
+      KPt k;
+      for (int a = 0; a < 3; ++a) k.kf[a] = kf[3 * i + a];
+      k.w = w[i] / tot;
+      kpts_.push_back(k);
+    }
+  }
+
+  // Host basis of every k (shifted sphere, grid indices, |k+G|^2/2, k+G)
+  // and the device arrays: per k the basis, projectors and bands; shared
+  // FFT grids, subspace matrices and per-(k, band) scalars.
+  void k_build(HostCand& c) {
+    k_free();
+    const int nb = c.nb, nproj = c.nproj, nk = nkpts();
+    const double gmax = std::sqrt(2.0 * c.ecut);
+    int npw_max = 0;
+    std::vector<std::vector<int>> boxes(nk);
+    std::vector<std::vector<double>> kins(nk), qs(nk);
+    for (int ik = 0; ik < nk; ++ik) {
+      KPt& k = kpts_[ik];
+      int mmax[3];
+      for (int i = 0; i < 3; ++i) {
+        const double an = std::sqrt(c.A[3 * i] * c.A[3 * i] + c.A[3 * i + 1] * c.A[3 * i + 1] +
+                                    c.A[3 * i + 2] * c.A[3 * i + 2]);
+        mmax[i] = (int)std::floor(gmax * an / (2.0 * M_PI) + std::fabs(k.kf[i])) + 1;
+      }
+      for (int m1 = -mmax[0]; m1 <= mmax[0]; ++m1)
+        for (int m2 = -mmax[1]; m2 <= mmax[1]; ++m2)
+          for (int m3 = -mmax[2]; m3 <= mmax[2]; ++m3) {
+            const double f[3] = {m1 + k.kf[0], m2 + k.kf[1], m3 + k.kf[2]};
+            double q[3];
+            for (int a = 0; a < 3; ++a) q[a] = f[0] * c.B[a] + f[1] * c.B[3 + a] + f[2] * c.B[6 + a];
+            const double q2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+            if (0.5 * q2 > c.ecut) continue;
+            const int m[3] = {m1, m2, m3};
+            for (int a = 0; a < 3; ++a)
+              if (2 * std::abs(m[a]) + 1 > c.N[a])
+                throw Error(SGO_EINVAL, "FFT grid too small for the wavefunction sphere at a k-point");
+            const int x = ((m1 % c.N[0]) + c.N[0]) % c.N[0], y = ((m2 % c.N[1]) + c.N[1]) % c.N[1],
+                      z = ((m3 % c.N[2]) + c.N[2]) % c.N[2];
+            boxes[ik].push_back((z * c.N[1] + y) * c.N[0] + x);
+            kins[ik].push_back(0.5 * q2);
+            for (int a = 0; a < 3; ++a) qs[ik].push_back(q[a]);
+          }
+      k.npw = (int)boxes[ik].size();
+      if (k.npw < nb) throw Error(SGO_EINVAL, "fewer plane waves than bands at a k-point");
+      npw_max = std::max(npw_max, k.npw);
+    }
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t zc = sizeof(cplx<double>);
+    for (int ik = 0; ik < nk; ++ik) {
+      KPt& k = kpts_[ik];
+      const size_t n = k.npw;
+      const size_t bytes = al(n * 4) + al(n * 8) + al(n * 24) + al((size_t)nproj * n * zc) + 4 * al((size_t)nb * n * zc);
+      HIPCHK(hipMalloc(&k.mem, bytes));
+      char* p = k.mem;
+      int* box = (int*)p;
+      p += al(n * 4);
+      double* kin = (double*)p;
+      p += al(n * 8);
+      double* q = (double*)p;
+      p += al(n * 24);
+      k.kb.beta = (cplx<double>*)p;
+      p += al((size_t)nproj * n * zc);
+      k.X = (cplx<double>*)p;
+      p += al((size_t)nb * n * zc);
+      k.HX = (cplx<double>*)p;
+      p += al((size_t)nb * n * zc);
+      k.D = (cplx<double>*)p;
+      p += al((size_t)nb * n * zc);
+      k.HD = (cplx<double>*)p;
+      HIPCHK(hipMemcpy(box, boxes[ik].data(), n * 4, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(kin, kins[ik].data(), n * 8, hipMemcpyHostToDevice));
+      HIPCHK(hipMemcpy(q, qs[ik].data(), n * 24, hipMemcpyHostToDevice));
+      k.kb.npw = k.npw;
+      k.kb.nb = nb;
+      k.kb.nproj = nproj;
+      k.kb.box = box;
+      k.kb.kin = kin;
+      k.kb.q = q;
+    }
+    const size_t nbb = (size_t)nb * nb, nkb = (size_t)nk * nb;
+    const size_t pw = std::max<size_t>(nproj, 1) * nb;
+    const size_t bytes = al((size_t)nb * c.ntot * zc) + 6 * al(nbb * zc) + al(pw * zc) + al(3 * pw * zc) +
+                         al((size_t)nb * npw_max * zc) + 4 * al(nkb * 8) + al((size_t)nk * 8) +
+                         al((size_t)3 * c.nat * 8) + al(8);
+    HIPCHK(hipMalloc(&kshared_, bytes));
+    char* p = kshared_;
+    auto take = [&](size_t b) {
+      char* r = p;
+      p += al(b);
+      return r;
+    };
+    kz_ = (cplx<double>*)take((size_t)nb * c.ntot * zc);
+    kS_ = (cplx<double>*)take(nbb * zc);
+    kH_ = (cplx<double>*)take(nbb * zc);
+    kW_ = (cplx<double>*)take(nbb * zc);
+    kV_ = (cplx<double>*)take(nbb * zc);
+    kM_ = (cplx<double>*)take(nbb * zc);
+    kC_ = (cplx<double>*)take(nbb * zc);
+    kP_ = (cplx<double>*)take(pw * zc);
+    kdP_ = (cplx<double>*)take(3 * pw * zc);
+    ktmp_ = (cplx<double>*)take((size_t)nb * npw_max * zc);
+    keps_ = (double*)take(nkb * 8);
+    kocc_ = (double*)take(nkb * 8);
+    kgam_ = (double*)take(nkb * 8);
+    kbandw_ = (double*)take(nkb * 8);
+    kw_ = (double*)take((size_t)nk * 8);
+    kfnl_ = (double*)take((size_t)3 * c.nat * 8);
+    kfail_ = (int*)take(8);
+    std::vector<double> w(nk);
+    for (int ik = 0; ik < nk; ++ik) w[ik] = kpts_[ik].w;
+    HIPCHK(hipMemcpy(kw_, w.data(), nk * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(kfail_, 0, 8));
+    k_nb_ = nb;
+  }
+
+  // Rayleigh-Ritz of one k: S = X^H X, H = X^H HX, Cholesky and complex
+  // Jacobi (k_kpt_subspace), then X, HX (and D) <- . M
+  void k_rr(const HostCand& c, KPt& k, double* eps, bool with_d) {
+    const int nb = c.nb, npw = k.npw;
+    kpt_zdot(stream_, k.X, nb, k.X, nb, npw, kS_, nb, nullptr, 0);
+    kpt_zdot(stream_, k.X, nb, k.HX, nb, npw, kH_, nb, nullptr, 0);
+    kpt_subspace(stream_, kS_, kH_, kW_, kV_, kM_, eps, nb, 3, kfail_);
+    cplx<double>* arr[3] = {k.X, k.HX, k.D};
+    for (int a = 0; a < (with_d ? 3 : 2); ++a) {
+      kpt_zgemm(stream_, arr[a], nb, kM_, nb, ktmp_, nb, npw, 1.0, 0.0, nullptr);
+      kpt_copy(stream_, arr[a], ktmp_, (long)nb * npw);
+    }
+  }
+
+  // Algorithm 1 at one k: H psi, subspace diagonalisation, then ncg steps
+  // of residual, preconditioning, projection, line minimisation and
+  // Rayleigh-Ritz.
+  void k_eigensolve(const HostCand& c, int ik, int ncg) {
+    KPt& k = kpts_[ik];
+    double* eps = keps_ + (size_t)ik * c.nb;
+    double* gam = kgam_ + (size_t)ik * c.nb;
+    kpt_hpsi(stream_, k.kb, k.X, k.HX, kz_, c.d.veff_r, c.N, c.plan, kP_, c.d.hproj);
+    k_rr(c, k, eps, false);
+    for (int st = 0; st < ncg; ++st) {
+      kpt_cg_dir(stream_, k.kb, k.X, k.HX, k.D, eps, gam, st == 0 ? 1 : 0);
+      kpt_zdot(stream_, k.X, c.nb, k.D, c.nb, k.npw, kC_, c.nb, nullptr, 0);
+      kpt_zgemm(stream_, k.X, c.nb, kC_, c.nb, k.D, c.nb, k.npw, -1.0, 1.0, nullptr);
+      kpt_hpsi(stream_, k.kb, k.D, k.HD, kz_, c.d.veff_r, c.N, c.plan, kP_, c.d.hproj);
+      kpt_linemin(stream_, k.kb, k.X, k.HX, k.D, k.HD);
+      k_rr(c, k, eps, true);
+    }
+  }
+
+  // One SCF iteration at the k-points: bands of every k, occupations with
+  // one chemical potential, the k-weighted density into the structure's
+  // density chunk, then the Gamma path's density, residual and control.
+  void k_iteration(const LaunchCtx& L, HostCand& c, const sgo_scf_opts& o, int ncg) {
+    const int nk = nkpts(), nb = c.nb;
+    for (int ik = 0; ik < nk; ++ik) k_eigensolve(c, ik, ncg);
+    kpt_occupations(stream_, keps_, kw_, nk, nb, c.nelec, c.occ_kind, c.sigma, kocc_, c.d.scal);
+    for (int ik = 0; ik < nk; ++ik) kpt_band_kinetic(stream_, kpts_[ik].kb, kpts_[ik].X, kbandw_ + (size_t)ik * nb);
+    kpt_kinetic_total(stream_, kbandw_, kocc_, kw_, nk, nb, c.d.occ, c.d.bandw, c.nb);
+    for (int ik = 0; ik < nk; ++ik) {
+      KPt& k = kpts_[ik];
+      kpt_zero(stream_, kz_, (long)nb * c.ntot);
+      k_density_grid(c, k);
+      kpt_density(stream_, kz_, kocc_ + (size_t)ik * nb, k.w, nb, c.ntot, c.d.dens_part, ik == 0 ? 1 : 0);
+    }
+    launch_density_finalize(L);
+    launch_grid_fft(L, -1);
+    launch_gspace_residual(L);
+    launch_scf_control(L, o.tol_e, o.tol_rho, 0.0);
+    launch_iter_set(L, d_iter_, 1, 1);
+  }
+
+  // u_n(r) of every band of k on the grid (kz_)
+  void k_density_grid(const HostCand& c, KPt& k) {
+    kpt_scatter_bands(stream_, kz_, k.X, k.kb, c.ntot);
+    kpt_fft3(stream_, kz_, c.nb, c.N, c.plan, +1);
+  }
+
+  int scf_k(const sgo_scf_opts& o) {
+    if (cands_.size() != 1) throw Error(SGO_EINVAL, "k-point sampling is for a single structure");
+    const int hist = std::max(2, std::min(kMaxHist, o.history));
+    BatchGeom g = prepare(o.seed, hist);
+    HostCand& c = cands_[0];
+    LaunchCtx L = ctx(g);
+    launch_iter_set(L, d_iter_, 0, 0);
+    setup_geometry<double>(L);
+    k_build(c);
+    for (auto& k : kpts_) kpt_beta(stream_, k.kb, c.d.proj_atom, c.d.proj_lm, c.d.proj_r, c.d.pos, c.omega);
+    // the k density goes into the structure's first density chunk
+    c.d.ndens_chunk = 1;
+    upload_desc();
+    struct RestoreChunks {
+      HostCand& c;
+      ~RestoreChunks() { c.d.ndens_chunk = c.dens_chunks; }
+    } restore{c};
+    for (int ik = 0; ik < nkpts(); ++ik) {
+      KPt& k = kpts_[ik];
+      kpt_init(stream_, k.kb, k.X, o.seed, ik);
+    }
+    launch_mix(L, 1, o.mix_alpha, o.kerker_q0);
+    launch_grid_fft(L, +1);
+    launch_potential_finalize<double>(L);
+    k_iteration(L, c, o, o.ncg_first);
+    HIPCHK(hipGetLastError());
+    int it = 0;
+    int nactive = update_active(it);
+    for (it = 1; it < o.max_iter && nactive > 0; ++it) {
+      launch_mix(L, 0, o.mix_alpha, o.kerker_q0);
+      launch_grid_fft(L, +1);
+      launch_potential_finalize<double>(L);
+      k_iteration(L, c, o, o.ncg);
+      HIPCHK(hipGetLastError());
+      nactive = update_active(it);
+    }
+    int fail = 0;
+    HIPCHK(hipMemcpy(&fail, kfail_, sizeof(int), hipMemcpyDeviceToHost));
+    if (c.d.active) c.status = SGO_ENOTCONV;
+    if (fail) c.status = SGO_ENUMERIC;
+    c.d.active = 1;
+    upload_desc();
+    // forces: local (from rho) + nonlocal at every k + Ewald
+    launch_force_local(L);
+    for (int ik = 0; ik < nkpts(); ++ik) {
+      KPt& k = kpts_[ik];
+      if (c.nproj > 0) {
+        kpt_zdot(stream_, k.kb.beta, c.nproj, k.X, c.nb, k.npw, kP_, c.nb, nullptr, 0);
+        for (int a = 0; a < 3; ++a)
+          kpt_zdot(stream_, k.kb.beta, c.nproj, k.X, c.nb, k.npw, kdP_ + (size_t)a * c.nproj * c.nb, c.nb,
+                   k.kb.q, a);
+      }
+      kpt_force_nl(stream_, kP_, kdP_, c.nproj, c.nb, c.d.hproj, c.d.proj_atom, kocc_ + (size_t)ik * c.nb,
+                   k.w, c.nat, kfnl_, ik == 0 ? 1 : 0);
+    }
+    kpt_force_total(stream_, c.d.force_part, kfnl_, c.d.force_ew, c.nat, c.d.force,
+                    c.d.force_part + 3 * c.nat);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(stream_));
+    c.have_psi = false;  // the Gamma bands were not solved
+    c.have_scf = true;
+    k_solved_ = true;
+    return c.status;
+  }
+
+  void kpoint_eigenvalues(double* eig, double* occ) {
+    if (!k_solved_) throw Error(SGO_ESTATE, "no k-point solve");
+    HIPCHK(hipSetDevice(device_));
+    const size_t n = (size_t)nkpts() * k_nb_;
+    HIPCHK(hipMemcpy(eig, keps_, n * 8, hipMemcpyDeviceToHost));
+    if (occ) HIPCHK(hipMemcpy(occ, kocc_, n * 8, hipMemcpyDeviceToHost));
+  }
+
   int scf(const sgo_scf_opts& o) {
     HIPCHK(hipSetDevice(device_));
+    if (kmode()) return scf_k(o);
     return prec_ == SGO_FP64 ? scf_t<double>(o) : scf_t<float>(o);
   }
 
@@ -1390,6 +1782,15 @@ class Engine {
     alloc_user_ = user;
   }
 
+  // Input density of candidate i's last SCF iteration (the one V_eff was
+  // built from), [N3][N2][N1].
+  void get_input_density(int i, double* rho_in) {
+    HostCand& c = cand(i);
+    require_scf(c);
+    HIPCHK(hipSetDevice(device_));
+    HIPCHK(hipMemcpy(rho_in, c.d.rho_in_r, c.ntot * 8, hipMemcpyDeviceToHost));
+  }
+
   // Host copy of candidate i's state (FP64); any pointer may be null.
   void get_state(int i, int* info, int* millers, double* psi, double* eig, double* occ,
                  double* rho, double* veff, sgo_energy_terms* t) {
@@ -1441,6 +1842,8 @@ class Engine {
   std::vector<HostCand> cands_;
   CandDesc* d_desc_ = nullptr;
   size_t desc_cap_ = 0;
+  CandDesc* d_desc_act_ = nullptr;  // descriptors of the active candidates only
+  size_t desc_act_cap_ = 0;
   int* d_iter_ = nullptr;             // SCF iteration counter (device)
   double* d_scal_all_ = nullptr;
   int* d_jac_done_ = nullptr;  // Jacobi convergence flags [capacity]
@@ -1507,6 +1910,7 @@ void sgo_default_opts(sgo_scf_opts* o) {
   o->max_iter = 100;
   o->ncg = 3;
   o->ncg_first = 8;
+  o->cg_tol = 0.0;
   o->tol_e = 1e-5;
   o->tol_rho = 1e-4;
   o->mix_alpha = 0.5;
@@ -1669,10 +2073,28 @@ int sgo_scf(sgo_ctx* c, const sgo_scf_opts* opts, sgo_scf_info* info) {
     if (!(c->cell && c->atoms && c->cutoff) || c->eng->size() == 0)
       throw Error(SGO_ESTATE, "set species, cell, atoms and cutoff first");
     const sgo_scf_opts o = opts_or_default(opts);
-    if (o.max_iter < 1 || o.ncg < 1 || o.ncg_first < 1) throw Error(SGO_EINVAL, "bad options");
+    if (o.max_iter < 1 || o.ncg < 1 || o.ncg_first < 1 || !(o.cg_tol >= 0.0))
+      throw Error(SGO_EINVAL, "bad options");
     int rc = c->eng->scf(o);
     if (info) *info = c->eng->cand(0).info;
     return rc;
+  });
+}
+
+int sgo_set_kpoints(sgo_ctx* c, int nk, const double* kfrac, const double* weights) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    c->eng->set_kpoints(nk, kfrac, weights);
+    return SGO_OK;
+  });
+}
+
+int sgo_kpoint_eigenvalues(sgo_ctx* c, double* eig, double* occ) {
+  if (!c) return SGO_EINVAL;
+  return guard(&c->err, [&] {
+    if (!eig) throw Error(SGO_EINVAL, "NULL eig");
+    c->eng->kpoint_eigenvalues(eig, occ);
+    return SGO_OK;
   });
 }
 
@@ -1718,6 +2140,7 @@ int sgo_stress(sgo_ctx* c, double stress[9], double* parts) {
   return guard(&c->err, [&] {
     if (!stress) throw Error(SGO_EINVAL, "NULL stress");
     if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    if (c->eng->kmode()) throw Error(SGO_EINVAL, "no stress with k-point sampling");
     auto& hc = c->eng->cand(0);
     c->eng->require_scf(hc);
     c->eng->stress();
@@ -1735,6 +2158,7 @@ int sgo_eigenvalues(sgo_ctx* c, double* eig, double* occ) {
   return guard(&c->err, [&] {
     if (!eig) throw Error(SGO_EINVAL, "NULL eig");
     if (c->eng->size() == 0) throw Error(SGO_ESTATE, "no structure");
+    if (c->eng->kmode()) throw Error(SGO_EINVAL, "k-point sampling: use sgo_kpoint_eigenvalues");
     auto& hc = c->eng->cand(0);
     c->eng->require_scf(hc);
     c->eng->get(hc.d.eps, eig, hc.nb * sizeof(double));
@@ -1753,6 +2177,8 @@ int sgo_adjoint(sgo_ctx* c, double gE, double* grad_pos, double* grad_lattice) {
     std::vector<double> f(3 * hc.nat);
     c->eng->get(hc.d.force, f.data(), f.size() * sizeof(double));
     for (size_t k = 0; k < f.size(); ++k) grad_pos[k] = -gE * f[k];
+    if (grad_lattice && c->eng->kmode())
+      throw Error(SGO_EINVAL, "no lattice gradient with k-point sampling");
     if (grad_lattice) {
       // E(A, R) with Cartesian R held fixed: under r -> (1 + eps) r both A
       // and R move, so (dE/dA)^T A - sum_I F_I R_I^T = Omega sigma, i.e.
@@ -1842,16 +2268,41 @@ int sgo_profile_begin(const char* kernel) {
 }
 
 int sgo_profile_end(int* launches, double* total_ms, long long* cand_launches,
-                    long long* cand_rows) {
+                    long long* cand_rows, double* union_ms) {
   return guard(nullptr, [&] {
     std::lock_guard<std::mutex> lk(sgo::g_prof_mu);
     auto& P = sgo::g_prof;
     double ms = 0.0;
+    std::vector<std::pair<double, double>> iv;
     for (size_t k = 0; k + 1 < P.used; k += 2) {
       HIPCHK(hipEventSynchronize(P.ev[k + 1]));
-      float t = 0.f;
+      float t = 0.f, t0 = 0.f, t1 = 0.f;
       HIPCHK(hipEventElapsedTime(&t, P.ev[k], P.ev[k + 1]));
       ms += t;
+      if (union_ms) {
+        HIPCHK(hipEventElapsedTime(&t0, P.ev[0], P.ev[k]));
+        HIPCHK(hipEventElapsedTime(&t1, P.ev[0], P.ev[k + 1]));
+        iv.emplace_back(t0, t1);
+      }
+    }
+    if (union_ms) {
+      // time during which at least one profiled launch ran (launches of
+      // concurrent batches on other streams overlap)
+      std::sort(iv.begin(), iv.end());
+      double u = 0.0, lo = 0.0, hi = 0.0;
+      bool open = false;
+      for (auto& x : iv) {
+        if (open && x.first <= hi) {
+          hi = std::max(hi, x.second);
+          continue;
+        }
+        if (open) u += hi - lo;
+        lo = x.first;
+        hi = x.second;
+        open = true;
+      }
+      if (open) u += hi - lo;
+      *union_ms = u;
     }
     if (launches) *launches = (int)(P.used / 2);
     if (total_ms) *total_ms = ms;
@@ -1975,7 +2426,7 @@ int sgo_set_tuning(const char* key, int value) {
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
                                 "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
                                 "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL", "SGO_PCG_TRIAL",
-                                "SGO_PCG_FLOOR", "SGO_JAC_GRID", "SGO_PLANE_GROUP"};
+                                "SGO_PCG_FLOOR", "SGO_JAC_GRID", "SGO_PLANE_GROUP", "SGO_COMPACT"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;
@@ -2244,6 +2695,14 @@ int sgo_batch_get_state(sgo_batch* b, int i, int* info, int* millers, double* ps
   if (!b) return SGO_EINVAL;
   return guard(&b->err, [&] {
     b->eng->get_state(i, info, millers, psi, eig, occ, rho, veff, terms);
+    return SGO_OK;
+  });
+}
+
+int sgo_batch_get_input_density(sgo_batch* b, int i, double* rho_in) {
+  if (!b || !rho_in) return SGO_EINVAL;
+  return guard(&b->err, [&] {
+    b->eng->get_input_density(i, rho_in);
     return SGO_OK;
   });
 }

@@ -232,7 +232,8 @@ __global__ void __launch_bounds__(kNT) k_gspace_residual(const CandDesc* __restr
 
 // Pulay coefficients, total free energy, convergence flags (one block per
 // candidate; the work is a few dozen scalars).
-__global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_atom, double tol_rho) {
+__global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_atom, double tol_rho,
+                              double res_tol) {
   const CandDesc& cd = cds[blockIdx.x];
   if (!cd.active) return;
   const IterSlots sl = slots_of(*cd.iter_state, cd.hist_len);
@@ -244,6 +245,7 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
   __shared__ double A[kMaxHist + 1][kMaxHist + 2];
   __shared__ double x[kMaxHist + 1];
   double ekin_w = 0.0;
+  double res_worst = 0.0;
   {
     // block partials of k_density_finalize and k_gspace_residual, summed in
     // a fixed order (one wavefront: lane-strided, then the cross-lane tree)
@@ -263,6 +265,15 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
     double ek = 0.0;
     for (int i = threadIdx.x; i < cd.nb; i += 64) ek += cd.occ[i] * cd.bandw[i];
     ekin_w = wave_sum(ek);
+    // largest squared occupation-weighted residual (last CG direction) of
+    // the bands holding charge, over all 64 lanes before lane 0 goes on alone
+    double rw = 0.0;
+    if (res_tol > 0.0)
+      for (int i = threadIdx.x; i < cd.nb; i += 64)
+        if (cd.occ[i] > 1e-6) rw = fmax(rw, 0.25 * cd.occ[i] * cd.occ[i] * cd.resn[i]);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) rw = fmax(rw, __shfl_xor(rw, o, 64));
+    res_worst = rw;
     if (threadIdx.x != 0) return;
     const double w = cd.omega / cd.ntot;
     sc[S_DRHO] = w * v[0] / fmax(cd.nelec, 1e-30);
@@ -335,7 +346,16 @@ __global__ void k_scf_control(const CandDesc* __restrict__ cds, double tol_e_ato
   sc[S_EPREV] = etot;
   sc[S_ETOT] = etot;
   sc[S_ITER] = iter + 1;
-  sc[S_CONV] = (iter > 0 && de < tol_e_atom * cd.nat && sc[S_DRHO] < tol_rho) ? 1.0 : 0.0;
+  // with a residual gate, self-consistency also asks the bands holding
+  // charge to be eigenvectors of the last V_eff: occupation-weighted
+  // residual (as of the last CG direction) <= max(res_tol, 0.1 sqrt(tol_e
+  // per atom))
+  bool bands_ok = true;
+  if (res_tol > 0.0) {
+    const double tau = fmax(res_tol, 0.1 * sqrt(tol_e_atom));
+    bands_ok = res_worst <= tau * tau;
+  }
+  sc[S_CONV] = (iter > 0 && de < tol_e_atom * cd.nat && sc[S_DRHO] < tol_rho && bands_ok) ? 1.0 : 0.0;
   if (!isfinite(etot) || !isfinite(sc[S_DRHO])) sc[S_ERR] = 1.0;
 }
 
@@ -1352,10 +1372,91 @@ void launch_gather_scal(const LaunchCtx& L, double* out) {
   hipLaunchKernelGGL(k_gather_scal, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, out);
   check_launch("k_gather_scal");
 }
-void launch_scf_control(const LaunchCtx& L, double tol_e_atom, double tol_rho) {
+// Residual gate of the all-band CG steps.  Algorithm 1 repeats its CG steps
+// until the band residuals meet the convergence condition; here a candidate
+// leaves the remaining CG steps of the current SCF iteration once every band
+// holding charge has (f/2) |H psi - eps psi| <= tau (the residual weighted
+// by the band's occupation fraction, which is how far it moves the density
+// and the energy; a band with f near 0 does not hold the others back), with
+// tau = max(tol, 0.1 sqrt(|dE| per atom)) from the previous SCF iteration's
+// energy change (loose while the density still moves, tight near
+// self-consistency).  The candidate's descriptor is masked on the device
+// and S_CGSKIP set; k_cg_release undoes it before the iteration goes on.
+// Not applied before the energy change is known (first two iterations of a
+// solve).
+__global__ void k_cg_gate(CandDesc* __restrict__ cds, double tol) {
+  CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active) return;
+  const double* sc = cd.scal;
+  if (sc[S_ITER] < 2.0) return;
+  const double de = sc[S_DE] / (double)max(cd.nat, 1);
+  const double tau = fmax(tol, 0.1 * sqrt(de));
+  double worst = 0.0;
+  for (int i = threadIdx.x; i < cd.nb; i += 64)
+    if (cd.occ[i] > 1e-6) worst = fmax(worst, 0.25 * cd.occ[i] * cd.occ[i] * cd.resn[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) worst = fmax(worst, __shfl_xor(worst, o, 64));
+  if (threadIdx.x == 0 && worst <= tau * tau) {
+    cd.scal[S_CGSKIP] = 1.0;
+    cd.active = 0;
+  }
+}
+
+// phase 0: candidates that left the CG steps early are unmasked (for their
+// final full subspace diagonalisation) and the ones that ran every step are
+// held (masked, S_CGHOLD); phase 1: the held ones are unmasked.  Candidates
+// masked by the host carry neither flag and stay masked.
+__global__ void k_cg_release(CandDesc* __restrict__ cds, int n, int phase) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  CandDesc& cd = cds[c];
+  double* sc = cd.scal;
+  if (phase == 0) {
+    if (sc[S_CGSKIP] != 0.0) {
+      sc[S_CGSKIP] = 0.0;
+      cd.active = 1;
+    } else if (cd.active) {
+      sc[S_CGHOLD] = 1.0;
+      cd.active = 0;
+    }
+  } else if (sc[S_CGHOLD] != 0.0) {
+    sc[S_CGHOLD] = 0.0;
+    cd.active = 1;
+  }
+}
+
+// A candidate whose SCF has converged (or failed) masks itself on the device
+// for the rest of a captured multi-iteration graph; the host reads the
+// status once per graph and keeps its own mask in step.
+__global__ void k_mask_done(CandDesc* __restrict__ cds, int n) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  CandDesc& cd = cds[c];
+  if (cd.active && (cd.scal[S_CONV] != 0.0 || cd.scal[S_ERR] != 0.0)) cd.active = 0;
+}
+
+void launch_mask_done(const LaunchCtx& L) {
+  hipLaunchKernelGGL(k_mask_done, dim3((L.g.ncand + 63) / 64), dim3(64), 0, L.stream,
+                     const_cast<CandDesc*>(L.desc), L.g.ncand);
+  check_launch("k_mask_done");
+}
+
+void launch_cg_gate(const LaunchCtx& L, double tol) {
+  hipLaunchKernelGGL(k_cg_gate, dim3(L.g.ncand), dim3(64), 0, L.stream, const_cast<CandDesc*>(L.desc),
+                     tol);
+  check_launch("k_cg_gate");
+}
+
+void launch_cg_release(const LaunchCtx& L, int phase) {
+  hipLaunchKernelGGL(k_cg_release, dim3((L.g.ncand + 63) / 64), dim3(64), 0, L.stream,
+                     const_cast<CandDesc*>(L.desc), L.g.ncand, phase);
+  check_launch("k_cg_release");
+}
+
+void launch_scf_control(const LaunchCtx& L, double tol_e_atom, double tol_rho, double res_tol) {
   prof_before("k_scf_control", L.stream);
   hipLaunchKernelGGL(k_scf_control, dim3(L.g.ncand), dim3(64), 0, L.stream, L.desc, tol_e_atom,
-                     tol_rho);
+                     tol_rho, res_tol);
   check_launch("k_scf_control");
   prof_after("k_scf_control", L.stream);
 }
@@ -1575,6 +1676,7 @@ void configure_kernels() {
   allow_lds((const void*)k_subspace);
   configure_wave();
   configure_plane_kernels();
+  configure_kpt_kernels();
 }
 
 }  // namespace sgo

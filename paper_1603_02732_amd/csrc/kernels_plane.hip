@@ -16,6 +16,8 @@
 #include "fft_reg.hpp"
 #include "launch.hpp"
 
+#include <algorithm>
+
 namespace sgo {
 
 #define SGO_LINE_SIZES(X) \
@@ -55,12 +57,12 @@ __device__ __forceinline__ void column_pass(const PlaneLds& p, int lane) {
   for (int k = 0; k < N2; ++k) p.Q[k * p.sx + lane] = w[k];
 }
 
-template <int S>
+template <int S, int NMAX>
 __device__ __forceinline__ void column_pass_rt(const PlaneLds& p, int N2, int lane) {
   switch (N2) {
 #define SGO_CASE(N)              \
   case N:                        \
-    column_pass<N, S>(p, lane); \
+    if constexpr (N <= NMAX) column_pass<N, S>(p, lane); \
     break;
     SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -163,6 +165,7 @@ __device__ __forceinline__ void scatter_sticks(const CandDesc& cd, const PlaneLd
 
 // H psi, local part, of one plane of one band pair: sticks are read, and
 // overwritten by the forward transform of V_eff times the inverse transform.
+template <int NMAX>
 __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __restrict__ cds) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
@@ -173,7 +176,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __rest
   const int lane = threadIdx.x;
   cplx<float>* st = (cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
   scatter_sticks(cd, p, st, lane);
-  column_pass_rt<+1>(p, cd.N2, lane);
+  column_pass_rt<+1, NMAX>(p, cd.N2, lane);
   __syncthreads();
   // strides re-declared opaque between phases: per-line offsets are then
   // recomputed in each phase instead of being held across all of them
@@ -183,7 +186,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __rest
     switch (cd.N1) {
 #define SGO_CASE(N)                       \
   case N:                                 \
-    row_pass_hpsi<N>(p, lane, V);         \
+    if constexpr (N <= NMAX) row_pass_hpsi<N>(p, lane, V);         \
     break;
       SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -193,7 +196,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __rest
   }
   __syncthreads();
   asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
-  column_pass_rt<-1>(p, cd.N2, lane);
+  column_pass_rt<-1, NMAX>(p, cd.N2, lane);
   __syncthreads();
   for (int s0 = lane; s0 < cd.nst; s0 += 256) {
     int xy[4];
@@ -214,6 +217,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __rest
 // k_plane_hpsi_reg; the planes lie one after another in LDS, each compact
 // (N2 rows of stride sx).
 constexpr int kPlaneGroupThreads = 256;
+constexpr int kPlaneGroupMax = 8;  // largest group (SGO_PLANE_GROUP)
 
 template <int N2, int S>
 __device__ __forceinline__ void column_lines(cplx<float>* Q0, int pstride, int sx, int nx, int nlines,
@@ -234,13 +238,13 @@ __device__ __forceinline__ void column_lines(cplx<float>* Q0, int pstride, int s
   }
 }
 
-template <int S>
+template <int S, int NMAX>
 __device__ __forceinline__ void column_lines_rt(cplx<float>* Q0, int pstride, int sx, int nx, int N2,
                                                 int nlines, int tid) {
   switch (N2) {
 #define SGO_CASE(N)                                                 \
   case N:                                                           \
-    column_lines<N, S>(Q0, pstride, sx, nx, nlines, tid);           \
+    if constexpr (N <= NMAX) column_lines<N, S>(Q0, pstride, sx, nx, nlines, tid);           \
     break;
     SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -262,6 +266,7 @@ __device__ __forceinline__ void row_lines_hpsi(const PlaneLds& p0, int pstride, 
   }
 }
 
+template <int NMAX>
 __global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
     const CandDesc* __restrict__ cds, int group) {
   const CandDesc& cd = cds[blockIdx.z];
@@ -279,6 +284,8 @@ __global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
   // stick positions are read once per batch and serve every plane
   for (int e = tid; e < np * pstride; e += kPlaneGroupThreads) p.Q[e] = {0.f, 0.f};
   __syncthreads();
+  // every plane's stick values of a batch are loaded before any is stored,
+  // so the group waits for one memory latency per batch, not one per plane
   for (int s0 = tid; s0 < nst; s0 += 4 * kPlaneGroupThreads) {
     int off[4];
 #pragma unroll
@@ -287,20 +294,22 @@ __global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
       const int xy = s < nst ? cd.stick_xy[s] : 0;
       off[u] = (xy >> 16) * p.sx + col_of_x(p, N1, xy & 0xFFFF);
     }
-    for (int j = 0; j < np; ++j) {
-      cplx<float> v[4];
+    cplx<float> v[kPlaneGroupMax][4];
+#pragma unroll
+    for (int j = 0; j < kPlaneGroupMax; ++j)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int s = s0 + kPlaneGroupThreads * u;
-        v[u] = s < nst ? st[(size_t)j * nst + s] : cplx<float>{0.f, 0.f};
+        v[j][u] = (j < np && s < nst) ? st[(size_t)j * nst + s] : cplx<float>{0.f, 0.f};
       }
 #pragma unroll
+    for (int j = 0; j < kPlaneGroupMax; ++j)
+#pragma unroll
       for (int u = 0; u < 4; ++u)
-        if (s0 + kPlaneGroupThreads * u < nst) p.Q[j * pstride + off[u]] = v[u];
-    }
+        if (j < np && s0 + kPlaneGroupThreads * u < nst) p.Q[j * pstride + off[u]] = v[j][u];
   }
   __syncthreads();
-  column_lines_rt<+1>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
+  column_lines_rt<+1, NMAX>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
   __syncthreads();
   asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
   {
@@ -308,7 +317,7 @@ __global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
     switch (N1) {
 #define SGO_CASE(N)                                              \
   case N:                                                        \
-    row_lines_hpsi<N>(p, pstride, N2, np * N2, V0, tid);         \
+    if constexpr (N <= NMAX) row_lines_hpsi<N>(p, pstride, N2, np * N2, V0, tid);         \
     break;
       SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -318,7 +327,7 @@ __global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
   }
   __syncthreads();
   asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
-  column_lines_rt<-1>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
+  column_lines_rt<-1, NMAX>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
   __syncthreads();
   for (int s0 = tid; s0 < nst; s0 += 4 * kPlaneGroupThreads) {
     int off[4];
@@ -363,6 +372,7 @@ __device__ __forceinline__ void row_pass_density(const PlaneLds& p, int y, float
   });
 }
 
+template <int NMAX>
 __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __restrict__ cds) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
@@ -384,7 +394,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __r
     asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
     const cplx<float>* st = (const cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
     scatter_sticks(cd, p, st, lane);
-    column_pass_rt<+1>(p, N2, lane);
+    column_pass_rt<+1, NMAX>(p, N2, lane);
     __syncthreads();
     const double fa = cd.occ[2 * pair];
     const double fb = 2 * pair + 1 < cd.nb ? cd.occ[2 * pair + 1] : 0.0;
@@ -392,7 +402,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __r
       switch (N1) {
 #define SGO_CASE(N)                                   \
   case N:                                             \
-    row_pass_density<N>(p, lane, acc, fa, fb);        \
+    if constexpr (N <= NMAX) row_pass_density<N>(p, lane, acc, fa, fb);        \
     break;
         SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -448,6 +458,7 @@ __device__ __forceinline__ ZChunk zchunk(const CandDesc& cd, int c) {
   return z;
 }
 
+template <int NMAX>
 __global__ void __launch_bounds__(64, 2) k_z_inverse_reg(const CandDesc* __restrict__ cds, int src) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
@@ -495,7 +506,7 @@ __global__ void __launch_bounds__(64, 2) k_z_inverse_reg(const CandDesc* __restr
     switch (N3) {
 #define SGO_CASE(N)                                  \
   case N:                                            \
-    zline_inv<N>(A + lane * S, out, cd.nst);         \
+    if constexpr (N <= NMAX) zline_inv<N>(A + lane * S, out, cd.nst);         \
     break;
       SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -505,6 +516,7 @@ __global__ void __launch_bounds__(64, 2) k_z_inverse_reg(const CandDesc* __restr
   }
 }
 
+template <int NMAX>
 __global__ void __launch_bounds__(64, 2) k_z_forward_reg(const CandDesc* __restrict__ cds, int src,
                                                          int dst) {
   const CandDesc& cd = cds[blockIdx.z];
@@ -520,7 +532,7 @@ __global__ void __launch_bounds__(64, 2) k_z_forward_reg(const CandDesc* __restr
     switch (N3) {
 #define SGO_CASE(N)                                  \
   case N:                                            \
-    zline_fwd<N>(in, cd.nst, A + lane * S);          \
+    if constexpr (N <= NMAX) zline_fwd<N>(in, cd.nst, A + lane * S);          \
     break;
       SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -581,11 +593,22 @@ __global__ void __launch_bounds__(64, 2) k_z_forward_reg(const CandDesc* __restr
 size_t z_reg_lds(const BatchGeom& g) {
   return (size_t)2 * kZPairs * (g.N3max | 1) * sizeof(cplx<float>);
 }
+// Largest line length a launch must handle: 48 or 64.  The kernels carry
+// the line transforms of every length up to it; the 64 class holds the
+// longest register-resident lines (and the registers they need), so a
+// population whose lines all fit 48 runs the lighter instantiation.
+static bool small_lines(const BatchGeom& g) {
+  return std::max(g.N1max, std::max(g.N2max, g.N3max)) <= 48;
+}
+
 void launch_z_inverse_reg(const LaunchCtx& L, int src) {
   const BatchGeom& g = L.g;
   dim3 gz((g.nsp_max + kZPairs - 1) / kZPairs, g.npair_max, g.ncand);
   prof_before("k_z_inverse", L.stream);
-  hipLaunchKernelGGL(k_z_inverse_reg, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src);
+  if (small_lines(g))
+    hipLaunchKernelGGL(k_z_inverse_reg<48>, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src);
+  else
+    hipLaunchKernelGGL(k_z_inverse_reg<64>, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src);
   check_launch("k_z_inverse");
   prof_after("k_z_inverse", L.stream);
 }
@@ -593,7 +616,10 @@ void launch_z_forward_reg(const LaunchCtx& L, int src, int dst) {
   const BatchGeom& g = L.g;
   dim3 gz((g.nsp_max + kZPairs - 1) / kZPairs, g.npair_max, g.ncand);
   prof_before("k_z_forward", L.stream);
-  hipLaunchKernelGGL(k_z_forward_reg, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src, dst);
+  if (small_lines(g))
+    hipLaunchKernelGGL(k_z_forward_reg<48>, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src, dst);
+  else
+    hipLaunchKernelGGL(k_z_forward_reg<64>, gz, dim3(64), z_reg_lds(g), L.stream, L.desc, src, dst);
   check_launch("k_z_forward");
   prof_after("k_z_forward", L.stream);
 }
@@ -619,7 +645,7 @@ int plane_group_size(const BatchGeom& g, size_t lds_per_cu, int forced) {
   const double single = 2.0 * rounds(nx, 64) + 2.0 * rounds(N2, 64);
   int best = 1;
   double best_t = single;
-  for (int P = 2; P <= 8; ++P) {
+  for (int P = 2; P <= kPlaneGroupMax; ++P) {
     if (2 * plane_group_lds(g, P) > lds_per_cu) break;
     const double t = 4.0 * (2 * rounds(P * nx, kPlaneGroupThreads) +
                             2 * rounds(P * N2, kPlaneGroupThreads)) / P;
@@ -637,11 +663,18 @@ void launch_plane_hpsi_reg(const LaunchCtx& L) {
   prof_before("k_plane_hpsi", L.stream);
   if (g.plane_group > 1) {
     dim3 gp((g.N3max + g.plane_group - 1) / g.plane_group, g.npair_max, g.ncand);
-    hipLaunchKernelGGL(k_plane_hpsi_group, gp, dim3(kPlaneGroupThreads),
-                       plane_group_lds(g, g.plane_group), L.stream, L.desc, g.plane_group);
+    if (small_lines(g))
+      hipLaunchKernelGGL(k_plane_hpsi_group<48>, gp, dim3(kPlaneGroupThreads),
+                         plane_group_lds(g, g.plane_group), L.stream, L.desc, g.plane_group);
+    else
+      hipLaunchKernelGGL(k_plane_hpsi_group<64>, gp, dim3(kPlaneGroupThreads),
+                         plane_group_lds(g, g.plane_group), L.stream, L.desc, g.plane_group);
   } else {
     dim3 gp(g.N3max, g.npair_max, g.ncand);
-    hipLaunchKernelGGL(k_plane_hpsi_reg, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
+    if (small_lines(g))
+      hipLaunchKernelGGL(k_plane_hpsi_reg<48>, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
+    else
+      hipLaunchKernelGGL(k_plane_hpsi_reg<64>, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
   }
   check_launch("k_plane_hpsi");
   prof_after("k_plane_hpsi", L.stream);
@@ -651,17 +684,25 @@ void launch_plane_density_reg(const LaunchCtx& L) {
   const BatchGeom& g = L.g;
   dim3 gp(g.N3max, g.dens_chunks, g.ncand);
   prof_before("k_plane_density", L.stream);
-  hipLaunchKernelGGL(k_plane_density_reg, gp, dim3(64), plane_reg_lds(g, true), L.stream, L.desc);
+  if (small_lines(g))
+    hipLaunchKernelGGL(k_plane_density_reg<48>, gp, dim3(64), plane_reg_lds(g, true), L.stream, L.desc);
+  else
+    hipLaunchKernelGGL(k_plane_density_reg<64>, gp, dim3(64), plane_reg_lds(g, true), L.stream, L.desc);
   check_launch("k_plane_density");
   prof_after("k_plane_density", L.stream);
 }
 
 void configure_plane_kernels() {
-  allow_lds((const void*)k_plane_hpsi_reg);
-  allow_lds((const void*)k_plane_hpsi_group);
-  allow_lds((const void*)k_plane_density_reg);
-  allow_lds((const void*)k_z_inverse_reg);
-  allow_lds((const void*)k_z_forward_reg);
+  allow_lds((const void*)k_plane_hpsi_reg<48>);
+  allow_lds((const void*)k_plane_hpsi_group<48>);
+  allow_lds((const void*)k_plane_density_reg<48>);
+  allow_lds((const void*)k_z_inverse_reg<48>);
+  allow_lds((const void*)k_z_forward_reg<48>);
+  allow_lds((const void*)k_plane_hpsi_reg<64>);
+  allow_lds((const void*)k_plane_hpsi_group<64>);
+  allow_lds((const void*)k_plane_density_reg<64>);
+  allow_lds((const void*)k_z_inverse_reg<64>);
+  allow_lds((const void*)k_z_forward_reg<64>);
 }
 
 }  // namespace sgo

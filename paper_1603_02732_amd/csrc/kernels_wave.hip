@@ -702,14 +702,16 @@ __global__ void __launch_bounds__(kNT) k_cg_direction(const CandDesc* __restrict
   block_sum<1>(v1, sh);
   const double ek = fmax(v1[0], 1e-8);
   const double e = cd.eps[i];
-  double v2[1] = {0.0};
+  double v2[2] = {0.0, 0.0};
   for (int k = threadIdx.x; k < K; k += blockDim.x) {
     const double r = (double)hx[k] - e * (double)x[k];
     const double g = tpa(cd.kin[k >> 1] / ek) * r;
     v2[0] += g * r;
+    v2[1] += r * r;
   }
-  block_sum<1>(v2, sh);
+  block_sum<2>(v2, sh);
   const double gam = v2[0];
+  if (threadIdx.x == 0) cd.resn[i] = v2[1];
   double beta = 0.0;
   if (!first) {
     const double gp = cd.gam[i];
@@ -838,7 +840,7 @@ __global__ void __launch_bounds__(kBandNT) k_cg_direction_r(const CandDesc* __re
   if (!cd.active) return;
   const int i = blockIdx.x;
   if (i >= cd.nb) return;
-  __shared__ double sh[16];
+  __shared__ double sh[16 * 2];
   const int Kp = cd.Kp, npwh = cd.npwh;
   const float* x = (const float*)cd.X + (size_t)i * Kp;
   const float* hx = (const float*)cd.HX + (size_t)i * Kp;
@@ -862,19 +864,22 @@ __global__ void __launch_bounds__(kBandNT) k_cg_direction_r(const CandDesc* __re
   const double ek = fmax(v[0], 1e-8);
   const float e = (float)cd.eps[i];
   const float iek = (float)(1.0 / ek);
-  double w[1] = {0.0};
+  double w[2] = {0.0, 0.0};
 #pragma unroll
   for (int j = 0; j < J; ++j) {
     // residual r = H x - e x, preconditioned g = K(|G|^2/2 / ek) r
     R[j] = make_float4(R[j].x - e * X[j].x, R[j].y - e * X[j].y, R[j].z - e * X[j].z,
                        R[j].w - e * X[j].w);
+    const double ra = (double)R[j].x * R[j].x + (double)R[j].y * R[j].y;
+    const double rb = (double)R[j].z * R[j].z + (double)R[j].w * R[j].w;
     const float ka = (float)tpa((double)(KN[j].x * iek)), kb = (float)tpa((double)(KN[j].y * iek));
-    w[0] += (double)ka * ((double)R[j].x * R[j].x + (double)R[j].y * R[j].y) +
-            (double)kb * ((double)R[j].z * R[j].z + (double)R[j].w * R[j].w);
+    w[0] += (double)ka * ra + (double)kb * rb;
+    w[1] += ra + rb;
     R[j] = make_float4(ka * R[j].x, ka * R[j].y, kb * R[j].z, kb * R[j].w);
   }
-  block_sum<1>(w, sh);
+  block_sum<2>(w, sh);
   const double gam = w[0];
+  if (threadIdx.x == 0) cd.resn[i] = w[1];
   float beta = 0.f;
   if (!first) {
     const double gp = cd.gam[i];

@@ -77,7 +77,15 @@ void launch_occupations(const LaunchCtx& L);
 void launch_grid_fft(const LaunchCtx& L, int sign);
 void launch_density_finalize(const LaunchCtx& L);
 void launch_gspace_residual(const LaunchCtx& L);
-void launch_scf_control(const LaunchCtx& L, double tol_e_atom, double tol_rho);
+// res_tol > 0: convergence also needs the charged bands' residuals at the
+// gate (max(res_tol, 0.1 sqrt(tol_e_atom))).
+void launch_scf_control(const LaunchCtx& L, double tol_e_atom, double tol_rho, double res_tol);
+// Residual gate of the CG steps (masks candidates whose bands meet the
+// residual condition, device side) and its release (phase 0, then 1).
+void launch_cg_gate(const LaunchCtx& L, double tol);
+// Converged or failed candidates masked on the device (multi-iteration graphs).
+void launch_mask_done(const LaunchCtx& L);
+void launch_cg_release(const LaunchCtx& L, int phase);
 void launch_iter_set(const LaunchCtx& L, int* state, int value, int add);
 void launch_mix(const LaunchCtx& L, int initial, double alpha, double q0);
 void launch_setup_grid(const LaunchCtx& L);
@@ -101,6 +109,47 @@ void launch_plane_density_reg(const LaunchCtx& L);
 void launch_z_inverse_reg(const LaunchCtx& L, int src);
 void launch_z_forward_reg(const LaunchCtx& L, int src, int dst);
 void configure_plane_kernels();
+// ---- k-point sampling (kernels_kpt.hip): complex bands on the shifted
+// sphere |k+G|^2/2 <= Ecut of one k-point, FP64
+struct KptBands {
+  int npw, nb, nproj;
+  const int* box;        // [npw] index of each coefficient in the [N3][N2][N1] grid
+  const double* kin;     // [npw] |k+G|^2 / 2
+  const double* q;       // [npw][3] k + G (Cartesian, bohr^-1)
+  cplx<double>* beta;    // [nproj][npw] projectors at k + G
+};
+void kpt_zero(hipStream_t s, cplx<double>* a, long n);
+void kpt_scatter_bands(hipStream_t s, cplx<double>* zk, const cplx<double>* X, const KptBands& kb, long ntot);
+void kpt_fft3(hipStream_t s, cplx<double>* zk, int nb, const int N[3], const FftPlan* plans, int sign);
+void kpt_hpsi(hipStream_t s, const KptBands& kb, const cplx<double>* X, cplx<double>* Y, cplx<double>* zk,
+              const double* veff, const int N[3], const FftPlan* plans, cplx<double>* P, const double* h);
+void kpt_zdot(hipStream_t s, const cplx<double>* A, int na, const cplx<double>* B, int nbb, int npw,
+              cplx<double>* C, int ldc, const double* q, int qa);
+void kpt_zgemm(hipStream_t s, const cplx<double>* X, int nx, const cplx<double>* M, int ldm, cplx<double>* Y,
+               int ny, int npw, double alpha, double beta, const double* h);
+void kpt_copy(hipStream_t s, cplx<double>* dst, const cplx<double>* src, long n);
+void kpt_beta(hipStream_t s, const KptBands& kb, const int* patom, const int* plm, const double* pr,
+              const double* pos, double omega);
+void kpt_subspace(hipStream_t s, cplx<double>* S, cplx<double>* H, cplx<double>* W, cplx<double>* V,
+                  cplx<double>* M, double* eps, int n, int mode, int* fail);
+void kpt_cg_dir(hipStream_t s, const KptBands& kb, const cplx<double>* X, const cplx<double>* HX,
+                cplx<double>* D, const double* eps, double* gam, int first);
+void kpt_linemin(hipStream_t s, const KptBands& kb, cplx<double>* X, cplx<double>* HX,
+                 const cplx<double>* D, const cplx<double>* HD);
+void kpt_init(hipStream_t s, const KptBands& kb, cplx<double>* X, unsigned seed, int kidx);
+void kpt_occupations(hipStream_t s, const double* eps, const double* wk, int nk, int nb, double nelec,
+                     int kind, double sigma, double* occ, double* scal);
+void kpt_band_kinetic(hipStream_t s, const KptBands& kb, const cplx<double>* X, double* out);
+void kpt_kinetic_total(hipStream_t s, const double* bandw_k, const double* occ_k, const double* wk, int nk,
+                       int nb, double* occ_s, double* bandw_s, int nb_s);
+void kpt_density(hipStream_t s, const cplx<double>* zk, const double* occ, double wk, int nb, long ntot,
+                 double* dens, int first);
+void kpt_force_nl(hipStream_t s, const cplx<double>* P, const cplx<double>* dP, int nproj, int nb,
+                  const double* h, const int* patom, const double* occ, double wk, int nat, double* fnl,
+                  int first);
+void kpt_force_total(hipStream_t s, const double* floc, const double* fnl, const double* few, int nat,
+                     double* force, double* fnl_part);
+void configure_kpt_kernels();
 // BF16-input projector products (FP32_BF16PROJ form).
 void launch_beta_bf16(const LaunchCtx& L);
 void launch_proj_bf16(const LaunchCtx& L, int src, int dst);

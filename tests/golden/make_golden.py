@@ -3,6 +3,9 @@
 Calls only the oracle (FP64 CPU) on the seeded inputs of `workloads`; no
 value here comes from the HIP path.  Usage:
     python tests/golden/make_golden.py C1 [C2 C3 ...]
+A name may end in ":cluster" to run the oracle's mixing with the weak Kerker
+damping that suits a few atoms in a vacuum box (alpha 0.3, q0 0.3 bohr^-1,
+up to 400 iterations); the fixed point is the same, only the path differs.
 Each result is written to tests/golden/<name>.json with the total free
 energy, its terms, eigenvalues, occupations and Hellmann-Feynman forces.
 """
@@ -34,6 +37,10 @@ def golden(system, **kw):
 
 def main(names):
     for name in names:
+        kw = {"tol_e": 1e-11, "tol_rho": 1e-9}
+        if name.endswith(":cluster"):
+            name = name[:-len(":cluster")]
+            kw.update(mix_alpha=0.3, kerker_q0=0.3, maxiter=400)
         if name == "C1":
             systems = [workloads.config_c1()]
         elif name == "C2":
@@ -49,7 +56,7 @@ def main(names):
         else:
             raise SystemExit("unknown workload " + name)
         for s in systems:
-            g = golden(s, tol_e=1e-11, tol_rho=1e-9)
+            g = golden(s, **kw)
             path = os.path.join(HERE, s["name"] + ".json")
             with open(path, "w") as f:
                 json.dump(g, f, indent=1)

@@ -63,13 +63,17 @@ def full_coefficients(psi, millers_gpu, oracle_millers):
     return C
 
 
-def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say, stress=None, s_tol=None):
-    """Hand the GPU's converged state (bands, occupations, density, V_eff) to
-    the oracle and recompute, in FP64 with the oracle's own arithmetic: the
-    density from the bands, every energy term, the Hellmann-Feynman forces and
-    the eigen-residual under the oracle's Hamiltonian at V_eff."""
+def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say, stress=None, s_tol=None,
+                       res_tol=None, v_tol=1e-8):
+    """Hand the GPU's converged state (bands, occupations, input and output
+    density, V_eff) to the oracle and recompute, in FP64 with the oracle's own
+    arithmetic: V_eff from the input density, the output density from the
+    bands, every energy term, the Hellmann-Feynman forces and the
+    eigen-residual |H psi - eps psi| of every band holding charge under the
+    oracle's Hamiltonian at V_eff (asserted below res_tol: the bands are the
+    self-consistent solution, not only self-consistent with themselves)."""
     from oracle.hamiltonian import Setup
-    from oracle.scf import energy_terms, occupations
+    from oracle.scf import energy_terms, occupations, potentials
     from oracle.forces import hf_forces
     st = Setup(system)
     C = full_coefficients(stt["psi"], stt["millers"], st.millers)
@@ -77,6 +81,10 @@ def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say, stress=None,
     rho = np.transpose(stt["rho"], (2, 1, 0))
     veff = np.transpose(stt["veff"], (2, 1, 0))
     say("  oracle check: setup done, %d plane waves" % st.npw)
+    out_v = None
+    if "rho_in" in stt:
+        veff_o, _ = potentials(st, np.transpose(stt["rho_in"], (2, 1, 0)))
+        out_v = np.abs(veff_o - veff).max()
     rho_o = st.density(C, f)
     say("  oracle check: density done")
     d_rho = np.abs(rho_o - rho).max() / np.abs(rho).max()
@@ -97,7 +105,13 @@ def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say, stress=None,
         say("  oracle check: stress done")
     HC = st.apply_h(veff, C)
     res = np.linalg.norm(HC - C * stt["eig"][None, :], axis=0)
-    out["residual_charged"] = res[f > 1e-2].max()
+    charged = f > 1e-6
+    out["residual_charged"] = res[charged].max()
+    # weighted by the occupation fraction f/2: how far each band moves the
+    # density and the energy (what the residual gate of the solver bounds)
+    out["residual_weighted"] = (0.5 * f[charged] * res[charged]).max()
+    if out_v is not None:
+        out["veff_from_rho_in"] = out_v
     say("  oracle check of GPU state: " + "  ".join("%s %.1e" % kv for kv in out.items()))
     assert d_rho < e_rtol
     for k in ("kinetic", "nonlocal", "local", "hartree", "xc", "ewald"):
@@ -105,4 +119,8 @@ def oracle_state_check(system, stt, forces, e_rtol, f_tol, say=say, stress=None,
     assert out["forces"] < f_tol
     if stress is not None:
         assert out["stress"] < s_tol
+    if out_v is not None:
+        assert out_v < v_tol
+    if res_tol is not None:
+        assert out["residual_weighted"] < res_tol
     return out

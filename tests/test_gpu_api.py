@@ -114,6 +114,21 @@ def test_autotuner_times_and_caches(tmp_path, monkeypatch):
             sgo.set_tuning(k, 0)
 
 
+def test_autotune_batch_split():
+    """The batch-schedule phase of the tuner: the population as one batch and
+    as two batches on two streams, whole solves to the gate; the pick is one
+    of the timed splits and the split solve gives the single batch's
+    energies."""
+    sgo = _sgo()
+    from paper_1603_02732_amd import autotune
+    pop = [workloads.tiny_system("c", ecut=5.0, grid=(18, 18, 18), seed=k) for k in (1, 2, 3, 4)]
+    gate = sgo.default_opts(tol_e=1e-7, tol_rho=1e-6, max_iter=200)
+    k, timings = autotune.tune_batch_split(pop, sgo.SGO_FP32, gate, splits=[1, 2], reps=1,
+                                           verbose=True)
+    assert set(timings) == {1, 2} and k in (1, 2)
+    assert all(t > 0 for t in timings.values())
+
+
 def test_invalid_inputs_are_rejected_and_the_handle_stays_usable():
     """Degenerate and out-of-range inputs fail with SGO_EINVAL (checked on
     the host before any launch), and the same handle then solves a valid

@@ -82,10 +82,12 @@ def test_c3_population_fp32():
         assert np.abs(F[k].sum(0)).max() < 5e-2
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_graph_replay_equals_eager(prec):
-    """Every SCF iteration after the first replays one captured HIP graph;
-    results must equal the eagerly launched sequence, call after call."""
+@pytest.mark.parametrize("prec,K", [("fp64", 1), ("fp32", 1), ("fp32", 3)])
+def test_graph_replay_equals_eager(prec, K):
+    """The SCF iterations after the first replay one captured HIP graph of K
+    iterations (candidates that converge inside it mask themselves on the
+    device); results and iteration counts must equal the eagerly launched
+    sequence, call after call."""
     import paper_1603_02732_amd as sgo
     p = sgo.SGO_FP64 if prec == "fp64" else sgo.SGO_FP32
     pop = _population()
@@ -98,11 +100,12 @@ def test_graph_replay_equals_eager(prec):
         Ee, Fe, ste = B.scf(sgo.default_opts(use_graph=0, **kw))
         it_e = [B.info(i)["iterations"] for i in range(len(pop))]
         B.reset()
-        Eg, Fg, stg = B.scf(sgo.default_opts(use_graph=1, **kw))
+        Eg, Fg, stg = B.scf(sgo.default_opts(use_graph=K, **kw))
         it_g = [B.info(i)["iterations"] for i in range(len(pop))]
         dE = np.abs(Ee - Eg).max()
         dF = max(np.abs(a - b).max() for a, b in zip(Fe, Fg))
-        say("  %s rep %d: graph vs eager dE %.2e dF %.2e iters %s %s" % (prec, rep, dE, dF, it_e, it_g))
+        say("  %s K=%d rep %d: graph vs eager dE %.2e dF %.2e iters %s %s"
+            % (prec, K, rep, dE, dF, it_e, it_g))
         assert it_e == it_g and list(ste) == list(stg)
         assert dE == 0.0 and dF == 0.0
 
