@@ -77,33 +77,41 @@ def folded():
     supercell at Gamma: the supercell's plane waves are exactly the union of
     the two primitive spheres, its grid doubles along a1 at the same
     spacing, so the two are one discrete problem."""
-    s = tiny_system("sip", ecut=3.0, grid=(12, 12, 12), occupation=FIXED)
+    # Fermi-Dirac smearing (one chemical potential for both sides) with 16
+    # buffer bands per k above the 16 occupied ones: the states one side keeps
+    # and the other drops then hold charge far below the tolerances below
+    # (with 8 buffer bands their tails still move the terms by ~1e-7)
+    s = tiny_system("sip", ecut=3.0, grid=(12, 12, 12), nbands=32)
     A = np.array(s["lattice"])
     pos = np.array(s["positions"])
     sup = make_system("super", np.vstack([2 * A[0], A[1], A[2]]), s["symbols"] * 2,
-                      np.vstack([pos, pos + A[0]]), s["ecut"], (24, 12, 12), 2 * s["nbands"], FIXED)
-    rs = run_scf(sup)
+                      np.vstack([pos, pos + A[0]]), s["ecut"], (24, 12, 12), 2 * s["nbands"],
+                      s["occupation"])
+    rs = run_scf(sup, tol_e=1e-13, tol_rho=1e-11)
     Fs, _ = hf_forces(rs)
-    rk = run_scf_k(s, [[0.0, 0.0, 0.0], [0.5, 0.0, 0.0]], [0.5, 0.5])
+    rk = run_scf_k(s, [[0.0, 0.0, 0.0], [0.5, 0.0, 0.0]], [0.5, 0.5], tol_e=1e-13, tol_rho=1e-11)
     Fk, _ = hf_forces_k(rk)
     return s, rs, Fs, rk, Fk
 
 
 def test_supercell_folding_energy(folded):
     s, rs, Fs, rk, Fk = folded
-    assert abs(rs["energy"] - 2 * rk["energy"]) < 2e-8
-    for t in ("kinetic", "nonlocal", "local", "hartree", "xc", "ewald"):
-        assert abs(rs["terms"][t] - 2 * rk["terms"][t]) < 2e-8, t
-    # the supercell spectrum is the union of the two k spectra
+    assert abs(rs["energy"] - 2 * rk["energy"]) < 1e-10
+    for t in ("kinetic", "nonlocal", "local", "hartree", "xc", "ewald", "entropy"):
+        assert abs(rs["terms"][t] - 2 * rk["terms"][t]) < 1e-10, t
+    # the supercell spectrum is the union of the two k spectra (below the
+    # highest kept state of either k)
     both = np.sort(np.concatenate(rk["eigenvalues"]))
-    assert np.abs(np.sort(rs["eigenvalues"])[:32] - both[:32]).max() < 1e-7
+    top = min(e[-1] for e in rk["eigenvalues"])
+    keep = both[both <= top]
+    assert np.abs(np.sort(rs["eigenvalues"])[:len(keep)] - keep).max() < 1e-10
 
 
 def test_supercell_folding_forces(folded):
     s, rs, Fs, rk, Fk = folded
     n = len(s["symbols"])
-    assert np.abs(Fs[:n] - Fk).max() < 1e-6
-    assert np.abs(Fs[n:] - Fk).max() < 1e-6
+    assert np.abs(Fs[:n] - Fk).max() < 1e-10
+    assert np.abs(Fs[n:] - Fk).max() < 1e-10
     assert np.abs(Fk).max() > 1e-3  # the jittered cell carries real forces
 
 
