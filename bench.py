@@ -49,6 +49,28 @@ HOOK_OF = {"k_gemm_f32": "k_gemm_acc", "k_plane_hpsi_reg": "k_plane_hpsi",
            "k_cg_direction_r": "k_cg_direction"}
 
 
+STALE_REFERENCES = []
+
+def stored_reference(name, system):
+    """The oracle's stored result for workload `name` (tests/golden), or
+    None if none is stored; a result stored for another problem (say an
+    older band count) is reported as stale and never gates."""
+    import numpy as np
+    p = os.path.join(ROOT, "tests", "golden", name + ".json")
+    if not os.path.exists(p):
+        return None
+    ref = json.load(open(p))
+    a = ref["system"]
+    same = (a["nbands"] == system["nbands"] and list(a["grid"]) == list(system["grid"])
+            and a["ecut"] == system["ecut"] and list(a["symbols"]) == list(system["symbols"])
+            and np.array_equal(np.asarray(a["lattice"]), np.asarray(system["lattice"]))
+            and np.array_equal(np.asarray(a["positions"]), np.asarray(system["positions"]))
+            and a["occupation"] == system["occupation"])
+    if not same:
+        STALE_REFERENCES.append(name)
+        return None
+    return ref
+
 def kernel_digest():
     """SHA-256 over the kernel sources (a counter summary is valid only for
     the kernels it was taken on)."""
@@ -460,9 +482,8 @@ def main():
     # parity gate on the candidates that have a stored oracle result
     gates, fgates = [], []
     for k in range(len(pop)):
-        p = os.path.join(ROOT, "tests", "golden", "C3-%d.json" % k)
-        if os.path.exists(p):
-            ref = json.load(open(p))
+        ref = stored_reference("C3-%d" % k, pop[k])
+        if ref is not None:
             gates.append(abs(E[k] - ref["energy"]) / 13)
             fgates.append(float(np.abs(np.asarray(F[k]) - np.asarray(ref["forces"])).max()))
     # an evaluation counts only if it converged and, where the oracle's
@@ -504,6 +525,8 @@ def main():
                                "measured_if_failed": None if gate_ok else value},
                       "dE_per_atom_vs_oracle": gates, "max_dF_vs_oracle": fgates},
            "plain": plain, "roofline": roof, "cpu_baseline": cpu}
+    if STALE_REFERENCES:
+        out["stale_references"] = sorted(set(STALE_REFERENCES))
     print(json.dumps(out), flush=True)
 
 
@@ -611,9 +634,8 @@ def c4_run(sgo, workloads, sync):
     B.close()
     gates = {}
     for k in range(len(pop)):
-        p = os.path.join(ROOT, "tests", "golden", "C4-%d.json" % k)
-        if os.path.exists(p):
-            ref = json.load(open(p))
+        ref = stored_reference("C4-%d" % k, pop[k])
+        if ref is not None:
             gates[k] = {"dE_per_atom": abs(E[k] - ref["energy"]) / len(pop[k]["symbols"]),
                         "max_dF": float(np.abs(np.asarray(F[k]) - np.asarray(ref["forces"])).max())}
     ok = bool((st == 0).all()) and all(v["dE_per_atom"] <= E_GATE and v["max_dF"] <= F_GATE
@@ -692,9 +714,9 @@ def bf16proj_run(sgo, pop, opts, sync, steps=2):
     dt = (time.perf_counter() - t0) / steps
     gates = []
     for k in range(len(pop)):
-        p = os.path.join(ROOT, "tests", "golden", "C3-%d.json" % k)
-        if os.path.exists(p):
-            gates.append(abs(E[k] - json.load(open(p))["energy"]) / 13)
+        ref = stored_reference("C3-%d" % k, pop[k])
+        if ref is not None:
+            gates.append(abs(E[k] - ref["energy"]) / 13)
     B.close()
     return {"evals_per_s": len(pop) / dt, "ms_per_step": dt * 1e3,
             "all_converged": bool((st == 0).all()), "dE_per_atom_vs_oracle": gates}

@@ -264,6 +264,9 @@ class Context:
         self._h = h
         self.natoms = 0
         self.species_ids = {}
+        # bumped by every call that changes the structure or the held state,
+        # so that a deferred adjoint can tell whether its solve is still held
+        self.generation = 0
 
     def _check(self, rc, h=-1, allow=()):
         if rc != SGO_OK and rc not in allow:
@@ -286,6 +289,7 @@ class Context:
         self._check(self._lib.sgo_set_stream(self._h, ctypes.c_void_p(stream_ptr)))
 
     def set_species(self, sid, params):
+        self.generation += 1
         sp = make_species(params)
         self._check(self._lib.sgo_set_species(self._h, sid, ctypes.byref(sp)))
 
@@ -299,10 +303,12 @@ class Context:
             self._check(self._lib.sgo_set_allocator(self._h, hooks.alloc, hooks.free, None))
 
     def set_cell(self, lattice):
+        self.generation += 1
         a = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
         self._check(self._lib.sgo_set_cell(self._h, _dptr(a)))
 
     def set_atoms(self, species, positions):
+        self.generation += 1
         s = np.ascontiguousarray(species, dtype=np.int32)
         p = np.ascontiguousarray(positions, dtype=np.float64).reshape(-1)
         self._check(self._lib.sgo_set_atoms(self._h, len(s), _iptr(s), _dptr(p)))
@@ -310,6 +316,7 @@ class Context:
         self.atom_species = s.copy()
 
     def set_cutoff(self, ecut, grid, nbands, occ_kind=SGO_OCC_FIXED, sigma=0.0):
+        self.generation += 1
         g = np.ascontiguousarray(grid, dtype=np.int32)
         self._check(self._lib.sgo_set_cutoff(self._h, float(ecut), _iptr(g), int(nbands),
                                              int(occ_kind), float(sigma)))
@@ -332,6 +339,7 @@ class Context:
         o = opts if opts is not None else default_opts(**kw)
         info = sgo_scf_info()
         allow = (SGO_ENOTCONV,) if allow_notconv else ()
+        self.generation += 1
         rc = self._check(self._lib.sgo_scf(self._h, ctypes.byref(o), ctypes.byref(info)),
                          allow=allow)
         return {"status": rc, "iterations": info.iterations, "converged": bool(info.converged),
@@ -345,6 +353,7 @@ class Context:
         w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64).reshape(-1))
         if len(k) != len(w):
             raise ValueError("one weight per k-point")
+        self.generation += 1
         self.nk = len(k)
         self._check(self._lib.sgo_set_kpoints(self._h, len(k), _dptr(k) if len(k) else None,
                                               _dptr(w) if len(w) else None))
@@ -407,6 +416,7 @@ class Context:
 
     def apply_h(self, veff_zyx, psi):
         """H[V] psi for packed bands psi (nb, 2*npw_half); veff indexed [z][y][x]."""
+        self.generation += 1  # the library drops the held solve
         v = np.ascontiguousarray(veff_zyx, dtype=np.float64)
         x = np.ascontiguousarray(psi, dtype=np.float64)
         out = np.zeros_like(x)
@@ -422,6 +432,7 @@ class Context:
         return rho.reshape(shape), veff.reshape(shape)
 
     def reset(self):
+        self.generation += 1
         self._check(self._lib.sgo_reset(self._h))
 
     def geometry(self):

@@ -933,6 +933,127 @@ __device__ __forceinline__ void jacobi_rot(const double* A, int n, int ld, int p
   *s = t * cc;
 }
 
+// Blocked Cholesky S = L L^T (lower, over A in place) and W = L^-1 (into Wm)
+// for the global-memory solver, on one workgroup.  Panels of kCholB
+// columns: the panel (already updated by the earlier panels) is factored in
+// LDS column by column, written back, and the trailing matrix takes one
+// rank-kCholB update from the panel rows held in LDS (4 x 4 register tiles)
+// instead of kCholB rank-1 sweeps through global memory.  W is formed one
+// block row at a time: thread c owns column c, sums the earlier block rows'
+// contribution T[r][c] = sum_k L[i0+r][k] W[k][c] in registers, then finishes
+// the block by forward substitution against the diagonal block, without
+// barriers.  Returns false (A partly factored) at the first pivot <= 0.
+// LDS: chol_inv_lds_doubles(n) doubles at `sm`.
+constexpr int kCholB = 32;
+__host__ __device__ constexpr int chol_inv_lds_doubles(int n) {
+  return n * (kCholB + 1) > kCholB * (n + 1) ? n * (kCholB + 1) : kCholB * (n + 1);
+}
+__device__ bool chol_inv_blocked(double* __restrict__ A, double* __restrict__ Wm, int n, int ld,
+                                 double* __restrict__ sm, int tid, int nthr) {
+  constexpr int B = kCholB, PS = kCholB + 1;
+  __shared__ double piv[kCholB];
+  __shared__ int bad;
+  for (int p0 = 0; p0 < n; p0 += B) {
+    const int pb = min(B, n - p0), m = n - p0;
+    for (int e = tid; e < m * pb; e += nthr) {
+      const int r = e / pb, c = e - r * pb;
+      sm[r * PS + c] = A[(size_t)(p0 + r) * ld + p0 + c];
+    }
+    if (tid == 0) bad = 0;
+    __syncthreads();
+    for (int k = 0; k < pb; ++k) {
+      const double d = sm[k * PS + k];
+      if (!(d > 0.0)) {  // every thread reads the same pivot: a uniform exit
+        if (tid == 0) bad = 1;
+        break;
+      }
+      const double pk = sqrt(d), inv = 1.0 / pk;
+      if (tid == 0) piv[k] = pk;
+      for (int r = k + 1 + tid; r < m; r += nthr) sm[r * PS + k] *= inv;
+      __syncthreads();
+      const int w = pb - k - 1, rows = m - k - 1;
+      for (int t = tid; t < rows * w; t += nthr) {
+        const int r = k + 1 + t / w, j = k + 1 + t % w;
+        if (r >= j) sm[r * PS + j] -= sm[r * PS + k] * sm[j * PS + k];
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    if (bad) return false;
+    for (int e = tid; e < m * pb; e += nthr) {
+      const int r = e / pb, c = e - r * pb;
+      if (r >= c) A[(size_t)(p0 + r) * ld + p0 + c] = r == c ? piv[c] : sm[r * PS + c];
+    }
+    // trailing update over rows/columns p0 + pb .. n-1 (lower triangle)
+    const int mt = (m - pb + 3) / 4;
+    for (int t = tid; t < mt * mt; t += nthr) {
+      const int I = t / mt, J = t - I * mt;
+      if (J > I) continue;
+      const int r0 = pb + 4 * I, q0 = pb + 4 * J;
+      double acc[4][4] = {};
+      for (int c = 0; c < pb; ++c) {
+        double a[4], b[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          a[u] = r0 + u < m ? sm[(r0 + u) * PS + c] : 0.0;
+          b[u] = q0 + u < m ? sm[(q0 + u) * PS + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = r0 + u, q = q0 + v;
+          if (r < m && q <= r) A[(size_t)(p0 + r) * ld + p0 + q] -= acc[u][v];
+        }
+    }
+    __syncthreads();
+  }
+  // W = L^-1, block row by block row
+  for (int i0 = 0; i0 < n; i0 += B) {
+    const int ib = min(B, n - i0), cols = i0 + ib, LS = cols | 1;
+    // rows i0 .. i0+B-1 of L (columns < cols) into LDS; rows past n are zero
+    for (int e = tid; e < B * cols; e += nthr) {
+      const int r = e / cols, k = e - r * cols;
+      sm[r * LS + k] = (r < ib && k <= i0 + r) ? A[(size_t)(i0 + r) * ld + k] : 0.0;
+    }
+    __syncthreads();
+    for (int c = tid; c < n; c += nthr) {
+      if (c >= cols) {  // above the diagonal
+        for (int r = 0; r < ib; ++r) Wm[(size_t)(i0 + r) * ld + c] = 0.0;
+        continue;
+      }
+      double x[B];
+#pragma unroll
+      for (int r = 0; r < B; ++r) x[r] = 0.0;
+      for (int k = c; k < i0; ++k) {
+        const double w = Wm[(size_t)k * ld + c];
+#pragma unroll
+        for (int r = 0; r < B; ++r) x[r] = fma(sm[r * LS + k], w, x[r]);
+      }
+      // forward substitution against the diagonal block (rows past n stay 0)
+#pragma unroll
+      for (int r = 0; r < B; ++r) {
+        if (r < ib) {
+          double s = (i0 + r == c ? 1.0 : 0.0) - x[r];
+#pragma unroll
+          for (int q = 0; q < r; ++q) s = fma(-sm[r * LS + i0 + q], x[q], s);
+          x[r] = s / sm[r * LS + i0 + r];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < B; ++r)
+        if (r < ib) Wm[(size_t)(i0 + r) * ld + c] = x[r];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 // phase 0: the whole solve; 1: Cholesky and W = L^-1 only (the congruence,
 // the Jacobi rounds and M = W^T V then run over the whole GPU: k_sub_*,
 // k_jac_*); 2: eigenvalue order and the sorted M, eps from the converged H'
@@ -979,57 +1100,66 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     if (tid == 0) fail = 0;
     if (clk && tid == 0) clk[0] = clock64();
     __syncthreads();
-    // Cholesky S = L L^T (lower, in place, right-looking; two barriers per
-    // column).  The pivots are kept aside in P3 and written to the diagonal at
-    // the end, so no thread overwrites a pivot another thread still reads.
-    for (int k = 0; k < n; ++k) {
-      __syncthreads();  // trailing update of the previous column is complete
-      const double d = P0[k * ld + k];
-      if (!(d > 0.0)) {
-        if (tid == 0) fail = 1;
-        break;
+    if (!use_lds) {
+      // global-memory solver: blocked, panels in the dynamic LDS
+      if (!chol_inv_blocked(P0, P2, n, ld, (double*)smem, tid, nthr)) {
+        if (tid == 0) cd.scal[S_ERR] = 2.0;
+        for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
+        return;
       }
-      const double piv = sqrt(d);
-      const double inv = 1.0 / piv;
-      if (tid == 0) P3[k] = piv;
-      for (int i = k + 1 + tid; i < n; i += nthr) P0[i * ld + k] *= inv;
-      __syncthreads();
-      const int m = n - k - 1;
-      for (int t = tid; t < m * m; t += nthr) {
-        const int i = k + 1 + t / m, j = k + 1 + t % m;
-        if (j <= i) P0[i * ld + j] -= P0[i * ld + k] * P0[j * ld + k];
-      }
-    }
-    __syncthreads();
-    if (!fail)
-      for (int k = tid; k < n; k += nthr) P0[k * ld + k] = P3[k];
-    __syncthreads();
-    if (fail) {
-      if (tid == 0) cd.scal[S_ERR] = 2.0;
-      for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
-      return;
-    }
-    // W = L^-1 by elimination on [L | I]: at step j, rows i > j subtract
-    // L[i][j] * row j (final since step j-1); row j+1 is complete after this
-    // step and is divided by its pivot.  One barrier per step.
-    for (int e = tid; e < n * n; e += nthr) {
-      const int i = e / n, j = e % n;
-      P2[i * ld + j] = i == j ? (i == 0 ? 1.0 / P0[0] : 1.0) : 0.0;
-    }
-    __syncthreads();
-    for (int j = 0; j + 1 < n; ++j) {
-      const int rows = n - 1 - j, cols = j + 1;
-      for (int t = tid; t < rows * cols + 1; t += nthr) {
-        if (t == rows * cols) {
-          P2[(j + 1) * ld + j + 1] = 1.0 / P0[(j + 1) * ld + j + 1];
-          continue;
+    } else {
+      // Cholesky S = L L^T (lower, in place, right-looking; two barriers per
+      // column).  The pivots are kept aside in P3 and written to the diagonal at
+      // the end, so no thread overwrites a pivot another thread still reads.
+      for (int k = 0; k < n; ++k) {
+        __syncthreads();  // trailing update of the previous column is complete
+        const double d = P0[k * ld + k];
+        if (!(d > 0.0)) {
+          if (tid == 0) fail = 1;
+          break;
         }
-        const int i = j + 1 + t / cols, c = t % cols;
-        double w = P2[i * ld + c] - P0[i * ld + j] * P2[j * ld + c];
-        if (i == j + 1) w /= P0[i * ld + i];
-        P2[i * ld + c] = w;
+        const double piv = sqrt(d);
+        const double inv = 1.0 / piv;
+        if (tid == 0) P3[k] = piv;
+        for (int i = k + 1 + tid; i < n; i += nthr) P0[i * ld + k] *= inv;
+        __syncthreads();
+        const int m = n - k - 1;
+        for (int t = tid; t < m * m; t += nthr) {
+          const int i = k + 1 + t / m, j = k + 1 + t % m;
+          if (j <= i) P0[i * ld + j] -= P0[i * ld + k] * P0[j * ld + k];
+        }
       }
       __syncthreads();
+      if (!fail)
+        for (int k = tid; k < n; k += nthr) P0[k * ld + k] = P3[k];
+      __syncthreads();
+      if (fail) {
+        if (tid == 0) cd.scal[S_ERR] = 2.0;
+        for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
+        return;
+      }
+      // W = L^-1 by elimination on [L | I]: at step j, rows i > j subtract
+      // L[i][j] * row j (final since step j-1); row j+1 is complete after this
+      // step and is divided by its pivot.  One barrier per step.
+      for (int e = tid; e < n * n; e += nthr) {
+        const int i = e / n, j = e % n;
+        P2[i * ld + j] = i == j ? (i == 0 ? 1.0 / P0[0] : 1.0) : 0.0;
+      }
+      __syncthreads();
+      for (int j = 0; j + 1 < n; ++j) {
+        const int rows = n - 1 - j, cols = j + 1;
+        for (int t = tid; t < rows * cols + 1; t += nthr) {
+          if (t == rows * cols) {
+            P2[(j + 1) * ld + j + 1] = 1.0 / P0[(j + 1) * ld + j + 1];
+            continue;
+          }
+          const int i = j + 1 + t / cols, c = t % cols;
+          double w = P2[i * ld + c] - P0[i * ld + j] * P2[j * ld + c];
+          if (i == j + 1) w /= P0[i * ld + i];
+          P2[i * ld + c] = w;
+        }
+        __syncthreads();
+      }
     }
     if (clk && tid == 0) clk[1] = clock64();
     if (mode == 1) {
@@ -1532,11 +1662,14 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   // used while a graph is being captured.
   const int n = L.g.nb_max;
   const int use_lds = n <= 64 ? 1 : 0;
-  size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1) : 0;  // rows padded to n + 1
+  // LDS: the four matrices (rows padded to n + 1), or the panels of the
+  // blocked Cholesky and inverse of the global-memory solver
+  const size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1)
+                             : sizeof(double) * (size_t)chol_inv_lds_doubles(n);
   const int nthr = L.g.sub_threads;
   prof_before("k_subspace", L.stream);
   if (mode == 3 && n >= L.g.jac_grid && L.jac_done && host_sync_allowed()) {
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode, 0,
                        max_sweeps, 1);
     check_launch("k_subspace");
     const dim3 ge((n * n + kNT - 1) / kNT, L.g.ncand);
@@ -1655,7 +1788,8 @@ int subspace_noalloc(int device, int n, int mode, const double* S, const double*
                      mode == 3 ? H : nullptr, nn);
   check_launch("k_noalloc_stage");
   const int use_lds = n <= 64 ? 1 : 0;
-  const size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1) : 0;
+  const size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1)
+                             : sizeof(double) * (size_t)chol_inv_lds_doubles(n);
   hipLaunchKernelGGL(k_subspace, dim3(1), dim3(nthreads), lds, stream, dd, mode, use_lds, 40, 0);
   check_launch("k_subspace");
   if (status) {

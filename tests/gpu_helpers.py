@@ -44,12 +44,28 @@ def random_real_function_coeffs(npw, nb, pos, neg, seed):
     return C
 
 
-def load_golden(name):
+def same_system(a, b):
+    """True when two workload dicts describe the same discrete problem."""
+    return (a["nbands"] == b["nbands"] and list(a["grid"]) == list(b["grid"])
+            and a["ecut"] == b["ecut"] and list(a["symbols"]) == list(b["symbols"])
+            and np.array_equal(np.asarray(a["lattice"]), np.asarray(b["lattice"]))
+            and np.array_equal(np.asarray(a["positions"]), np.asarray(b["positions"]))
+            and a["occupation"] == b["occupation"])
+
+
+def load_golden(name, system=None):
+    """The oracle's stored result for `name`, or None if none is stored.
+    With `system`, a stored result computed for a different problem (say
+    an older band count) is an error, not a reference."""
     path = os.path.join(GOLDEN, name + ".json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
-        return json.load(f)
+        ref = json.load(f)
+    if system is not None:
+        assert same_system(ref["system"], system), \
+            "stored oracle result %s was computed for another problem; regenerate it" % name
+    return ref
 
 
 def full_coefficients(psi, millers_gpu, oracle_millers):

@@ -40,14 +40,51 @@ def test_autograd_matches_finite_differences_fp64():
         assert abs(float(g[I, a]) - fd) < 1e-5
 
 
+def test_backward_recomputes_a_state_the_context_no_longer_holds():
+    """Two forward passes on one context, then the backward of the first:
+    its solve is no longer held, so backward solves again at the saved
+    positions before the adjoint; both gradients equal -F of fresh contexts
+    solved at the same positions, and a backward whose state is still held
+    takes the adjoint directly."""
+    import torch
+    import paper_1603_02732_amd as sgo
+    from paper_1603_02732_amd.autograd import ScfEnergy
+    s = _sheet_small()
+    ctx = sgo.context_from_system(s, sgo.SGO_FP64)
+    opts = sgo.default_opts(tol_e=1e-12, tol_rho=1e-9, max_iter=300)
+    P1 = np.array(s["positions"])
+    P2 = P1.copy()
+    P2[2, 0] += 0.05
+    R1 = torch.tensor(P1, dtype=torch.float64, requires_grad=True)
+    R2 = torch.tensor(P2, dtype=torch.float64, requires_grad=True)
+    E1 = ScfEnergy.apply(R1, ctx, opts)
+    E2 = ScfEnergy.apply(R2, ctx, opts)
+    (g1,) = torch.autograd.grad(E1, R1)
+    assert E1.grad_fn.recomputed
+    (g2,) = torch.autograd.grad(E2, R2)
+    assert E2.grad_fn.recomputed  # the first backward's solve replaced it
+    for P, g in ((P1, g1), (P2, g2)):
+        t = dict(s)
+        t["positions"] = P.tolist()
+        f = sgo.context_from_system(t, sgo.SGO_FP64)
+        f.scf(opts)
+        dF = np.abs(g.numpy() + f.forces()).max()
+        say("  recomputed backward vs fresh solve: max dF %.2e" % dF)
+        assert dF < 1e-6
+    E3 = ScfEnergy.apply(R2, ctx, opts)
+    (g3,) = torch.autograd.grad(E3, R2)
+    assert not E3.grad_fn.recomputed
+    assert np.abs(g3.numpy() - g2.numpy()).max() < 1e-6
+
+
 def test_autograd_fp32_sheet_matches_oracle_forces():
     import torch
     import paper_1603_02732_amd as sgo
     from paper_1603_02732_amd.autograd import ScfEnergy
-    ref = load_golden("C2")
+    s = workloads.config_c2()
+    ref = load_golden("C2", s)
     if ref is None:
         pytest.skip("C2 oracle reference not generated")
-    s = workloads.config_c2()
     ctx = sgo.context_from_system(s, sgo.SGO_FP32)
     opts = sgo.default_opts(tol_e=1e-8, tol_rho=1e-6, max_iter=200)
     R = torch.tensor(np.array(s["positions"]), dtype=torch.float64, requires_grad=True)

@@ -69,7 +69,7 @@ def test_c3_population_fp32():
     say("  status", list(st), "iters", [B.info(i)["iterations"] for i in range(len(pop))])
     assert np.all(st == 0)
     for k in range(2):
-        ref = load_golden("C3-%d" % k)
+        ref = load_golden("C3-%d" % k, pop[k])
         if ref is None:
             continue
         dE = abs(E[k] - ref["energy"]) / 13

@@ -45,7 +45,7 @@ def test_c4_uneven_population_fp32():
         assert np.abs(F[i].sum(0)).max() < 5e-2  # egg-box level
     checked = 0
     for k in C4_GOLDEN:
-        ref = load_golden("C4-%d" % k)
+        ref = load_golden("C4-%d" % k, pop[k])
         if ref is None:
             continue
         dE = abs(E[k] - ref["energy"]) / nat[k]

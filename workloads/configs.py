@@ -65,12 +65,15 @@ def config_c3(count=32, seed0=100):
 
 def config_c4(count=64, seed0=200, ecut=15.0):
     """Uneven population of 8-40 carbon atoms in 12-22 bohr cells; grid by
-    the 2^a3^b5^c rule at h <= 0.375 bohr; bands = even ceil(1.2 x occupied)."""
+    the 2^a3^b5^c rule at h <= 0.375 bohr; bands = even ceil(1.4 x occupied)
+    (the random clusters carry many dangling-bond states near the Fermi
+    level: with 1.2 x occupied the top band of several candidates still holds
+    charge at self-consistency, and their SCF stalls)."""
     out = []
     for k, (lat, pos) in enumerate(population_uneven(count, seed0)):
         n = len(pos)
         grid = [grid_rule(lat[i, i]) for i in range(3)]
-        nb = nbands_rule(2 * n)  # 4 electrons per atom -> 2n occupied bands
+        nb = nbands_rule(2 * n, 1.4)  # 4 electrons per atom -> 2n occupied bands
         out.append(make_system("C4-%d" % k, lat, ["C-G"] * n, pos, ecut, grid,
                                nb, FERMI, "fp32"))
     return out
