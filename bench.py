@@ -165,6 +165,12 @@ CLUSTER_MIXING = {"mix_alpha": 0.3, "kerker_q0": 0.3, "ncg_first": 6}
 # density residual below RHO_GATE (the residual bounds the force error at
 # termination: 3e-4 keeps it well inside the FP32 force tolerance)
 RHO_GATE = 3e-4
+# residual gate on the CG steps (library option cg_tol): a candidate counts
+# as converged only when every band holding charge has its occupation-
+# weighted residual at the gate; without it a slowly converging cluster can
+# meet the energy and density gates early (one stopped at 1.5e-5 Ha/atom
+# from the oracle's energy after 21 iterations; 35 with the gate, 2.5e-6)
+CG_GATE = 1e-4
 # solver settings of the uneven population: mixing weight 0.3 (the dilute
 # metallic candidates oscillate at the dense-cell default 0.5) and the
 # residual gate on the CG steps (a candidate is converged only when its
@@ -246,6 +252,9 @@ def kernel_amount(name, g, prof, tsize=4):
 LEGS = {
     "C4_uneven_population_batched": lambda sgo, wl, sync: c4_run(sgo, wl, sync),
     "C5_large_cell": lambda sgo, wl, sync: c5_run(sgo, wl, sync),
+    "C3_one_batch": lambda sgo, wl, sync: one_batch_run(
+        sgo, wl.config_c3(32), sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, cg_tol=CG_GATE,
+                                                max_iter=150, **CLUSTER_MIXING), sync),
     "cpu_oracle": lambda sgo, wl, sync: cpu_oracle_run(wl),
 }
 CPU_PROFILE = os.path.join(ROOT, "profiles", "cpu_oracle_baseline.txt")
@@ -356,7 +365,7 @@ def main():
         for s in pop[bounds[j]:bounds[j + 1]]:
             b.add_system(s)
         Bs.append(b)
-    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=150,
+    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, cg_tol=CG_GATE, max_iter=150,
                             use_graph=int(schedule["use_graph"]) if schedule else 0,
                             **CLUSTER_MIXING)
     geoms = []
@@ -517,7 +526,8 @@ def main():
                                          "%d concurrent batches of %d on %d streams (autotuner's "
                                          "pick)" % (nsplit, len(pop) // nsplit, nsplit)),
                       "candidates_per_step": len(pop), "all_converged": status_ok,
-                      "scf_gate": {"dE_per_atom": 1e-5, "density_residual": RHO_GATE},
+                      "scf_gate": {"dE_per_atom": 1e-5, "density_residual": RHO_GATE,
+                                   "weighted_band_residual": CG_GATE},
                       "solver": dict(CLUSTER_MIXING, history=8, mixing="Pulay+Kerker", ncg=3),
                       "launch_schedule": schedule or "library defaults",
                       "gate": {"passed": gate_ok, "dE_per_atom": E_GATE, "max_dF": F_GATE,
@@ -594,7 +604,7 @@ def c5_run(sgo, workloads, sync):
     cold solve with forces, then the fixed-basis stress."""
     s = workloads.config_c5()
     ctx = sgo.context_from_system(s, sgo.SGO_FP32)
-    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=200)
+    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, cg_tol=CG_GATE, max_iter=200)
     ctx.scf(opts)  # warm-up (allocation)
     sync()
     ctx.reset()
@@ -730,7 +740,8 @@ def plain_runs(sgo, workloads, sync):
                                ("C3_cluster", workloads.config_c3(1)[0], sgo.SGO_FP32),
                                ("C3_cluster_fp64", workloads.config_c3(1)[0], sgo.SGO_FP64)):
         ctx = sgo.context_from_system(system, prec)
-        opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=150, **CLUSTER_MIXING)
+        opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, cg_tol=CG_GATE, max_iter=150,
+                                **CLUSTER_MIXING)
 
         def step():
             ctx.reset()

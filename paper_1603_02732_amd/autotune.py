@@ -210,8 +210,8 @@ def _main():
             B.add_system(s)
         res = autotune(B, pop, SGO_FP32, iters=a.iters, use_cache=False, verbose=True)
         B.close()
-        gate = default_opts(tol_e=1e-5, tol_rho=3e-4, max_iter=150, mix_alpha=0.3, kerker_q0=0.3,
-                            ncg_first=6, use_graph=res["use_graph"])
+        gate = default_opts(tol_e=1e-5, tol_rho=3e-4, cg_tol=1e-4, max_iter=150, mix_alpha=0.3,
+                            kerker_q0=0.3, ncg_first=6, use_graph=res["use_graph"])
         k, tk = tune_batch_split(pop, SGO_FP32, gate, verbose=True)
         res["batches"] = k
         path = a.table_path if a.write_table else cache_path()

@@ -590,11 +590,14 @@ __global__ void __launch_bounds__(kNT) k_gemm_acc(const CandDesc* __restrict__ c
 // float4 per lane.
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 // TT: 16-row output tiles per pass (2 when every output has at most 32 rows:
-// half the accumulator registers, more resident waves).
-template <int TT>
-__global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cds, int y0, int y1,
-                                                 int y2, int a0, int a1, int a2, int mat, float alpha,
-                                                 float beta, int use_h) {
+// half the accumulator registers, more resident waves).  NW wavefronts
+// share one staged slice and take turns over the output row tiles: with
+// many bands the slice fills most of the LDS a compute unit has, and a
+// single wavefront per slice would leave the matrix cores idle.
+template <int TT, int NW>
+__global__ void __launch_bounds__(64 * NW) k_gemm_f32(const CandDesc* __restrict__ cds, int y0,
+                                                      int y1, int y2, int a0, int a1, int a2,
+                                                      int mat, float alpha, float beta, int use_h) {
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
   const int arr = blockIdx.y;
@@ -608,29 +611,31 @@ __global__ void __launch_bounds__(64) k_gemm_f32(const CandDesc* __restrict__ cd
   const float* A = warr<float>(cd, wa);
   float* Y = warr<float>(cd, wy);
   const double* M = marr(cd, mat);
-  const int lane = threadIdx.x, n = lane & 15, g = lane >> 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n = lane & 15, g = lane >> 4;
   const int kc = k0 + 4 * n;          // first of this lane's four columns
   const bool kin = kc < Kp;           // Kp is a multiple of 32: all four or none
   extern __shared__ __align__(16) char smem[];
   float4* As = (float4*)smem;         // [nin][16] float4 = [nin][64] floats
-  // staged in batches of 8 rows per lane: the loads of a batch are all in
+  // staged in batches of 8 rows per thread: the loads of a batch are all in
   // flight before the first store (one memory latency per batch)
-  for (int jb = g; jb < nin; jb += 32) {
+  const int gs = threadIdx.x >> 4, ng = 4 * NW;  // row group of this thread, groups
+  for (int jb = gs; jb < nin; jb += 8 * ng) {
     float4 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int j = jb + 4 * u;
+      const int j = jb + ng * u;
       v[u] = (kin && j < nin) ? *(const float4*)(A + (size_t)j * Kp + kc)
                               : make_float4(0.f, 0.f, 0.f, 0.f);
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const int j = jb + 4 * u;
+      const int j = jb + ng * u;
       if (j < nin) As[j * 16 + n] = v[u];
     }
   }
   __syncthreads();
-  for (int i0 = 0; i0 < nout; i0 += 16 * TT) {
+  for (int i0 = 16 * TT * wave; i0 < nout; i0 += 16 * TT * NW) {
     floatx4 acc[TT][4];
 #pragma unroll
     for (int t = 0; t < TT; ++t)
@@ -1255,21 +1260,22 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
     nin_max = std::max(nin_max, nin);
     rows_moved += nin + (alpha != 0.0 ? 2 : 1) * g.nb_max;
   }
-  // the MFMA kernel stages all nin input rows of its 64 columns in LDS, one
-  // wavefront per slice: beyond 64 KB (256 rows) too few slices stay resident
-  // per compute unit and the VALU kernel is faster (282 bands: 1.8 against
-  // 3.5 ms per rotation)
+  // the MFMA kernel stages all nin input rows of its 64 columns in LDS; from
+  // 128 bands (32 KB a slice: few slices resident per compute unit) four
+  // wavefronts share a slice, each taking every fourth 32-row output tile
   const size_t lds32 = (size_t)nin_max * 64 * sizeof(float);
-  if (std::is_same<T, float>::value && lds32 <= 65536 && g.gemm_f32) {
+  if (std::is_same<T, float>::value && lds32 <= g.lds_limit && g.gemm_f32) {
     prof_before("k_gemm_acc", L.stream);
-    if (g.nb_max <= 32)
-      hipLaunchKernelGGL(k_gemm_f32<2>, dim3((g.K_max + 63) / 64, narr, g.ncand), dim3(64), lds32,
-                         L.stream, L.desc, y[0], y1, y2, a[0], a1, a2, mat, (float)alpha,
-                         (float)beta, use_h);
+    const dim3 grid32((g.K_max + 63) / 64, narr, g.ncand);
+    if (nin_max >= 128)
+      hipLaunchKernelGGL((k_gemm_f32<2, 4>), grid32, dim3(256), lds32, L.stream, L.desc, y[0], y1,
+                         y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
+    else if (g.nb_max <= 32)
+      hipLaunchKernelGGL((k_gemm_f32<2, 1>), grid32, dim3(64), lds32, L.stream, L.desc, y[0], y1,
+                         y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
     else
-      hipLaunchKernelGGL(k_gemm_f32<4>, dim3((g.K_max + 63) / 64, narr, g.ncand), dim3(64), lds32,
-                         L.stream, L.desc, y[0], y1, y2, a[0], a1, a2, mat, (float)alpha,
-                         (float)beta, use_h);
+      hipLaunchKernelGGL((k_gemm_f32<4, 1>), grid32, dim3(64), lds32, L.stream, L.desc, y[0], y1,
+                         y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
     check_launch("k_gemm_acc");
     prof_after("k_gemm_acc", L.stream, rows_moved);
     return;
@@ -1407,8 +1413,9 @@ static void configure_t() {
   allow_lds((const void*)k_gemm_acc<T, 5>);
 }
 void configure_wave() {
-  allow_lds((const void*)k_gemm_f32<2>);
-  allow_lds((const void*)k_gemm_f32<4>);
+  allow_lds((const void*)k_gemm_f32<2, 1>);
+  allow_lds((const void*)k_gemm_f32<4, 1>);
+  allow_lds((const void*)k_gemm_f32<2, 4>);
   configure_t<float>();
   configure_t<double>();
 }
