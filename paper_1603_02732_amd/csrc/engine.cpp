@@ -978,7 +978,9 @@ class Engine {
     const int hist = std::max(2, std::min(kMaxHist, o.history));
     BatchGeom g = prepare(o.seed, hist);
     hipStream_t user_stream = stream_;
-    if (o.use_graph && !stream_) {
+    // a stream of its own when none is set and something will be captured:
+    // the K-iteration graphs, or the Jacobi sweeps over the GPU
+    if ((o.use_graph || g.nb_max >= g.jac_grid) && !stream_) {
       if (!own_stream_) HIPCHK(hipStreamCreateWithFlags(&own_stream_, hipStreamNonBlocking));
       stream_ = own_stream_;
     }

@@ -1065,12 +1065,15 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   if (!cd.active) return;
   const int n = cd.nb;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  // use_lds 1: the four matrices in LDS; 0: in global memory; 2: in global
+  // memory except H', which the Jacobi rounds keep in LDS (up to 128 bands)
+  const bool all_lds = use_lds == 1;
   // row stride of the four matrices: n + 1 in LDS (rows and columns of
   // FP64 entries then fall in different banks), n in global memory
-  const int ld = use_lds ? n + 1 : n;
+  const int ld = all_lds ? n + 1 : n;
   extern __shared__ __align__(16) char smem[];
   double *P0, *P1, *P2, *P3;  // L, H / H', W = L^-1, scratch / V
-  if (use_lds) {
+  if (all_lds) {
     P0 = (double*)smem;
     P1 = P0 + n * ld;
     P2 = P1 + n * ld;
@@ -1086,6 +1089,9 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     P2 = cd.C;
     P3 = cd.M;
   }
+  // H' from the congruence on (the input H stays in P1)
+  double* H1 = use_lds == 2 ? (double*)smem : P1;
+  const int ldh = use_lds == 2 ? n + 1 : ld;
   __shared__ int fail;
   __shared__ double sh[16 * 2];
   __shared__ int rank[640];
@@ -1100,7 +1106,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     if (tid == 0) fail = 0;
     if (clk && tid == 0) clk[0] = clock64();
     __syncthreads();
-    if (!use_lds) {
+    if (!all_lds) {
       // global-memory solver: blocked, panels in the dynamic LDS
       if (!chol_inv_blocked(P0, P2, n, ld, (double*)smem, tid, nthr)) {
         if (tid == 0) cd.scal[S_ERR] = 2.0;
@@ -1179,15 +1185,15 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       const int i = e / n, j = e % n;
       double s = 0.0;
       for (int k = 0; k <= j; ++k) s = fma(P3[i * ld + k], P2[j * ld + k], s);
-      P1[i * ld + j] = s;
+      H1[i * ldh + j] = s;
     }
     __syncthreads();
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
       if (i < j) {
-        const double a = 0.5 * (P1[i * ld + j] + P1[j * ld + i]);
-        P1[i * ld + j] = a;
-        P1[j * ld + i] = a;
+        const double a = 0.5 * (H1[i * ldh + j] + H1[j * ldh + i]);
+        H1[i * ldh + j] = a;
+        H1[j * ldh + i] = a;
       }
       P3[i * ld + j] = (i == j) ? 1.0 : 0.0;
     }
@@ -1206,7 +1212,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       double v[2] = {0.0, 0.0};
       for (int e = tid; e < n * n; e += nthr) {
         const int i = e / n, j = e % n;
-        const double a = P1[i * ld + j];
+        const double a = H1[i * ldh + j];
         if (i == j) v[1] += a * a;
         else v[0] += a * a;
       }
@@ -1218,7 +1224,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
           int p, q;
           jacobi_pair(r, k, n2, &p, &q);
           double c, sn;
-          jacobi_rot(P1, n, ld, p, q, &c, &sn);
+          jacobi_rot(H1, n, ldh, p, q, &c, &sn);
           rp[k] = p;
           rq[k] = q;
           rc[k] = c;
@@ -1238,18 +1244,18 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
             const double cP = rc[P], cQ = rc[Q];
             const int p1 = rp[P], p2 = rq[P], q1 = rp[Q], q2 = rq[Q];
             const bool p2v = p2 < n, q2v = q2 < n;
-            const double a11 = P1[p1 * ld + q1];
-            const double a12 = q2v ? P1[p1 * ld + q2] : 0.0;
-            const double a21 = p2v ? P1[p2 * ld + q1] : 0.0;
-            const double a22 = (p2v && q2v) ? P1[p2 * ld + q2] : 0.0;
+            const double a11 = H1[p1 * ldh + q1];
+            const double a12 = q2v ? H1[p1 * ldh + q2] : 0.0;
+            const double a21 = p2v ? H1[p2 * ldh + q1] : 0.0;
+            const double a22 = (p2v && q2v) ? H1[p2 * ldh + q2] : 0.0;
             // rows: (a1j, a2j) -> (c a1j - s a2j, s a1j + c a2j)
             const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
             const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
             // columns: (bi1, bi2) -> (c bi1 - s bi2, s bi1 + c bi2)
-            P1[p1 * ld + q1] = cQ * b11 - sQ * b12;
-            if (q2v) P1[p1 * ld + q2] = sQ * b11 + cQ * b12;
-            if (p2v) P1[p2 * ld + q1] = cQ * b21 - sQ * b22;
-            if (p2v && q2v) P1[p2 * ld + q2] = sQ * b21 + cQ * b22;
+            H1[p1 * ldh + q1] = cQ * b11 - sQ * b12;
+            if (q2v) H1[p1 * ldh + q2] = sQ * b11 + cQ * b12;
+            if (p2v) H1[p2 * ldh + q1] = cQ * b21 - sQ * b22;
+            if (p2v && q2v) H1[p2 * ldh + q2] = sQ * b21 + cQ * b22;
           }
         } else {
           // V is stored transposed (P3[q][i] = V[i][q]): the column rotation of
@@ -1275,10 +1281,10 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   }
   // ranks of the eigenvalues (ascending, ties by index)
   for (int i = tid; i < n; i += nthr) {
-    const double li = P1[i * ld + i];
+    const double li = H1[i * ldh + i];
     int rnk = 0;
     for (int j = 0; j < n; ++j) {
-      const double lj = P1[j * ld + j];
+      const double lj = H1[j * ldh + j];
       if (lj < li || (lj == li && j < i)) ++rnk;
     }
     rank[i] = rnk;
@@ -1298,7 +1304,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     const int j = e / n, i = e % n;
     cd.M[j * n + rank[i]] = P0[j * ld + i];
   }
-  for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = P1[i * ld + i];
+  for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = H1[i * ldh + i];
   if (clk && tid == 0) clk[4] = clock64();
 }
 
@@ -1653,6 +1659,73 @@ void launch_occupations(const LaunchCtx& L) {
   check_launch("k_occupations");
   prof_after("k_occupations", L.stream);
 }
+// Where the subspace solver keeps its matrices: all four in LDS up to 64
+// bands, H' alone in LDS up to 128 (the Jacobi rounds then touch global
+// memory only for V's column pairs), else all in global memory; and the
+// dynamic LDS that form needs (the blocked Cholesky's panels share it).
+static int sub_lds_form(int n) { return n <= 64 ? 1 : (n <= 128 ? 2 : 0); }
+static size_t sub_lds_bytes(int n, int form) {
+  if (form == 1) return sizeof(double) * 4 * (size_t)n * (n + 1);
+  const size_t chol = (size_t)chol_inv_lds_doubles(n);
+  const size_t h = form == 2 ? (size_t)n * (n + 1) : 0;
+  return sizeof(double) * std::max(chol, h);
+}
+
+// One Jacobi sweep over the GPU (n2 - 1 rounds of two launches each),
+// replayed from a graph captured once per (device, descriptor array,
+// candidates, bands, stream): a sweep of 282 bands is 562 short launches, and
+// the host's launch rate, not the kernels, set its pace.  The graphs live
+// until the process ends (at most kSweepGraphs; past that, and on the legacy
+// null stream, sweeps launch eagerly); the kernels read every size from the descriptors, so a graph
+// stays valid for any batch whose descriptor array lands at the same address
+// with the same candidate and band counts.
+namespace {
+struct SweepGraph {
+  int dev;
+  const void* desc;
+  int ncand, n;
+  hipStream_t stream;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+constexpr size_t kSweepGraphs = 16;
+std::mutex g_sweep_mu;
+std::vector<SweepGraph> g_sweeps;
+}  // namespace
+
+static void jacobi_rounds(const LaunchCtx& L, int n2, dim3 gp, dim3 ga) {
+  for (int r = 0; r < n2 - 1; ++r) {
+    hipLaunchKernelGGL(k_jac_params, gp, dim3(kNT), 0, L.stream, L.desc, r);
+    hipLaunchKernelGGL(k_jac_apply, ga, dim3(kNT), 0, L.stream, L.desc);
+  }
+}
+
+static void jacobi_sweep(const LaunchCtx& L, int n, int n2, dim3 gp, dim3 ga) {
+  int dev = 0;
+  hip_check(hipGetDevice(&dev), "current device");
+  std::lock_guard<std::mutex> lk(g_sweep_mu);
+  for (const auto& e : g_sweeps)
+    if (e.dev == dev && e.desc == (const void*)L.desc && e.ncand == L.g.ncand && e.n == n &&
+        e.stream == L.stream) {
+      hip_check(hipGraphLaunch(e.exec, L.stream), "Jacobi sweep");
+      return;
+    }
+  // the legacy null stream cannot be captured
+  if (g_sweeps.size() >= kSweepGraphs || L.stream == nullptr) {
+    jacobi_rounds(L, n2, gp, ga);
+    check_launch("k_jac_apply");
+    return;
+  }
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hip_check(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal), "sweep capture");
+  jacobi_rounds(L, n2, gp, ga);
+  hip_check(hipStreamEndCapture(L.stream, &graph), "sweep capture");
+  hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "sweep graph");
+  g_sweeps.push_back({dev, (const void*)L.desc, L.g.ncand, n, L.stream, graph, exec});
+  hip_check(hipGraphLaunch(exec, L.stream), "Jacobi sweep");
+}
+
 void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   // up to 64 bands the matrices live in LDS; the thread count is a tuning
   // parameter (a single wavefront makes barriers almost free).  From
@@ -1661,16 +1734,13 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   // that needs a host read of the convergence flags per sweep, so it is not
   // used while a graph is being captured.
   const int n = L.g.nb_max;
-  const int use_lds = n <= 64 ? 1 : 0;
-  // LDS: the four matrices (rows padded to n + 1), or the panels of the
-  // blocked Cholesky and inverse of the global-memory solver
-  const size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1)
-                             : sizeof(double) * (size_t)chol_inv_lds_doubles(n);
+  const int use_lds = sub_lds_form(n);
+  const size_t lds = sub_lds_bytes(n, use_lds);
   const int nthr = L.g.sub_threads;
   prof_before("k_subspace", L.stream);
   if (mode == 3 && n >= L.g.jac_grid && L.jac_done && host_sync_allowed()) {
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode, 0,
-                       max_sweeps, 1);
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), sub_lds_bytes(n, 0), L.stream,
+                       L.desc, mode, 0, max_sweeps, 1);
     check_launch("k_subspace");
     const dim3 ge((n * n + kNT - 1) / kNT, L.g.ncand);
     hipLaunchKernelGGL(k_sub_wh, ge, dim3(kNT), 0, L.stream, L.desc);
@@ -1691,11 +1761,7 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
       bool all = true;
       for (int c = 0; c < L.g.ncand; ++c) all = all && L.jac_done_host[c] != 0;
       if (all) break;
-      for (int r = 0; r < n2 - 1; ++r) {
-        hipLaunchKernelGGL(k_jac_params, gp, dim3(kNT), 0, L.stream, L.desc, r);
-        hipLaunchKernelGGL(k_jac_apply, ga, dim3(kNT), 0, L.stream, L.desc);
-      }
-      check_launch("k_jac_apply");
+      jacobi_sweep(L, n, n2, gp, ga);
       ++done_sweeps;
     }
     hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
@@ -1787,9 +1853,8 @@ int subspace_noalloc(int device, int n, int mode, const double* S, const double*
   hipLaunchKernelGGL(k_noalloc_stage, dim3((nel + kNT - 1) / kNT), dim3(kNT), 0, stream, d, dd, S,
                      mode == 3 ? H : nullptr, nn);
   check_launch("k_noalloc_stage");
-  const int use_lds = n <= 64 ? 1 : 0;
-  const size_t lds = use_lds ? sizeof(double) * 4 * (size_t)n * (n + 1)
-                             : sizeof(double) * (size_t)chol_inv_lds_doubles(n);
+  const int use_lds = sub_lds_form(n);
+  const size_t lds = sub_lds_bytes(n, use_lds);
   hipLaunchKernelGGL(k_subspace, dim3(1), dim3(nthreads), lds, stream, dd, mode, use_lds, 40, 0);
   check_launch("k_subspace");
   if (status) {

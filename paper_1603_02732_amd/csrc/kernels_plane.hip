@@ -1,19 +1,17 @@
 // FP32 plane kernels of the band FFTs with register-resident line transforms
 // (the H psi step of Algorithm 1: the local-potential product in real
-// space; Section 2.4: the output density).  Each lane transforms a whole
-// line in registers (fft_reg.hpp):
-//   y pass   one lane per active column (the projection of the wavefunction
-//            sphere, |m1| <= m1max; the other columns are zero),
+// space; Section 2.4: the output density).  One wavefront takes one z-plane
+// of one band pair.  The plane lives in LDS only over its active x columns
+// (the projection of the wavefunction sphere, |m1| <= m1max, stored
+// compactly with an odd row stride so that both the column-wise and the
+// row-wise accesses are free of bank conflicts).  Each lane transforms a
+// whole line in registers (fft_reg.hpp):
+//   y pass   one lane per active column (the other columns are zero),
 //   x pass   one lane per row: inverse transform, times V_eff, forward
-//            transform (H psi), or the squared moduli (density),
-//   y pass   forward, then the stick values are gathered (H psi).
-// The H psi kernel keeps its planes at full width with a compile-time odd
-// row stride; the density kernel, one plane per wavefront next to its FP32
-// accumulator, keeps only the active columns (compact, odd runtime stride).
-// Odd strides keep both the column-wise and the row-wise accesses free of
-// bank conflicts.  The y and x phases are dispatched on N2 and N1
-// separately, so a kernel carries one instantiation per supported length
-// and axis, not per pair.
+//            transform, keeping only the active columns,
+//   y pass   forward, then the stick values are gathered.
+// The y and x phases are dispatched on N2 and N1 separately, so the kernel
+// carries one instantiation per supported length and axis, not per pair.
 #include "device.hpp"
 #include "fft_reg.hpp"
 #include "launch.hpp"
@@ -35,6 +33,54 @@ bool plane_reg_length_ok(int n) {
 #undef SGO_CASE
     default:
       return false;
+  }
+}
+
+struct PlaneLds {
+  cplx<float>* Q;  // [N2][sx], active columns only
+  int sx;          // row stride (odd, >= nx)
+  int nx, nxl;     // active columns: x < nxl and x >= N1 - (nx - nxl)
+};
+
+__device__ __forceinline__ int col_of_x(const PlaneLds& p, int N1, int x) {
+  return x < p.nxl ? x : x - (N1 - p.nx);
+}
+
+template <int N2, int S>
+__device__ __forceinline__ void column_pass(const PlaneLds& p, int lane) {
+  if (lane >= p.nx) return;
+  cplx<float> v[N2], w[N2];
+#pragma unroll
+  for (int k = 0; k < N2; ++k) v[k] = p.Q[k * p.sx + lane];
+  freg::fft<float, S, N2>(v, w);
+#pragma unroll
+  for (int k = 0; k < N2; ++k) p.Q[k * p.sx + lane] = w[k];
+}
+
+template <int S, int NMAX>
+__device__ __forceinline__ void column_pass_rt(const PlaneLds& p, int N2, int lane) {
+  switch (N2) {
+#define SGO_CASE(N)              \
+  case N:                        \
+    if constexpr (N <= NMAX) column_pass<N, S>(p, lane); \
+    break;
+    SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+    default:
+      break;
+  }
+}
+
+// Row y of the plane into registers (zeros outside the active columns).
+template <int N1>
+__device__ __forceinline__ void load_row(const PlaneLds& p, int y, cplx<float> (&v)[N1]) {
+  const int hi0 = N1 - (p.nx - p.nxl);
+#pragma unroll
+  for (int k = 0; k < N1; ++k) {
+    const bool act = k < p.nxl || k >= hi0;
+    const int c = act ? (k < p.nxl ? k : k - hi0 + p.nxl) : 0;
+    const cplx<float> q = p.Q[y * p.sx + c];
+    v[k] = act ? q : cplx<float>{0.f, 0.f};
   }
 }
 
@@ -62,134 +108,85 @@ __device__ __forceinline__ void load_vrow(const float* __restrict__ V, float (&r
   }
 }
 
-// H psi, local part, of a group of P consecutive z-planes of one band pair
-// per workgroup (P = 1 on one wavefront; larger groups on up to four
-// wavefronts share the lanes between planes whose line counts leave part of
-// a wavefront idle).  Unlike the density kernel's compact plane, each plane
-// is held at full width, Q[y * SX + x] for x < N1, with the compile-time odd
-// row stride SX = NMAX + 1: every LDS offset of a line is then an immediate,
-// the row pass reads and writes whole rows without selecting the active
-// columns, and only the column passes map lanes to the active columns.
-// Zeros outside the sticks are written once per plane; the row pass writes
-// all N1 values back (the forward column pass reads only the active ones).
-constexpr int kPlaneGroupMax = 8;  // largest group (SGO_PLANE_GROUP)
-
-template <int NMAX>
-constexpr int full_sx() { return NMAX + 1; }
-
-template <int N2, int S, int SX>
-__device__ __forceinline__ void hpsi_columns(cplx<float>* Q0, int pstride, int N1, int nx, int nxl,
-                                             int nlines, int tid, int nthreads) {
-  for (int l = tid; l < nlines; l += nthreads) {
-    const int j = l / nx, c = l - j * nx;
-    const int x = c < nxl ? c : c + (N1 - nx);
-    cplx<float>* q = Q0 + j * pstride + x;
-    cplx<float> v[N2], w[N2];
+// x pass of H psi for row y: inverse transform, V_eff product, forward
+// transform; the active columns are written back.
+template <int N1>
+__device__ __forceinline__ void row_pass_hpsi(const PlaneLds& p, int y, const float* __restrict__ V) {
+  cplx<float> v[N1], w[N1];
+  load_row<N1>(p, y, v);
+  freg::fft<float, +1, N1>(v, w);
+  float vr[N1];
+  load_vrow<N1>(V, vr);
 #pragma unroll
-    for (int k = 0; k < N2; ++k) v[k] = q[k * SX];
-    freg::fft<float, S, N2>(v, w);
+  for (int k = 0; k < N1; ++k) {
+    w[k].x *= vr[k];
+    w[k].y *= vr[k];
+  }
+  freg::fft<float, -1, N1>(w, v);
+  const int hi0 = N1 - (p.nx - p.nxl);
 #pragma unroll
-    for (int k = 0; k < N2; ++k) q[k * SX] = w[k];
+  for (int k = 0; k < N1; ++k) {
+    if (k < p.nxl) p.Q[y * p.sx + k] = v[k];
+    else if (k >= hi0) p.Q[y * p.sx + k - hi0 + p.nxl] = v[k];
   }
 }
 
-template <int S, int NMAX>
-__device__ __forceinline__ void hpsi_columns_rt(cplx<float>* Q0, int pstride, int N1, int N2, int nx, int nxl,
-                                                int nlines, int tid, int nthreads) {
-  switch (N2) {
-#define SGO_CASE(N)                                                                            \
-  case N:                                                                                      \
-    if constexpr (N <= NMAX)                                                                   \
-      hpsi_columns<N, S, full_sx<NMAX>()>(Q0, pstride, N1, nx, nxl, nlines, tid, nthreads);   \
-    break;
-    SGO_LINE_SIZES(SGO_CASE)
-#undef SGO_CASE
-    default:
-      break;
-  }
+__device__ __forceinline__ PlaneLds plane_of(const CandDesc& cd, cplx<float>* base) {
+  PlaneLds p;
+  p.Q = base;
+  p.nx = cd.pl_nx;
+  p.nxl = cd.pl_nxl;
+  p.sx = cd.pl_sx;
+  return p;
 }
 
-// x pass: inverse transform of each whole row, V_eff product, forward
-// transform, whole row written back.
-template <int N1, int SX>
-__device__ __forceinline__ void hpsi_rows(cplx<float>* Q0, int pstride, int N2, int nlines,
-                                          const float* __restrict__ V0, int tid, int nthreads) {
-  for (int l = tid; l < nlines; l += nthreads) {
-    const int j = l / N2, y = l - j * N2;
-    cplx<float>* q = Q0 + j * pstride + y * SX;
-    cplx<float> v[N1], w[N1];
-#pragma unroll
-    for (int k = 0; k < N1; ++k) v[k] = q[k];
-    freg::fft<float, +1, N1>(v, w);
-    float vr[N1];
-    load_vrow<N1>(V0 + ((size_t)j * N2 + y) * N1, vr);
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      w[k].x *= vr[k];
-      w[k].y *= vr[k];
-    }
-    freg::fft<float, -1, N1>(w, v);
-#pragma unroll
-    for (int k = 0; k < N1; ++k) q[k] = v[k];
-  }
-}
-
-template <int NMAX>
-__global__ void __launch_bounds__(256, 2) k_plane_hpsi_full(const CandDesc* __restrict__ cds, int group) {
-  constexpr int SX = full_sx<NMAX>();
-  const CandDesc& cd = cds[blockIdx.z];
-  if (!cd.active) return;
-  const int z0 = blockIdx.x * group, pair = blockIdx.y;
-  if (z0 >= cd.N3 || pair >= cd.npair) return;
-  const int np = min(group, cd.N3 - z0);
-  const int tid = threadIdx.x, nthreads = blockDim.x;
-  extern __shared__ __align__(16) char smem[];
-  cplx<float>* Q = (cplx<float>*)smem;
-  const int N1 = cd.N1, N2 = cd.N2, nst = cd.nst, nx = cd.pl_nx, nxl = cd.pl_nxl;
-  const int pstride = N2 * SX;
-  cplx<float>* st = (cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z0) * nst;
-  // zeros over the np planes, two values per store (the tail value apart)
-  {
-    const int n = np * pstride;
-    float4* Q4 = (float4*)smem;
-    for (int e = tid; e < n / 2; e += nthreads) Q4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if ((n & 1) && tid == 0) Q[n - 1] = {0.f, 0.f};
-  }
+// Sticks of plane (pair, z) into the compact plane (zeros elsewhere).
+__device__ __forceinline__ void scatter_sticks(const CandDesc& cd, const PlaneLds& p,
+                                               const cplx<float>* __restrict__ st, int lane) {
+  const int n = cd.N2 * p.sx;
+  for (int e = lane; e < n; e += 64) p.Q[e] = {0.f, 0.f};
   __syncthreads();
-  // sticks into the planes: every plane's stick values of a batch are
-  // loaded before any is stored, so the group waits for one memory latency
-  // per batch, not one per plane; the stick positions serve every plane
-  for (int s0 = tid; s0 < nst; s0 += 4 * nthreads) {
-    int off[4];
+  // batches of 4 sticks per lane: loads first, then the LDS stores
+  for (int s0 = lane; s0 < cd.nst; s0 += 256) {
+    int xy[4];
+    cplx<float> v[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int s = s0 + nthreads * u;
-      const int xy = s < nst ? cd.stick_xy[s] : 0;
-      off[u] = (xy >> 16) * SX + (xy & 0xFFFF);
+      const int s = s0 + 64 * u;
+      xy[u] = s < cd.nst ? cd.stick_xy[s] : 0;
+      v[u] = s < cd.nst ? st[s] : cplx<float>{0.f, 0.f};
     }
-    cplx<float> v[kPlaneGroupMax][4];
 #pragma unroll
-    for (int j = 0; j < kPlaneGroupMax; ++j)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int s = s0 + nthreads * u;
-        v[j][u] = (j < np && s < nst) ? st[(size_t)j * nst + s] : cplx<float>{0.f, 0.f};
-      }
-#pragma unroll
-    for (int j = 0; j < kPlaneGroupMax; ++j)
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (j < np && s0 + nthreads * u < nst) Q[j * pstride + off[u]] = v[j][u];
+    for (int u = 0; u < 4; ++u)
+      if (s0 + 64 * u < cd.nst) p.Q[(xy[u] >> 16) * p.sx + col_of_x(p, cd.N1, xy[u] & 0xFFFF)] = v[u];
   }
   __syncthreads();
-  hpsi_columns_rt<+1, NMAX>(Q, pstride, N1, N2, nx, nxl, np * nx, tid, nthreads);
+}
+
+// H psi, local part, of one plane of one band pair: sticks are read, and
+// overwritten by the forward transform of V_eff times the inverse transform.
+template <int NMAX>
+__global__ void __launch_bounds__(64, 2) k_plane_hpsi_reg(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int z = blockIdx.x, pair = blockIdx.y;
+  if (z >= cd.N3 || pair >= cd.npair) return;
+  extern __shared__ __align__(16) char smem[];
+  PlaneLds p = plane_of(cd, (cplx<float>*)smem);
+  const int lane = threadIdx.x;
+  cplx<float>* st = (cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
+  scatter_sticks(cd, p, st, lane);
+  column_pass_rt<+1, NMAX>(p, cd.N2, lane);
   __syncthreads();
-  {
-    const float* V0 = (const float*)cd.veff_t + (size_t)z0 * N2 * N1;
-    switch (N1) {
-#define SGO_CASE(N)                                                                \
-  case N:                                                                          \
-    if constexpr (N <= NMAX) hpsi_rows<N, SX>(Q, pstride, N2, np * N2, V0, tid, nthreads); \
+  // strides re-declared opaque between phases: per-line offsets are then
+  // recomputed in each phase instead of being held across all of them
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  if (lane < cd.N2) {
+    const float* V = (const float*)cd.veff_t + ((size_t)z * cd.N2 + lane) * cd.N1;
+    switch (cd.N1) {
+#define SGO_CASE(N)                       \
+  case N:                                 \
+    if constexpr (N <= NMAX) row_pass_hpsi<N>(p, lane, V);         \
     break;
       SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -198,21 +195,153 @@ __global__ void __launch_bounds__(256, 2) k_plane_hpsi_full(const CandDesc* __re
     }
   }
   __syncthreads();
-  hpsi_columns_rt<-1, NMAX>(Q, pstride, N1, N2, nx, nxl, np * nx, tid, nthreads);
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  column_pass_rt<-1, NMAX>(p, cd.N2, lane);
   __syncthreads();
-  for (int s0 = tid; s0 < nst; s0 += 4 * nthreads) {
+  for (int s0 = lane; s0 < cd.nst; s0 += 256) {
+    int xy[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) xy[u] = s0 + 64 * u < cd.nst ? cd.stick_xy[s0 + 64 * u] : 0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (s0 + 64 * u < cd.nst)
+        st[s0 + 64 * u] = p.Q[(xy[u] >> 16) * p.sx + col_of_x(p, cd.N1, xy[u] & 0xFFFF)];
+  }
+}
+
+// H psi, local part, of a group of consecutive z-planes of one band pair
+// per workgroup of four wavefronts.  The line transforms of all the planes
+// of the group are spread over the 256 lanes, so that planes whose line
+// counts leave part of a wavefront idle (say 35 active columns and 48 rows
+// on 64 lanes) share the lanes.  Each line is transformed exactly as in
+// k_plane_hpsi_reg; the planes lie one after another in LDS, each compact
+// (N2 rows of stride sx).
+constexpr int kPlaneGroupThreads = 256;
+constexpr int kPlaneGroupMax = 8;  // largest group (SGO_PLANE_GROUP)
+
+template <int N2, int S>
+__device__ __forceinline__ void column_lines(cplx<float>* Q0, int pstride, int sx, int nx, int nlines,
+                                             int tid) {
+  for (int l = tid; l < nlines; l += kPlaneGroupThreads) {
+    // strides re-declared opaque per line: the per-element offsets are
+    // recomputed in each pass of the loop instead of all being hoisted
+    int sxl = sx, psl = pstride;
+    asm volatile("" : "+s"(sxl), "+s"(psl));
+    const int j = l / nx, c = l - j * nx;
+    cplx<float>* q = Q0 + j * psl + c;
+    cplx<float> v[N2], w[N2];
+#pragma unroll
+    for (int k = 0; k < N2; ++k) v[k] = q[k * sxl];
+    freg::fft<float, S, N2>(v, w);
+#pragma unroll
+    for (int k = 0; k < N2; ++k) q[k * sxl] = w[k];
+  }
+}
+
+template <int S, int NMAX>
+__device__ __forceinline__ void column_lines_rt(cplx<float>* Q0, int pstride, int sx, int nx, int N2,
+                                                int nlines, int tid) {
+  switch (N2) {
+#define SGO_CASE(N)                                                 \
+  case N:                                                           \
+    if constexpr (N <= NMAX) column_lines<N, S>(Q0, pstride, sx, nx, nlines, tid);           \
+    break;
+    SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+    default:
+      break;
+  }
+}
+
+template <int N1>
+__device__ __forceinline__ void row_lines_hpsi(const PlaneLds& p0, int pstride, int N2, int nlines,
+                                               const float* __restrict__ V0, int tid) {
+  for (int l = tid; l < nlines; l += kPlaneGroupThreads) {
+    const int j = l / N2, y = l - j * N2;
+    PlaneLds p = p0;
+    int psl = pstride;
+    asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl), "+s"(psl));
+    p.Q = p0.Q + j * psl;
+    row_pass_hpsi<N1>(p, y, V0 + ((size_t)j * N2 + y) * N1);
+  }
+}
+
+template <int NMAX>
+__global__ void __launch_bounds__(kPlaneGroupThreads, 2) k_plane_hpsi_group(
+    const CandDesc* __restrict__ cds, int group) {
+  const CandDesc& cd = cds[blockIdx.z];
+  if (!cd.active) return;
+  const int z0 = blockIdx.x * group, pair = blockIdx.y;
+  if (z0 >= cd.N3 || pair >= cd.npair) return;
+  const int np = min(group, cd.N3 - z0);
+  extern __shared__ __align__(16) char smem[];
+  PlaneLds p = plane_of(cd, (cplx<float>*)smem);
+  const int tid = threadIdx.x;
+  const int N1 = cd.N1, N2 = cd.N2, nst = cd.nst;
+  const int pstride = N2 * p.sx;
+  cplx<float>* st = (cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z0) * nst;
+  // sticks of the np planes into the compact planes (zeros elsewhere); the
+  // stick positions are read once per batch and serve every plane
+  for (int e = tid; e < np * pstride; e += kPlaneGroupThreads) p.Q[e] = {0.f, 0.f};
+  __syncthreads();
+  // every plane's stick values of a batch are loaded before any is stored,
+  // so the group waits for one memory latency per batch, not one per plane
+  for (int s0 = tid; s0 < nst; s0 += 4 * kPlaneGroupThreads) {
     int off[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int s = s0 + nthreads * u;
+      const int s = s0 + kPlaneGroupThreads * u;
       const int xy = s < nst ? cd.stick_xy[s] : 0;
-      off[u] = (xy >> 16) * SX + (xy & 0xFFFF);
+      off[u] = (xy >> 16) * p.sx + col_of_x(p, N1, xy & 0xFFFF);
+    }
+    cplx<float> v[kPlaneGroupMax][4];
+#pragma unroll
+    for (int j = 0; j < kPlaneGroupMax; ++j)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int s = s0 + kPlaneGroupThreads * u;
+        v[j][u] = (j < np && s < nst) ? st[(size_t)j * nst + s] : cplx<float>{0.f, 0.f};
+      }
+#pragma unroll
+    for (int j = 0; j < kPlaneGroupMax; ++j)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j < np && s0 + kPlaneGroupThreads * u < nst) p.Q[j * pstride + off[u]] = v[j][u];
+  }
+  __syncthreads();
+  column_lines_rt<+1, NMAX>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
+  __syncthreads();
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  {
+    const float* V0 = (const float*)cd.veff_t + (size_t)z0 * N2 * N1;
+    switch (N1) {
+#define SGO_CASE(N)                                              \
+  case N:                                                        \
+    if constexpr (N <= NMAX) row_lines_hpsi<N>(p, pstride, N2, np * N2, V0, tid);         \
+    break;
+      SGO_LINE_SIZES(SGO_CASE)
+#undef SGO_CASE
+      default:
+        break;
+    }
+  }
+  __syncthreads();
+  asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+  column_lines_rt<-1, NMAX>(p.Q, pstride, p.sx, p.nx, N2, np * p.nx, tid);
+  __syncthreads();
+  for (int s0 = tid; s0 < nst; s0 += 4 * kPlaneGroupThreads) {
+    int off[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int s = s0 + kPlaneGroupThreads * u;
+      const int xy = s < nst ? cd.stick_xy[s] : 0;
+      off[u] = (xy >> 16) * p.sx + col_of_x(p, N1, xy & 0xFFFF);
     }
     for (int j = 0; j < np; ++j) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int s = s0 + nthreads * u;
-        if (s < nst) st[(size_t)j * nst + s] = Q[j * pstride + off[u]];
+        const int s = s0 + kPlaneGroupThreads * u;
+        if (s < nst) st[(size_t)j * nst + s] = p.Q[j * pstride + off[u]];
       }
     }
   }
@@ -221,21 +350,21 @@ __global__ void __launch_bounds__(256, 2) k_plane_hpsi_full(const CandDesc* __re
 // Density of one plane summed over a chunk of band pairs,
 // part[chunk][z][y][x] = sum_pairs f_a Re(u)^2 + f_b Im(u)^2 (u = psi_a + i psi_b,
 // unnormalised), accumulated in FP32 in LDS over the chunk's band pairs (row
-// stride N1 | 1); the chunks are summed in FP64 by k_density_finalize.  One
-// wavefront per plane; the plane is held at full width as in the H psi
-// kernel, the row pass reads whole rows and writes nothing back.
-template <int N1, int SX>
-__device__ __forceinline__ void density_row(const cplx<float>* q, float* a, float fa32, float fb32) {
+// stride N1 | 1); the chunks are summed in FP64 by k_density_finalize.
+template <int N1>
+__device__ __forceinline__ void row_pass_density(const PlaneLds& p, int y, float* acc, double fa,
+                                                 double fb) {
   cplx<float> v[N1], w[N1];
-#pragma unroll
-  for (int k = 0; k < N1; ++k) v[k] = q[k];
+  load_row<N1>(p, y, v);
   freg::fft<float, +1, N1>(v, w);
   // this pair's contribution, accumulated in FP32 over the chunk's band
   // pairs (a few per chunk; the chunks are summed in FP64 afterwards) in
   // groups of 8 (a scheduling fence per group keeps the accumulator loads
   // from all being hoisted at once)
-  freg::static_for<0, (N1 + 7) / 8>([&](auto qq) {
-    constexpr int K0 = 8 * decltype(qq)::value;
+  const float fa32 = (float)fa, fb32 = (float)fb;
+  float* a = acc + y * (N1 | 1);
+  freg::static_for<0, (N1 + 7) / 8>([&](auto q) {
+    constexpr int K0 = 8 * decltype(q)::value;
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = K0; k < (K0 + 8 < N1 ? K0 + 8 : N1); ++k)
@@ -245,51 +374,35 @@ __device__ __forceinline__ void density_row(const cplx<float>* q, float* a, floa
 
 template <int NMAX>
 __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __restrict__ cds) {
-  constexpr int SX = full_sx<NMAX>();
   const CandDesc& cd = cds[blockIdx.z];
   if (!cd.active) return;
   const int z = blockIdx.x, chunk = blockIdx.y;
   if (z >= cd.N3 || chunk >= cd.ndens_chunk) return;
   extern __shared__ __align__(16) char smem[];
-  cplx<float>* Q = (cplx<float>*)smem;
+  const PlaneLds p_outer = plane_of(cd, (cplx<float>*)smem);
+  float* acc = (float*)(smem + (size_t)cd.N2 * p_outer.sx * sizeof(cplx<float>));
   const int lane = threadIdx.x;
-  const int N1 = cd.N1, N2 = cd.N2, ar = N1 | 1, nst = cd.nst, nx = cd.pl_nx, nxl = cd.pl_nxl;
-  const int n = N2 * SX;  // plane size in complex values
-  float* acc = (float*)(smem + (size_t)n * sizeof(cplx<float>));
+  const int N1 = cd.N1, N2 = cd.N2, ar = N1 | 1;
   for (int e = lane; e < N2 * ar; e += 64) acc[e] = 0.f;
   const int per = (cd.npair + cd.ndens_chunk - 1) / cd.ndens_chunk;
   const int p0 = chunk * per, p1 = min(cd.npair, p0 + per);
   for (int pair = p0; pair < p1; ++pair) {
-    // zeros, then the sticks of this pair
-    float4* Q4 = (float4*)smem;
-    for (int e = lane; e < n / 2; e += 64) Q4[e] = make_float4(0.f, 0.f, 0.f, 0.f);
-    if ((n & 1) && lane == 0) Q[n - 1] = {0.f, 0.f};
+    // the plane strides are re-declared opaque in every iteration, so the
+    // per-line offsets of all line lengths are not hoisted out of the loop
+    // (they would exhaust the scalar registers)
+    PlaneLds p = p_outer;
+    asm volatile("" : "+s"(p.sx), "+s"(p.nx), "+s"(p.nxl));
+    const cplx<float>* st = (const cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z) * cd.nst;
+    scatter_sticks(cd, p, st, lane);
+    column_pass_rt<+1, NMAX>(p, N2, lane);
     __syncthreads();
-    const cplx<float>* st = (const cplx<float>*)cd.sticks + ((size_t)pair * cd.N3 + z) * nst;
-    for (int s0 = lane; s0 < nst; s0 += 256) {
-      int off[4];
-      cplx<float> v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int s = s0 + 64 * u;
-        const int xy = s < nst ? cd.stick_xy[s] : 0;
-        off[u] = (xy >> 16) * SX + (xy & 0xFFFF);
-        v[u] = s < nst ? st[s] : cplx<float>{0.f, 0.f};
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-        if (s0 + 64 * u < nst) Q[off[u]] = v[u];
-    }
-    __syncthreads();
-    hpsi_columns_rt<+1, NMAX>(Q, 0, N1, N2, nx, nxl, nx, lane, 64);
-    __syncthreads();
-    const float fa = (float)cd.occ[2 * pair];
-    const float fb = 2 * pair + 1 < cd.nb ? (float)cd.occ[2 * pair + 1] : 0.f;
+    const double fa = cd.occ[2 * pair];
+    const double fb = 2 * pair + 1 < cd.nb ? cd.occ[2 * pair + 1] : 0.0;
     if (lane < N2) {
       switch (N1) {
-#define SGO_CASE(N)                                                                      \
-  case N:                                                                                \
-    if constexpr (N <= NMAX) density_row<N, SX>(Q + lane * SX, acc + lane * ar, fa, fb); \
+#define SGO_CASE(N)                                   \
+  case N:                                             \
+    if constexpr (N <= NMAX) row_pass_density<N>(p, lane, acc, fa, fb);        \
     break;
         SGO_LINE_SIZES(SGO_CASE)
 #undef SGO_CASE
@@ -299,6 +412,7 @@ __global__ void __launch_bounds__(64, 2) k_plane_density_reg(const CandDesc* __r
     }
     __syncthreads();
   }
+  __syncthreads();
   double* out = cd.dens_part + (size_t)chunk * cd.ntot + (size_t)z * N1 * N2;
   for (int e = lane; e < N1 * N2; e += 64) out[e] = (double)acc[(e / N1) * ar + e % N1];
 }
@@ -510,42 +624,32 @@ void launch_z_forward_reg(const LaunchCtx& L, int src, int dst) {
   prof_after("k_z_forward", L.stream);
 }
 
-static int plane_nmax(const BatchGeom& g) { return small_lines(g) ? 48 : 64; }
-
-// LDS of the density kernel: one full-width plane and its accumulator
 size_t plane_reg_lds(const BatchGeom& g, bool density) {
-  size_t b = (size_t)g.N2max * (plane_nmax(g) + 1) * sizeof(cplx<float>);
+  size_t b = (size_t)g.N2max * g.pl_sx_max * sizeof(cplx<float>);
   if (density) b += (size_t)g.N2max * (g.N1max | 1) * sizeof(float);
   return b;
 }
 
 size_t plane_group_lds(const BatchGeom& g, int group) {
-  return (size_t)group * g.N2max * (plane_nmax(g) + 1) * sizeof(cplx<float>);
-}
-
-// Lanes of the H psi plane kernel for a group of P planes: enough
-// wavefronts for the larger of the two line counts, at most four.
-static int plane_group_threads(const BatchGeom& g, int group) {
-  const int lines = group * std::max(std::max(1, g.pl_sx_max), std::max(1, g.N2max));
-  return std::min(256, (lines + 63) / 64 * 64);
+  return (size_t)group * g.N2max * g.pl_sx_max * sizeof(cplx<float>);
 }
 
 int plane_group_size(const BatchGeom& g, size_t lds_per_cu, int forced) {
-  // wavefront line-transform rounds per plane: a group of P planes runs
-  // ceil(P nx / 64) wavefronts over the two column passes and ceil(P N2 / 64)
-  // over the row pass (two transforms per row); at least two groups must fit
-  // one compute unit's LDS
-  auto waves = [](int lines) { return (lines + 63) / 64; };
+  // wavefront time per plane, in line-transform rounds of one wavefront:
+  // one plane per wavefront takes 2 column rounds and 2 row rounds
+  // (ceil(lines / 64) each); a group of P planes on four wavefronts takes
+  // 4 x the rounds over 256 lanes, shared by P planes.  Two groups must fit
+  // one compute unit's LDS, as two one-plane wavefronts per SIMD do.
+  auto rounds = [](int lines, int lanes) { return (lines + lanes - 1) / lanes; };
   const int nx = std::max(1, g.pl_sx_max), N2 = std::max(1, g.N2max);
-  const double single = 2.0 * waves(nx) + 2.0 * waves(N2);
+  const double single = 2.0 * rounds(nx, 64) + 2.0 * rounds(N2, 64);
   int best = 1;
   double best_t = single;
   for (int P = 2; P <= kPlaneGroupMax; ++P) {
-    if (2 * plane_group_lds(g, P) > lds_per_cu || plane_group_threads(g, P) > 256 ||
-        P * std::max(nx, N2) > 256)
-      break;
+    if (2 * plane_group_lds(g, P) > lds_per_cu) break;
+    const double t = 4.0 * (2 * rounds(P * nx, kPlaneGroupThreads) +
+                            2 * rounds(P * N2, kPlaneGroupThreads)) / P;
     if (forced == P) return P;
-    const double t = (2.0 * waves(P * nx) + 2.0 * waves(P * N2)) / P;
     if (t < 0.9 * best_t) {
       best = P;
       best_t = t;
@@ -556,14 +660,22 @@ int plane_group_size(const BatchGeom& g, size_t lds_per_cu, int forced) {
 
 void launch_plane_hpsi_reg(const LaunchCtx& L) {
   const BatchGeom& g = L.g;
-  const int P = std::max(1, g.plane_group);
-  dim3 gp((g.N3max + P - 1) / P, g.npair_max, g.ncand);
-  const dim3 threads(plane_group_threads(g, P));
   prof_before("k_plane_hpsi", L.stream);
-  if (small_lines(g))
-    hipLaunchKernelGGL(k_plane_hpsi_full<48>, gp, threads, plane_group_lds(g, P), L.stream, L.desc, P);
-  else
-    hipLaunchKernelGGL(k_plane_hpsi_full<64>, gp, threads, plane_group_lds(g, P), L.stream, L.desc, P);
+  if (g.plane_group > 1) {
+    dim3 gp((g.N3max + g.plane_group - 1) / g.plane_group, g.npair_max, g.ncand);
+    if (small_lines(g))
+      hipLaunchKernelGGL(k_plane_hpsi_group<48>, gp, dim3(kPlaneGroupThreads),
+                         plane_group_lds(g, g.plane_group), L.stream, L.desc, g.plane_group);
+    else
+      hipLaunchKernelGGL(k_plane_hpsi_group<64>, gp, dim3(kPlaneGroupThreads),
+                         plane_group_lds(g, g.plane_group), L.stream, L.desc, g.plane_group);
+  } else {
+    dim3 gp(g.N3max, g.npair_max, g.ncand);
+    if (small_lines(g))
+      hipLaunchKernelGGL(k_plane_hpsi_reg<48>, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
+    else
+      hipLaunchKernelGGL(k_plane_hpsi_reg<64>, gp, dim3(64), plane_reg_lds(g, false), L.stream, L.desc);
+  }
   check_launch("k_plane_hpsi");
   prof_after("k_plane_hpsi", L.stream);
 }
@@ -581,11 +693,13 @@ void launch_plane_density_reg(const LaunchCtx& L) {
 }
 
 void configure_plane_kernels() {
-  allow_lds((const void*)k_plane_hpsi_full<48>);
+  allow_lds((const void*)k_plane_hpsi_reg<48>);
+  allow_lds((const void*)k_plane_hpsi_group<48>);
   allow_lds((const void*)k_plane_density_reg<48>);
   allow_lds((const void*)k_z_inverse_reg<48>);
   allow_lds((const void*)k_z_forward_reg<48>);
-  allow_lds((const void*)k_plane_hpsi_full<64>);
+  allow_lds((const void*)k_plane_hpsi_reg<64>);
+  allow_lds((const void*)k_plane_hpsi_group<64>);
   allow_lds((const void*)k_plane_density_reg<64>);
   allow_lds((const void*)k_z_inverse_reg<64>);
   allow_lds((const void*)k_z_forward_reg<64>);
