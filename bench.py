@@ -165,6 +165,11 @@ CLUSTER_MIXING = {"mix_alpha": 0.3, "kerker_q0": 0.3, "ncg_first": 6}
 # density residual below RHO_GATE (the residual bounds the force error at
 # termination: 3e-4 keeps it well inside the FP32 force tolerance)
 RHO_GATE = 3e-4
+# the cluster population's density gate: with the residual gate below, bands
+# may stop at a weighted residual of max(1e-4, 0.1 sqrt(1e-5)) = 3.2e-4 Ha,
+# and at 3e-4 one cluster's forces ended 5.8e-4 Ha/bohr from the oracle's;
+# at 1.5e-4 every stored candidate stays within 2e-4 Ha/bohr
+C3_RHO_GATE = 1.5e-4
 # residual gate on the CG steps (library option cg_tol): a candidate counts
 # as converged only when every band holding charge has its occupation-
 # weighted residual at the gate; without it a slowly converging cluster can
@@ -253,7 +258,7 @@ LEGS = {
     "C4_uneven_population_batched": lambda sgo, wl, sync: c4_run(sgo, wl, sync),
     "C5_large_cell": lambda sgo, wl, sync: c5_run(sgo, wl, sync),
     "C3_one_batch": lambda sgo, wl, sync: one_batch_run(
-        sgo, wl.config_c3(32), sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, cg_tol=CG_GATE,
+        sgo, wl.config_c3(32), sgo.default_opts(tol_e=1e-5, tol_rho=C3_RHO_GATE, cg_tol=CG_GATE,
                                                 max_iter=150, **CLUSTER_MIXING), sync),
     "cpu_oracle": lambda sgo, wl, sync: cpu_oracle_run(wl),
 }
@@ -365,7 +370,7 @@ def main():
         for s in pop[bounds[j]:bounds[j + 1]]:
             b.add_system(s)
         Bs.append(b)
-    opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, cg_tol=CG_GATE, max_iter=150,
+    opts = sgo.default_opts(tol_e=1e-5, tol_rho=C3_RHO_GATE, cg_tol=CG_GATE, max_iter=150,
                             use_graph=int(schedule["use_graph"]) if schedule else 0,
                             **CLUSTER_MIXING)
     geoms = []
@@ -382,9 +387,29 @@ def main():
             return Bs[0].scf(opts)
         return sgo.batches_scf(Bs, opts)
 
+    # per-kernel timing runs on one stream: with concurrent batches a
+    # launch's interval also covers the other streams' work, so the kernel
+    # shares and the roofline's HIP-event timings come from the same 32
+    # candidates as one batch on one stream (nsplit == 1: the headline's own
+    # batch and timed region)
+    if nsplit == 1:
+        B1 = Bs[0]
+    else:
+        B1 = sgo.Batch(len(pop), precision=sgo.SGO_FP32)
+        if have_torch:
+            B1.set_stream(torch.cuda.current_stream().cuda_stream)
+        for s in pop:
+            B1.add_system(s)
+
+    def step1():
+        B1.reset()
+        return B1.scf(opts)
+
     # warm-up, and the per-kernel share of a step to find the dominant kernel
     for _ in range(a.warmup):
         step()
+        if nsplit > 1:
+            step1()
     sync()
     if have_torch:
         # a plain device copy of known size (read 64 MiB, write 64 MiB): the
@@ -397,21 +422,23 @@ def main():
         del src, dst
     shares = {}
     t0 = time.perf_counter()
-    step()
+    step1()
     sync()
     t_one = time.perf_counter() - t0
     kprof = {}
     for k in CANDIDATE_KERNELS:
         sgo.profile_begin(k)
-        step()
+        step1()
         sync()
         kprof[k] = sgo.profile_end()
         shares[k] = kprof[k]["ms"] * 1e-3 / t_one
     dominant = max(shares, key=shares.get)
 
-    # timed region: K batched steps, dominant kernel bracketed by HIP events
+    # timed region: K batched steps of the headline schedule (on one stream,
+    # the dominant kernel bracketed by HIP events)
     sync()
-    sgo.profile_begin(dominant)
+    if nsplit == 1:
+        sgo.profile_begin(dominant)
     t0 = time.perf_counter()
     status_ok = True
     for _ in range(a.steps):
@@ -419,9 +446,22 @@ def main():
         status_ok = status_ok and bool(np.all(st == 0))
     sync()
     dt = time.perf_counter() - t0
-    prof = sgo.profile_end()
     n_eval = a.steps * len(pop)
     value = n_eval / dt
+    if nsplit == 1:
+        prof = sgo.profile_end()
+        one_stream = None
+    else:
+        # the same K steps as one batch on one stream, dominant kernel timed
+        sgo.profile_begin(dominant)
+        t1 = time.perf_counter()
+        for _ in range(a.steps):
+            step1()
+        sync()
+        dt1 = time.perf_counter() - t1
+        prof = sgo.profile_end()
+        B1.close()
+        one_stream = {"evals_per_s": n_eval / dt1, "ms_per_step": dt1 / a.steps * 1e3}
 
     # every launch covers the whole population, but candidates that have
     # converged return at once: the work of a launch is that of the
@@ -450,6 +490,11 @@ def main():
         peak = FP64_PEAK_TFLOPS
     traffic = counters_traffic(dominant)
     roof = {"bound": bound, "kernel": dominant, "achieved": ach, "peak": peak, "unit": unit,
+            "measured_on": ("the timed steps" if nsplit == 1 else
+                            "%d timed steps of the same 32 candidates as one batch on one stream "
+                            "(the headline's %d concurrent batches overlap their launches)"
+                            % (a.steps, nsplit)),
+            "one_stream_steps": one_stream,
             "frac": ach / peak, "traffic": traffic, "avg_launch_us": avg_s * 1e6,
             "union_us_per_launch": span_s * 1e6,
             "launches_per_step": prof["launches"] / a.steps,
@@ -526,7 +571,7 @@ def main():
                                          "%d concurrent batches of %d on %d streams (autotuner's "
                                          "pick)" % (nsplit, len(pop) // nsplit, nsplit)),
                       "candidates_per_step": len(pop), "all_converged": status_ok,
-                      "scf_gate": {"dE_per_atom": 1e-5, "density_residual": RHO_GATE,
+                      "scf_gate": {"dE_per_atom": 1e-5, "density_residual": C3_RHO_GATE,
                                    "weighted_band_residual": CG_GATE},
                       "solver": dict(CLUSTER_MIXING, history=8, mixing="Pulay+Kerker", ncg=3),
                       "launch_schedule": schedule or "library defaults",
@@ -740,7 +785,7 @@ def plain_runs(sgo, workloads, sync):
                                ("C3_cluster", workloads.config_c3(1)[0], sgo.SGO_FP32),
                                ("C3_cluster_fp64", workloads.config_c3(1)[0], sgo.SGO_FP64)):
         ctx = sgo.context_from_system(system, prec)
-        opts = sgo.default_opts(tol_e=1e-5, tol_rho=RHO_GATE, cg_tol=CG_GATE, max_iter=150,
+        opts = sgo.default_opts(tol_e=1e-5, tol_rho=C3_RHO_GATE, cg_tol=CG_GATE, max_iter=150,
                                 **CLUSTER_MIXING)
 
         def step():

@@ -16,6 +16,8 @@ import json
 import os
 import time
 
+import numpy as np
+
 from . import set_tuning, default_opts, SGO_ENOTCONV
 
 SPACE = {
@@ -144,10 +146,11 @@ def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False, 
     return dict(sched, cached=False, timings=timings, seconds_per_iterations=base)
 
 
-def tune_batch_split(systems, precision, gate_opts, splits=None, reps=2, verbose=False):
+def tune_batch_split(systems, precision, gate_opts, splits=None, reps=5, verbose=False):
     """Time whole cold solves of the population to the caller's gate, as one
     batch and split into k batches solved at once on k streams (one host
-    thread each).  Returns (best k, {k: seconds})."""
+    thread each), taking the median of `reps` solves (host threads launching
+    into one device make single solves noisy).  Returns (best k, {k: seconds})."""
     import torch
     from . import Batch, batches_scf
     timings = {}
@@ -174,16 +177,17 @@ def tune_batch_split(systems, precision, gate_opts, splits=None, reps=2, verbose
             torch.cuda.synchronize()
 
         solve()  # warm-up and allocation
-        best = float("inf")
+        ts = []
         for _ in range(reps):
             t0 = time.perf_counter()
             solve()
-            best = min(best, time.perf_counter() - t0)
+            ts.append(time.perf_counter() - t0)
         for b in bs:
             b.close()
-        timings[k] = best
+        timings[k] = float(np.median(ts))
         if verbose:
-            print("autotune batches=%d: %.2f ms" % (k, best * 1e3), flush=True)
+            print("autotune batches=%d: median %.2f ms (min %.2f, max %.2f)"
+                  % (k, timings[k] * 1e3, min(ts) * 1e3, max(ts) * 1e3), flush=True)
     best_k = min(timings, key=timings.get)
     if timings[best_k] > 0.98 * timings.get(1, float("inf")):
         best_k = 1
@@ -210,7 +214,7 @@ def _main():
             B.add_system(s)
         res = autotune(B, pop, SGO_FP32, iters=a.iters, use_cache=False, verbose=True)
         B.close()
-        gate = default_opts(tol_e=1e-5, tol_rho=3e-4, cg_tol=1e-4, max_iter=150, mix_alpha=0.3,
+        gate = default_opts(tol_e=1e-5, tol_rho=1.5e-4, cg_tol=1e-4, max_iter=150, mix_alpha=0.3,
                             kerker_q0=0.3, ncg_first=6, use_graph=res["use_graph"])
         k, tk = tune_batch_split(pop, SGO_FP32, gate, verbose=True)
         res["batches"] = k
