@@ -149,8 +149,11 @@ def autotune(batch, systems, precision, iters=4, use_cache=True, verbose=False, 
 def tune_batch_split(systems, precision, gate_opts, splits=None, reps=5, verbose=False):
     """Time whole cold solves of the population to the caller's gate, as one
     batch and split into k batches solved at once on k streams (one host
-    thread each), taking the median of `reps` solves (host threads launching
-    into one device make single solves noisy).  Returns (best k, {k: seconds})."""
+    thread each), taking the median of `reps` solves.  Each stream should
+    have a hardware queue of its own (GPU_MAX_HW_QUEUES >= k + 4 set before
+    the HIP runtime starts): with HIP's default of 4 the streams share queues
+    depending on how many streams the process created before them.  Returns
+    (best k, {k: seconds})."""
     import torch
     from . import Batch, batches_scf
     timings = {}
@@ -196,6 +199,10 @@ def tune_batch_split(systems, precision, gate_opts, splits=None, reps=5, verbose
 
 def _main():
     """Tune the standard populations on this device and write the table."""
+    # a hardware queue per concurrent batch (see tune_batch_split), raised
+    # to at least 8 before the runtime starts
+    if int(os.environ.get("GPU_MAX_HW_QUEUES", "4") or 4) < 8:
+        os.environ["GPU_MAX_HW_QUEUES"] = "8"
     import argparse
     import sys
     ap = argparse.ArgumentParser()

@@ -641,20 +641,33 @@ __global__ void __launch_bounds__(64 * NW) k_gemm_f32(const CandDesc* __restrict
     for (int t = 0; t < TT; ++t)
 #pragma unroll
       for (int c = 0; c < 4; ++c) acc[t][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int j0 = 0; j0 < nin; j0 += 4) {
-      const int j = j0 + g;
-      const float4 b = j < nin ? As[j * 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
-      const double hj = (use_h && j < nin) ? cd.hproj[j] : 1.0;
+    // four 4-deep steps per pass: their M loads (global, FP64) and LDS
+    // loads are all issued before the first product, so a pass waits for
+    // one load latency instead of four
+    for (int j00 = 0; j00 < nin; j00 += 16) {
+      float4 b[4];
+      float a[4][TT];
 #pragma unroll
-      for (int t = 0; t < TT; ++t) {
-        if (i0 + 16 * t >= nout) break;
-        const int i = i0 + 16 * t + n;
-        const float a = (j < nin && i < nout) ? (float)(hj * M[(size_t)j * nout + i]) : 0.f;
-        acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.x, acc[t][0], 0, 0, 0);
-        acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.y, acc[t][1], 0, 0, 0);
-        acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.z, acc[t][2], 0, 0, 0);
-        acc[t][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b.w, acc[t][3], 0, 0, 0);
+      for (int u = 0; u < 4; ++u) {
+        const int j = j00 + 4 * u + g;
+        b[u] = j < nin ? As[j * 16 + n] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const double hj = (use_h && j < nin) ? cd.hproj[j] : 1.0;
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          const int i = i0 + 16 * t + n;
+          a[u][t] = (j < nin && i < nout) ? (float)(hj * M[(size_t)j * nout + i]) : 0.f;
+        }
       }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) {
+          if (i0 + 16 * t >= nout) break;
+          acc[t][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][t], b[u].x, acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][t], b[u].y, acc[t][1], 0, 0, 0);
+          acc[t][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][t], b[u].z, acc[t][2], 0, 0, 0);
+          acc[t][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][t], b[u].w, acc[t][3], 0, 0, 0);
+        }
     }
     if (!kin) continue;
 #pragma unroll
