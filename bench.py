@@ -92,9 +92,10 @@ def kernel_digest():
 
 def summarize_counters(fetch_csv, write_csv):
     """Per-kernel HBM bytes per dispatch from two rocprofv3 --pmc runs of the
-    bench (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
-    the same counter reads for the calibration copy (torch add of 64 MiB:
-    reads 64 MiB, writes 64 MiB).  Prints the summary text."""
+    one-stream leg (--leg C3_one_batch: the launches the roofline times;
+    FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the
+    same counter reads for the calibration copy (torch add of 64 MiB: reads
+    64 MiB, writes 64 MiB).  Prints the summary text."""
     import collections
     import csv
 
@@ -428,14 +429,7 @@ def main():
             step1()
     sync()
     if have_torch:
-        # a plain device copy of known size (read 64 MiB, write 64 MiB): the
-        # reference that scales hardware byte counters (FETCH_SIZE,
-        # WRITE_SIZE) of a profiled run to bytes
-        src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.add(src, 0.0, out=dst)
-        sync()
-        del src, dst
+        calibration_copy(sync)
     shares = {}
     t0 = time.perf_counter()
     step1()
@@ -716,6 +710,18 @@ def c4_run(sgo, workloads, sync):
             "solver": C4_OPTS}
 
 
+def calibration_copy(sync):
+    """A plain device copy of known size (read 64 MiB, write 64 MiB): the
+    reference that scales the hardware byte counters (FETCH_SIZE, WRITE_SIZE)
+    of a profiled run to bytes."""
+    import torch
+    src = torch.ones(16 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.add(src, 0.0, out=dst)
+    sync()
+    del src, dst
+
+
 def one_batch_run(sgo, pop, opts, sync, steps=3):
     """The same population as one batch on one stream (every launch covers
     all 32 candidates), timed the same way, beside the tuned schedule."""
@@ -730,6 +736,10 @@ def one_batch_run(sgo, pop, opts, sync, steps=3):
 
     step()
     sync()
+    try:
+        calibration_copy(sync)  # for counter runs of this leg
+    except ImportError:
+        pass
     t0 = time.perf_counter()
     for _ in range(steps):
         E, F, st = step()

@@ -1055,10 +1055,12 @@ __device__ bool chol_inv_blocked(double* __restrict__ A, double* __restrict__ Wm
 }
 
 // phase 0: the whole solve; 1: Cholesky and W = L^-1 only (the congruence,
-// the Jacobi rounds and M = W^T V then run over the whole GPU: k_sub_*,
-// k_jac_*); 2: eigenvalue order and the sorted M, eps from the converged H'
-// and the product W^T V already in S.  Phases 1 and 2 keep the matrices in
-// global memory (use_lds = 0).
+// and M = W^T V then run over the whole GPU: k_sub_*; the Jacobi rounds too
+// from g.jac_grid bands, k_jac_*); 3: the Jacobi rounds of the H' that
+// k_sub_wh/k_sub_twt formed, in the workgroup (H' in LDS up to 128 bands);
+// 2: eigenvalue order and the sorted M, eps from the converged H' and the
+// product W^T V already in S.  Phases 1-3 keep W, V and the products in
+// global memory.
 __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict__ cds, int mode,
                                                      int use_lds, int max_sweeps, int phase) {
   const CandDesc& cd = cds[blockIdx.x];
@@ -1102,7 +1104,24 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     clk[3] = clock64();
     clk[5] = max_sweeps;  // the sweeps the grid rounds took
   }
+  if (phase == 2 && cd.scal[S_ERR] == 2.0) {
+    // this call's Cholesky failed: the rotation stays the identity
+    for (int e = tid; e < n * n; e += nthr) cd.M[e] = (e / n == e % n) ? 1.0 : 0.0;
+    return;
+  }
+  if (phase == 3) {
+    // Jacobi of the H' that the products over the GPU formed (in Hs; V^T = I
+    // in M), unless this call's Cholesky failed
+    if (cd.scal[S_ERR] == 2.0) return;
+    if (use_lds == 2)
+      for (int e = tid; e < n * n; e += nthr) {
+        const int i = e / n, j = e - i * n;
+        H1[i * ldh + j] = cd.Hs[e];
+      }
+    __syncthreads();
+  }
   if (phase != 2) {
+   if (phase != 3) {
     if (tid == 0) fail = 0;
     if (clk && tid == 0) clk[0] = clock64();
     __syncthreads();
@@ -1198,6 +1217,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
       P3[i * ld + j] = (i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
+   }
     // Cyclic Jacobi with the round-robin ordering of disjoint index pairs.
     // Phase A computes the rotations of a round; in phase B the threads take
     // the (row pair, column pair) 2x2 blocks, rotating them in place, then
@@ -1277,6 +1297,15 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     if (clk && tid == 0) {
       clk[3] = clock64();
       clk[5] = nsweep;
+    }
+    if (phase == 3) {
+      // H' back for the sort (phase 2); M = W^T V runs over the GPU
+      if (use_lds == 2)
+        for (int e = tid; e < n * n; e += nthr) {
+          const int i = e / n, j = e - i * n;
+          cd.Hs[e] = H1[i * ldh + j];
+        }
+      return;
     }
   }
   // ranks of the eigenvalues (ascending, ties by index)
@@ -1769,6 +1798,25 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
     // phase 2 takes the sweep count in place of the sweep limit (debug clocks)
     hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
                        done_sweeps, 2);
+    check_launch("k_subspace");
+  } else if (mode == 3 && n > 64) {
+    // Cholesky and W in the workgroup, the congruence and M = W^T V over the
+    // whole GPU (one thread per element: these n^3 products were the slow
+    // part of the one-workgroup solve in global memory), the Jacobi rounds
+    // in the workgroup with H' in LDS up to 128 bands; no host sync, so the
+    // same path serves graph capture
+    const dim3 ge((n * n + kNT - 1) / kNT, L.g.ncand);
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), sub_lds_bytes(n, 0), L.stream,
+                       L.desc, mode, 0, max_sweeps, 1);
+    hipLaunchKernelGGL(k_sub_wh, ge, dim3(kNT), 0, L.stream, L.desc);
+    hipLaunchKernelGGL(k_sub_twt, ge, dim3(kNT), 0, L.stream, L.desc);
+    const int jl = n <= 128 ? 2 : 0;
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr),
+                       jl == 2 ? sizeof(double) * (size_t)n * (n + 1) : 0, L.stream, L.desc, mode, jl,
+                       max_sweeps, 3);
+    hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
+    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
+                       max_sweeps, 2);
     check_launch("k_subspace");
   } else {
     hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode,
