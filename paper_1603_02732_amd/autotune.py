@@ -30,11 +30,12 @@ SPACE = {
     "SGO_DENS_CHUNKS": [1, 2, 4, 8],
     "SGO_RR_SWEEPS": [1, 2],
     "SGO_JAC_GRID": [96, 160, 100000],
+    "SGO_GEMM_WAVES": [4, 6],
     "use_graph": [0, 1, 2, 4],
 }
 # keys that only act from some band count on (largest band count of the
 # population must reach it, else the key is not timed)
-MIN_BANDS = {"SGO_JAC_GRID": 96}
+MIN_BANDS = {"SGO_JAC_GRID": 96, "SGO_GEMM_WAVES": 128}
 # batch schedule: the population split into this many batches, each on its
 # own stream from its own host thread (sgo_batches_scf), timed as whole
 # solves to the caller's gate

@@ -701,6 +701,7 @@ class Engine {
     // that fills the lanes better (tuning key SGO_PLANE_GROUP, 1 = off)
     g.plane_group = g.plane_reg ? plane_group_size(g, (size_t)g_lds_limit, tune("SGO_PLANE_GROUP", 0)) : 1;
     g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
+    g.gemm_waves = tune("SGO_GEMM_WAVES", 8);
     g.gram_f32 = tsize() == 4 && tune("SGO_GRAM_KERNEL", 1) == 2 ? 1 : 0;
     g.bf16proj = prec_ == SGO_FP32_BF16PROJ ? 1 : 0;
     g.lds_limit = (size_t)g_lds_limit;
@@ -2428,7 +2429,8 @@ int sgo_set_tuning(const char* key, int value) {
   static const char* known[] = {"SGO_GRAM_KC", "SGO_SUB_THREADS", "SGO_SP_CHUNK",
                                 "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
                                 "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL", "SGO_PCG_TRIAL",
-                                "SGO_PCG_FLOOR", "SGO_JAC_GRID", "SGO_PLANE_GROUP", "SGO_COMPACT"};
+                                "SGO_PCG_FLOOR", "SGO_JAC_GRID", "SGO_PLANE_GROUP", "SGO_COMPACT",
+                                "SGO_GEMM_WAVES"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;

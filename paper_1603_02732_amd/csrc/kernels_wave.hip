@@ -1274,13 +1274,21 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
     rows_moved += nin + (alpha != 0.0 ? 2 : 1) * g.nb_max;
   }
   // the MFMA kernel stages all nin input rows of its 64 columns in LDS; from
-  // 128 bands (32 KB a slice: few slices resident per compute unit) four
-  // wavefronts share a slice, each taking every fourth 32-row output tile
+  // 128 bands (32 KB a slice: few slices resident per compute unit) several
+  // wavefronts share a slice, each taking every NW-th output tile (282 bands:
+  // 809 ms per evaluation of the 128-atom cell with 4 wavefronts and 32-row
+  // tiles, 745 with 8 and 16-row tiles)
   const size_t lds32 = (size_t)nin_max * 64 * sizeof(float);
   if (std::is_same<T, float>::value && lds32 <= g.lds_limit && g.gemm_f32) {
     prof_before("k_gemm_acc", L.stream);
     const dim3 grid32((g.K_max + 63) / 64, narr, g.ncand);
-    if (nin_max >= 128)
+    if (nin_max >= 128 && g.gemm_waves >= 8)
+      hipLaunchKernelGGL((k_gemm_f32<1, 8>), grid32, dim3(512), lds32, L.stream, L.desc, y[0], y1,
+                         y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
+    else if (nin_max >= 128 && g.gemm_waves >= 6)
+      hipLaunchKernelGGL((k_gemm_f32<1, 6>), grid32, dim3(384), lds32, L.stream, L.desc, y[0], y1,
+                         y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
+    else if (nin_max >= 128)
       hipLaunchKernelGGL((k_gemm_f32<2, 4>), grid32, dim3(256), lds32, L.stream, L.desc, y[0], y1,
                          y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
     else if (g.nb_max <= 32)
@@ -1429,6 +1437,8 @@ void configure_wave() {
   allow_lds((const void*)k_gemm_f32<2, 1>);
   allow_lds((const void*)k_gemm_f32<4, 1>);
   allow_lds((const void*)k_gemm_f32<2, 4>);
+  allow_lds((const void*)k_gemm_f32<1, 6>);
+  allow_lds((const void*)k_gemm_f32<1, 8>);
   configure_t<float>();
   configure_t<double>();
 }
