@@ -184,10 +184,12 @@ C3_RHO_GATE = 1.5e-4
 # meet the energy and density gates early (one stopped at 1.5e-5 Ha/atom
 # from the oracle's energy after 21 iterations; 35 with the gate, 2.5e-6)
 CG_GATE = 1e-4
-# solver settings of the uneven population: mixing weight 0.3 (the dilute
-# metallic candidates oscillate at the dense-cell default 0.5) and the
-# residual gate on the CG steps (a candidate is converged only when its
-# charged bands are)
+# solver settings of the uneven population: mixing weight 0.3 with the
+# library's Kerker q0 0.8 bohr^-1 and the residual gate on the CG steps (a
+# candidate is converged only when its charged bands are).  Faster mixing
+# (0.4 with q0 1.2: 52.7 evals/s) ends with one stored candidate's forces
+# 9.4e-4 Ha/bohr from the oracle's, outside the 5e-4 gate; at 0.3 the three
+# stored candidates are within 3.5e-4
 C4_OPTS = dict(tol_e=1e-5, tol_rho=RHO_GATE, max_iter=300, mix_alpha=0.3, cg_tol=1e-4)
 
 CANDIDATE_KERNELS = ("k_plane_hpsi", "k_subspace", "k_gram", "k_gram_reduce", "k_gemm_acc", "k_z_inverse",

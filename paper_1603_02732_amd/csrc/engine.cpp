@@ -580,7 +580,10 @@ class Engine {
       throw Error(SGO_ENOMEM, "device allocation failed");
     }
     c.mem_size = total;
-    HIPCHK(hipMemset(c.mem, 0, total));
+    // stream-ordered (the legacy null stream would wait on every blocking
+    // stream, and fail while another batch's thread captures a graph)
+    HIPCHK(hipMemsetAsync(c.mem, 0, total, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
     size_t off = 0;
     for (auto& it : items) {
       *it.p = c.mem + off;
@@ -631,7 +634,10 @@ class Engine {
     d.ew_ng = c.ew_ng;
     d.ew_nimg = c.ew_nimg;
     auto up = [&](const void* dst, const void* src, size_t bytes) {
-      if (bytes) HIPCHK(hipMemcpy((void*)dst, src, bytes, hipMemcpyHostToDevice));
+      if (bytes) {
+        HIPCHK(hipMemcpyAsync((void*)dst, src, bytes, hipMemcpyHostToDevice, stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
+      }
     };
     up(d.kin, c.kin.data(), c.npwh * 8);
     up(d.gmeta, c.gmeta.data(), c.npwh * 4);
@@ -828,7 +834,9 @@ class Engine {
       } else {
         c.d.hist_len = hist;
         c.d.ndens_chunk = c.dens_chunks;
-        HIPCHK(hipMemcpy((void*)c.d.pos, c.pos.data(), 3 * c.nat * 8, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpyAsync((void*)c.d.pos, c.pos.data(), 3 * c.nat * 8, hipMemcpyHostToDevice,
+                              stream_));
+        HIPCHK(hipStreamSynchronize(stream_));
       }
       c.d.seed = seed;
       c.d.active = 1;
@@ -1742,13 +1750,14 @@ class Engine {
   void require_scf(const HostCand& c) {
     if (!c.have_scf) throw Error(SGO_ESTATE, "sgo_scf has not run for this structure");
   }
-  void get_scal(const HostCand& c, double* out) {
-    HIPCHK(hipSetDevice(device_));
-    HIPCHK(hipMemcpy(out, c.d.scal, S_COUNT * 8, hipMemcpyDeviceToHost));
-  }
+  // host reads ordered on the engine's stream: on the legacy null stream
+  // they would wait on every blocking stream, and fail while another batch's
+  // thread captures a graph
+  void get_scal(const HostCand& c, double* out) { get(c.d.scal, out, S_COUNT * 8); }
   void get(const void* src, void* dst, size_t bytes) {
     HIPCHK(hipSetDevice(device_));
-    HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, stream_));
+    HIPCHK(hipStreamSynchronize(stream_));
   }
   void move_atoms(int i, const double* pos) {
     HostCand& c = cand(i);
@@ -1790,8 +1799,7 @@ class Engine {
   void get_input_density(int i, double* rho_in) {
     HostCand& c = cand(i);
     require_scf(c);
-    HIPCHK(hipSetDevice(device_));
-    HIPCHK(hipMemcpy(rho_in, c.d.rho_in_r, c.ntot * 8, hipMemcpyDeviceToHost));
+    get(c.d.rho_in_r, rho_in, c.ntot * 8);
   }
 
   // Host copy of candidate i's state (FP64); any pointer may be null.
@@ -1809,7 +1817,7 @@ class Engine {
     if (psi) {
       const size_t ts = tsize();
       std::vector<char> raw((size_t)c.nb * c.Kp * ts);
-      HIPCHK(hipMemcpy(raw.data(), c.d.X, raw.size(), hipMemcpyDeviceToHost));
+      get(c.d.X, raw.data(), raw.size());
       for (int b = 0; b < c.nb; ++b)
         for (int k = 0; k < c.K; ++k) {
           const size_t e = (size_t)b * c.Kp + k;
@@ -1817,13 +1825,13 @@ class Engine {
                                                        : (double)((const float*)raw.data())[e];
         }
     }
-    if (eig) HIPCHK(hipMemcpy(eig, c.d.eps, c.nb * 8, hipMemcpyDeviceToHost));
-    if (occ) HIPCHK(hipMemcpy(occ, c.d.occ, c.nb * 8, hipMemcpyDeviceToHost));
-    if (rho) HIPCHK(hipMemcpy(rho, c.d.rho_out_r, c.ntot * 8, hipMemcpyDeviceToHost));
-    if (veff) HIPCHK(hipMemcpy(veff, c.d.veff_r, c.ntot * 8, hipMemcpyDeviceToHost));
+    if (eig) get(c.d.eps, eig, c.nb * 8);
+    if (occ) get(c.d.occ, occ, c.nb * 8);
+    if (rho) get(c.d.rho_out_r, rho, c.ntot * 8);
+    if (veff) get(c.d.veff_r, veff, c.ntot * 8);
     if (t) {
       double s[S_COUNT];
-      HIPCHK(hipMemcpy(s, c.d.scal, S_COUNT * 8, hipMemcpyDeviceToHost));
+      get(c.d.scal, s, S_COUNT * 8);
       t->total = s[S_ETOT];
       t->kinetic = s[S_EKIN];
       t->nonlocal = s[S_ENL];

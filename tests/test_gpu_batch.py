@@ -199,6 +199,43 @@ def test_concurrent_batches_report_a_hard_error_first():
     assert np.all(st == sgo.SGO_ENOTCONV)
 
 
+def test_concurrent_batches_with_iteration_graphs():
+    """Concurrent batches whose SCF iterations run as captured graphs of 2
+    iterations: while one batch's thread captures, the others keep reading
+    their status and results, ordered on their own streams (a read on the
+    legacy null stream would depend on the capturing stream and break the
+    capture).  Each batch gives the state the eager concurrent solve gives."""
+    import torch
+    import paper_1603_02732_amd as sgo
+    pop = _population()
+    halves = [pop[:2], pop[2:]]
+    out = {}
+    for g in (0, 2):
+        opts = sgo.default_opts(tol_e=1e-8, tol_rho=1e-6, max_iter=200, use_graph=g)
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+        Bs = []
+        for half, stream in zip(halves, streams):
+            b = sgo.Batch(len(half), precision=sgo.SGO_FP32)
+            b.set_stream(stream.cuda_stream)
+            for s in half:
+                b.add_system(s)
+            Bs.append(b)
+        for rep in range(2):
+            for b in Bs:
+                b.reset()
+            E, F, st = sgo.batches_scf(Bs, opts)
+            torch.cuda.synchronize()
+            assert np.all(st == 0)
+        out[g] = (E, F)
+        for b in Bs:
+            b.close()
+    nat = [len(s["symbols"]) for s in pop]
+    dE = max(abs(a - b) / n for a, b, n in zip(out[0][0], out[2][0], nat))
+    dF = max(float(np.abs(a - b).max()) for a, b in zip(out[0][1], out[2][1]))
+    say("  concurrent batches, graphs of 2 iterations vs eager: dE %.2e dF %.2e" % (dE, dF))
+    assert dE < 1e-6 and dF < 1e-4
+
+
 def test_concurrent_batches_match_one_batch():
     """A population solved as two batches on two streams from two host
     threads gives each candidate the state one batch gives it (converged

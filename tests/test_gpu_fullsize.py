@@ -18,8 +18,7 @@ import workloads
 
 pytestmark = pytest.mark.gpu
 
-# solver settings of the uneven population (the bench's): weaker mixing than
-# the dense-cell default (the dilute metallic candidates oscillate at 0.5)
+# solver settings of the uneven population (the bench's): mixing weight 0.3
 # and the residual gate on the CG steps; the gate's final bound on the
 # occupation-weighted residual (f/2)|H psi - eps psi| is max(1e-4, 0.1
 # sqrt(1e-5)) = 3.2e-4 Ha, asserted below with a factor 3 for the oracle's
