@@ -325,6 +325,8 @@ int sgo_subspace_solve_noalloc(int device, int n, int mode, const double* S, con
  * "SGO_GEMM_WAVES" (wavefronts that share one staged 64-column slice of the
  * FP32 MFMA band products from 128 input rows: 4 (32-row output tiles), 6 or
  * 8 (16-row tiles, the default)),
+ * "SGO_GRAM_TILE" (output tile of the Gram products: 32 rows, the default,
+ * or 64),
  * "SGO_GRAM_KERNEL" (FP32 Gram products S, H, C: 1 = FP64 MFMA, each product
  * exact, the default; 2 = FP32 MFMA with FP32 sums over each wavefront's
  * K share (at most SGO_GRAM_KC/4 terms) and FP64 sums of those),

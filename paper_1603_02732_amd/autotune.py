@@ -31,6 +31,7 @@ SPACE = {
     "SGO_RR_SWEEPS": [1, 2],
     "SGO_JAC_GRID": [96, 160, 100000],
     "SGO_GEMM_WAVES": [4, 6],
+    "SGO_GRAM_TILE": [64],
     "use_graph": [0, 1, 2, 4],
 }
 # keys that only act from some band count on (largest band count of the

@@ -708,6 +708,7 @@ class Engine {
     g.plane_group = g.plane_reg ? plane_group_size(g, (size_t)g_lds_limit, tune("SGO_PLANE_GROUP", 0)) : 1;
     g.gemm_f32 = tune("SGO_GEMM_KERNEL", 1) == 1 ? 1 : 0;
     g.gemm_waves = tune("SGO_GEMM_WAVES", 8);
+    g.gram_tile = tune("SGO_GRAM_TILE", 0);
     g.gram_f32 = tsize() == 4 && tune("SGO_GRAM_KERNEL", 1) == 2 ? 1 : 0;
     g.bf16proj = prec_ == SGO_FP32_BF16PROJ ? 1 : 0;
     g.lds_limit = (size_t)g_lds_limit;
@@ -2438,7 +2439,7 @@ int sgo_set_tuning(const char* key, int value) {
                                 "SGO_DENS_CHUNKS", "SGO_RR_SWEEPS", "SGO_PLANE_KERNEL",
                                 "SGO_GEMM_KERNEL", "SGO_GRAM_KERNEL", "SGO_PCG_TRIAL",
                                 "SGO_PCG_FLOOR", "SGO_JAC_GRID", "SGO_PLANE_GROUP", "SGO_COMPACT",
-                                "SGO_GEMM_WAVES"};
+                                "SGO_GEMM_WAVES", "SGO_GRAM_TILE"};
   bool ok = false;
   for (const char* k : known) ok = ok || std::strcmp(k, key) == 0;
   if (!ok) return SGO_EINVAL;

@@ -1215,8 +1215,10 @@ void launch_gram(const LaunchCtx& L, int nprod, const int* a, const int* b, cons
       rows_read += ops[q] == W_BETA ? g.nproj_max : g.nb_max;
     }
   }
-  // 32x32 tiles when every product fits one (fewer registers, more waves)
-  const int TB = rows <= 32 ? 2 : 4;
+  // 32x32 output tiles (88 registers, 4 waves per SIMD; 64x64 tiles take
+  // 351 registers, one wave per SIMD, and were 10% slower on the uneven
+  // population's 56-112 bands); the tuning key SGO_GRAM_TILE = 64 selects them
+  const int TB = g.gram_tile == 64 ? 4 : 2;
   const int TT = 16 * TB;
   const int nt = (rows + TT - 1) / TT;
   dim3 grid(nt * nt * g.nkc_max, nprod, g.ncand);
