@@ -323,7 +323,7 @@ int sgo_subspace_solve_noalloc(int device, int n, int mode, const double* S, con
  * "SGO_GEMM_KERNEL" (FP32 band products X M: 1 = FP32 MFMA with FP32
  * accumulation, the default; 2 = FP64 MFMA on the FP32 data),
  * "SGO_GEMM_WAVES" (wavefronts that share one staged 64-column slice of the
- * FP32 MFMA band products from 128 input rows: 4 (32-row output tiles), 6 or
+ * FP32 MFMA band products from 64 input rows: 4 (32-row output tiles), 6 or
  * 8 (16-row tiles, the default)),
  * "SGO_GRAM_TILE" (output tile of the Gram products: 32 rows, the default,
  * or 64),

@@ -36,7 +36,7 @@ SPACE = {
 }
 # keys that only act from some band count on (largest band count of the
 # population must reach it, else the key is not timed)
-MIN_BANDS = {"SGO_JAC_GRID": 96, "SGO_GEMM_WAVES": 128}
+MIN_BANDS = {"SGO_JAC_GRID": 96, "SGO_GEMM_WAVES": 64}
 # batch schedule: the population split into this many batches, each on its
 # own stream from its own host thread (sgo_batches_scf), timed as whole
 # solves to the caller's gate

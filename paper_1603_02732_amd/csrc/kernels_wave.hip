@@ -1257,6 +1257,9 @@ reduce:
   prof_after("k_gram_reduce", L.stream);
 }
 
+// input rows from which several wavefronts share a staged slice
+constexpr int kGemmWavesFrom = 64;
+
 template <typename T>
 void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, int mat,
                      double alpha, double beta, int use_h) {
@@ -1276,21 +1279,23 @@ void launch_gemm_acc(const LaunchCtx& L, int narr, const int* y, const int* a, i
     rows_moved += nin + (alpha != 0.0 ? 2 : 1) * g.nb_max;
   }
   // the MFMA kernel stages all nin input rows of its 64 columns in LDS; from
-  // 128 bands (32 KB a slice: few slices resident per compute unit) several
-  // wavefronts share a slice, each taking every NW-th output tile (282 bands:
-  // 809 ms per evaluation of the 128-atom cell with 4 wavefronts and 32-row
-  // tiles, 745 with 8 and 16-row tiles)
+  // kGemmWavesFrom input rows (16 KB a slice and more: few slices resident
+  // per compute unit) several wavefronts share a slice, each taking every
+  // NW-th output tile (282 bands: 809 ms per evaluation of the 128-atom cell
+  // with 4 wavefronts and 32-row tiles, 745 with 8 and 16-row tiles; the
+  // uneven population of 24 to 112 bands: 52.5 evaluations/s from 64 rows
+  // against 49.4 from 128)
   const size_t lds32 = (size_t)nin_max * 64 * sizeof(float);
   if (std::is_same<T, float>::value && lds32 <= g.lds_limit && g.gemm_f32) {
     prof_before("k_gemm_acc", L.stream);
     const dim3 grid32((g.K_max + 63) / 64, narr, g.ncand);
-    if (nin_max >= 128 && g.gemm_waves >= 8)
+    if (nin_max >= kGemmWavesFrom && g.gemm_waves >= 8)
       hipLaunchKernelGGL((k_gemm_f32<1, 8>), grid32, dim3(512), lds32, L.stream, L.desc, y[0], y1,
                          y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
-    else if (nin_max >= 128 && g.gemm_waves >= 6)
+    else if (nin_max >= kGemmWavesFrom && g.gemm_waves >= 6)
       hipLaunchKernelGGL((k_gemm_f32<1, 6>), grid32, dim3(384), lds32, L.stream, L.desc, y[0], y1,
                          y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
-    else if (nin_max >= 128)
+    else if (nin_max >= kGemmWavesFrom)
       hipLaunchKernelGGL((k_gemm_f32<2, 4>), grid32, dim3(256), lds32, L.stream, L.desc, y[0], y1,
                          y2, a[0], a1, a2, mat, (float)alpha, (float)beta, use_h);
     else if (g.nb_max <= 32)

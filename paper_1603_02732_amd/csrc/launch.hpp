@@ -22,7 +22,7 @@ struct BatchGeom {
   int plane_reg;   // 1: FP32 register-FFT plane kernels for every candidate
   int pl_sx_max;   // largest compact plane row stride
   int gemm_f32;    // 1: FP32-MFMA band products in the FP32 path
-  int gemm_waves = 8;  // wavefronts sharing a staged slice from 128 input rows (4, 6 or 8)
+  int gemm_waves = 8;  // wavefronts sharing a staged slice from 64 input rows (4, 6 or 8)
   int gram_tile = 0;   // Gram output tile: 64 rows when set to 64, else 32
   int gram_f32;    // 1: FP32-MFMA Gram products (FP64 sums of the K ranges)
   int bf16proj;    // 1: projector products with BF16 inputs (FP32_BF16PROJ form)
