@@ -889,10 +889,21 @@ constexpr int kSubNT = 512;
 
 // Pair k of round r of the round-robin (circle) schedule on n2 indices:
 // index 0 stays fixed, indices 1..n2-1 rotate.  Returns p < q.
+// For rounds r < n2 - 1 and pairs k < n2 / 2 both r + k - 1 and
+// r + (n2 - 1 - k) - 1 stay below 2 (n2 - 1), so each remainder modulo
+// n2 - 1 is one conditional subtraction.
 __device__ __forceinline__ void jacobi_pair(int r, int k, int n2, int* p, int* q) {
-  const int a = k == 0 ? 0 : ((r + k - 1) % (n2 - 1)) + 1;
-  const int kb = n2 - 1 - k;
-  const int b = kb == 0 ? 0 : ((r + kb - 1) % (n2 - 1)) + 1;
+  const int m = n2 - 1;
+  int a = 0, b = 0;
+  if (k != 0) {
+    a = r + k - 1;
+    a = (a >= m ? a - m : a) + 1;
+  }
+  const int kb = m - k;
+  if (kb != 0) {
+    b = r + kb - 1;
+    b = (b >= m ? b - m : b) + 1;
+  }
   *p = min(a, b);
   *q = max(a, b);
 }
@@ -931,6 +942,114 @@ __device__ __forceinline__ void jacobi_rot(const double* A, int n, int ld, int p
   const double cc = rsq_nr(fma(t, t, 1.0));
   *c = cc;
   *s = t * cc;
+}
+
+// Cyclic Jacobi sweeps on H' in LDS with one barrier per round (up to 128
+// indices, i.e. 64 pairs).  A round is a chain of dependent steps (pair
+// indices, loads, rotation, update), and one wavefront issues a vector
+// instruction every few cycles, so the round's time is that chain's
+// instruction count and LDS latency, not its FP64 work:
+//  - H' alternates between two buffers: a round reads the current one and
+//    writes every entry of the other, so no thread overwrites an entry
+//    another thread of the round still reads, and one barrier ends a round;
+//  - a work item is the 2x2 block (row pair P, column pair Q) of H' together
+//    with columns 2Q and 2Q + 1 of V^T's rows of pair P (V^T is rotated in
+//    place: pair P owns its two rows in the round); wavefronts without
+//    items skip the round;
+//  - each wavefront computes the round's rotations itself (lane k: pair
+//    k mod npair) and the items read them, and the pair indices, from those
+//    lanes' registers (no LDS round trip); the item loads depend only on the
+//    pair indices, so they overlap the rotation arithmetic.
+// The rotations and the updates are those of the two-barrier form, entry for
+// entry.  Stops when the off-diagonal norm is below 1e-13 of the diagonal
+// norm; returns the sweeps done and the buffer that holds the final H' in *Hc.
+constexpr int kJacDbPairs = 64;
+__device__ int jacobi_sweeps_db(double* Ha, double* Hb, int ldh, double* Vt, int ldv, int n,
+                                int max_sweeps, double* sh, int tid, int nthr, double** Hc) {
+  const int n2 = n + (n & 1), npair = n2 / 2, m = n2 - 1;
+  const int lane = tid & 63;
+  // item t = P npair + Q; t / npair as a multiply-shift (exact for t < 4096,
+  // npair <= 64)
+  const int nitem = npair * npair;
+  const unsigned inv = (1u << 20) / (unsigned)npair + 1u;
+  const int kl = lane % npair;
+  int nsweep = 0;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // the norms in the two-barrier form's order (the same sweep counts)
+    double v[2] = {0.0, 0.0};
+    for (int e = tid; e < n * n; e += nthr) {
+      const int i = e / n, j = e - i * n;
+      const double a = Ha[i * ldh + j];
+      if (i == j) v[1] += a * a;
+      else v[0] += a * a;
+    }
+    block_sum<2>(v, sh);
+    if (!(v[0] > 1e-26 * v[1] + 1e-300)) break;
+    ++nsweep;
+    for (int r = 0; r < m; ++r) {
+      // wavefronts without items sit the round out (uniform branch)
+      if ((tid & ~63) < nitem) {
+        // lane k of every wavefront: the rotation of pair k mod npair (the
+        // lanes above npair repeat it: branch-free, so the register reads
+        // between lanes below see every lane)
+        int pk, qk;
+        jacobi_pair(r, kl, n2, &pk, &qk);
+        double ck, sk;
+        jacobi_rot(Ha, n, ldh, pk, qk, &ck, &sk);
+        for (int base = 0; base < nitem; base += 2 * nthr) {
+          // wavefronts without items in this pass skip it (uniform branches)
+          if (base + (tid & ~63) >= nitem) continue;
+          const bool wv1 = base + nthr + (tid & ~63) < nitem;
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (u == 1 && !wv1) continue;
+            const int t = base + tid + u * nthr;
+            const bool ok = t < nitem;
+            const int tc = ok ? t : 0;
+            const int P = (int)(((unsigned)tc * inv) >> 20), Q = tc - P * npair;
+            // pair indices and rotations of P and Q from the lanes that hold them
+            const int p1 = __shfl(pk, P), p2 = __shfl(qk, P), q1 = __shfl(pk, Q), q2 = __shfl(qk, Q);
+            const bool p2v = p2 < n, q2v = q2 < n;
+            const int p2c = p2v ? p2 : p1, q2c = q2v ? q2 : q1;
+            const double a11 = Ha[p1 * ldh + q1];
+            const double a12 = q2v ? Ha[p1 * ldh + q2c] : 0.0;
+            const double a21 = p2v ? Ha[p2c * ldh + q1] : 0.0;
+            const double a22 = (p2v && q2v) ? Ha[p2c * ldh + q2c] : 0.0;
+            const int i0 = min(2 * Q, n - 1), i1 = min(2 * Q + 1, n - 1);
+            const double vp0 = Vt[p1 * ldv + i0], vq0 = Vt[p2c * ldv + i0];
+            const double vp1 = Vt[p1 * ldv + i1], vq1 = Vt[p2c * ldv + i1];
+            const double cP = __shfl(ck, P), sP = __shfl(sk, P);
+            const double cQ = __shfl(ck, Q), sQ = __shfl(sk, Q);
+            if (!ok) continue;
+            // x y -/+ z w as fma(x, y, -/+ z w): the rounding of the in-place
+            // two-barrier rounds, so both forms give the same bits
+            const double b11 = fma(cP, a11, -(sP * a21)), b21 = fma(sP, a11, cP * a21);
+            const double b12 = fma(cP, a12, -(sP * a22)), b22 = fma(sP, a12, cP * a22);
+            Hb[p1 * ldh + q1] = fma(cQ, b11, -(sQ * b12));
+            if (q2v) Hb[p1 * ldh + q2] = fma(sQ, b11, cQ * b12);
+            if (p2v) Hb[p2 * ldh + q1] = fma(cQ, b21, -(sQ * b22));
+            if (p2v && q2v) Hb[p2 * ldh + q2] = fma(sQ, b21, cQ * b22);
+            if (p2v && sP != 0.0) {
+              if (2 * Q < n) {
+                Vt[p1 * ldv + 2 * Q] = fma(cP, vp0, -(sP * vq0));
+                Vt[p2 * ldv + 2 * Q] = fma(sP, vp0, cP * vq0);
+              }
+              if (2 * Q + 1 < n) {
+                Vt[p1 * ldv + 2 * Q + 1] = fma(cP, vp1, -(sP * vq1));
+                Vt[p2 * ldv + 2 * Q + 1] = fma(sP, vp1, cP * vq1);
+              }
+            }
+          }
+        }
+      }
+      __syncthreads();
+      double* tmp = Ha;
+      Ha = Hb;
+      Hb = tmp;
+    }
+  }
+  *Hc = Ha;
+  return nsweep;
 }
 
 // Blocked Cholesky S = L L^T (lower, over A in place) and W = L^-1 (into Wm)
@@ -1061,14 +1180,20 @@ __device__ bool chol_inv_blocked(double* __restrict__ A, double* __restrict__ Wm
 // 2: eigenvalue order and the sorted M, eps from the converged H' and the
 // product W^T V already in S.  Phases 1-3 keep W, V and the products in
 // global memory.
+// USE_LDS (see below) is a template parameter: the matrix pointers of each
+// form then come from one address space only, so the LDS-resident ones are
+// accessed with LDS instructions rather than flat ones
+template <int USE_LDS>
 __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict__ cds, int mode,
-                                                     int use_lds, int max_sweeps, int phase) {
+                                                     int max_sweeps, int phase) {
+  constexpr int use_lds = USE_LDS;
   const CandDesc& cd = cds[blockIdx.x];
   if (!cd.active) return;
   const int n = cd.nb;
   const int tid = threadIdx.x, nthr = blockDim.x;
   // use_lds 1: the four matrices in LDS; 0: in global memory; 2: in global
-  // memory except H', which the Jacobi rounds keep in LDS (up to 128 bands)
+  // memory except H', which the Jacobi rounds keep in LDS (up to 128 bands);
+  // 3: as 2 with a second H' buffer in LDS for the one-barrier rounds
   const bool all_lds = use_lds == 1;
   // row stride of the four matrices: n + 1 in LDS (rows and columns of
   // FP64 entries then fall in different banks), n in global memory
@@ -1092,8 +1217,9 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     P3 = cd.M;
   }
   // H' from the congruence on (the input H stays in P1)
-  double* H1 = use_lds == 2 ? (double*)smem : P1;
-  const int ldh = use_lds == 2 ? n + 1 : ld;
+  const bool h_lds = use_lds == 2 || use_lds == 3;
+  double* H1 = h_lds ? (double*)smem : P1;
+  const int ldh = h_lds ? n + 1 : ld;
   __shared__ int fail;
   __shared__ double sh[16 * 2];
   __shared__ int rank[640];
@@ -1113,7 +1239,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     // Jacobi of the H' that the products over the GPU formed (in Hs; V^T = I
     // in M), unless this call's Cholesky failed
     if (cd.scal[S_ERR] == 2.0) return;
-    if (use_lds == 2)
+    if (h_lds)
       for (int e = tid; e < n * n; e += nthr) {
         const int i = e / n, j = e - i * n;
         H1[i * ldh + j] = cd.Hs[e];
@@ -1193,20 +1319,42 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     }
     if (phase == 1) return;  // W is ready; the products run over the GPU
     // H' = W H W^T (symmetrised)
-    for (int e = tid; e < n * n; e += nthr) {
-      const int i = e / n, j = e % n;
-      double s = 0.0;
-      for (int k = 0; k <= i; ++k) s = fma(P2[i * ld + k], P1[k * ld + j], s);
-      P3[i * ld + j] = s;
+    if (all_lds) {
+      // lane j: column j (32 or 64 columns per wavefront), rows over the
+      // wavefronts; one operand of each product is an LDS broadcast
+      const int lw = n <= 32 ? 32 : 64, j = tid & (lw - 1);
+      const int r0 = (tid >> 6) * (64 / lw) + ((tid & 63) >= lw ? 1 : 0);
+      const int rstep = (nthr >> 6) * (64 / lw);
+      if (j < n)
+        for (int i = r0; i < n; i += rstep) {
+          double s = 0.0;
+          for (int k = 0; k <= i; ++k) s = fma(P2[i * ld + k], P1[k * ld + j], s);
+          P3[i * ld + j] = s;
+        }
+      __syncthreads();
+      if (j < n)
+        for (int i = r0; i < n; i += rstep) {
+          double s = 0.0;
+          for (int k = 0; k <= j; ++k) s = fma(P3[i * ld + k], P2[j * ld + k], s);
+          H1[i * ldh + j] = s;
+        }
+      __syncthreads();
+    } else {
+      for (int e = tid; e < n * n; e += nthr) {
+        const int i = e / n, j = e % n;
+        double s = 0.0;
+        for (int k = 0; k <= i; ++k) s = fma(P2[i * ld + k], P1[k * ld + j], s);
+        P3[i * ld + j] = s;
+      }
+      __syncthreads();
+      for (int e = tid; e < n * n; e += nthr) {
+        const int i = e / n, j = e % n;
+        double s = 0.0;
+        for (int k = 0; k <= j; ++k) s = fma(P3[i * ld + k], P2[j * ld + k], s);
+        H1[i * ldh + j] = s;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int e = tid; e < n * n; e += nthr) {
-      const int i = e / n, j = e % n;
-      double s = 0.0;
-      for (int k = 0; k <= j; ++k) s = fma(P3[i * ld + k], P2[j * ld + k], s);
-      H1[i * ldh + j] = s;
-    }
-    __syncthreads();
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e % n;
       if (i < j) {
@@ -1228,7 +1376,21 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     const int npair = n2 / 2;
     if (clk && tid == 0) clk[2] = clock64();
     int nsweep = 0;
-    for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    // second H' buffer of the one-barrier rounds: L's storage when all four
+    // matrices are in LDS (L is not needed again), else the LDS after H'
+    double* H2 = all_lds ? P0 : (use_lds == 3 ? H1 + n * ldh : nullptr);
+    if (H2 && npair <= kJacDbPairs) {
+      double* Hc = H1;
+      nsweep = jacobi_sweeps_db(H1, H2, ldh, P3, ld, n, max_sweeps, sh, tid, nthr, &Hc);
+      if (Hc != H1) {
+        for (int e = tid; e < n * n; e += nthr) {
+          const int i = e / n, j = e - i * n;
+          H1[i * ldh + j] = Hc[i * ldh + j];
+        }
+        __syncthreads();
+      }
+    }
+    for (int sweep = 0; sweep < (H2 && npair <= kJacDbPairs ? 0 : max_sweeps); ++sweep) {
       double v[2] = {0.0, 0.0};
       for (int e = tid; e < n * n; e += nthr) {
         const int i = e / n, j = e % n;
@@ -1300,7 +1462,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     }
     if (phase == 3) {
       // H' back for the sort (phase 2); M = W^T V runs over the GPU
-      if (use_lds == 2)
+      if (h_lds)
         for (int e = tid; e < n * n; e += nthr) {
           const int i = e / n, j = e - i * n;
           cd.Hs[e] = H1[i * ldh + j];
@@ -1320,7 +1482,18 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   }
   // M = W^T V into P0 (L is no longer needed); P3 holds V^T.  In phase 2
   // the product has already been formed over the GPU (k_sub_compose).
-  if (phase != 2) {
+  if (phase != 2 && all_lds) {
+    // lane i: column i of M (V^T row i), rows j over the wavefronts
+    const int lw = n <= 32 ? 32 : 64, i = tid & (lw - 1);
+    const int r0 = (tid >> 6) * (64 / lw) + ((tid & 63) >= lw ? 1 : 0);
+    const int rstep = (nthr >> 6) * (64 / lw);
+    if (i < n)
+      for (int j = r0; j < n; j += rstep) {
+        double s = 0.0;
+        for (int k = j; k < n; ++k) s = fma(P2[k * ld + j], P3[i * ld + k], s);
+        P0[j * ld + i] = s;
+      }
+  } else if (phase != 2) {
     for (int e = tid; e < n * n; e += nthr) {
       const int j = e / n, i = e % n;
       double s = 0.0;
@@ -1692,12 +1865,37 @@ void launch_occupations(const LaunchCtx& L) {
 // bands, H' alone in LDS up to 128 (the Jacobi rounds then touch global
 // memory only for V's column pairs), else all in global memory; and the
 // dynamic LDS that form needs (the blocked Cholesky's panels share it).
-static int sub_lds_form(int n) { return n <= 64 ? 1 : (n <= 128 ? 2 : 0); }
+// LDS form of the subspace solver by band count: 1 up to 64 (all four
+// matrices), 3 up to kSubDbBands (two H' buffers: 2 (n^2 + n) doubles, 124 KB
+// at 88 bands, which leave the static arrays room in 160 KB), 2 up to 128
+// (one H' buffer), else 0
+constexpr int kSubDbBands = 88;
+static int sub_lds_form(int n) {
+  return n <= 64 ? 1 : (n <= kSubDbBands ? 3 : (n <= 128 ? 2 : 0));
+}
 static size_t sub_lds_bytes(int n, int form) {
   if (form == 1) return sizeof(double) * 4 * (size_t)n * (n + 1);
   const size_t chol = (size_t)chol_inv_lds_doubles(n);
-  const size_t h = form == 2 ? (size_t)n * (n + 1) : 0;
+  const size_t h = (form == 2 ? 1 : (form == 3 ? 2 : 0)) * (size_t)n * (n + 1);
   return sizeof(double) * std::max(chol, h);
+}
+
+static void launch_k_subspace(int form, dim3 grid, dim3 block, size_t lds, hipStream_t st,
+                              const CandDesc* desc, int mode, int max_sweeps, int phase) {
+  switch (form) {
+    case 1:
+      hipLaunchKernelGGL(k_subspace<1>, grid, block, lds, st, desc, mode, max_sweeps, phase);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_subspace<2>, grid, block, lds, st, desc, mode, max_sweeps, phase);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_subspace<3>, grid, block, lds, st, desc, mode, max_sweeps, phase);
+      break;
+    default:
+      hipLaunchKernelGGL(k_subspace<0>, grid, block, lds, st, desc, mode, max_sweeps, phase);
+  }
+  check_launch("k_subspace");
 }
 
 // One Jacobi sweep over the GPU (n2 - 1 rounds of two launches each),
@@ -1768,9 +1966,8 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
   const int nthr = L.g.sub_threads;
   prof_before("k_subspace", L.stream);
   if (mode == 3 && n >= L.g.jac_grid && L.jac_done && host_sync_allowed()) {
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), sub_lds_bytes(n, 0), L.stream,
-                       L.desc, mode, 0, max_sweeps, 1);
-    check_launch("k_subspace");
+    launch_k_subspace(0, dim3(L.g.ncand), dim3(nthr), sub_lds_bytes(n, 0), L.stream, L.desc, mode,
+                      max_sweeps, 1);
     const dim3 ge((n * n + kNT - 1) / kNT, L.g.ncand);
     hipLaunchKernelGGL(k_sub_wh, ge, dim3(kNT), 0, L.stream, L.desc);
     hipLaunchKernelGGL(k_sub_twt, ge, dim3(kNT), 0, L.stream, L.desc);
@@ -1796,9 +1993,7 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
     hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
     check_launch("k_sub_compose");
     // phase 2 takes the sweep count in place of the sweep limit (debug clocks)
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
-                       done_sweeps, 2);
-    check_launch("k_subspace");
+    launch_k_subspace(0, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, done_sweeps, 2);
   } else if (mode == 3 && n > 64) {
     // Cholesky and W in the workgroup, the congruence and M = W^T V over the
     // whole GPU (one thread per element: these n^3 products were the slow
@@ -1806,22 +2001,18 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
     // in the workgroup with H' in LDS up to 128 bands; no host sync, so the
     // same path serves graph capture
     const dim3 ge((n * n + kNT - 1) / kNT, L.g.ncand);
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), sub_lds_bytes(n, 0), L.stream,
-                       L.desc, mode, 0, max_sweeps, 1);
+    launch_k_subspace(0, dim3(L.g.ncand), dim3(nthr), sub_lds_bytes(n, 0), L.stream, L.desc, mode,
+                      max_sweeps, 1);
     hipLaunchKernelGGL(k_sub_wh, ge, dim3(kNT), 0, L.stream, L.desc);
     hipLaunchKernelGGL(k_sub_twt, ge, dim3(kNT), 0, L.stream, L.desc);
-    const int jl = n <= 128 ? 2 : 0;
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr),
-                       jl == 2 ? sizeof(double) * (size_t)n * (n + 1) : 0, L.stream, L.desc, mode, jl,
-                       max_sweeps, 3);
+    const int jl = n <= kSubDbBands ? 3 : (n <= 128 ? 2 : 0);
+    launch_k_subspace(jl, dim3(L.g.ncand), dim3(nthr),
+                      sizeof(double) * (size_t)(jl == 3 ? 2 : (jl == 2 ? 1 : 0)) * n * (n + 1), L.stream,
+                      L.desc, mode, max_sweeps, 3);
     hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, 0,
-                       max_sweeps, 2);
-    check_launch("k_subspace");
+    launch_k_subspace(0, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, max_sweeps, 2);
   } else {
-    hipLaunchKernelGGL(k_subspace, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode,
-                       use_lds, max_sweeps, 0);
-    check_launch("k_subspace");
+    launch_k_subspace(use_lds, dim3(L.g.ncand), dim3(nthr), lds, L.stream, L.desc, mode, max_sweeps, 0);
   }
   prof_after("k_subspace", L.stream);
 }
@@ -1903,8 +2094,7 @@ int subspace_noalloc(int device, int n, int mode, const double* S, const double*
   check_launch("k_noalloc_stage");
   const int use_lds = sub_lds_form(n);
   const size_t lds = sub_lds_bytes(n, use_lds);
-  hipLaunchKernelGGL(k_subspace, dim3(1), dim3(nthreads), lds, stream, dd, mode, use_lds, 40, 0);
-  check_launch("k_subspace");
+  launch_k_subspace(use_lds, dim3(1), dim3(nthreads), lds, stream, dd, mode, 40, 0);
   if (status) {
     hipLaunchKernelGGL(k_noalloc_status, dim3(1), dim3(64), 0, stream, d.scal, status, fail_code);
     check_launch("k_noalloc_status");
@@ -1920,7 +2110,10 @@ void configure_wave();
 void configure_kernels() {
   allow_lds((const void*)k_grid_fft_x);
   allow_lds((const void*)k_grid_fft_yz);
-  allow_lds((const void*)k_subspace);
+  allow_lds((const void*)k_subspace<0>);
+  allow_lds((const void*)k_subspace<1>);
+  allow_lds((const void*)k_subspace<2>);
+  allow_lds((const void*)k_subspace<3>);
   configure_wave();
   configure_plane_kernels();
   configure_kpt_kernels();

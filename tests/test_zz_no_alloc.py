@@ -67,6 +67,14 @@ def test_noalloc_matches_the_allocating_step_twice_smaller_second():
     _check(S, H, 3, False)
 
 
+def test_noalloc_two_buffer_lds_form():
+    # 65..88 bands: H' in two LDS buffers, the other matrices in the workspace
+    S, H = _problem(80, 3)
+    _check(S, H, 3, True)
+    S, H = _problem(71, 4)
+    _check(S, H, 3, False)
+
+
 def test_noalloc_cholesky_mode_and_status():
     S, H = _problem(100, 3)
     _check(S, H, 1, True)
