@@ -944,28 +944,82 @@ __device__ __forceinline__ void jacobi_rot(const double* A, int n, int ld, int p
   *s = t * cc;
 }
 
-// Cyclic Jacobi sweeps on H' in LDS with one barrier per round (up to 128
-// indices, i.e. 64 pairs).  A round is a chain of dependent steps (pair
-// indices, loads, rotation, update), and one wavefront issues a vector
-// instruction every few cycles, so the round's time is that chain's
-// instruction count and LDS latency, not its FP64 work:
-//  - H' alternates between two buffers: a round reads the current one and
-//    writes every entry of the other, so no thread overwrites an entry
-//    another thread of the round still reads, and one barrier ends a round;
+// Cyclic Jacobi sweeps, in place, for up to 128 indices (64 pairs).  A round
+// is a chain of dependent steps (pair indices, loads, rotation, update), and
+// one wavefront issues a vector instruction every few cycles, so the round's
+// time is that chain's instruction count and memory latency, not its FP64
+// work:
 //  - a work item is the 2x2 block (row pair P, column pair Q) of H' together
-//    with columns 2Q and 2Q + 1 of V^T's rows of pair P (V^T is rotated in
-//    place: pair P owns its two rows in the round); wavefronts without
-//    items skip the round;
+//    with columns 2Q and 2Q + 1 of V^T's rows of pair P: items own disjoint
+//    entries, so they update in place; wavefronts without items skip the
+//    round;
 //  - each wavefront computes the round's rotations itself (lane k: pair
 //    k mod npair) and the items read them, and the pair indices, from those
-//    lanes' registers (no LDS round trip); the item loads depend only on the
-//    pair indices, so they overlap the rotation arithmetic.
-// The rotations and the updates are those of the two-barrier form, entry for
-// entry.  Stops when the off-diagonal norm is below 1e-13 of the diagonal
-// norm; returns the sweeps done and the buffer that holds the final H' in *Hc.
-constexpr int kJacDbPairs = 64;
-__device__ int jacobi_sweeps_db(double* Ha, double* Hb, int ldh, double* Vt, int ldv, int n,
-                                int max_sweeps, double* sh, int tid, int nthr, double** Hc) {
+//    lanes' registers; the first items' loads are issued beside the
+//    rotations, and one barrier then separates every read of the round's
+//    rotation inputs from the first write.
+// The updates are written as fma(x, y, -/+ z w) for x y -/+ z w, the rounding
+// the compiler gives the two-barrier form below, so both give the same bits.
+// Stops when the off-diagonal norm is below 1e-13 of the diagonal norm;
+// returns the sweeps done.
+// One work item of a fast Jacobi round: block (P, Q) of H' and columns 2Q,
+// 2Q + 1 of V^T's rows of pair P, loaded into registers, then rotated and
+// stored.  Every lane of the wavefront calls load and update (the pair
+// indices and rotations come from other lanes' registers).
+struct JacItem {
+  int P, Q, p1, p2, q1, q2;
+  bool ok;
+  double a11, a12, a21, a22, vp0, vq0, vp1, vq1;
+  __device__ __forceinline__ void load(const double* H, int ldh, const double* Vt, int ldv, int n,
+                                       int npair, unsigned inv, int nitem, int t, int pk, int qk) {
+    ok = t < nitem;
+    const int tc = ok ? t : 0;
+    P = (int)(((unsigned)tc * inv) >> 20);
+    Q = tc - P * npair;
+    p1 = __shfl(pk, P);
+    p2 = __shfl(qk, P);
+    q1 = __shfl(pk, Q);
+    q2 = __shfl(qk, Q);
+    const bool p2v = p2 < n, q2v = q2 < n;
+    const int p2c = p2v ? p2 : p1, q2c = q2v ? q2 : q1;
+    a11 = H[p1 * ldh + q1];
+    a12 = q2v ? H[p1 * ldh + q2c] : 0.0;
+    a21 = p2v ? H[p2c * ldh + q1] : 0.0;
+    a22 = (p2v && q2v) ? H[p2c * ldh + q2c] : 0.0;
+    const int i0 = min(2 * Q, n - 1), i1 = min(2 * Q + 1, n - 1);
+    vp0 = Vt[p1 * ldv + i0];
+    vq0 = Vt[p2c * ldv + i0];
+    vp1 = Vt[p1 * ldv + i1];
+    vq1 = Vt[p2c * ldv + i1];
+  }
+  __device__ __forceinline__ void update(double* H, int ldh, double* Vt, int ldv, int n, double ck,
+                                         double sk) const {
+    const double cP = __shfl(ck, P), sP = __shfl(sk, P);
+    const double cQ = __shfl(ck, Q), sQ = __shfl(sk, Q);
+    if (!ok) return;
+    const bool p2v = p2 < n, q2v = q2 < n;
+    const double b11 = fma(cP, a11, -(sP * a21)), b21 = fma(sP, a11, cP * a21);
+    const double b12 = fma(cP, a12, -(sP * a22)), b22 = fma(sP, a12, cP * a22);
+    H[p1 * ldh + q1] = fma(cQ, b11, -(sQ * b12));
+    if (q2v) H[p1 * ldh + q2] = fma(sQ, b11, cQ * b12);
+    if (p2v) H[p2 * ldh + q1] = fma(cQ, b21, -(sQ * b22));
+    if (p2v && q2v) H[p2 * ldh + q2] = fma(sQ, b21, cQ * b22);
+    if (p2v && sP != 0.0) {
+      const int i = 2 * Q;
+      if (i < n) {
+        Vt[p1 * ldv + i] = fma(cP, vp0, -(sP * vq0));
+        Vt[p2 * ldv + i] = fma(sP, vp0, cP * vq0);
+      }
+      if (i + 1 < n) {
+        Vt[p1 * ldv + i + 1] = fma(cP, vp1, -(sP * vq1));
+        Vt[p2 * ldv + i + 1] = fma(sP, vp1, cP * vq1);
+      }
+    }
+  }
+};
+constexpr int kJacFastPairs = 64;
+__device__ int jacobi_sweeps_fast(double* H, int ldh, double* Vt, int ldv, int n, int max_sweeps,
+                                  double* sh, int tid, int nthr) {
   const int n2 = n + (n & 1), npair = n2 / 2, m = n2 - 1;
   const int lane = tid & 63;
   // item t = P npair + Q; t / npair as a multiply-shift (exact for t < 4096,
@@ -973,13 +1027,14 @@ __device__ int jacobi_sweeps_db(double* Ha, double* Hb, int ldh, double* Vt, int
   const int nitem = npair * npair;
   const unsigned inv = (1u << 20) / (unsigned)npair + 1u;
   const int kl = lane % npair;
+  const bool has_items = (tid & ~63) < nitem;
   int nsweep = 0;
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // the norms in the two-barrier form's order (the same sweep counts)
     double v[2] = {0.0, 0.0};
     for (int e = tid; e < n * n; e += nthr) {
       const int i = e / n, j = e - i * n;
-      const double a = Ha[i * ldh + j];
+      const double a = H[i * ldh + j];
       if (i == j) v[1] += a * a;
       else v[0] += a * a;
     }
@@ -987,68 +1042,29 @@ __device__ int jacobi_sweeps_db(double* Ha, double* Hb, int ldh, double* Vt, int
     if (!(v[0] > 1e-26 * v[1] + 1e-300)) break;
     ++nsweep;
     for (int r = 0; r < m; ++r) {
-      // wavefronts without items sit the round out (uniform branch)
-      if ((tid & ~63) < nitem) {
-        // lane k of every wavefront: the rotation of pair k mod npair (the
-        // lanes above npair repeat it: branch-free, so the register reads
-        // between lanes below see every lane)
-        int pk, qk;
+      int pk = 0, qk = 0;
+      double ck = 1.0, sk = 0.0;
+      JacItem it;
+      if (has_items) {
+        // lane k: the rotation of pair k mod npair (the lanes above npair
+        // repeat it: branch-free, so the register reads below see every lane)
         jacobi_pair(r, kl, n2, &pk, &qk);
-        double ck, sk;
-        jacobi_rot(Ha, n, ldh, pk, qk, &ck, &sk);
-        for (int base = 0; base < nitem; base += 2 * nthr) {
-          // wavefronts without items in this pass skip it (uniform branches)
-          if (base + (tid & ~63) >= nitem) continue;
-          const bool wv1 = base + nthr + (tid & ~63) < nitem;
-#pragma unroll
-          for (int u = 0; u < 2; ++u) {
-            if (u == 1 && !wv1) continue;
-            const int t = base + tid + u * nthr;
-            const bool ok = t < nitem;
-            const int tc = ok ? t : 0;
-            const int P = (int)(((unsigned)tc * inv) >> 20), Q = tc - P * npair;
-            // pair indices and rotations of P and Q from the lanes that hold them
-            const int p1 = __shfl(pk, P), p2 = __shfl(qk, P), q1 = __shfl(pk, Q), q2 = __shfl(qk, Q);
-            const bool p2v = p2 < n, q2v = q2 < n;
-            const int p2c = p2v ? p2 : p1, q2c = q2v ? q2 : q1;
-            const double a11 = Ha[p1 * ldh + q1];
-            const double a12 = q2v ? Ha[p1 * ldh + q2c] : 0.0;
-            const double a21 = p2v ? Ha[p2c * ldh + q1] : 0.0;
-            const double a22 = (p2v && q2v) ? Ha[p2c * ldh + q2c] : 0.0;
-            const int i0 = min(2 * Q, n - 1), i1 = min(2 * Q + 1, n - 1);
-            const double vp0 = Vt[p1 * ldv + i0], vq0 = Vt[p2c * ldv + i0];
-            const double vp1 = Vt[p1 * ldv + i1], vq1 = Vt[p2c * ldv + i1];
-            const double cP = __shfl(ck, P), sP = __shfl(sk, P);
-            const double cQ = __shfl(ck, Q), sQ = __shfl(sk, Q);
-            if (!ok) continue;
-            // x y -/+ z w as fma(x, y, -/+ z w): the rounding of the in-place
-            // two-barrier rounds, so both forms give the same bits
-            const double b11 = fma(cP, a11, -(sP * a21)), b21 = fma(sP, a11, cP * a21);
-            const double b12 = fma(cP, a12, -(sP * a22)), b22 = fma(sP, a12, cP * a22);
-            Hb[p1 * ldh + q1] = fma(cQ, b11, -(sQ * b12));
-            if (q2v) Hb[p1 * ldh + q2] = fma(sQ, b11, cQ * b12);
-            if (p2v) Hb[p2 * ldh + q1] = fma(cQ, b21, -(sQ * b22));
-            if (p2v && q2v) Hb[p2 * ldh + q2] = fma(sQ, b21, cQ * b22);
-            if (p2v && sP != 0.0) {
-              if (2 * Q < n) {
-                Vt[p1 * ldv + 2 * Q] = fma(cP, vp0, -(sP * vq0));
-                Vt[p2 * ldv + 2 * Q] = fma(sP, vp0, cP * vq0);
-              }
-              if (2 * Q + 1 < n) {
-                Vt[p1 * ldv + 2 * Q + 1] = fma(cP, vp1, -(sP * vq1));
-                Vt[p2 * ldv + 2 * Q + 1] = fma(sP, vp1, cP * vq1);
-              }
-            }
-          }
+        jacobi_rot(H, n, ldh, pk, qk, &ck, &sk);
+        it.load(H, ldh, Vt, ldv, n, npair, inv, nitem, tid, pk, qk);  // the first pass's item
+      }
+      __syncthreads();  // every rotation input is read before any block is written
+      if (has_items) {
+        for (int base = 0; base < nitem; base += nthr) {
+          if (base + (tid & ~63) >= nitem) break;  // uniform per wavefront
+          // later passes load after the barrier: their entries belong to
+          // their own items only
+          if (base > 0) it.load(H, ldh, Vt, ldv, n, npair, inv, nitem, base + tid, pk, qk);
+          it.update(H, ldh, Vt, ldv, n, ck, sk);
         }
       }
       __syncthreads();
-      double* tmp = Ha;
-      Ha = Hb;
-      Hb = tmp;
     }
   }
-  *Hc = Ha;
   return nsweep;
 }
 
@@ -1067,7 +1083,7 @@ constexpr int kCholB = 32;
 __host__ __device__ constexpr int chol_inv_lds_doubles(int n) {
   return n * (kCholB + 1) > kCholB * (n + 1) ? n * (kCholB + 1) : kCholB * (n + 1);
 }
-__device__ bool chol_inv_blocked(double* __restrict__ A, double* __restrict__ Wm, int n, int ld,
+__device__ __forceinline__ bool chol_inv_blocked(double* __restrict__ A, double* __restrict__ Wm, int n, int ld,
                                  double* __restrict__ sm, int tid, int nthr) {
   constexpr int B = kCholB, PS = kCholB + 1;
   __shared__ double piv[kCholB];
@@ -1192,8 +1208,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   const int n = cd.nb;
   const int tid = threadIdx.x, nthr = blockDim.x;
   // use_lds 1: the four matrices in LDS; 0: in global memory; 2: in global
-  // memory except H', which the Jacobi rounds keep in LDS (up to 128 bands);
-  // 3: as 2 with a second H' buffer in LDS for the one-barrier rounds
+  // memory except H', which the Jacobi rounds keep in LDS (up to 128 bands)
   const bool all_lds = use_lds == 1;
   // row stride of the four matrices: n + 1 in LDS (rows and columns of
   // FP64 entries then fall in different banks), n in global memory
@@ -1217,7 +1232,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     P3 = cd.M;
   }
   // H' from the congruence on (the input H stays in P1)
-  const bool h_lds = use_lds == 2 || use_lds == 3;
+  const bool h_lds = use_lds == 2;
   double* H1 = h_lds ? (double*)smem : P1;
   const int ldh = h_lds ? n + 1 : ld;
   __shared__ int fail;
@@ -1376,21 +1391,9 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     const int npair = n2 / 2;
     if (clk && tid == 0) clk[2] = clock64();
     int nsweep = 0;
-    // second H' buffer of the one-barrier rounds: L's storage when all four
-    // matrices are in LDS (L is not needed again), else the LDS after H'
-    double* H2 = all_lds ? P0 : (use_lds == 3 ? H1 + n * ldh : nullptr);
-    if (H2 && npair <= kJacDbPairs) {
-      double* Hc = H1;
-      nsweep = jacobi_sweeps_db(H1, H2, ldh, P3, ld, n, max_sweeps, sh, tid, nthr, &Hc);
-      if (Hc != H1) {
-        for (int e = tid; e < n * n; e += nthr) {
-          const int i = e / n, j = e - i * n;
-          H1[i * ldh + j] = Hc[i * ldh + j];
-        }
-        __syncthreads();
-      }
-    }
-    for (int sweep = 0; sweep < (H2 && npair <= kJacDbPairs ? 0 : max_sweeps); ++sweep) {
+    const bool fast = npair <= kJacFastPairs;
+    if (fast) nsweep = jacobi_sweeps_fast(H1, ldh, P3, ld, n, max_sweeps, sh, tid, nthr);
+    for (int sweep = 0; sweep < (fast ? 0 : max_sweeps); ++sweep) {
       double v[2] = {0.0, 0.0};
       for (int e = tid; e < n * n; e += nthr) {
         const int i = e / n, j = e % n;
@@ -1866,17 +1869,12 @@ void launch_occupations(const LaunchCtx& L) {
 // memory only for V's column pairs), else all in global memory; and the
 // dynamic LDS that form needs (the blocked Cholesky's panels share it).
 // LDS form of the subspace solver by band count: 1 up to 64 (all four
-// matrices), 3 up to kSubDbBands (two H' buffers: 2 (n^2 + n) doubles, 124 KB
-// at 88 bands, which leave the static arrays room in 160 KB), 2 up to 128
-// (one H' buffer), else 0
-constexpr int kSubDbBands = 88;
-static int sub_lds_form(int n) {
-  return n <= 64 ? 1 : (n <= kSubDbBands ? 3 : (n <= 128 ? 2 : 0));
-}
+// matrices), 2 up to 128 (H' only), else 0
+static int sub_lds_form(int n) { return n <= 64 ? 1 : (n <= 128 ? 2 : 0); }
 static size_t sub_lds_bytes(int n, int form) {
   if (form == 1) return sizeof(double) * 4 * (size_t)n * (n + 1);
   const size_t chol = (size_t)chol_inv_lds_doubles(n);
-  const size_t h = (form == 2 ? 1 : (form == 3 ? 2 : 0)) * (size_t)n * (n + 1);
+  const size_t h = form == 2 ? (size_t)n * (n + 1) : 0;
   return sizeof(double) * std::max(chol, h);
 }
 
@@ -1888,9 +1886,6 @@ static void launch_k_subspace(int form, dim3 grid, dim3 block, size_t lds, hipSt
       break;
     case 2:
       hipLaunchKernelGGL(k_subspace<2>, grid, block, lds, st, desc, mode, max_sweeps, phase);
-      break;
-    case 3:
-      hipLaunchKernelGGL(k_subspace<3>, grid, block, lds, st, desc, mode, max_sweeps, phase);
       break;
     default:
       hipLaunchKernelGGL(k_subspace<0>, grid, block, lds, st, desc, mode, max_sweeps, phase);
@@ -2005,10 +2000,9 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
                       max_sweeps, 1);
     hipLaunchKernelGGL(k_sub_wh, ge, dim3(kNT), 0, L.stream, L.desc);
     hipLaunchKernelGGL(k_sub_twt, ge, dim3(kNT), 0, L.stream, L.desc);
-    const int jl = n <= kSubDbBands ? 3 : (n <= 128 ? 2 : 0);
-    launch_k_subspace(jl, dim3(L.g.ncand), dim3(nthr),
-                      sizeof(double) * (size_t)(jl == 3 ? 2 : (jl == 2 ? 1 : 0)) * n * (n + 1), L.stream,
-                      L.desc, mode, max_sweeps, 3);
+    const int jl = n <= 128 ? 2 : 0;
+    launch_k_subspace(jl, dim3(L.g.ncand), dim3(nthr), jl == 2 ? sizeof(double) * (size_t)n * (n + 1) : 0,
+                      L.stream, L.desc, mode, max_sweeps, 3);
     hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
     launch_k_subspace(0, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, max_sweeps, 2);
   } else {
@@ -2113,7 +2107,6 @@ void configure_kernels() {
   allow_lds((const void*)k_subspace<0>);
   allow_lds((const void*)k_subspace<1>);
   allow_lds((const void*)k_subspace<2>);
-  allow_lds((const void*)k_subspace<3>);
   configure_wave();
   configure_plane_kernels();
   configure_kpt_kernels();
