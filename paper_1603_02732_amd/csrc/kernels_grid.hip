@@ -1018,8 +1018,11 @@ struct JacItem {
   }
 };
 constexpr int kJacFastPairs = 64;
+// nthr_norm: the thread stride of the off-diagonal norm's partial sums (the
+// block's thread count, or a smaller one whose sums another launch shape
+// must reproduce bit for bit)
 __device__ int jacobi_sweeps_fast(double* H, int ldh, double* Vt, int ldv, int n, int max_sweeps,
-                                  double* sh, int tid, int nthr) {
+                                  double* sh, int tid, int nthr, int nthr_norm) {
   const int n2 = n + (n & 1), npair = n2 / 2, m = n2 - 1;
   const int lane = tid & 63;
   // item t = P npair + Q; t / npair as a multiply-shift (exact for t < 4096,
@@ -1032,12 +1035,13 @@ __device__ int jacobi_sweeps_fast(double* H, int ldh, double* Vt, int ldv, int n
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     // the norms in the two-barrier form's order (the same sweep counts)
     double v[2] = {0.0, 0.0};
-    for (int e = tid; e < n * n; e += nthr) {
-      const int i = e / n, j = e - i * n;
-      const double a = H[i * ldh + j];
-      if (i == j) v[1] += a * a;
-      else v[0] += a * a;
-    }
+    if (tid < nthr_norm)
+      for (int e = tid; e < n * n; e += nthr_norm) {
+        const int i = e / n, j = e - i * n;
+        const double a = H[i * ldh + j];
+        if (i == j) v[1] += a * a;
+        else v[0] += a * a;
+      }
     block_sum<2>(v, sh);
     if (!(v[0] > 1e-26 * v[1] + 1e-300)) break;
     ++nsweep;
@@ -1392,7 +1396,7 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
     if (clk && tid == 0) clk[2] = clock64();
     int nsweep = 0;
     const bool fast = npair <= kJacFastPairs;
-    if (fast) nsweep = jacobi_sweeps_fast(H1, ldh, P3, ld, n, max_sweeps, sh, tid, nthr);
+    if (fast) nsweep = jacobi_sweeps_fast(H1, ldh, P3, ld, n, max_sweeps, sh, tid, nthr, nthr);
     for (int sweep = 0; sweep < (fast ? 0 : max_sweeps); ++sweep) {
       double v[2] = {0.0, 0.0};
       for (int e = tid; e < n * n; e += nthr) {
@@ -1511,6 +1515,34 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
   }
   for (int i = tid; i < n; i += nthr) cd.eps[rank[i]] = H1[i * ldh + i];
   if (clk && tid == 0) clk[4] = clock64();
+}
+
+// The Jacobi rounds of the mid path (65-128 bands) on their own: H' (formed
+// over the GPU, in Hs) in LDS, V^T (= I, in M) rotated in global memory.  A
+// round of 111 rounds per sweep at 112 bands has 3,136 items; 1024 threads
+// take them in four passes where k_subspace's 512 (bounded by the registers
+// of its Cholesky) need seven.  The off-diagonal norm keeps the partial sums
+// of `nthr_norm` threads, so the results are those of k_subspace's phase 3
+// bit for bit.
+constexpr int kSubJacThreads = 1024;
+__global__ void __launch_bounds__(kSubJacThreads) k_sub_jacobi(const CandDesc* __restrict__ cds,
+                                                              int max_sweeps, int nthr_norm) {
+  const CandDesc& cd = cds[blockIdx.x];
+  if (!cd.active || cd.scal[S_ERR] == 2.0) return;  // inactive, or this call's Cholesky failed
+  const int n = cd.nb, tid = threadIdx.x, nthr = blockDim.x, ldh = n + 1;
+  extern __shared__ __align__(16) char smem[];
+  double* H = (double*)smem;
+  __shared__ double sh[16 * 2];
+  for (int e = tid; e < n * n; e += nthr) {
+    const int i = e / n, j = e - i * n;
+    H[i * ldh + j] = cd.Hs[e];
+  }
+  __syncthreads();
+  jacobi_sweeps_fast(H, ldh, cd.M, n, n, max_sweeps, sh, tid, nthr, min(nthr_norm, nthr));
+  for (int e = tid; e < n * n; e += nthr) {
+    const int i = e / n, j = e - i * n;
+    cd.Hs[e] = H[i * ldh + j];
+  }
 }
 
 // ------------------------------------- subspace products over the GPU
@@ -2000,9 +2032,13 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
                       max_sweeps, 1);
     hipLaunchKernelGGL(k_sub_wh, ge, dim3(kNT), 0, L.stream, L.desc);
     hipLaunchKernelGGL(k_sub_twt, ge, dim3(kNT), 0, L.stream, L.desc);
-    const int jl = n <= 128 ? 2 : 0;
-    launch_k_subspace(jl, dim3(L.g.ncand), dim3(nthr), jl == 2 ? sizeof(double) * (size_t)n * (n + 1) : 0,
-                      L.stream, L.desc, mode, max_sweeps, 3);
+    if (n <= 128) {
+      hipLaunchKernelGGL(k_sub_jacobi, dim3(L.g.ncand), dim3(kSubJacThreads),
+                         sizeof(double) * (size_t)n * (n + 1), L.stream, L.desc, max_sweeps, nthr);
+      check_launch("k_sub_jacobi");
+    } else {
+      launch_k_subspace(0, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, max_sweeps, 3);
+    }
     hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
     launch_k_subspace(0, dim3(L.g.ncand), dim3(nthr), 0, L.stream, L.desc, mode, max_sweeps, 2);
   } else {
@@ -2107,6 +2143,7 @@ void configure_kernels() {
   allow_lds((const void*)k_subspace<0>);
   allow_lds((const void*)k_subspace<1>);
   allow_lds((const void*)k_subspace<2>);
+  allow_lds((const void*)k_sub_jacobi);
   configure_wave();
   configure_plane_kernels();
   configure_kpt_kernels();
