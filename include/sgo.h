@@ -313,7 +313,8 @@ int sgo_subspace_solve_noalloc(int device, int n, int mode, const double* S, con
 
 /* Launch-schedule tuning (process-wide; read when a solve starts).  Keys:
  * "SGO_GRAM_KC" (K range of one split-K Gram block, multiple of 32),
- * "SGO_SUB_THREADS" (threads of the subspace solver, 64..512),
+ * "SGO_SUB_THREADS" (threads of the subspace solver's workgroup, 64..512; the
+ * Jacobi rounds of 65 to 128 bands always run on 1024 threads),
  * "SGO_SP_CHUNK" (stick pairs per block of the z transforms),
  * "SGO_DENS_CHUNKS" (band-pair chunks of the density planes),
  * "SGO_RR_SWEEPS" (Jacobi sweeps of the intermediate subspace steps),
