@@ -315,7 +315,8 @@ int sgo_subspace_solve_noalloc(int device, int n, int mode, const double* S, con
  * "SGO_GRAM_KC" (K range of one split-K Gram block, multiple of 32),
  * "SGO_SUB_THREADS" (threads of the subspace solver's workgroup, 64..512; the
  * Jacobi rounds of 65 to 128 bands always run on 1024 threads),
- * "SGO_SP_CHUNK" (stick pairs per block of the z transforms),
+ * "SGO_SP_CHUNK" (stick pairs per block of the LDS z transforms, used by
+ * FP64 and by lines longer than 64; the FP32 register z passes take 16),
  * "SGO_DENS_CHUNKS" (band-pair chunks of the density planes),
  * "SGO_RR_SWEEPS" (Jacobi sweeps of the intermediate subspace steps),
  * "SGO_PLANE_KERNEL" (FP32 plane transforms: 1 = register-resident line
