@@ -944,24 +944,6 @@ __device__ __forceinline__ void jacobi_rot(const double* A, int n, int ld, int p
   *s = t * cc;
 }
 
-// Cyclic Jacobi sweeps, in place, for up to 128 indices (64 pairs).  A round
-// is a chain of dependent steps (pair indices, loads, rotation, update), and
-// one wavefront issues a vector instruction every few cycles, so the round's
-// time is that chain's instruction count and memory latency, not its FP64
-// work:
-//  - a work item is the 2x2 block (row pair P, column pair Q) of H' together
-//    with columns 2Q and 2Q + 1 of V^T's rows of pair P: items own disjoint
-//    entries, so they update in place; wavefronts without items skip the
-//    round;
-//  - each wavefront computes the round's rotations itself (lane k: pair
-//    k mod npair) and the items read them, and the pair indices, from those
-//    lanes' registers; the first items' loads are issued beside the
-//    rotations, and one barrier then separates every read of the round's
-//    rotation inputs from the first write.
-// The updates are written as fma(x, y, -/+ z w) for x y -/+ z w, the rounding
-// the compiler gives the two-barrier form below, so both give the same bits.
-// Stops when the off-diagonal norm is below 1e-13 of the diagonal norm;
-// returns the sweeps done.
 // One work item of a fast Jacobi round: block (P, Q) of H' and columns 2Q,
 // 2Q + 1 of V^T's rows of pair P, loaded into registers, then rotated and
 // stored.  Every lane of the wavefront calls load and update (the pair
@@ -1017,6 +999,25 @@ struct JacItem {
     }
   }
 };
+// Cyclic Jacobi sweeps, in place, for up to 128 indices (64 pairs).  A round
+// is a chain of dependent steps (pair indices, loads, rotation, update), and
+// one wavefront issues a vector instruction every few cycles, so the round's
+// time is that chain's instruction count and memory latency, not its FP64
+// work:
+//  - a work item is the 2x2 block (row pair P, column pair Q) of H' together
+//    with columns 2Q and 2Q + 1 of V^T's rows of pair P: items own disjoint
+//    entries, so they update in place; wavefronts without items skip the
+//    round;
+//  - each wavefront computes the round's rotations itself (lane k: pair
+//    k mod npair) and the items read them, and the pair indices, from those
+//    lanes' registers; the first items' loads are issued beside the
+//    rotations, and one barrier then separates every read of the round's
+//    rotation inputs from the first write.
+// The updates are written as fma(x, y, -/+ z w) for x y -/+ z w, the rounding
+// the compiler gives the two-barrier rounds in k_subspace (used above 128
+// bands), so both give the same bits.
+// Stops when the off-diagonal norm is below 1e-13 of the diagonal norm;
+// returns the sweeps done.
 constexpr int kJacFastPairs = 64;
 // nthr_norm: the thread stride of the off-diagonal norm's partial sums (the
 // block's thread count, or a smaller one whose sums another launch shape
@@ -1518,10 +1519,10 @@ __global__ void __launch_bounds__(kSubNT) k_subspace(const CandDesc* __restrict_
 }
 
 // The Jacobi rounds of the mid path (65-128 bands) on their own: H' (formed
-// over the GPU, in Hs) in LDS, V^T (= I, in M) rotated in global memory.  A
-// round of 111 rounds per sweep at 112 bands has 3,136 items; 1024 threads
-// take them in four passes where k_subspace's 512 (bounded by the registers
-// of its Cholesky) need seven.  The off-diagonal norm keeps the partial sums
+// over the GPU, in Hs) in LDS, V^T (= I, in M) rotated in global memory.  At
+// 112 bands a sweep has 111 rounds of 3,136 items each; 1024 threads take a
+// round's items in four passes where k_subspace's 512 (bounded by the
+// registers of its Cholesky) need seven.  The off-diagonal norm keeps the partial sums
 // of `nthr_norm` threads, so the results are those of k_subspace's phase 3
 // bit for bit.
 constexpr int kSubJacThreads = 1024;
