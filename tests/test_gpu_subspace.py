@@ -72,3 +72,24 @@ def test_not_positive_definite_is_an_error():
     S[2, 2] = -1.0
     with pytest.raises(sgo.SgoError):
         sgo.subspace_solve(S, np.eye(4), mode=3)
+
+
+@pytest.mark.parametrize("threads", [64, 128, 256])
+@pytest.mark.parametrize("n", [32, 80])
+def test_rayleigh_ritz_at_other_workgroup_sizes(threads, n, monkeypatch):
+    # the thread count is a tuning key: the Jacobi rounds, the norms and the
+    # passes over the items depend on it, the results must not
+    import paper_1603_02732_amd as sgo
+    monkeypatch.setenv("SGO_SUB_THREADS", str(threads))
+    rng = np.random.default_rng(300 + n)
+    A = rng.standard_normal((n, n))
+    H = (A + A.T) / 2
+    E = rng.standard_normal((n, n)) * 0.05 / np.sqrt(n)
+    S = np.eye(n) + (E + E.T) / 2
+    S = S @ S.T
+    M, eps, _, _ = sgo.subspace_solve(S, H, mode=3)
+    ref = scipy.linalg.eigh(H, S, eigvals_only=True)
+    say("n=%d threads=%d eig err %.2e" % (n, threads, np.abs(eps - ref).max()))
+    assert np.abs(eps - ref).max() < 1e-11 * max(1, np.abs(ref).max())
+    assert np.abs(M.T @ S @ M - np.eye(n)).max() < 1e-10
+    assert np.abs(M.T @ H @ M - np.diag(eps)).max() < 1e-10 * max(1, np.abs(ref).max())
